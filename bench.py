@@ -1,0 +1,173 @@
+"""Benchmark: smoothed steps per second per iteration of the parallel iterated
+smoother on one MI355X.
+
+Workload (default): coordinated-turn target, two bearing sensors, T = 2^15
+measurements (32769 slots), FP64, Taylor (IEKS) linearisation.  One "step" of
+this benchmark is one full iteration of the method: linearise every slot,
+build the filtering elements, prefix-scan them, build the smoothing elements,
+suffix-scan them, and reduce the convergence statistic.  Inputs are resident
+on the GPU before timing starts.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--lin taylor|cubature|unscented]
+
+Prints one JSON line on stdout; details go to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "smoothed steps/sec per iteration at T=2^15 FP64; time-to-converge learned vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: int, K: int = 2) -> float:
+    """Minimum bytes each kernel family must move per slot / scan position:
+    every input read once, every output written once (FP words of `word` bytes)."""
+    s = n * (n + 1) // 2
+    sp = p * (p + 1) // 2
+    fe = n * n + 2 * n + 2 * s          # filtering element (A, b, C, eta, J)
+    se = n * n + n + s                  # smoothing element (E, g, L)
+    car = n + s                         # carry / trajectory slot (mean, packed covariance)
+    lin_words = n * n + n + s + p * n + p + sp + p
+    words = {
+        "linearize": n + p + (s if lin != "taylor" else 0) + lin_words,
+        "filter_elements": lin_words + fe,
+        "scan_up_filter": fe + fe / K,
+        "scan_top_filter": fe + car,
+        "scan_down_filter": fe + fe / K + car,
+        "smoother_elements": car + (n * n + n + s) + se,
+        "scan_up_smoother": se + se / K,
+        "scan_top_smoother": se + car,
+        "scan_down_smoother": se + se / K + car,
+        "delta": 2 * n,
+        "reset_delta": 1,
+        "sequential": lin_words + 2 * car,
+    }[kernel]
+    extra = {"linearize": 1, "filter_elements": 1, "smoother_elements": 1, "delta": 4}.get(kernel, 0)
+    return words * word + extra
+
+
+def cpu_baseline(pb, lin: str, budget_s: float) -> dict:
+    """The oracle, untuned, on one host core: repeated full iterations of the same
+    workload until about budget_s seconds of CPU time have been spent."""
+    import oracle
+    T = int(pb.offsets[1])
+    t0 = time.perf_counter()
+    iters = 0
+    while True:
+        oracle.smoother(pb, 1, lin, filtered=False)
+        iters += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": T * iters / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"T={T}, {iters} iterations from the prior broadcast ({dt:.1f} s, 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--T", type=int, default=2 ** 15)
+    ap.add_argument("--lin", default="taylor", choices=["taylor", "cubature", "unscented"])
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the smoother's single-track "
+                          "workload is not sharded across GPUs", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2102_00514_amd import binding
+    from paper_2102_00514_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    pb = wl.config_c2(args.T)
+    T = int(pb.offsets[1])
+    stream = torch.cuda.current_stream()
+    total_iters = args.warmup + args.steps + args.profile_iters
+    sm = binding.Smoother(pb, stream=stream.cuda_stream, n_iter=total_iters, lin=args.lin,
+                          precision=args.precision)
+    S, _, dev_bytes = sm.info()
+    log(f"workload: T={T} slots={S} lin={args.lin} precision={args.precision} device_bytes={dev_bytes}")
+
+    sm.iterate(args.warmup, want_delta=False)
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_stop = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    sm.iterate(args.steps, want_delta=False)
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_start.elapsed_time(t_stop)
+    ms_per_step = ms_total / args.steps
+    value = T / (ms_per_step * 1e-3)
+    log(f"timed {args.steps} iterations: {ms_total:.3f} ms (events), {wall * 1e3:.3f} ms (host wall); "
+        f"{ms_per_step * 1e3:.1f} us/iteration")
+
+    # per-kernel durations from HIP events around each launch (separate pass)
+    prof = sm.profile(args.profile_iters)
+    torch.cuda.synchronize()
+    word = 8 if args.precision == "f64" else 4
+    rows = []
+    for name, (launches, tot_ms, positions) in prof.items():
+        per_iter_us = tot_ms * 1e3 / args.profile_iters
+        bpp = algorithmic_bytes_per_position(name, pb.nx, pb.ny, args.lin, word)
+        gbs = (bpp * positions) / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+        rows.append((per_iter_us, name, launches, tot_ms, positions, bpp, gbs))
+    rows.sort(reverse=True)
+    log(f"{'kernel':22s} {'us/iter':>9s} {'launches':>8s} {'avg us':>8s} {'B/pos':>7s} {'GB/s':>8s}")
+    for per_iter_us, name, launches, tot_ms, positions, bpp, gbs in rows:
+        log(f"{name:22s} {per_iter_us:9.2f} {launches:8d} {tot_ms * 1e3 / launches:8.2f} {bpp:7.0f} {gbs:8.1f}")
+    sum_us = sum(r[0] for r in rows)
+    log(f"sum of kernel time per iteration: {sum_us:.1f} us (vs {ms_per_step * 1e3:.1f} us end to end)")
+    dom = rows[0]
+    avg_launch_s = dom[3] * 1e-3 / dom[2]
+    bytes_per_launch = dom[5] * dom[4] / dom[2]
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom[1], "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": int(bytes_per_launch)}
+    sm.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(pb, args.lin, args.cpu_seconds)
+        log(f"cpu oracle: {cpu['value']:.4g} steps/s ({cpu['sample']})")
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"coordinated-turn + 2 bearings, T={T} ({S} slots), single track, "
+                               f"{'IEKS (Taylor)' if args.lin == 'taylor' else args.lin + ' SLR'}, "
+                               f"one iteration per step",
+                   "T": T, "nx": pb.nx, "ny": pb.ny, "lin": args.lin, "parallelism": "time-axis scan, 1 GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

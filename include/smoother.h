@@ -1,0 +1,167 @@
+/*
+ * smoother.h -- C ABI of the MI355X (gfx950) parallel-in-time iterated smoother.
+ *
+ * The library computes the iterated extended (Taylor) or sigma-point
+ * (statistical linear regression) Kalman smoother of Yaghoobi, Corenflos,
+ * Hassan and Sarkka, "Parallel Iterated Extended and Sigma-Point Kalman
+ * Smoothers" (ICASSP 2021), with the filter and the smoother of every
+ * iteration evaluated as associative scans (Section 4, eq. 13-19).
+ *
+ * Problem (Section 3, eq. 4): for every track,
+ *     x_k = f(x_{k-1}) + q_{k-1},   q ~ N(0, Q),      k = 1..T
+ *     y_k = h(x_k) + r_k,           r ~ N(0, R),
+ *     x_0 ~ N(m0, P0);
+ * wanted: Gaussian approximations N(xbar_k, Pbar_k) of p(x_k | y_{1:T}),
+ * k = 0..T, after M re-linearisations around the previous smoothed trajectory.
+ *
+ * f and h cannot cross a C ABI as device code, so they are chosen from a
+ * compiled-in registry (sm_model) with a parameter block:
+ *   SM_MODEL_LINEAR:      params = [F (nx*nx), c (nx), H (ny*nx), d (ny)],
+ *                         row-major; f(x) = F x + c, h(x) = H x + d.
+ *   SM_MODEL_CT_BEARINGS: params = [dt, (sx, sy, target) * ny]; the state is
+ *                         nx/5 stacked coordinated-turn blocks
+ *                         [px, py, vx, vy, omega]; sensor s measures
+ *                         atan2(py - sy, px - sx) of block `target`.
+ *                         Bearing innovations are wrapped to [-pi, pi) around
+ *                         h(xbar_k) of the current linearisation point.
+ *
+ * Conventions shared by every call:
+ *   - Status: every call returns sm_status and never aborts or throws across the
+ *     ABI; smoother_last_error() returns a message for the last failure.
+ *   - Ownership: smoother_init copies every input; the caller keeps its buffers.
+ *     The handle owns all device memory it allocates.  Result buffers are
+ *     caller-owned, on the host (smoother_result) or on the device
+ *     (smoother_result_device).
+ *   - Layout: row-major; tracks are concatenated.  Track i has
+ *     T_i = offsets[i+1] - offsets[i] >= 1 measurements and T_i + 1 states
+ *     (slots) x_0..x_T; state arrays hold the slots of track 0, then track 1, ...
+ *   - Streams: all device work of a handle is queued on the stream given to
+ *     smoother_init (NULL = the default stream).  One handle per host thread at
+ *     a time; handles on different streams are independent.
+ */
+#ifndef SMOOTHER_H_
+#define SMOOTHER_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smoother* smoother_t;
+
+typedef enum {
+  SM_OK = 0,
+  SM_EINVAL = 1,    /* invalid argument; decided on the host before device work */
+  SM_ENOMEM = 2,    /* device allocation failed or exceeds max_device_bytes */
+  SM_EDEVICE = 3,   /* HIP runtime error */
+  SM_ENUMERIC = 4,  /* non-finite iterate (see smoother_track_deltas) */
+  SM_ESTATE = 5     /* call not valid for this handle (e.g. NULL handle) */
+} sm_status;
+
+typedef enum { SM_MODEL_LINEAR = 0, SM_MODEL_CT_BEARINGS = 1 } sm_model;
+
+/* Linearisation (Section 3): first-order Taylor at the previous smoothed mean
+ * (eq. 10, IEKS) or statistical linear regression with sigma points of the
+ * previous smoothed mean and covariance (eq. 7-9, IPLS). */
+typedef enum { SM_LIN_TAYLOR = 0, SM_LIN_CUBATURE = 1, SM_LIN_UNSCENTED = 2 } sm_lin;
+
+typedef enum { SM_FP64 = 0, SM_FP32 = 1 } sm_precision;
+
+/* SM_SCAN_PARALLEL: prefix/suffix associative scans (eq. 15, eq. 19).
+ * SM_SCAN_SEQUENTIAL: the same linearised model filtered and smoothed by the
+ * sequential Kalman/RTS recursions, one lane per track (comparison baseline). */
+typedef enum { SM_SCAN_PARALLEL = 0, SM_SCAN_SEQUENTIAL = 1 } sm_scan;
+
+typedef struct {
+  int32_t nx, ny;                 /* state / measurement dimension */
+  int32_t n_tracks;               /* >= 1 */
+  const int64_t* offsets;         /* host [n_tracks+1], offsets[0] = 0, strictly increasing */
+  int32_t model;                  /* sm_model */
+  const double* params;           /* host [n_params], see sm_model */
+  int32_t n_params;
+  const double* Q;                /* host [nx*nx], symmetric positive definite */
+  const double* R;                /* host [ny*ny], symmetric positive definite */
+  const double* m0;               /* host [n_tracks*nx] */
+  const double* P0;               /* host [n_tracks*nx*nx], each symmetric positive definite */
+  const double* y;                /* host [offsets[n_tracks]*ny], y_1..y_T of each track */
+  int32_t n_iter;                 /* M, iterations run by smoother_iterate(h, 0) */
+  int32_t lin;                    /* sm_lin */
+  double ut_alpha, ut_beta, ut_kappa;  /* unscented parameters (lambda = alpha^2 (n+kappa) - n);
+                                          beta is accepted and unused: one weight set */
+  int32_t precision;              /* sm_precision */
+  int32_t scan;                   /* sm_scan */
+  const double* init_mean;        /* optional host [S*nx], S = sum(T_i+1); NULL = m0 broadcast */
+  const double* init_cov;         /* optional host [S*nx*nx]; NULL = P0 broadcast */
+  int64_t max_device_bytes;       /* 0 = no cap; otherwise SM_ENOMEM if the plan needs more */
+} sm_problem;
+
+/* Fills *pb with defaults: n_tracks = 1, n_iter = 10, lin = SM_LIN_TAYLOR,
+ * ut_alpha = 1, ut_beta = 0, ut_kappa = 1, FP64, parallel scan, no init, no cap. */
+void smoother_problem_defaults(sm_problem* pb);
+
+/* Validates the problem on the host (dimensions supported by the compiled
+ * kernels, offsets, finite inputs, positive-definite Q, R, P0), allocates
+ * device memory, copies the inputs to the device on `hip_stream` and sets the
+ * initial trajectory (eq. 4 prior broadcast, or init_mean/init_cov).
+ * On success *out is a new handle; on failure *out is NULL and the status says
+ * why (the message is available from smoother_last_error(NULL)). */
+sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out);
+
+/* Runs `k` more iterations (k <= 0: the iterations left up to n_iter).  Each
+ * iteration re-linearises around the current trajectory (Section 3), builds the
+ * filtering elements (eq. 13-14) and combines them with a prefix scan
+ * (eq. 15), builds the smoothing elements (eq. 16-18) and combines them with
+ * a suffix scan (eq. 19).  Work is queued on the handle's stream; when
+ * max_delta_out is not NULL the call waits and stores
+ * max_{tracks,k,j} |xbar_k,j^(i) - xbar_k,j^(i-1)| of the last iteration run.
+ * iters_done_out (nullable) receives the total number of iterations so far.
+ * Returns SM_ENUMERIC when max_delta_out was requested and is not finite. */
+sm_status smoother_iterate(smoother_t h, int32_t k, double* max_delta_out, int32_t* iters_done_out);
+
+/* Waits for the handle's stream and copies the current trajectory to host
+ * buffers: mean [S*nx], cov [S*nx*nx] (full symmetric matrices); either may be
+ * NULL.  S = sum(T_i + 1), slots of track 0 first. */
+sm_status smoother_result(smoother_t h, double* mean, double* cov);
+
+/* As smoother_result, into caller-owned device buffers (same layouts, double
+ * for SM_FP64 handles, float for SM_FP32 handles), queued on the handle's
+ * stream without a host wait. */
+sm_status smoother_result_device(smoother_t h, void* d_mean, void* d_cov);
+
+/* Per-track maximum |xbar^(i) - xbar^(i-1)| of the last iteration, host
+ * [n_tracks]; waits for the stream. */
+sm_status smoother_track_deltas(smoother_t h, double* deltas);
+
+/* Per-kernel timing record filled by smoother_profile. */
+typedef struct {
+  char name[40];        /* kernel family, e.g. "scan_up_filter" */
+  int32_t launches;     /* launches timed */
+  double total_ms;      /* sum of HIP-event durations of those launches */
+  int64_t positions;    /* sum over launches of the slots / scan positions processed */
+} sm_kernel_time;
+
+/* Runs k iterations exactly like smoother_iterate(h, k, NULL, NULL) but with a
+ * HIP event pair recorded on the handle's stream around every kernel launch,
+ * waits, and reports per-kernel-family totals in out[0..*n_out-1] (at most cap
+ * records).  The iterations advance the trajectory like any others. */
+sm_status smoother_profile(smoother_t h, int32_t k, sm_kernel_time* out, int32_t cap, int32_t* n_out);
+
+/* Number of slots S, tracks and the device bytes held by the handle. */
+sm_status smoother_info(smoother_t h, int64_t* n_slots, int32_t* n_tracks, int64_t* device_bytes);
+
+/* Message for the last failure of a call on h (h = NULL: the last failure of
+ * smoother_init on this thread).  Valid until the next call on h. */
+const char* smoother_last_error(smoother_t h);
+
+/* Releases the handle and its device memory; NULL-safe. */
+void smoother_destroy(smoother_t h);
+
+/* Library version string. */
+const char* smoother_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMOOTHER_H_ */

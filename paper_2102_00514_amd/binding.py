@@ -1,0 +1,253 @@
+"""Thin ctypes binding of ``libsmoother.so`` (include/smoother.h).
+
+Argument marshalling only: every step of the smoother runs in the HIP
+library.  If the library is missing, importing this module raises -- there is
+no fallback path.  PyTorch supplies device memory (result buffers) and the
+HIP stream the work is queued on.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from .workloads import Problem
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsmoother.so")
+
+SM_OK, SM_EINVAL, SM_ENOMEM, SM_EDEVICE, SM_ENUMERIC, SM_ESTATE = range(6)
+STATUS_NAMES = {0: "SM_OK", 1: "SM_EINVAL", 2: "SM_ENOMEM", 3: "SM_EDEVICE", 4: "SM_ENUMERIC", 5: "SM_ESTATE"}
+SM_MODEL_LINEAR, SM_MODEL_CT_BEARINGS = 0, 1
+LIN = {"taylor": 0, "cubature": 1, "unscented": 2}
+PRECISION = {"f64": 0, "f32": 1}
+SCAN = {"parallel": 0, "sequential": 1}
+
+EXPORTS = ("smoother_problem_defaults", "smoother_init", "smoother_iterate", "smoother_result",
+           "smoother_result_device", "smoother_track_deltas", "smoother_info", "smoother_last_error",
+           "smoother_destroy", "smoother_version", "smoother_profile")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class sm_problem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n_tracks", ctypes.c_int32),
+        ("offsets", _i64p),
+        ("model", ctypes.c_int32), ("params", _dp), ("n_params", ctypes.c_int32),
+        ("Q", _dp), ("R", _dp), ("m0", _dp), ("P0", _dp), ("y", _dp),
+        ("n_iter", ctypes.c_int32), ("lin", ctypes.c_int32),
+        ("ut_alpha", ctypes.c_double), ("ut_beta", ctypes.c_double), ("ut_kappa", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("scan", ctypes.c_int32),
+        ("init_mean", _dp), ("init_cov", _dp),
+        ("max_device_bytes", ctypes.c_int64),
+    ]
+
+
+class sm_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double),
+                ("positions", ctypes.c_int64)]
+
+
+class SmootherError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built (python -m paper_2102_00514_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.smoother_problem_defaults.argtypes = [ctypes.POINTER(sm_problem)]
+    lib.smoother_problem_defaults.restype = None
+    lib.smoother_init.argtypes = [ctypes.POINTER(sm_problem), vp, ctypes.POINTER(vp)]
+    lib.smoother_init.restype = ctypes.c_int
+    lib.smoother_iterate.argtypes = [vp, ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int32)]
+    lib.smoother_iterate.restype = ctypes.c_int
+    lib.smoother_result.argtypes = [vp, _dp, _dp]
+    lib.smoother_result.restype = ctypes.c_int
+    lib.smoother_result_device.argtypes = [vp, vp, vp]
+    lib.smoother_result_device.restype = ctypes.c_int
+    lib.smoother_track_deltas.argtypes = [vp, _dp]
+    lib.smoother_track_deltas.restype = ctypes.c_int
+    lib.smoother_info.argtypes = [vp, _i64p, ctypes.POINTER(ctypes.c_int32), _i64p]
+    lib.smoother_info.restype = ctypes.c_int
+    lib.smoother_last_error.argtypes = [vp]
+    lib.smoother_last_error.restype = ctypes.c_char_p
+    lib.smoother_destroy.argtypes = [vp]
+    lib.smoother_destroy.restype = None
+    lib.smoother_profile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(sm_kernel_time), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32)]
+    lib.smoother_profile.restype = ctypes.c_int
+    lib.smoother_version.argtypes = []
+    lib.smoother_version.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(h, st):
+    if st != SM_OK:
+        raise SmootherError(st, smoother_last_error(h))
+
+
+def smoother_last_error(h=None) -> str:
+    return _lib.smoother_last_error(h).decode()
+
+
+def make_problem(pb: Problem, n_iter: int = 10, lin: str = "taylor", precision: str = "f64",
+                 scan: str = "parallel", init_mean=None, init_cov=None, ut_alpha=1.0, ut_beta=0.0,
+                 ut_kappa=1.0, max_device_bytes: int = 0):
+    """sm_problem for a workloads.Problem; returns (struct, keep-alive arrays)."""
+    s = sm_problem()
+    _lib.smoother_problem_defaults(ctypes.byref(s))
+    keep = {
+        "offsets": np.ascontiguousarray(pb.offsets, dtype=np.int64),
+        "params": _f64(pb.params), "Q": _f64(pb.Q), "R": _f64(pb.R),
+        "m0": _f64(pb.m0), "P0": _f64(pb.P0), "y": _f64(pb.y),
+    }
+    if init_mean is not None:
+        keep["init_mean"] = _f64(init_mean)
+    if init_cov is not None:
+        keep["init_cov"] = _f64(init_cov)
+    s.nx, s.ny, s.n_tracks = pb.nx, pb.ny, pb.n_tracks
+    s.offsets = keep["offsets"].ctypes.data_as(_i64p)
+    s.model = pb.model
+    s.params, s.n_params = keep["params"].ctypes.data_as(_dp), keep["params"].size
+    for k in ("Q", "R", "m0", "P0", "y"):
+        setattr(s, k, keep[k].ctypes.data_as(_dp))
+    s.n_iter = n_iter
+    s.lin = LIN[lin]
+    s.ut_alpha, s.ut_beta, s.ut_kappa = ut_alpha, ut_beta, ut_kappa
+    s.precision = PRECISION[precision]
+    s.scan = SCAN[scan]
+    if "init_mean" in keep:
+        s.init_mean = keep["init_mean"].ctypes.data_as(_dp)
+    if "init_cov" in keep:
+        s.init_cov = keep["init_cov"].ctypes.data_as(_dp)
+    s.max_device_bytes = max_device_bytes
+    return s, keep
+
+
+def smoother_init(pb: Problem, stream: Optional[int] = None, **kw) -> int:
+    """Creates a handle; ``stream`` is a HIP stream handle (torch's
+    ``torch.cuda.current_stream().cuda_stream``), None = default stream."""
+    s, _keep = make_problem(pb, **kw)
+    h = ctypes.c_void_p()
+    st = _lib.smoother_init(ctypes.byref(s), ctypes.c_void_p(stream or 0), ctypes.byref(h))
+    if st != SM_OK:
+        raise SmootherError(st, smoother_last_error(None))
+    return h.value
+
+
+def smoother_iterate(h: int, k: int = 0, want_delta: bool = True):
+    """Runs k iterations (k <= 0: up to n_iter).  Returns (max_delta or None, iterations done)."""
+    d = ctypes.c_double(0.0)
+    it = ctypes.c_int32(0)
+    st = _lib.smoother_iterate(h, k, ctypes.byref(d) if want_delta else None, ctypes.byref(it))
+    if st == SM_ENUMERIC:
+        return float("nan"), it.value
+    _check(h, st)
+    return (d.value if want_delta else None), it.value
+
+
+def smoother_info(h: int):
+    S, T, B = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    _check(h, _lib.smoother_info(h, ctypes.byref(S), ctypes.byref(T), ctypes.byref(B)))
+    return S.value, T.value, B.value
+
+
+def smoother_result(h: int, nx: int):
+    """Host copy of the current trajectory: mean [S, nx], cov [S, nx, nx]."""
+    S, _, _ = smoother_info(h)
+    mean = np.empty((S, nx))
+    cov = np.empty((S, nx, nx))
+    _check(h, _lib.smoother_result(h, mean.ctypes.data_as(_dp), cov.ctypes.data_as(_dp)))
+    return mean, cov
+
+
+def smoother_result_device(h: int, mean_ptr: int, cov_ptr: int) -> None:
+    """Writes the trajectory into caller-owned device buffers (e.g. torch tensors' data_ptr())."""
+    _check(h, _lib.smoother_result_device(h, ctypes.c_void_p(mean_ptr), ctypes.c_void_p(cov_ptr)))
+
+
+def smoother_track_deltas(h: int) -> np.ndarray:
+    _, T, _ = smoother_info(h)
+    out = np.empty(T)
+    _check(h, _lib.smoother_track_deltas(h, out.ctypes.data_as(_dp)))
+    return out
+
+
+def smoother_profile(h: int, k: int) -> dict:
+    """Runs k iterations with per-launch HIP events; returns
+    {kernel family: (launches, total_ms, positions)}."""
+    cap = 64
+    recs = (sm_kernel_time * cap)()
+    n = ctypes.c_int32(0)
+    _check(h, _lib.smoother_profile(h, k, recs, cap, ctypes.byref(n)))
+    return {recs[i].name.decode(): (recs[i].launches, recs[i].total_ms, recs[i].positions) for i in range(n.value)}
+
+
+def smoother_destroy(h: int) -> None:
+    _lib.smoother_destroy(h)
+
+
+def smoother_version() -> str:
+    return _lib.smoother_version().decode()
+
+
+class Smoother:
+    """Owning wrapper around one handle (same calls, context-managed)."""
+
+    def __init__(self, pb: Problem, stream: Optional[int] = None, **kw):
+        self.nx = pb.nx
+        self.h = smoother_init(pb, stream, **kw)
+
+    def iterate(self, k: int = 0, want_delta: bool = True):
+        return smoother_iterate(self.h, k, want_delta)
+
+    def result(self):
+        return smoother_result(self.h, self.nx)
+
+    def result_device(self, mean_ptr: int, cov_ptr: int):
+        smoother_result_device(self.h, mean_ptr, cov_ptr)
+
+    def track_deltas(self):
+        return smoother_track_deltas(self.h)
+
+    def info(self):
+        return smoother_info(self.h)
+
+    def profile(self, k: int):
+        return smoother_profile(self.h, k)
+
+    def close(self):
+        if self.h:
+            smoother_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

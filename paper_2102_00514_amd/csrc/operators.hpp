@@ -1,0 +1,246 @@
+// The two associative operators of the method, per lane, on register tiles.
+//
+// Filtering (eq. 15), for a_i = (A_i, b_i, C_i, eta_i, J_i) followed by a_j:
+//   A_ij = A_j (I + C_i J_j)^-1 A_i
+//   b_ij = A_j (I + C_i J_j)^-1 (b_i + C_i eta_j) + b_j
+//   C_ij = A_j (I + C_i J_j)^-1 C_i A_j^T + C_j
+//   eta_ij = A_i^T (I + J_j C_i)^-1 (eta_j - J_j b_i) + eta_i
+//   J_ij = A_i^T (I + J_j C_i)^-1 J_j A_i + J_i
+// evaluated without forming or pivoting (I + C_i J_j): with C_i = U U^T
+// (Cholesky) and G = I + U^T J_j U = Lg Lg^T (symmetric, eigenvalues >= 1),
+//   M := (I + C_i J_j)^-1 C_i = U G^-1 U^T = W^T W,  W = Lg^-1 U^T,
+//   (I + C_i J_j)^-1 = I - M J_j,   (I + J_j C_i)^-1 = I - J_j M,
+// so with v = eta_j - J_j b_i and u = M v:
+//   b_ij = A_j (b_i + u) + b_j,        C_ij = A_j M A_j^T + C_j,
+//   A_ij = (A_j - A_j M J_j) A_i,      eta_ij = A_i^T (v - J_j u) + eta_i,
+//   J_ij = A_i^T (J_j - X^T X) A_i + J_i,   X = W J_j.
+// M, C_ij and J_ij are symmetric by construction.
+//
+// Smoothing (eq. 19): (E_i, g_i, L_i) x (E_j, g_j, L_j) =
+//   (E_i E_j, E_i g_j + g_i, E_i L_j E_i^T + L_i).
+//
+// Carries.  A filtering prefix that starts at a prior element (A = 0,
+// eta = 0, J = 0) keeps A = eta = J = 0, so it is carried as (b, C) = the
+// filtered mean and covariance; a smoothing suffix that ends at an end element
+// (E = 0) is carried as (g, L) = the smoothed mean and covariance.
+//
+// Scan order.  Both scans run left to right over "scan positions"; the
+// smoothing scan visits slots from last to first, so its scan-order combine of
+// an earlier position x with a later position y is y (x) x in the paper's order.
+#pragma once
+
+#include "linalg.hpp"
+
+namespace pks {
+
+template <int N, typename R>
+struct FilterOp {
+  struct Elem {
+    R A[N][N], b[N], C[N][N], eta[N], J[N][N];
+  };
+  struct Carry {
+    R b[N], C[N][N];
+  };
+  static constexpr int kS = sym_size<N>();
+  static constexpr int kElemWords = N * N + 2 * N + 2 * kS;
+  static constexpr int kCarryWords = N + kS;
+
+  static PKS_DEV void load(const R* p, size_t st, size_t i, Elem& e) {
+    ld_mat<N, N>(p, st, i, e.A);
+    ld_vec<N>(p + N * N * st, st, i, e.b);
+    ld_sym<N>(p + (N * N + N) * st, st, i, e.C);
+    ld_vec<N>(p + (N * N + N + kS) * st, st, i, e.eta);
+    ld_sym<N>(p + (N * N + 2 * N + kS) * st, st, i, e.J);
+  }
+  static PKS_DEV void store(R* p, size_t st, size_t i, const Elem& e) {
+    st_mat<N, N>(p, st, i, e.A);
+    st_vec<N>(p + N * N * st, st, i, e.b);
+    st_sym<N>(p + (N * N + N) * st, st, i, e.C);
+    st_vec<N>(p + (N * N + N + kS) * st, st, i, e.eta);
+    st_sym<N>(p + (N * N + 2 * N + kS) * st, st, i, e.J);
+  }
+  static PKS_DEV void load(const R* p, size_t st, size_t i, Carry& c) {
+    ld_vec<N>(p, st, i, c.b);
+    ld_sym<N>(p + N * st, st, i, c.C);
+  }
+  static PKS_DEV void store(R* p, size_t st, size_t i, const Carry& c) {
+    st_vec<N>(p, st, i, c.b);
+    st_sym<N>(p + N * st, st, i, c.C);
+  }
+  // A carry-form element (prior element or a prefix from one): take (b, C).
+  static PKS_DEV void to_carry(const Elem& e, Carry& c) {
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      c.b[i] = e.b[i];
+      PKS_UNROLL for (int j = 0; j < N; ++j) c.C[i][j] = e.C[i][j];
+    }
+  }
+
+  // M = (I + C J)^-1 C as W^T W; returns W (so that M = W^T W). ok = false if
+  // C is not positive definite.
+  static PKS_DEV bool core(const R (&Ci)[N][N], const R (&Jj)[N][N], R (&W)[N][N], R (&M)[N][N]) {
+    R U[N][N];
+    PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) U[i][j] = Ci[i][j];
+    bool ok = chol_inplace<N>(U);
+    PKS_UNROLL for (int i = 0; i < N; ++i) U[i][i] = R(1) / U[i][i];
+    // JU = J U (U lower triangular)
+    R JU[N][N];
+    PKS_UNROLL for (int i = 0; i < N; ++i)
+      PKS_UNROLL for (int k = 0; k < N; ++k) {
+        R s = Jj[i][k] * U[k][k];
+        PKS_UNROLL for (int t = k + 1; t < N; ++t) s += Jj[i][t] * U[t][k];
+        JU[i][k] = s;
+      }
+    // G = I + U^T J U
+    R G[N][N];
+    PKS_UNROLL for (int a = 0; a < N; ++a)
+      PKS_UNROLL for (int b = a; b < N; ++b) {
+        R s = (a == b) ? R(1) : R(0);
+        PKS_UNROLL for (int t = a; t < N; ++t) s += U[t][a] * JU[t][b];
+        G[a][b] = s;
+        G[b][a] = s;
+      }
+    ok = chol_inplace<N>(G) && ok;
+    // W = Lg^-1 U^T
+    PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) W[i][j] = (j >= i) ? U[j][i] : R(0);
+    chol_fwd<N, N>(G, W);
+    gram<N, N>(W, M);
+    return ok;
+  }
+
+  // out = l (x) r
+  static PKS_DEV void combine(const Elem& l, const Elem& r, Elem& o) {
+    R W[N][N], M[N][N];
+    const bool ok = core(l.C, r.J, W, M);
+    R v[N], u[N], Ju[N], bu[N];
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      R s = r.eta[i];
+      PKS_UNROLL for (int t = 0; t < N; ++t) s -= r.J[i][t] * l.b[t];
+      v[i] = s;
+    }
+    mat_vec<N, N>(M, v, u);
+    mat_vec<N, N>(r.J, u, Ju);
+    PKS_UNROLL for (int i = 0; i < N; ++i) bu[i] = l.b[i] + u[i];
+    // b, C
+    R AM[N][N];
+    mat_mul<N, N, N>(r.A, M, AM);
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      R s = r.b[i];
+      PKS_UNROLL for (int t = 0; t < N; ++t) s += r.A[i][t] * bu[t];
+      o.b[i] = s;
+    }
+    PKS_UNROLL for (int i = 0; i < N; ++i)
+      PKS_UNROLL for (int j = i; j < N; ++j) {
+        R s = r.C[i][j];
+        PKS_UNROLL for (int t = 0; t < N; ++t) s += AM[i][t] * r.A[j][t];
+        o.C[i][j] = s;
+        o.C[j][i] = s;
+      }
+    // A = (A_j - A_j M J_j) A_i
+    R T1[N][N];
+    PKS_UNROLL for (int i = 0; i < N; ++i)
+      PKS_UNROLL for (int j = 0; j < N; ++j) {
+        R s = r.A[i][j];
+        PKS_UNROLL for (int t = 0; t < N; ++t) s -= AM[i][t] * r.J[t][j];
+        T1[i][j] = s;
+      }
+    mat_mul<N, N, N>(T1, l.A, o.A);
+    // eta = A_i^T (v - J u) + eta_i
+    PKS_UNROLL for (int i = 0; i < N; ++i) v[i] -= Ju[i];
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      R s = l.eta[i];
+      PKS_UNROLL for (int t = 0; t < N; ++t) s += l.A[t][i] * v[t];
+      o.eta[i] = s;
+    }
+    // J = A_i^T (J_j - X^T X) A_i + J_i, X = W J_j
+    R X[N][N], MJ[N][N];
+    mat_mul<N, N, N>(W, r.J, X);
+    PKS_UNROLL for (int a = 0; a < N; ++a)
+      PKS_UNROLL for (int b = a; b < N; ++b) {
+        R s = r.J[a][b];
+        PKS_UNROLL for (int t = 0; t < N; ++t) s -= X[t][a] * X[t][b];
+        MJ[a][b] = s;
+        MJ[b][a] = s;
+      }
+    tsandwich_add<N, N>(l.A, MJ, l.J, o.J);
+    if (!ok) o.b[0] = quiet_nan<R>();
+  }
+
+  // out = c (x) r for a carry c
+  static PKS_DEV void apply(const Carry& c, const Elem& r, Carry& o) {
+    R W[N][N], M[N][N];
+    const bool ok = core(c.C, r.J, W, M);
+    R v[N], u[N], bu[N];
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      R s = r.eta[i];
+      PKS_UNROLL for (int t = 0; t < N; ++t) s -= r.J[i][t] * c.b[t];
+      v[i] = s;
+    }
+    mat_vec<N, N>(M, v, u);
+    PKS_UNROLL for (int i = 0; i < N; ++i) bu[i] = c.b[i] + u[i];
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      R s = r.b[i];
+      PKS_UNROLL for (int t = 0; t < N; ++t) s += r.A[i][t] * bu[t];
+      o.b[i] = s;
+    }
+    sandwich_add<N, N>(r.A, M, r.C, o.C);
+    if (!ok) o.b[0] = quiet_nan<R>();
+  }
+};
+
+template <int N, typename R>
+struct SmootherOp {
+  struct Elem {
+    R E[N][N], g[N], L[N][N];
+  };
+  struct Carry {
+    R g[N], L[N][N];
+  };
+  static constexpr int kS = sym_size<N>();
+  static constexpr int kElemWords = N * N + N + kS;
+  static constexpr int kCarryWords = N + kS;
+
+  static PKS_DEV void load(const R* p, size_t st, size_t i, Elem& e) {
+    ld_mat<N, N>(p, st, i, e.E);
+    ld_vec<N>(p + N * N * st, st, i, e.g);
+    ld_sym<N>(p + (N * N + N) * st, st, i, e.L);
+  }
+  static PKS_DEV void store(R* p, size_t st, size_t i, const Elem& e) {
+    st_mat<N, N>(p, st, i, e.E);
+    st_vec<N>(p + N * N * st, st, i, e.g);
+    st_sym<N>(p + (N * N + N) * st, st, i, e.L);
+  }
+  static PKS_DEV void load(const R* p, size_t st, size_t i, Carry& c) {
+    ld_vec<N>(p, st, i, c.g);
+    ld_sym<N>(p + N * st, st, i, c.L);
+  }
+  static PKS_DEV void store(R* p, size_t st, size_t i, const Carry& c) {
+    st_vec<N>(p, st, i, c.g);
+    st_sym<N>(p + N * st, st, i, c.L);
+  }
+  static PKS_DEV void to_carry(const Elem& e, Carry& c) {
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      c.g[i] = e.g[i];
+      PKS_UNROLL for (int j = 0; j < N; ++j) c.L[i][j] = e.L[i][j];
+    }
+  }
+  // Scan order: x precedes y in the scan (x is the later slot); out = y (x) x.
+  static PKS_DEV void combine(const Elem& x, const Elem& y, Elem& o) {
+    mat_mul<N, N, N>(y.E, x.E, o.E);
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      R s = y.g[i];
+      PKS_UNROLL for (int t = 0; t < N; ++t) s += y.E[i][t] * x.g[t];
+      o.g[i] = s;
+    }
+    sandwich_add<N, N>(y.E, x.L, y.L, o.L);
+  }
+  static PKS_DEV void apply(const Carry& c, const Elem& y, Carry& o) {
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      R s = y.g[i];
+      PKS_UNROLL for (int t = 0; t < N; ++t) s += y.E[i][t] * c.g[t];
+      o.g[i] = s;
+    }
+    sandwich_add<N, N>(y.E, c.L, y.L, o.L);
+  }
+};
+
+}  // namespace pks

@@ -1,0 +1,180 @@
+// Device-wide inclusive scan with an expensive associative operator.
+//
+// Scan positions 0..m-1 are cut into tiles of B lanes x K positions.  Each lane
+// folds its K consecutive elements sequentially; the B lane aggregates of a
+// tile are scanned in LDS by a Kogge-Stone ladder (log2 B combine steps, all
+// lanes busy, entry-major LDS layout so that lane i touches word i of each row:
+// no bank conflicts).  The up-sweep writes every lane's exclusive prefix and the
+// tile aggregate; the tile aggregates are scanned recursively; the down-sweep
+// then starts each lane from (tile carry) (x) (lane exclusive prefix) and walks
+// its K elements with the cheap carry form of the operator, writing the
+// inclusive prefix of every position.
+//
+// The first scan position always holds a carry-form element (a prior element
+// for filtering, an end element for smoothing), so every prefix that starts at
+// position 0 is a carry and no identity element is ever needed.
+#pragma once
+
+#include "linalg.hpp"
+
+namespace pks {
+
+struct ScanArgs {
+  const void* elems;   // elements, [kElemWords][estride]
+  size_t estride;
+  int64_t m;           // number of scan positions
+  int reverse;         // position q is stored at index m-1-q (level 0 only)
+  int K;               // positions per lane
+  void* lane_excl;     // [kElemWords][lstride], lane exclusive prefixes
+  size_t lstride;
+  void* tile_agg;      // [kElemWords][tstride], tile aggregates (scan order)
+  size_t tstride;
+  const void* tile_carry;  // [kCarryWords][cstride], inclusive carries of the tiles
+  size_t cstride;
+  void* out;           // [kCarryWords][ostride], inclusive carry of every position
+  size_t ostride;
+};
+
+// Kogge-Stone over the lanes of a block.  On entry v holds the lane aggregate
+// (valid lanes only); on exit v holds the inclusive prefix over lanes 0..lane
+// and the LDS rows hold the same values.
+template <class Op, int B, typename R>
+PKS_DEV void block_ladder(R* lds, int lane, bool valid, typename Op::Elem& v) {
+  if (valid) Op::store(lds, B, lane, v);
+  __syncthreads();
+  PKS_UNROLL for (int d = 1; d < B; d <<= 1) {
+    typename Op::Elem left, res;
+    const bool act = valid && lane >= d;
+    if (act) {
+      Op::load(lds, B, lane - d, left);
+      Op::combine(left, v, res);
+    }
+    __syncthreads();
+    if (act) {
+      v = res;
+      Op::store(lds, B, lane, v);
+    }
+    __syncthreads();
+  }
+}
+
+template <class Op, int B, typename R>
+__global__ __launch_bounds__(B) void k_scan_up(ScanArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* lds = reinterpret_cast<R*>(smem_raw);
+  const R* E = static_cast<const R*>(a.elems);
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t first = (tile * B + lane) * a.K;
+  const bool valid = first < a.m;
+  typename Op::Elem v;
+  if (valid) {
+    const int64_t idx0 = a.reverse ? a.m - 1 - first : first;
+    Op::load(E, a.estride, idx0, v);
+    for (int j = 1; j < a.K; ++j) {
+      const int64_t q = first + j;
+      if (q >= a.m) break;
+      typename Op::Elem e, r;
+      Op::load(E, a.estride, a.reverse ? a.m - 1 - q : q, e);
+      Op::combine(v, e, r);
+      v = r;
+    }
+  }
+  block_ladder<Op, B, R>(lds, lane, valid, v);
+  R* LX = static_cast<R*>(a.lane_excl);
+  if (valid && lane > 0) {
+    typename Op::Elem ex;
+    Op::load(lds, B, lane - 1, ex);
+    Op::store(LX, a.lstride, tile * B + lane, ex);
+  }
+  // last valid lane of the tile publishes the tile aggregate
+  const int64_t rem = a.m - tile * B * (int64_t)a.K;
+  const int64_t nvalid = (rem + a.K - 1) / a.K;
+  const int last = nvalid < B ? int(nvalid) - 1 : B - 1;
+  if (lane == last) Op::store(static_cast<R*>(a.tile_agg), a.tstride, tile, v);
+}
+
+template <class Op, int B, typename R>
+PKS_DEV void lane_apply(const ScanArgs& a, int64_t first, bool have, typename Op::Carry& c) {
+  const R* E = static_cast<const R*>(a.elems);
+  R* O = static_cast<R*>(a.out);
+  for (int j = 0; j < a.K; ++j) {
+    const int64_t q = first + j;
+    if (q >= a.m) break;
+    const int64_t idx = a.reverse ? a.m - 1 - q : q;
+    typename Op::Elem e;
+    Op::load(E, a.estride, idx, e);
+    if (have) {
+      typename Op::Carry n;
+      Op::apply(c, e, n);
+      c = n;
+    } else {
+      Op::to_carry(e, c);
+      have = true;
+    }
+    Op::store(O, a.ostride, idx, c);
+  }
+}
+
+template <class Op, int B, typename R>
+__global__ __launch_bounds__(B) void k_scan_down(ScanArgs a) {
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t first = (tile * B + lane) * a.K;
+  if (first >= a.m) return;
+  typename Op::Carry c;
+  bool have = false;
+  if (tile > 0) {
+    Op::load(static_cast<const R*>(a.tile_carry), a.cstride, tile - 1, c);
+    have = true;
+  }
+  if (lane > 0) {
+    typename Op::Elem ex;
+    Op::load(static_cast<const R*>(a.lane_excl), a.lstride, tile * B + lane, ex);
+    if (have) {
+      typename Op::Carry n;
+      Op::apply(c, ex, n);
+      c = n;
+    } else {
+      Op::to_carry(ex, c);
+      have = true;
+    }
+  }
+  lane_apply<Op, B, R>(a, first, have, c);
+}
+
+// Whole scan in one block (m <= B*K).
+template <class Op, int B, typename R>
+__global__ __launch_bounds__(B) void k_scan_single(ScanArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* lds = reinterpret_cast<R*>(smem_raw);
+  const R* E = static_cast<const R*>(a.elems);
+  const int lane = threadIdx.x;
+  const int64_t first = (int64_t)lane * a.K;
+  const bool valid = first < a.m;
+  typename Op::Elem v;
+  if (valid) {
+    Op::load(E, a.estride, a.reverse ? a.m - 1 - first : first, v);
+    for (int j = 1; j < a.K; ++j) {
+      const int64_t q = first + j;
+      if (q >= a.m) break;
+      typename Op::Elem e, r;
+      Op::load(E, a.estride, a.reverse ? a.m - 1 - q : q, e);
+      Op::combine(v, e, r);
+      v = r;
+    }
+  }
+  block_ladder<Op, B, R>(lds, lane, valid, v);
+  if (!valid) return;
+  typename Op::Carry c;
+  bool have = false;
+  if (lane > 0) {
+    typename Op::Elem ex;
+    Op::load(lds, B, lane - 1, ex);
+    Op::to_carry(ex, c);
+    have = true;
+  }
+  lane_apply<Op, B, R>(a, first, have, c);
+}
+
+}  // namespace pks

@@ -1,0 +1,126 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects invalid problems on the host (validation happens
+before any device call)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2102_00514_amd import binding as B
+from paper_2102_00514_amd import workloads as wl
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "smoother.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(smoother_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 9
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_struct_layout_matches_header():
+    # field order of sm_problem in the header
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {"):text.index("} sm_problem;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"(\w+)\s*[;,]", body)
+    assert fields == [f for f, _ in B.sm_problem._fields_]
+
+
+def test_version_and_defaults():
+    assert "gfx950" in B.smoother_version()
+    s = B.sm_problem()
+    B.lib().smoother_problem_defaults(ctypes.byref(s))
+    assert (s.n_tracks, s.n_iter, s.lin, s.precision, s.scan) == (1, 10, 0, 0, 0)
+    assert (s.ut_alpha, s.ut_beta, s.ut_kappa) == (1.0, 0.0, 1.0)
+
+
+def _expect_einval(pb, match, **kw):
+    with pytest.raises(B.SmootherError) as ei:
+        B.smoother_init(pb, **kw)
+    assert ei.value.status == B.SM_EINVAL
+    assert re.search(match, str(ei.value)), str(ei.value)
+
+
+def _c1():
+    return wl.config_c1()
+
+
+def test_rejects_bad_dimensions():
+    pb = _c1()
+    pb.nx = 7
+    _expect_einval(pb, "unsupported")
+
+
+def test_rejects_bad_offsets():
+    pb = _c1()
+    pb.offsets = np.array([0, 0], dtype=np.int64)
+    _expect_einval(pb, "T >= 1")
+    pb = _c1()
+    pb.offsets = np.array([1, 100], dtype=np.int64)
+    _expect_einval(pb, r"offsets\[0\]")
+
+
+def test_rejects_non_spd_covariances():
+    pb = _c1()
+    pb.Q = pb.Q.copy()
+    pb.Q[0, 0] = -1.0
+    _expect_einval(pb, "Q must be")
+    pb = _c1()
+    pb.R = np.array([[1.0, 2.0], [2.0, 1.0]])
+    _expect_einval(pb, "R must be")
+    pb = _c1()
+    pb.P0 = pb.P0.copy()
+    pb.P0[0, 0, 1] = 0.5     # asymmetric
+    _expect_einval(pb, "P0")
+
+
+def test_rejects_non_finite_measurements():
+    pb = _c1()
+    pb.y = pb.y.copy()
+    pb.y[10, 1] = np.nan
+    _expect_einval(pb, "y must be finite")
+
+
+def test_rejects_bad_params():
+    pb = _c1()
+    pb.params = pb.params[:-1]
+    _expect_einval(pb, "params")
+    pb = _c1()
+    pb.params = pb.params.copy()
+    pb.params[3] = 1.0           # target index 1 does not exist for nx = 5
+    _expect_einval(pb, "target")
+    pb = _c1()
+    pb.params = pb.params.copy()
+    pb.params[0] = -0.01
+    _expect_einval(pb, "dt")
+
+
+def test_rejects_bad_options():
+    pb = _c1()
+    _expect_einval(pb, "unscented", lin="unscented", ut_alpha=1.0, ut_kappa=-5.0)
+    _expect_einval(pb, "n_iter", n_iter=-1)
+    S = pb.n_slots
+    _expect_einval(pb, "init_mean", init_mean=np.full((S, 5), np.inf))
+    bad_cov = np.tile(np.eye(5), (S, 1, 1))
+    bad_cov[3] *= -1
+    _expect_einval(pb, "init_cov", init_mean=np.zeros((S, 5)), init_cov=bad_cov)
+
+
+def test_null_handle_calls_are_state_errors():
+    lib = B.lib()
+    assert lib.smoother_iterate(None, 1, None, None) == B.SM_ESTATE
+    assert lib.smoother_result(None, None, None) == B.SM_ESTATE
+    assert lib.smoother_track_deltas(None, None) == B.SM_ESTATE
+    lib.smoother_destroy(None)   # NULL-safe
