@@ -31,31 +31,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: int, K: int = 2) -> float:
-    """Minimum bytes each kernel family must move per slot / scan position:
-    every input read once, every output written once (FP words of `word` bytes)."""
+def algorithmic_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: int, K: int) -> float:
+    """Minimum bytes each kernel family must move per slot: every input it needs
+    read once, every output it produces written once (FP words of `word` bytes).
+    K = slots per lane, so lane-level scan state is amortised over K slots."""
     s = n * (n + 1) // 2
     sp = p * (p + 1) // 2
     fe = n * n + 2 * n + 2 * s          # filtering element (A, b, C, eta, J)
     se = n * n + n + s                  # smoothing element (E, g, L)
-    car = n + s                         # carry / trajectory slot (mean, packed covariance)
+    car = n + s                         # trajectory slot (mean, packed covariance)
+    tr = n * n + n + s                  # transition (F, c, Q') kept for the smoothing elements
     lin_words = n * n + n + s + p * n + p + sp + p
+    xin = n + (s if lin != "taylor" else 0)   # linearisation point (mean [+ covariance])
     words = {
-        "linearize": n + p + (s if lin != "taylor" else 0) + lin_words,
-        "filter_elements": lin_words + fe,
-        "scan_up_filter": fe + fe / K,
-        "scan_top_filter": fe + car,
-        "scan_down_filter": fe + fe / K + car,
-        "smoother_elements": car + (n * n + n + s) + se,
-        "scan_up_smoother": se + se / K,
-        "scan_top_smoother": se + car,
-        "scan_down_smoother": se + se / K + car,
+        # linearise + filtering element + lane fold / ladder
+        "forward_up": (xin + p + tr if lin == "taylor" else lin_words) + fe + fe / K,
+        # carries + smoothing element + reverse lane fold / ladder
+        "forward_down_backward_up": fe + fe / K + tr + se + se / K,
+        # reverse carries, new trajectory in place, convergence statistic (reads old means)
+        "backward_down": se + se / K + n + car,
+        "tiles_up_filter": fe + fe / 2, "tiles_top_filter": fe + car, "tiles_down_filter": fe + fe / 2 + car,
+        "tiles_up_smoother": se + se / 2, "tiles_top_smoother": se + car, "tiles_down_smoother": se + se / 2 + car,
+        "linearize": xin + p + lin_words,
+        "sequential": lin_words + 2 * car,
         "delta": 2 * n,
         "reset_delta": 1,
-        "sequential": lin_words + 2 * car,
     }[kernel]
-    extra = {"linearize": 1, "filter_elements": 1, "smoother_elements": 1, "delta": 4}.get(kernel, 0)
-    return words * word + extra
+    return words * word
 
 
 def cpu_baseline(pb, lin: str, budget_s: float) -> dict:
@@ -86,6 +88,8 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile-lanes", type=int, default=0, help="scan schedule override (64 or 256)")
+    ap.add_argument("--lane-slots", type=int, default=0, help="scan schedule override (1..8)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -104,9 +108,11 @@ def main():
     stream = torch.cuda.current_stream()
     total_iters = args.warmup + args.steps + args.profile_iters
     sm = binding.Smoother(pb, stream=stream.cuda_stream, n_iter=total_iters, lin=args.lin,
-                          precision=args.precision)
+                          precision=args.precision, tile_lanes=args.tile_lanes, lane_slots=args.lane_slots)
     S, _, dev_bytes = sm.info()
-    log(f"workload: T={T} slots={S} lin={args.lin} precision={args.precision} device_bytes={dev_bytes}")
+    lanes, slots, tiles = sm.schedule()
+    log(f"workload: T={T} slots={S} lin={args.lin} precision={args.precision} device_bytes={dev_bytes} "
+        f"schedule: {tiles} tiles x {lanes} lanes x {slots} slots")
 
     sm.iterate(args.warmup, want_delta=False)
     torch.cuda.synchronize()
@@ -131,7 +137,7 @@ def main():
     rows = []
     for name, (launches, tot_ms, positions) in prof.items():
         per_iter_us = tot_ms * 1e3 / args.profile_iters
-        bpp = algorithmic_bytes_per_position(name, pb.nx, pb.ny, args.lin, word)
+        bpp = algorithmic_bytes_per_position(name, pb.nx, pb.ny, args.lin, word, slots)
         gbs = (bpp * positions) / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
         rows.append((per_iter_us, name, launches, tot_ms, positions, bpp, gbs))
     rows.sort(reverse=True)
@@ -162,7 +168,8 @@ def main():
         "config": {"workload": f"coordinated-turn + 2 bearings, T={T} ({S} slots), single track, "
                                f"{'IEKS (Taylor)' if args.lin == 'taylor' else args.lin + ' SLR'}, "
                                f"one iteration per step",
-                   "T": T, "nx": pb.nx, "ny": pb.ny, "lin": args.lin, "parallelism": "time-axis scan, 1 GPU"},
+                   "T": T, "nx": pb.nx, "ny": pb.ny, "lin": args.lin, "parallelism": "time-axis scan, 1 GPU",
+                   "schedule": {"tiles": tiles, "lanes_per_tile": lanes, "slots_per_lane": slots}},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

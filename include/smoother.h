@@ -94,10 +94,13 @@ typedef struct {
   const double* init_mean;        /* optional host [S*nx], S = sum(T_i+1); NULL = m0 broadcast */
   const double* init_cov;         /* optional host [S*nx*nx]; NULL = P0 broadcast */
   int64_t max_device_bytes;       /* 0 = no cap; otherwise SM_ENOMEM if the plan needs more */
+  int32_t tile_lanes;             /* scan schedule: lanes per tile (64 or 256; 0 = auto) */
+  int32_t lane_slots;             /* scan schedule: consecutive slots per lane (1..8; 0 = auto) */
 } sm_problem;
 
 /* Fills *pb with defaults: n_tracks = 1, n_iter = 10, lin = SM_LIN_TAYLOR,
- * ut_alpha = 1, ut_beta = 0, ut_kappa = 1, FP64, parallel scan, no init, no cap. */
+ * ut_alpha = 1, ut_beta = 0, ut_kappa = 1, FP64, parallel scan, no init, no cap,
+ * automatic scan schedule. */
 void smoother_problem_defaults(sm_problem* pb);
 
 /* Validates the problem on the host (dimensions supported by the compiled
@@ -149,6 +152,9 @@ sm_status smoother_profile(smoother_t h, int32_t k, sm_kernel_time* out, int32_t
 
 /* Number of slots S, tracks and the device bytes held by the handle. */
 sm_status smoother_info(smoother_t h, int64_t* n_slots, int32_t* n_tracks, int64_t* device_bytes);
+
+/* Scan schedule in use: lanes per tile, slots per lane, number of tiles. */
+sm_status smoother_schedule(smoother_t h, int32_t* tile_lanes, int32_t* lane_slots, int64_t* tiles);
 
 /* Message for the last failure of a call on h (h = NULL: the last failure of
  * smoother_init on this thread).  Valid until the next call on h. */

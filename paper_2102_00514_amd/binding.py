@@ -27,7 +27,7 @@ SCAN = {"parallel": 0, "sequential": 1}
 
 EXPORTS = ("smoother_problem_defaults", "smoother_init", "smoother_iterate", "smoother_result",
            "smoother_result_device", "smoother_track_deltas", "smoother_info", "smoother_last_error",
-           "smoother_destroy", "smoother_version", "smoother_profile")
+           "smoother_destroy", "smoother_version", "smoother_profile", "smoother_schedule")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -44,6 +44,7 @@ class sm_problem(ctypes.Structure):
         ("precision", ctypes.c_int32), ("scan", ctypes.c_int32),
         ("init_mean", _dp), ("init_cov", _dp),
         ("max_device_bytes", ctypes.c_int64),
+        ("tile_lanes", ctypes.c_int32), ("lane_slots", ctypes.c_int32),
     ]
 
 
@@ -84,6 +85,8 @@ def _load():
     lib.smoother_profile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(sm_kernel_time), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32)]
     lib.smoother_profile.restype = ctypes.c_int
+    lib.smoother_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _i64p]
+    lib.smoother_schedule.restype = ctypes.c_int
     lib.smoother_version.argtypes = []
     lib.smoother_version.restype = ctypes.c_char_p
     return lib
@@ -111,7 +114,7 @@ def smoother_last_error(h=None) -> str:
 
 def make_problem(pb: Problem, n_iter: int = 10, lin: str = "taylor", precision: str = "f64",
                  scan: str = "parallel", init_mean=None, init_cov=None, ut_alpha=1.0, ut_beta=0.0,
-                 ut_kappa=1.0, max_device_bytes: int = 0):
+                 ut_kappa=1.0, max_device_bytes: int = 0, tile_lanes: int = 0, lane_slots: int = 0):
     """sm_problem for a workloads.Problem; returns (struct, keep-alive arrays)."""
     s = sm_problem()
     _lib.smoother_problem_defaults(ctypes.byref(s))
@@ -140,6 +143,7 @@ def make_problem(pb: Problem, n_iter: int = 10, lin: str = "taylor", precision: 
     if "init_cov" in keep:
         s.init_cov = keep["init_cov"].ctypes.data_as(_dp)
     s.max_device_bytes = max_device_bytes
+    s.tile_lanes, s.lane_slots = tile_lanes, lane_slots
     return s, keep
 
 
@@ -202,6 +206,13 @@ def smoother_profile(h: int, k: int) -> dict:
     return {recs[i].name.decode(): (recs[i].launches, recs[i].total_ms, recs[i].positions) for i in range(n.value)}
 
 
+def smoother_schedule(h: int):
+    """(lanes per tile, slots per lane, tiles) of the scan schedule in use."""
+    B, K, T = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(h, _lib.smoother_schedule(h, ctypes.byref(B), ctypes.byref(K), ctypes.byref(T)))
+    return B.value, K.value, T.value
+
+
 def smoother_destroy(h: int) -> None:
     _lib.smoother_destroy(h)
 
@@ -234,6 +245,9 @@ class Smoother:
 
     def profile(self, k: int):
         return smoother_profile(self.h, k)
+
+    def schedule(self):
+        return smoother_schedule(self.h)
 
     def close(self):
         if self.h:

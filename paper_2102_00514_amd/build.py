@@ -7,10 +7,13 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import time
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "smoother.hip")
+CSRC = os.path.join(PKG, "csrc")
+UNITS = ["smoother.hip", "engine_ct_f64.hip", "engine_ct_f32.hip", "engine_linear_f64.hip",
+         "engine_linear_f32.hip"]
 LIB = os.path.join(PKG, "libsmoother.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -19,7 +22,6 @@ HIP_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # no packed FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -27,20 +29,41 @@ HIP_FLAGS = [
 
 
 def sources():
-    csrc = os.path.join(PKG, "csrc")
-    return [os.path.join(csrc, f) for f in sorted(os.listdir(csrc)) if f.endswith((".hip", ".hpp"))] + \
+    return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".hip", ".hpp"))] + \
         [os.path.join(ROOT, "include", "smoother.h")]
 
 
-def build(verbose: bool = False, extra=()) -> str:
+def build(verbose: bool = False, extra=(), jobs: int = 8) -> str:
+    """Compiles every translation unit in parallel, then links the shared library."""
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs = []
+    for unit in UNITS:
+        obj = os.path.join(objdir, unit.replace(".hip", ".o"))
+        cmd = [HIPCC, *HIP_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-c", "-o", obj,
+               os.path.join(CSRC, unit)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((unit, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                                  text=True)))
+        while sum(p.poll() is None for _, _, p in procs) >= jobs:
+            time.sleep(0.2)
+    failed = []
+    for unit, obj, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out)
+            failed.append(unit)
+    if failed:
+        raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *HIP_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for _, o, _ in procs]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
+        print(" ".join(link), flush=True)
+    res = subprocess.run(link, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed to build libsmoother.so")
+        raise RuntimeError("linking libsmoother.so failed")
     os.replace(tmp, LIB)
     return LIB
 

@@ -44,10 +44,8 @@ PKS_DEV bool slr(int lin, SigmaRule rule, const R (&xbar)[N], const R (&Pbar)[N]
                  R (&G)[Q][N], R (&g)[Q], R (&Lam)[Q][Q], R (&zc)[Q]) {
   R L[N][N];
   PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) L[i][j] = Pbar[i][j];
-  const bool ok = chol_inplace<N>(L);
-  // chol_inplace keeps reciprocal diagonals; restore the factor's diagonal
-  R Ld[N];
-  PKS_UNROLL for (int i = 0; i < N; ++i) Ld[i] = R(1) / L[i][i];
+  R Ld[N];  // diagonal of the factor (L itself keeps the reciprocals)
+  const bool ok = chol_inplace<N>(L, Ld);
   R gamma, w0, wj;
   sigma_weights<N, R>(lin, rule, gamma, w0, wj);
   eval(xbar, zc);

@@ -1,0 +1,483 @@
+// The engine template: device memory plan and kernel launch sequence for one
+// (model, nx, ny, precision).  Included only by the instantiation units.
+//
+// One handle owns a plan for a batch of tracks laid out slot by slot (tracks
+// concatenated, padded to whole tiles) and queues every iteration on the
+// caller's HIP stream as three fused kernels (fused.hpp):
+//   linearise + filtering elements + forward up-sweep  [+ top scan, last block]
+//   forward down-sweep + smoothing elements + reverse up-sweep  [+ top scan]
+//   reverse down-sweep + convergence statistic.
+// When the tile aggregates do not fit one block, they are scanned by the
+// generic multi-level kernels of scan.hpp between the fused kernels.
+// Tracks need no segmentation in the scans: the prior element that opens each
+// track has A = 0, eta = J = 0, and the end element that closes it has E = 0,
+// so no prefix or suffix leaks across a track boundary (the parts that do
+// cross -- A, eta, J of a filtering prefix -- never reach the outputs).
+#pragma once
+
+#include <memory>
+
+#include "engine_base.hpp"
+#include "scan.hpp"
+#include "slot_kernels.hpp"
+
+namespace pks {
+
+constexpr int kScanB = 64;        // lanes per scan tile (one wavefront)
+constexpr int kLevelK = 2;        // positions per lane below the top level
+constexpr int kTopMaxK = 8;       // a single block scans at most B * kTopMaxK tile aggregates
+
+struct ScanLevel {
+  int64_t m;
+  int K;
+  int64_t tiles;
+  void* lane_excl = nullptr;   // [elem words][tiles*B]
+  void* tile_agg = nullptr;    // [elem words][tiles]
+  void* tile_carry = nullptr;  // [carry words][tiles]
+};
+
+static std::vector<ScanLevel> plan_levels(int64_t S) {
+  std::vector<ScanLevel> lv;
+  int64_t m = S;
+  while (m > int64_t(kScanB) * kTopMaxK) {
+    ScanLevel L;
+    L.m = m;
+    L.K = kLevelK;
+    L.tiles = (m + int64_t(kScanB) * kLevelK - 1) / (int64_t(kScanB) * kLevelK);
+    lv.push_back(L);
+    m = L.tiles;
+  }
+  ScanLevel top;
+  top.m = m;
+  top.K = int((m + kScanB - 1) / kScanB);
+  top.tiles = 1;
+  lv.push_back(top);
+  return lv;
+}
+
+// Scan schedule: lanes per tile (B), slots per lane (K).
+struct Schedule {
+  int B = 256;
+  int K = 1;
+};
+
+static Schedule choose_schedule(int64_t S, int lanes, int slots) {
+  Schedule sc;
+  if (lanes == 64 || lanes == 256) {
+    sc.B = lanes;
+  } else {
+    sc.B = 256;
+  }
+  if (slots >= 1) {
+    sc.K = slots;
+  } else {
+    // small problems: K = 1 keeps the dependent chain short; large ones fold
+    // more slots per lane so fewer generic combines and tile aggregates occur
+    sc.K = S <= int64_t(sc.B) * sc.B * 4 ? 1 : 4;
+  }
+  return sc;
+}
+
+template <class Model, typename R>
+class Engine final : public EngineBase {
+ public:
+  static constexpr int N = Model::N, P = Model::P;
+  static constexpr int kSN = sym_size<N>();
+  static constexpr int kTrajW = N + kSN;
+  using FOp = FilterOp<N, R>;
+  using SOp = SmootherOp<N, R>;
+  using LL = LinLayout<N, P>;
+  using TL = TransLayout<N>;
+
+  sm_status setup(const sm_problem& pb, hipStream_t st) override {
+    stream = st;
+    cap = pb.max_device_bytes;
+    ntracks = pb.n_tracks;
+    n_iter = pb.n_iter;
+    lin_ = pb.lin;
+    seq_ = pb.scan == SM_SCAN_SEQUENTIAL;
+    rule_.alpha = pb.ut_alpha;
+    rule_.kappa = pb.ut_kappa;
+    slot_off_.resize(ntracks + 1);
+    for (int i = 0; i <= ntracks; ++i) slot_off_[i] = pb.offsets[i] + i;
+    S = slot_off_[ntracks];
+    sched_ = choose_schedule(S, pb.tile_lanes, pb.lane_slots);
+    const int64_t per_tile = int64_t(sched_.B) * sched_.K;
+    tiles_ = (S + per_tile - 1) / per_tile;
+    const int64_t S_pad = tiles_ * per_tile;
+    stride = size_t((S_pad + 63) / 64 * 64);
+    top_in_kernel_ = tiles_ <= int64_t(sched_.B) * kTopMaxK;
+    sched_lanes = sched_.B;
+    sched_slots = sched_.K;
+    sched_tiles = tiles_;
+    std::vector<unsigned char> flags(S, 0);
+    std::vector<int> track(S, 0);
+    for (int i = 0; i < ntracks; ++i) {
+      for (int64_t s = slot_off_[i]; s < slot_off_[i + 1]; ++s) track[s] = i;
+      flags[slot_off_[i]] |= kSlotFirst;
+      flags[slot_off_[i + 1] - 1] |= kSlotLast;
+    }
+    std::vector<R> prm(pb.params, pb.params + pb.n_params);
+    std::vector<R> Q(pb.Q, pb.Q + N * N), Rm(pb.R, pb.R + P * P);
+    std::vector<R> m0(size_t(N) * ntracks), P0(size_t(kSN) * ntracks);
+    for (int t = 0; t < ntracks; ++t) {
+      for (int i = 0; i < N; ++i) m0[size_t(i) * ntracks + t] = R(pb.m0[size_t(t) * N + i]);
+      for (int i = 0; i < N; ++i)
+        for (int j = i; j < N; ++j)
+          P0[size_t(sym_index<N>(i, j)) * ntracks + t] = R(pb.P0[(size_t(t) * N + i) * N + j]);
+    }
+    std::vector<R> yslot(size_t(P) * stride, R(0));
+    for (int t = 0; t < ntracks; ++t)
+      for (int64_t k = 1; k < slot_off_[t + 1] - slot_off_[t]; ++k) {
+        const int64_t s = slot_off_[t] + k, row = pb.offsets[t] + k - 1;
+        for (int i = 0; i < P; ++i) yslot[size_t(i) * stride + s] = R(pb.y[row * P + i]);
+      }
+    // device plan
+    hipError_t e = hipSuccess;
+    auto A = [&](void** p, size_t bytes) {
+      if (e == hipSuccess) e = dalloc(p, bytes);
+    };
+    A(&d_params_, sizeof(R) * std::max<size_t>(prm.size(), 1));
+    A(&d_Q_, sizeof(R) * N * N);
+    A(&d_R_, sizeof(R) * P * P);
+    A(&d_m0_, sizeof(R) * m0.size());
+    A(&d_P0_, sizeof(R) * P0.size());
+    A(reinterpret_cast<void**>(&d_flags_), S);
+    A(reinterpret_cast<void**>(&d_track_), sizeof(int) * S);
+    A(reinterpret_cast<void**>(&d_slot_off_), sizeof(int64_t) * (ntracks + 1));
+    A(&d_y_, sizeof(R) * yslot.size());
+    A(&d_traj_[0], sizeof(R) * kTrajW * stride);
+    A(reinterpret_cast<void**>(&delta_bits), sizeof(unsigned long long) * (ntracks + 1));
+    if (seq_) {
+      A(&d_traj_[1], sizeof(R) * kTrajW * stride);
+      A(&d_lin_, sizeof(R) * LL::kWords * stride);
+      A(&d_filt_, sizeof(R) * kTrajW * stride);
+    } else {
+      const size_t lanes = size_t(tiles_) * sched_.B;
+      if (lin_ == SM_LIN_TAYLOR) {
+        A(&d_trans_, sizeof(R) * TL::kWords * stride);
+      } else {
+        // sigma-point linearisation runs as its own pass; its arrays start with
+        // the transition rows the smoothing elements read
+        A(&d_lin_, sizeof(R) * LL::kWords * stride);
+        d_trans_ = d_lin_;
+      }
+      A(&d_felem_, sizeof(R) * FOp::kElemWords * stride);
+      A(&d_selem_, sizeof(R) * SOp::kElemWords * stride);
+      A(&lx_f_, sizeof(R) * FOp::kElemWords * lanes);
+      A(&ta_f_, sizeof(R) * FOp::kElemWords * tiles_);
+      A(&tc_f_, sizeof(R) * FOp::kCarryWords * tiles_);
+      A(&lx_s_, sizeof(R) * SOp::kElemWords * lanes);
+      A(&ta_s_, sizeof(R) * SOp::kElemWords * tiles_);
+      A(&tc_s_, sizeof(R) * SOp::kCarryWords * tiles_);
+      A(reinterpret_cast<void**>(&tickets_), sizeof(unsigned int) * 2);
+      if (!top_in_kernel_) {
+        // generic multi-level scan of the tile aggregates
+        levels_ = plan_levels(tiles_);
+        for (size_t l = 0; l + 1 < levels_.size(); ++l) {
+          ScanLevel& L = levels_[l];
+          A(&L.lane_excl, sizeof(R) * FOp::kElemWords * L.tiles * kScanB);
+          A(&L.tile_agg, sizeof(R) * FOp::kElemWords * L.tiles);
+          A(&L.tile_carry, sizeof(R) * FOp::kCarryWords * L.tiles);
+        }
+      }
+    }
+    if (e != hipSuccess)
+      return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE,
+                  hip_msg(e, "device allocation") + " (plan needs more than is available or allowed)");
+    e = set_lds_limits();
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "kernel attributes"));
+    auto H2D = [&](void* dst, const void* src, size_t bytes) {
+      if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
+    };
+    H2D(d_params_, prm.data(), sizeof(R) * prm.size());
+    H2D(d_Q_, Q.data(), sizeof(R) * Q.size());
+    H2D(d_R_, Rm.data(), sizeof(R) * Rm.size());
+    H2D(d_m0_, m0.data(), sizeof(R) * m0.size());
+    H2D(d_P0_, P0.data(), sizeof(R) * P0.size());
+    H2D(d_flags_, flags.data(), S);
+    H2D(d_track_, track.data(), sizeof(int) * S);
+    H2D(d_slot_off_, slot_off_.data(), sizeof(int64_t) * (ntracks + 1));
+    H2D(d_y_, yslot.data(), sizeof(R) * yslot.size());
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "upload of the problem"));
+    const int64_t grid = (S + kSlotBlock - 1) / kSlotBlock;
+    const SlotArgs a = slot_args(0);
+    if (pb.init_mean) {
+      std::vector<R> mean(pb.init_mean, pb.init_mean + size_t(S) * N);
+      std::vector<R> cov(size_t(S) * N * N);
+      for (int64_t s = 0; s < S; ++s)
+        for (int i = 0; i < N * N; ++i)
+          cov[size_t(s) * N * N + i] = R(pb.init_cov ? pb.init_cov[size_t(s) * N * N + i]
+                                                     : pb.P0[size_t(track[s]) * N * N + i]);
+      void *dm = nullptr, *dc = nullptr;
+      e = hipMalloc(&dm, sizeof(R) * mean.size());
+      if (e == hipSuccess) e = hipMalloc(&dc, sizeof(R) * cov.size());
+      H2D(dm, mean.data(), sizeof(R) * mean.size());
+      H2D(dc, cov.data(), sizeof(R) * cov.size());
+      if (e == hipSuccess)
+        hipLaunchKernelGGL((k_pack<N, R>), dim3(grid), dim3(kSlotBlock), 0, stream, S, stride,
+                           static_cast<const R*>(dm), static_cast<const R*>(dc), static_cast<R*>(d_traj_[0]));
+      if (e == hipSuccess) e = hipGetLastError();
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      if (dm) (void)hipFree(dm);
+      if (dc) (void)hipFree(dc);
+      if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "upload of the initial trajectory"));
+    } else {
+      hipLaunchKernelGGL((k_broadcast_prior<N, R>), dim3(grid), dim3(kSlotBlock), 0, stream, a,
+                         static_cast<R*>(d_traj_[0]));
+    }
+    hipLaunchKernelGGL(k_fill_u64, dim3((ntracks + 256) / 256), dim3(256), 0, stream, delta_bits,
+                       int64_t(ntracks + 1), 0ull);
+    if (tickets_)
+      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, tickets_, int64_t(2), 0u);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "initial trajectory"));
+    cur_ = 0;
+    return SM_OK;
+  }
+
+  size_t lds_filter() const { return sizeof(R) * FOp::kElemWords * sched_.B; }
+  size_t lds_smoother() const { return sizeof(R) * SOp::kElemWords * sched_.B; }
+
+  template <int B>
+  hipError_t set_lds_limits_b() {
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f, size_t bytes) {
+      if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+    };
+    set(reinterpret_cast<const void*>(&k_forward_up<Model, kInlineTaylor, B, R>), lds_filter());
+    set(reinterpret_cast<const void*>(&k_forward_up<Model, kStoredLin, B, R>), lds_filter());
+    set(reinterpret_cast<const void*>(&k_forward_down_backward_up<Model, B, R>), lds_smoother());
+    return e;
+  }
+
+  hipError_t set_lds_limits() {
+    if (seq_) return hipSuccess;
+    return sched_.B == 64 ? set_lds_limits_b<64>() : set_lds_limits_b<256>();
+  }
+
+  SlotArgs slot_args(int cur) const {
+    SlotArgs a{};
+    a.S = S;
+    a.stride = stride;
+    a.flags = d_flags_;
+    a.track = d_track_;
+    a.params = d_params_;
+    a.Q = d_Q_;
+    a.R = d_R_;
+    a.m0 = d_m0_;
+    a.P0 = d_P0_;
+    a.tstride = size_t(ntracks);
+    a.yslot = d_y_;
+    a.traj = d_traj_[cur];
+    a.lin = d_lin_;
+    a.filt = d_filt_;
+    a.traj_out = d_traj_[cur ^ 1];
+    a.delta_bits = delta_bits;
+    a.rule = rule_;
+    return a;
+  }
+
+  FusedArgs fused_args() const {
+    FusedArgs a{};
+    a.S = S;
+    a.stride = stride;
+    a.K = sched_.K;
+    a.tiles = tiles_;
+    a.top_in_kernel = top_in_kernel_ ? 1 : 0;
+    a.ntracks = ntracks;
+    a.flags = d_flags_;
+    a.track = d_track_;
+    a.params = d_params_;
+    a.Q = d_Q_;
+    a.R = d_R_;
+    a.m0 = d_m0_;
+    a.P0 = d_P0_;
+    a.yslot = d_y_;
+    a.traj = d_traj_[0];
+    a.trans = d_trans_;
+    a.felem = d_felem_;
+    a.selem = d_selem_;
+    a.filt = nullptr;
+    a.lx_f = lx_f_;
+    a.ta_f = ta_f_;
+    a.tc_f = tc_f_;
+    a.lx_s = lx_s_;
+    a.ta_s = ta_s_;
+    a.tc_s = tc_s_;
+    a.tickets = tickets_;
+    a.delta_bits = delta_bits;
+    a.rule = rule_;
+    return a;
+  }
+
+  // Generic multi-level scan of `m` elements stored in scan order (tile aggregates).
+  template <class Op>
+  void run_scan(const void* elems, int64_t m, void* out, const char* const (&names)[3]) {
+    const size_t lds = sizeof(R) * Op::kElemWords * kScanB;
+    const int L = int(levels_.size());
+    for (int l = 0; l + 1 < L; ++l) {
+      const ScanLevel& lv = levels_[l];
+      ScanArgs a{};
+      a.elems = l == 0 ? elems : levels_[l - 1].tile_agg;
+      a.estride = l == 0 ? size_t(m) : size_t(levels_[l - 1].tiles);
+      a.m = lv.m;
+      a.K = lv.K;
+      a.lane_excl = lv.lane_excl;
+      a.lstride = size_t(lv.tiles) * kScanB;
+      a.tile_agg = lv.tile_agg;
+      a.tstride = size_t(lv.tiles);
+      timed(names[0], lv.m, [&] {
+        hipLaunchKernelGGL((k_scan_up<Op, kScanB, R>), dim3(lv.tiles), dim3(kScanB), lds, stream, a);
+      });
+    }
+    {
+      const ScanLevel& top = levels_[L - 1];
+      ScanArgs a{};
+      a.elems = L == 1 ? elems : levels_[L - 2].tile_agg;
+      a.estride = L == 1 ? size_t(m) : size_t(levels_[L - 2].tiles);
+      a.m = top.m;
+      a.K = top.K;
+      a.out = L == 1 ? out : levels_[L - 2].tile_carry;
+      a.ostride = L == 1 ? size_t(m) : size_t(levels_[L - 2].tiles);
+      timed(names[1], top.m, [&] {
+        hipLaunchKernelGGL((k_scan_single<Op, kScanB, R>), dim3(1), dim3(kScanB), lds, stream, a);
+      });
+    }
+    for (int l = L - 2; l >= 0; --l) {
+      const ScanLevel& lv = levels_[l];
+      ScanArgs a{};
+      a.elems = l == 0 ? elems : levels_[l - 1].tile_agg;
+      a.estride = l == 0 ? size_t(m) : size_t(levels_[l - 1].tiles);
+      a.m = lv.m;
+      a.K = lv.K;
+      a.lane_excl = lv.lane_excl;
+      a.lstride = size_t(lv.tiles) * kScanB;
+      a.tile_carry = lv.tile_carry;
+      a.cstride = size_t(lv.tiles);
+      a.out = l == 0 ? out : levels_[l - 1].tile_carry;
+      a.ostride = l == 0 ? size_t(m) : size_t(levels_[l - 1].tiles);
+      timed(names[2], lv.m, [&] {
+        hipLaunchKernelGGL((k_scan_down<Op, kScanB, R>), dim3(lv.tiles), dim3(kScanB), 0, stream, a);
+      });
+    }
+  }
+
+  template <int B>
+  void launch_iteration(const FusedArgs& a) {
+    static const char* const kFilterNames[3] = {"tiles_up_filter", "tiles_top_filter", "tiles_down_filter"};
+    static const char* const kSmootherNames[3] = {"tiles_up_smoother", "tiles_top_smoother",
+                                                  "tiles_down_smoother"};
+    const dim3 grid{unsigned(tiles_)}, block{unsigned(B)};
+    if (lin_ == SM_LIN_TAYLOR) {
+      timed("forward_up", S, [&] {
+        hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R>), grid, block, lds_filter(), stream, a);
+      });
+    } else {
+      const dim3 sgrid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
+      const SlotArgs sa = slot_args(0);
+      timed("linearize", S, [&] { launch_linearize(sa, sgrid); });
+      timed("forward_up", S, [&] {
+        hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R>), grid, block, lds_filter(), stream, a);
+      });
+    }
+    if (!top_in_kernel_) run_scan<FOp>(ta_f_, tiles_, tc_f_, kFilterNames);
+    timed("forward_down_backward_up", S, [&] {
+      hipLaunchKernelGGL((k_forward_down_backward_up<Model, B, R>), grid, block, lds_smoother(), stream, a);
+    });
+    if (!top_in_kernel_) run_scan<SOp>(ta_s_, tiles_, tc_s_, kSmootherNames);
+    timed("backward_down", S, [&] {
+      hipLaunchKernelGGL((k_backward_down<Model, B, R>), grid, block, 0, stream, a);
+    });
+  }
+
+  void launch_linearize(const SlotArgs& a, dim3 grid) {
+    switch (lin_) {
+      case SM_LIN_TAYLOR:
+        hipLaunchKernelGGL((k_linearize<Model, kTaylor, R>), grid, dim3(kSlotBlock), 0, stream, a);
+        break;
+      case SM_LIN_CUBATURE:
+        hipLaunchKernelGGL((k_linearize<Model, kCubature, R>), grid, dim3(kSlotBlock), 0, stream, a);
+        break;
+      default:
+        hipLaunchKernelGGL((k_linearize<Model, kUnscented, R>), grid, dim3(kSlotBlock), 0, stream, a);
+        break;
+    }
+  }
+
+  sm_status iterate(int k) override {
+    const dim3 grid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
+    for (int it = 0; it < k; ++it) {
+      if (seq_) {
+        const SlotArgs a = slot_args(cur_);
+        timed("reset_delta", ntracks + 1, [&] {
+          hipLaunchKernelGGL(k_fill_u64, dim3((ntracks + 256) / 256), dim3(256), 0, stream, delta_bits,
+                             int64_t(ntracks + 1), 0ull);
+        });
+        timed("linearize", S, [&] { launch_linearize(a, grid); });
+        timed("sequential", S, [&] {
+          hipLaunchKernelGGL((k_sequential<N, P, R>), dim3((ntracks + 63) / 64), dim3(64), 0, stream, a,
+                             d_slot_off_, ntracks);
+        });
+        timed("delta", S, [&] { hipLaunchKernelGGL((k_delta<N, R>), grid, dim3(kSlotBlock), 0, stream, a); });
+        cur_ ^= 1;
+      } else {
+        const FusedArgs a = fused_args();
+        if (sched_.B == 64) launch_iteration<64>(a);
+        else launch_iteration<256>(a);
+      }
+      ++iters;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "kernel launch"));
+    return SM_OK;
+  }
+
+  sm_status result_host(double* mean, double* cov) override {
+    std::vector<R> h(size_t(kTrajW) * stride);
+    hipError_t e = hipMemcpyAsync(h.data(), d_traj_[cur_], sizeof(R) * h.size(), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "copy of the result"));
+    for (int64_t s = 0; s < S; ++s) {
+      if (mean)
+        for (int i = 0; i < N; ++i) mean[size_t(s) * N + i] = double(h[size_t(i) * stride + s]);
+      if (cov)
+        for (int i = 0; i < N; ++i)
+          for (int j = 0; j < N; ++j)
+            cov[(size_t(s) * N + i) * N + j] = double(h[size_t(N + sym_index<N>(i, j)) * stride + s]);
+    }
+    return SM_OK;
+  }
+
+  sm_status result_device(void* mean, void* cov) override {
+    const dim3 grid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
+    hipLaunchKernelGGL((k_unpack<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride,
+                       static_cast<const R*>(d_traj_[cur_]), static_cast<R*>(mean), static_cast<R*>(cov));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "result kernel"));
+    return SM_OK;
+  }
+
+ private:
+  int lin_ = 0;
+  bool seq_ = false;
+  SigmaRule rule_{1.0, 1.0};
+  int cur_ = 0;
+  Schedule sched_;
+  int64_t tiles_ = 0;
+  bool top_in_kernel_ = true;
+  std::vector<int64_t> slot_off_;
+  std::vector<ScanLevel> levels_;
+  void *d_params_ = nullptr, *d_Q_ = nullptr, *d_R_ = nullptr, *d_m0_ = nullptr, *d_P0_ = nullptr;
+  unsigned char* d_flags_ = nullptr;
+  int* d_track_ = nullptr;
+  int64_t* d_slot_off_ = nullptr;
+  void *d_y_ = nullptr, *d_traj_[2] = {nullptr, nullptr};
+  void *d_lin_ = nullptr, *d_filt_ = nullptr;  // sequential path
+  void *d_trans_ = nullptr, *d_felem_ = nullptr, *d_selem_ = nullptr;
+  void *lx_f_ = nullptr, *ta_f_ = nullptr, *tc_f_ = nullptr, *lx_s_ = nullptr, *ta_s_ = nullptr, *tc_s_ = nullptr;
+  unsigned int* tickets_ = nullptr;
+};
+
+}  // namespace pks

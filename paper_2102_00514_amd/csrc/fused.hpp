@@ -1,0 +1,358 @@
+// One iteration of the method in three kernels over tiles of B lanes x K slots.
+//
+//   k_forward_up    build the filtering element of every slot (eq. 13-14) from
+//                   its linearisation (Section 3: Taylor evaluated inline, or
+//                   sigma-point regression read from a separate pass), fold
+//                   each lane's K elements,
+//                   Kogge-Stone over the lanes (eq. 15) -> lane exclusive
+//                   prefixes and the tile aggregate; the last block scans the
+//                   tile aggregates.
+//   k_forward_down_backward_up
+//                   apply the tile and lane carries to every slot -> filtered
+//                   x*_k, P*_k; build the smoothing element (eq. 16-18); fold
+//                   and ladder them in reverse slot order (eq. 19) -> reverse
+//                   lane prefixes and tile aggregates; the last block scans the
+//                   reverse tile aggregates.
+//   k_backward_down apply the reverse carries -> smoothed xbar_k, Pbar_k,
+//                   written in place, and the convergence statistic.
+//
+// The slot range is padded to tiles * B * K with single-slot dummy tracks
+// (flags first|last, prior element (0, 0, I, 0, 0), end element (0, 0, I));
+// padding never mixes with real tracks because of the reset property of the
+// prior and end elements.  With the padded layout the forward tile t is the
+// reverse tile tiles-1-t and forward lane l is reverse lane B-1-l, so the
+// reverse scan runs over exactly the same slots as the forward one.
+#pragma once
+
+#include "elements.hpp"
+#include "operators.hpp"
+#include "scan.hpp"
+
+namespace pks {
+
+enum : unsigned { kSlotFirst = 1u, kSlotLast = 2u };
+
+struct FusedArgs {
+  int64_t S;            // real slots
+  size_t stride;        // row stride of every slot array (>= padded slots)
+  int K;                // slots per lane
+  int64_t tiles;        // tiles of B*K slots
+  int top_in_kernel;    // 1: the last block scans the tile aggregates
+  int ntracks;
+  const unsigned char* flags;
+  const int* track;
+  const void* params;
+  const void* Q;        // N*N
+  const void* R;        // P*P
+  const void* m0;       // [N][ntracks]
+  const void* P0;       // [s(N)][ntracks]
+  const void* yslot;    // [P][stride]
+  void* traj;           // [N + s(N)][stride]  xbar, Pbar (read by the forward kernel, updated in place at the end)
+  void* trans;          // [N*N + N + s(N)][stride]  F_k, c_k, Q'_k of the transition out of slot k
+  void* felem;          // [FilterOp words][stride]
+  void* selem;          // [SmootherOp words][stride]
+  void* filt;           // optional [N + s(N)][stride]  x*, P*
+  void *lx_f, *ta_f, *tc_f;  // forward lane exclusives [words][tiles*B], tile aggregates, tile carries
+  void *lx_s, *ta_s, *tc_s;  // same for the reverse scan, indexed by reverse tile
+  unsigned int* tickets;     // [2] last-block tickets
+  unsigned long long* delta_bits;  // [ntracks + 1]; entry ntracks = max over tracks
+  SigmaRule rule;
+};
+
+// Linearisation arrays written by the separate linearisation pass: transition
+// out of the slot F (N*N), c (N), Q' (s(N)); measurement at the slot H (P*N),
+// d (P), R' (s(P)), ytil (P).
+template <int N, int P>
+struct LinLayout {
+  static constexpr int kF = 0;
+  static constexpr int kc = kF + N * N;
+  static constexpr int kQ = kc + N;
+  static constexpr int kH = kQ + sym_size<N>();
+  static constexpr int kd = kH + P * N;
+  static constexpr int kR = kd + P;
+  static constexpr int ky = kR + sym_size<P>();
+  static constexpr int kWords = ky + P;
+};
+
+template <int N>
+struct TransLayout {
+  static constexpr int kF = 0, kc = N * N, kQ = N * N + N, kWords = N * N + N + sym_size<N>();
+};
+
+// Where the forward kernel takes each slot's linearisation from.
+enum LinSource : int {
+  kInlineTaylor = 0,  // Jacobians evaluated in the kernel; F, c, Q' stored for the smoothing elements
+  kStoredLin = 1      // read from the arrays a separate linearisation pass wrote (sigma-point SLR)
+};
+
+// Filtering element of slot s.
+template <class Model, int SRC, typename R>
+PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename FilterOp<Model::N, R>::Elem& e) {
+  constexpr int N = Model::N, P = Model::P;
+  using TL = TransLayout<N>;
+  const size_t st = a.stride;
+  const unsigned fl = s < a.S ? a.flags[s] : (kSlotFirst | kSlotLast);
+  if (fl & kSlotFirst) {
+    set_zero<N>(e.A);
+    set_zero<N>(e.eta);
+    set_zero<N>(e.J);
+    if (s < a.S) {
+      const int tr = a.track[s];
+      ld_vec<N>(static_cast<const R*>(a.m0), size_t(a.ntracks), tr, e.b);
+      ld_sym<N>(static_cast<const R*>(a.P0), size_t(a.ntracks), tr, e.C);
+    } else {
+      set_zero<N>(e.b);
+      set_zero<N>(e.C);
+      PKS_UNROLL for (int i = 0; i < N; ++i) e.C[i][i] = R(1);
+    }
+    return;
+  }
+  R F[N][N], c[N], Qp[N][N], H[P][N], d[P], Rp[P][P], yt[P];
+  if constexpr (SRC == kStoredLin) {
+    // transition into s from slot s-1, measurement model at s (LinLayout of the
+    // linearisation pass; its first rows are the TransLayout rows)
+    using LL = LinLayout<N, P>;
+    const R* lin = static_cast<const R*>(a.trans);
+    ld_mat<N, N>(lin + LL::kF * st, st, s - 1, F);
+    ld_vec<N>(lin + LL::kc * st, st, s - 1, c);
+    ld_sym<N>(lin + LL::kQ * st, st, s - 1, Qp);
+    ld_mat<P, N>(lin + LL::kH * st, st, s, H);
+    ld_vec<P>(lin + LL::kd * st, st, s, d);
+    ld_sym<P>(lin + LL::kR * st, st, s, Rp);
+    ld_vec<P>(lin + LL::ky * st, st, s, yt);
+  } else {
+    const Model md{static_cast<const R*>(a.params)};
+    const R* traj = static_cast<const R*>(a.traj);
+    {
+      R xp[N], Pp[N][N], Qm[N][N];
+      ld_vec<N>(traj, st, s - 1, xp);
+      set_zero<N>(Pp);
+      const R* Qg = static_cast<const R*>(a.Q);
+      PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) Qm[i][j] = Qg[i * N + j];
+      linearize_f<Model, R>(md, kTaylor, a.rule, Qm, xp, Pp, F, c, Qp);
+      R* tr = static_cast<R*>(a.trans);
+      st_mat<N, N>(tr + TL::kF * st, st, s - 1, F);
+      st_vec<N>(tr + TL::kc * st, st, s - 1, c);
+      st_sym<N>(tr + TL::kQ * st, st, s - 1, Qp);
+    }
+    {
+      R x[N], Px[N][N], Rm[P][P], y[P];
+      ld_vec<N>(traj, st, s, x);
+      set_zero<N>(Px);
+      const R* Rg = static_cast<const R*>(a.R);
+      PKS_UNROLL for (int i = 0; i < P; ++i) PKS_UNROLL for (int j = 0; j < P; ++j) Rm[i][j] = Rg[i * P + j];
+      ld_vec<P>(static_cast<const R*>(a.yslot), st, s, y);
+      linearize_h<Model, R>(md, kTaylor, a.rule, Rm, x, Px, y, H, d, Rp, yt);
+    }
+  }
+  const bool ok = filter_element<N, P, R>(F, c, Qp, H, d, Rp, yt, e.A, e.b, e.C, e.eta, e.J);
+  if (!ok) e.b[0] = quiet_nan<R>();
+}
+
+template <class Model, int SRC, int B, typename R>
+__global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
+  constexpr int N = Model::N;
+  using Op = FilterOp<N, R>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* lds = reinterpret_cast<R*>(smem_raw);
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t base = (tile * B + lane) * a.K;
+  if (tile == 0)
+    for (int i = lane; i <= a.ntracks; i += B) a.delta_bits[i] = 0ull;
+  R* felem = static_cast<R*>(a.felem);
+  // build and store all K elements first, then fold them back from memory: the
+  // running aggregate is never live while a slot is linearised
+  for (int j = 0; j < a.K; ++j) {
+    typename Op::Elem e;
+    build_filter_element<Model, SRC, R>(a, base + j, e);
+    Op::store(felem, a.stride, base + j, e);
+  }
+  typename Op::Elem acc;
+  Op::load(felem, a.stride, base, acc);
+  for (int j = 1; j < a.K; ++j) {
+    typename Op::Elem e, r;
+    Op::load(felem, a.stride, base + j, e);
+    Op::combine(acc, e, r);
+    acc = r;
+  }
+  block_ladder<Op, B, R>(lds, lane, true, acc);
+  if (lane > 0) {
+    typename Op::Elem ex;
+    Op::load(lds, B, lane - 1, ex);
+    Op::store(static_cast<R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
+  }
+  if (lane == B - 1) Op::store(static_cast<R*>(a.ta_f), size_t(a.tiles), tile, acc);
+  if (a.top_in_kernel)
+    last_block_scan<Op, B, R>(lds, lane, &a.tickets[0], a.tiles, static_cast<const R*>(a.ta_f),
+                              static_cast<R*>(a.tc_f));
+}
+
+template <class Model, int B, typename R>
+__global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
+  constexpr int N = Model::N;
+  using FOp = FilterOp<N, R>;
+  using SOp = SmootherOp<N, R>;
+  using TL = TransLayout<N>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* lds = reinterpret_cast<R*>(smem_raw);
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t base = (tile * B + lane) * a.K;
+  const size_t st = a.stride;
+  typename FOp::Carry c;
+  bool have = false;
+  if (tile > 0) {
+    FOp::load(static_cast<const R*>(a.tc_f), size_t(a.tiles), tile - 1, c);
+    have = true;
+  }
+  if (lane > 0) {
+    typename FOp::Elem ex;
+    FOp::load(static_cast<const R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
+    if (have) {
+      typename FOp::Carry n;
+      FOp::apply(c, ex, n);
+      c = n;
+    } else {
+      FOp::to_carry(ex, c);
+      have = true;
+    }
+  }
+  typename SOp::Elem sacc;
+  for (int j = 0; j < a.K; ++j) {
+    const int64_t s = base + j;
+    {
+      typename FOp::Elem e;
+      FOp::load(static_cast<const R*>(a.felem), st, s, e);
+      if (have) {
+        typename FOp::Carry n;
+        FOp::apply(c, e, n);
+        c = n;
+      } else {
+        FOp::to_carry(e, c);
+        have = true;
+      }
+    }
+    if (a.filt) FOp::store(static_cast<R*>(a.filt), st, s, c);
+    typename SOp::Elem se;
+    const unsigned fl = s < a.S ? a.flags[s] : (kSlotFirst | kSlotLast);
+    if (fl & kSlotLast) {
+      set_zero<N>(se.E);
+      PKS_UNROLL for (int i = 0; i < N; ++i) {
+        se.g[i] = c.b[i];
+        PKS_UNROLL for (int k = 0; k < N; ++k) se.L[i][k] = c.C[i][k];
+      }
+    } else {
+      const R* tr = static_cast<const R*>(a.trans);
+      R F[N][N], cc[N], Qp[N][N];
+      ld_mat<N, N>(tr + TL::kF * st, st, s, F);
+      ld_vec<N>(tr + TL::kc * st, st, s, cc);
+      ld_sym<N>(tr + TL::kQ * st, st, s, Qp);
+      const bool ok = smoother_element<N, R>(c.b, c.C, F, cc, Qp, se.E, se.g, se.L);
+      if (!ok) se.g[0] = quiet_nan<R>();
+    }
+    SOp::store(static_cast<R*>(a.selem), st, s, se);
+    // paper order: sacc covers earlier slots, so sacc <- sacc (x) se, i.e. the
+    // scan-order combine with se first
+    if (j == 0) {
+      sacc = se;
+    } else {
+      typename SOp::Elem r;
+      SOp::combine(se, sacc, r);
+      sacc = r;
+    }
+  }
+  __syncthreads();  // the forward carries above read no LDS, but the ladder reuses it
+  const int rl = B - 1 - lane;
+  const int64_t rt = a.tiles - 1 - tile;
+  block_ladder<SOp, B, R>(lds, rl, true, sacc);
+  if (rl > 0) {
+    typename SOp::Elem ex;
+    SOp::load(lds, B, rl - 1, ex);
+    SOp::store(static_cast<R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, ex);
+  }
+  if (rl == B - 1) SOp::store(static_cast<R*>(a.ta_s), size_t(a.tiles), rt, sacc);
+  if (a.top_in_kernel)
+    last_block_scan<SOp, B, R>(lds, lane, &a.tickets[1], a.tiles, static_cast<const R*>(a.ta_s),
+                               static_cast<R*>(a.tc_s));
+}
+
+PKS_DEV unsigned long long order_bits(double v) {
+  // non-negative doubles and NaN order like their bit patterns as unsigned
+  return static_cast<unsigned long long>(__double_as_longlong(v == v ? v : __builtin_nan("")));
+}
+
+template <class Model, int B, typename R>
+__global__ __launch_bounds__(B) void k_backward_down(FusedArgs a) {
+  constexpr int N = Model::N;
+  using SOp = SmootherOp<N, R>;
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t base = (tile * B + lane) * a.K;
+  const int rl = B - 1 - lane;
+  const int64_t rt = a.tiles - 1 - tile;
+  const size_t st = a.stride;
+  __shared__ unsigned long long s_max;
+  __shared__ int s_track;  // track of every real slot of the block, or -1 if several
+  if (lane == 0) {
+    s_max = 0ull;
+    const int64_t lo = tile * B * a.K;
+    const int64_t hi = (lo + int64_t(B) * a.K < a.S ? lo + int64_t(B) * a.K : a.S) - 1;
+    s_track = (lo <= hi && a.track[lo] == a.track[hi]) ? a.track[lo] : -1;
+  }
+  __syncthreads();
+  typename SOp::Carry c;
+  bool have = false;
+  if (rt > 0) {
+    SOp::load(static_cast<const R*>(a.tc_s), size_t(a.tiles), rt - 1, c);
+    have = true;
+  }
+  if (rl > 0) {
+    typename SOp::Elem ex;
+    SOp::load(static_cast<const R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, ex);
+    if (have) {
+      typename SOp::Carry n;
+      SOp::apply(c, ex, n);
+      c = n;
+    } else {
+      SOp::to_carry(ex, c);
+      have = true;
+    }
+  }
+  R* traj = static_cast<R*>(a.traj);
+  unsigned long long lane_max = 0ull;
+  for (int j = a.K - 1; j >= 0; --j) {
+    const int64_t s = base + j;
+    typename SOp::Elem e;
+    SOp::load(static_cast<const R*>(a.selem), st, s, e);
+    if (have) {
+      typename SOp::Carry n;
+      SOp::apply(c, e, n);
+      c = n;
+    } else {
+      SOp::to_carry(e, c);
+      have = true;
+    }
+    if (s < a.S) {
+      double m = 0.0;
+      bool nan = false;
+      PKS_UNROLL for (int i = 0; i < N; ++i) {
+        const double dlt = fabs(double(c.g[i]) - double(traj[i * st + s]));
+        nan = nan || !(dlt == dlt);
+        m = dlt > m ? dlt : m;
+      }
+      const unsigned long long b = order_bits(nan ? __builtin_nan("") : m);
+      SOp::store(traj, st, s, c);
+      if (s_track < 0) atomicMax(&a.delta_bits[a.track[s]], b);
+      lane_max = b > lane_max ? b : lane_max;
+    }
+  }
+  atomicMax(&s_max, lane_max);
+  __syncthreads();
+  if (lane == 0) {
+    if (s_track >= 0) atomicMax(&a.delta_bits[s_track], s_max);
+    atomicMax(&a.delta_bits[a.ntracks], s_max);
+  }
+}
+
+}  // namespace pks

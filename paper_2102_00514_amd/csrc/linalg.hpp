@@ -23,21 +23,52 @@ constexpr int sym_index(int i, int j) {
   return i <= j ? i * N - i * (i - 1) / 2 + (j - i) : j * N - j * (j - 1) / 2 + (i - j);
 }
 
-template <typename R> PKS_DEV R rsqrt_exact(R x) { return R(1) / sqrt(x); }
+// 1/sqrt(x) and 1/x from the hardware estimates refined by two Newton steps
+// (each step squares the relative error), instead of the long IEEE
+// square-root / divide sequences: these sit on the dependency chain of every
+// Cholesky factorisation in the scans.
+PKS_DEV double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  PKS_UNROLL for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+PKS_DEV float rsqrt_nr(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  const float e = fmaf(-x * y, y, 1.0f);
+  return fmaf(0.5f * y, e, y);
+}
+PKS_DEV double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  PKS_UNROLL for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+  }
+  return r;
+}
+PKS_DEV float rcp_nr(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  const float e = fmaf(-x, r, 1.0f);
+  return fmaf(r, e, r);
+}
 
 // ---------------------------------------------------------------------------
 // Cholesky: A = L L^T (lower L), in place on a full symmetric array.  The
-// diagonal of the result holds 1/L_jj (reciprocals are what the solves use).
-// Returns false if a pivot is not positive (the caller turns that into NaN).
+// diagonal of the result holds 1/L_jj (reciprocals are what the solves use);
+// if diag is given it receives L_jj itself.  Returns false if a pivot is not
+// positive (callers turn that into NaN outputs).
 // ---------------------------------------------------------------------------
 template <int N, typename R>
-PKS_DEV bool chol_inplace(R (&A)[N][N]) {
+PKS_DEV bool chol_inplace(R (&A)[N][N], R* diag = nullptr) {
   bool ok = true;
   PKS_UNROLL for (int j = 0; j < N; ++j) {
     R s = A[j][j];
     PKS_UNROLL for (int t = 0; t < j; ++t) s -= A[j][t] * A[j][t];
     ok = ok && (s > R(0));
-    const R inv = rsqrt_exact<R>(s);
+    const R inv = rsqrt_nr(s);
+    if (diag) diag[j] = s * inv;
     PKS_UNROLL for (int i = j + 1; i < N; ++i) {
       R v = A[i][j];
       PKS_UNROLL for (int t = 0; t < j; ++t) v -= A[i][t] * A[j][t];

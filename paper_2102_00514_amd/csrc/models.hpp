@@ -83,10 +83,10 @@ PKS_DEV void ct_terms(R w, R dt, R& s1, R& s2, R& d1, R& d2, R& sa, R& ca) {
     sa = R(2) * sh * chh;
     const R omc = R(2) * sh * sh;
     ca = R(1) - omc;
-    const R inv_w = R(1) / w;
+    const R inv_w = rcp_nr(w);
     s1 = sa * inv_w;
     s2 = omc * inv_w;
-    const R k = dt * dt / a2;
+    const R k = dt * dt * rcp_nr(a2);
     d1 = k * (a * ca - sa);
     d2 = k * (a * sa - omc);
   }
@@ -165,7 +165,7 @@ struct CtBearings {
       target_pos(x, t, px, py);
       const R dx = px - sx, dy = py - sy;
       hx[s] = atan2(dy, dx);
-      const R ir2 = R(1) / (dx * dx + dy * dy);
+      const R ir2 = rcp_nr(dx * dx + dy * dy);
       PKS_UNROLL for (int j = 0; j < N; ++j) Hx[s][j] = R(0);
       PKS_UNROLL for (int b = 0; b < NT; ++b) {
         Hx[s][5 * b] = (t == b) ? -dy * ir2 : R(0);

@@ -9,12 +9,13 @@
 // evaluated without forming or pivoting (I + C_i J_j): with C_i = U U^T
 // (Cholesky) and G = I + U^T J_j U = Lg Lg^T (symmetric, eigenvalues >= 1),
 //   M := (I + C_i J_j)^-1 C_i = U G^-1 U^T = W^T W,  W = Lg^-1 U^T,
-//   (I + C_i J_j)^-1 = I - M J_j,   (I + J_j C_i)^-1 = I - J_j M,
-// so with v = eta_j - J_j b_i and u = M v:
-//   b_ij = A_j (b_i + u) + b_j,        C_ij = A_j M A_j^T + C_j,
-//   A_ij = (A_j - A_j M J_j) A_i,      eta_ij = A_i^T (v - J_j u) + eta_i,
-//   J_ij = A_i^T (J_j - X^T X) A_i + J_i,   X = W J_j.
-// M, C_ij and J_ij are symmetric by construction.
+//   (I + C_i J_j)^-1 = I - M J_j,   (I + J_j C_i)^-1 = I - J_j M.
+// With Y = J_j A_i, Z = M Y, v = eta_j - J_j b_i and u = M v this gives
+//   A_ij = A_j (A_i - Z),               J_ij = A_i^T Y - Y^T Z + J_i,
+//   b_ij = A_j (b_i + u) + b_j,         eta_ij = A_i^T v - Y^T u + eta_i,
+//   C_ij = A_j M A_j^T + C_j,
+// where M, J_ij and C_ij are symmetric by construction (only the upper
+// triangles are computed).
 //
 // Smoothing (eq. 19): (E_i, g_i, L_i) x (E_j, g_j, L_j) =
 //   (E_i E_j, E_i g_j + g_i, E_i L_j E_i^T + L_i).
@@ -75,18 +76,16 @@ struct FilterOp {
     }
   }
 
-  // M = (I + C J)^-1 C as W^T W; returns W (so that M = W^T W). ok = false if
-  // C is not positive definite.
-  static PKS_DEV bool core(const R (&Ci)[N][N], const R (&Jj)[N][N], R (&W)[N][N], R (&M)[N][N]) {
-    R U[N][N];
+  // M = (I + C J)^-1 C, symmetric.  ok = false if C is not positive definite.
+  static PKS_DEV bool core(const R (&Ci)[N][N], const R (&Jj)[N][N], R (&M)[N][N]) {
+    R U[N][N], Ud[N];
     PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) U[i][j] = Ci[i][j];
-    bool ok = chol_inplace<N>(U);
-    PKS_UNROLL for (int i = 0; i < N; ++i) U[i][i] = R(1) / U[i][i];
-    // JU = J U (U lower triangular)
+    bool ok = chol_inplace<N>(U, Ud);
+    // JU = J U (U lower triangular, true diagonal Ud)
     R JU[N][N];
     PKS_UNROLL for (int i = 0; i < N; ++i)
       PKS_UNROLL for (int k = 0; k < N; ++k) {
-        R s = Jj[i][k] * U[k][k];
+        R s = Jj[i][k] * Ud[k];
         PKS_UNROLL for (int t = k + 1; t < N; ++t) s += Jj[i][t] * U[t][k];
         JU[i][k] = s;
       }
@@ -94,14 +93,16 @@ struct FilterOp {
     R G[N][N];
     PKS_UNROLL for (int a = 0; a < N; ++a)
       PKS_UNROLL for (int b = a; b < N; ++b) {
-        R s = (a == b) ? R(1) : R(0);
-        PKS_UNROLL for (int t = a; t < N; ++t) s += U[t][a] * JU[t][b];
+        R s = R(1) * (a == b) + Ud[a] * JU[a][b];
+        PKS_UNROLL for (int t = a + 1; t < N; ++t) s += U[t][a] * JU[t][b];
         G[a][b] = s;
         G[b][a] = s;
       }
     ok = chol_inplace<N>(G) && ok;
-    // W = Lg^-1 U^T
-    PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) W[i][j] = (j >= i) ? U[j][i] : R(0);
+    // W = Lg^-1 U^T (U^T upper triangular)
+    R W[N][N];
+    PKS_UNROLL for (int i = 0; i < N; ++i)
+      PKS_UNROLL for (int j = 0; j < N; ++j) W[i][j] = (j > i) ? U[j][i] : (j == i ? Ud[i] : R(0));
     chol_fwd<N, N>(G, W);
     gram<N, N>(W, M);
     return ok;
@@ -109,77 +110,62 @@ struct FilterOp {
 
   // out = l (x) r
   static PKS_DEV void combine(const Elem& l, const Elem& r, Elem& o) {
-    R W[N][N], M[N][N];
-    const bool ok = core(l.C, r.J, W, M);
-    R v[N], u[N], Ju[N], bu[N];
+    R M[N][N];
+    const bool ok = core(l.C, r.J, M);
+    R Y[N][N], Z[N][N];
+    mat_mul<N, N, N>(r.J, l.A, Y);
+    mat_mul<N, N, N>(M, Y, Z);
+    R v[N], u[N];
     PKS_UNROLL for (int i = 0; i < N; ++i) {
       R s = r.eta[i];
       PKS_UNROLL for (int t = 0; t < N; ++t) s -= r.J[i][t] * l.b[t];
       v[i] = s;
     }
     mat_vec<N, N>(M, v, u);
-    mat_vec<N, N>(r.J, u, Ju);
-    PKS_UNROLL for (int i = 0; i < N; ++i) bu[i] = l.b[i] + u[i];
-    // b, C
-    R AM[N][N];
-    mat_mul<N, N, N>(r.A, M, AM);
-    PKS_UNROLL for (int i = 0; i < N; ++i) {
-      R s = r.b[i];
-      PKS_UNROLL for (int t = 0; t < N; ++t) s += r.A[i][t] * bu[t];
-      o.b[i] = s;
-    }
-    PKS_UNROLL for (int i = 0; i < N; ++i)
-      PKS_UNROLL for (int j = i; j < N; ++j) {
-        R s = r.C[i][j];
-        PKS_UNROLL for (int t = 0; t < N; ++t) s += AM[i][t] * r.A[j][t];
-        o.C[i][j] = s;
-        o.C[j][i] = s;
-      }
-    // A = (A_j - A_j M J_j) A_i
-    R T1[N][N];
-    PKS_UNROLL for (int i = 0; i < N; ++i)
-      PKS_UNROLL for (int j = 0; j < N; ++j) {
-        R s = r.A[i][j];
-        PKS_UNROLL for (int t = 0; t < N; ++t) s -= AM[i][t] * r.J[t][j];
-        T1[i][j] = s;
-      }
-    mat_mul<N, N, N>(T1, l.A, o.A);
-    // eta = A_i^T (v - J u) + eta_i
-    PKS_UNROLL for (int i = 0; i < N; ++i) v[i] -= Ju[i];
+    // eta_ij = A_i^T v - Y^T u + eta_i
     PKS_UNROLL for (int i = 0; i < N; ++i) {
       R s = l.eta[i];
-      PKS_UNROLL for (int t = 0; t < N; ++t) s += l.A[t][i] * v[t];
+      PKS_UNROLL for (int t = 0; t < N; ++t) s += l.A[t][i] * v[t] - Y[t][i] * u[t];
       o.eta[i] = s;
     }
-    // J = A_i^T (J_j - X^T X) A_i + J_i, X = W J_j
-    R X[N][N], MJ[N][N];
-    mat_mul<N, N, N>(W, r.J, X);
+    // J_ij = A_i^T Y - Y^T Z + J_i
     PKS_UNROLL for (int a = 0; a < N; ++a)
       PKS_UNROLL for (int b = a; b < N; ++b) {
-        R s = r.J[a][b];
-        PKS_UNROLL for (int t = 0; t < N; ++t) s -= X[t][a] * X[t][b];
-        MJ[a][b] = s;
-        MJ[b][a] = s;
+        R s = l.J[a][b];
+        PKS_UNROLL for (int t = 0; t < N; ++t) s += l.A[t][a] * Y[t][b] - Y[t][a] * Z[t][b];
+        o.J[a][b] = s;
+        o.J[b][a] = s;
       }
-    tsandwich_add<N, N>(l.A, MJ, l.J, o.J);
+    // b_ij = A_j (b_i + u) + b_j
+    PKS_UNROLL for (int i = 0; i < N; ++i) u[i] += l.b[i];
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      R s = r.b[i];
+      PKS_UNROLL for (int t = 0; t < N; ++t) s += r.A[i][t] * u[t];
+      o.b[i] = s;
+    }
+    // A_ij = A_j (A_i - Z)
+    PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) Z[i][j] = l.A[i][j] - Z[i][j];
+    mat_mul<N, N, N>(r.A, Z, o.A);
+    // C_ij = A_j M A_j^T + C_j
+    sandwich_add<N, N>(r.A, M, r.C, o.C);
     if (!ok) o.b[0] = quiet_nan<R>();
   }
 
   // out = c (x) r for a carry c
   static PKS_DEV void apply(const Carry& c, const Elem& r, Carry& o) {
-    R W[N][N], M[N][N];
-    const bool ok = core(c.C, r.J, W, M);
-    R v[N], u[N], bu[N];
+    R M[N][N];
+    const bool ok = core(c.C, r.J, M);
+    R v[N], u[N];
     PKS_UNROLL for (int i = 0; i < N; ++i) {
       R s = r.eta[i];
       PKS_UNROLL for (int t = 0; t < N; ++t) s -= r.J[i][t] * c.b[t];
       v[i] = s;
     }
     mat_vec<N, N>(M, v, u);
-    PKS_UNROLL for (int i = 0; i < N; ++i) bu[i] = c.b[i] + u[i];
+    PKS_UNROLL for (int i = 0; i < N; ++i) u[i] += c.b[i];
     PKS_UNROLL for (int i = 0; i < N; ++i) {
       R s = r.b[i];
-      PKS_UNROLL for (int t = 0; t < N; ++t) s += r.A[i][t] * bu[t];
+      PKS_UNROLL for (int t = 0; t < N; ++t) s += r.A[i][t] * u[t];
       o.b[i] = s;
     }
     sandwich_add<N, N>(r.A, M, r.C, o.C);

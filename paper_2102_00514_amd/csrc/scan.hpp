@@ -143,23 +143,22 @@ __global__ __launch_bounds__(B) void k_scan_down(ScanArgs a) {
   lane_apply<Op, B, R>(a, first, have, c);
 }
 
-// Whole scan in one block (m <= B*K).
+// Whole inclusive scan of m positions by one block (K = ceil(m / B) per lane):
+// fold, ladder, then every lane walks its positions from its exclusive carry.
 template <class Op, int B, typename R>
-__global__ __launch_bounds__(B) void k_scan_single(ScanArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* lds = reinterpret_cast<R*>(smem_raw);
-  const R* E = static_cast<const R*>(a.elems);
-  const int lane = threadIdx.x;
-  const int64_t first = (int64_t)lane * a.K;
-  const bool valid = first < a.m;
+PKS_DEV void block_scan(R* lds, int lane, const R* E, size_t estride, int64_t m, int reverse, R* out,
+                        size_t ostride) {
+  const int K = int((m + B - 1) / B);
+  const int64_t first = (int64_t)lane * K;
+  const bool valid = first < m;
   typename Op::Elem v;
   if (valid) {
-    Op::load(E, a.estride, a.reverse ? a.m - 1 - first : first, v);
-    for (int j = 1; j < a.K; ++j) {
+    Op::load(E, estride, reverse ? m - 1 - first : first, v);
+    for (int j = 1; j < K; ++j) {
       const int64_t q = first + j;
-      if (q >= a.m) break;
+      if (q >= m) break;
       typename Op::Elem e, r;
-      Op::load(E, a.estride, a.reverse ? a.m - 1 - q : q, e);
+      Op::load(E, estride, reverse ? m - 1 - q : q, e);
       Op::combine(v, e, r);
       v = r;
     }
@@ -174,7 +173,49 @@ __global__ __launch_bounds__(B) void k_scan_single(ScanArgs a) {
     Op::to_carry(ex, c);
     have = true;
   }
-  lane_apply<Op, B, R>(a, first, have, c);
+  for (int j = 0; j < K; ++j) {
+    const int64_t q = first + j;
+    if (q >= m) break;
+    const int64_t idx = reverse ? m - 1 - q : q;
+    typename Op::Elem e;
+    Op::load(E, estride, idx, e);
+    if (have) {
+      typename Op::Carry n;
+      Op::apply(c, e, n);
+      c = n;
+    } else {
+      Op::to_carry(e, c);
+      have = true;
+    }
+    Op::store(out, ostride, idx, c);
+  }
+}
+
+// Whole scan in one block.
+template <class Op, int B, typename R>
+__global__ __launch_bounds__(B) void k_scan_single(ScanArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  block_scan<Op, B, R>(reinterpret_cast<R*>(smem_raw), threadIdx.x, static_cast<const R*>(a.elems), a.estride,
+                       a.m, a.reverse, static_cast<R*>(a.out), a.ostride);
+}
+
+// The block that finishes last (atomic ticket) scans the tile aggregates of
+// the launch.  No block ever waits for another, so there is no dependence on
+// how many blocks are resident.  Writers release their aggregates with a
+// device-scope fence before taking a ticket; the last block acquires with a
+// device-scope fence before reading them, and resets the ticket for the next
+// launch.
+template <class Op, int B, typename R>
+PKS_DEV void last_block_scan(R* lds, int lane, unsigned int* ticket, int64_t tiles, const R* agg, R* carry) {
+  __shared__ unsigned int s_ticket;
+  __threadfence();
+  __syncthreads();
+  if (lane == 0) s_ticket = atomicAdd(ticket, 1u);
+  __syncthreads();
+  if (s_ticket != unsigned(tiles - 1)) return;
+  __threadfence();
+  block_scan<Op, B, R>(lds, lane, agg, size_t(tiles), tiles, 0, carry, size_t(tiles));
+  if (lane == 0) *ticket = 0u;
 }
 
 }  // namespace pks

@@ -1,34 +1,17 @@
-// Per-slot kernels of one iteration and the sequential comparison kernel.
+// Per-slot helper kernels and the sequential comparison path.
 //
-// Device layout (structure of arrays, entry-major, `stride` >= S slots):
-//   traj  [N + s(N)][stride]   xbar, Pbar (upper-packed) of the current iterate
+// Device layout (structure of arrays, entry-major, `stride` >= slots):
+//   traj  [N + s(N)][stride]   xbar, Pbar (upper-packed) of an iterate
 //   yslot [P][stride]          y_k at the slot of x_k (unused at first slots)
-//   lin   [LinLayout::kWords][stride]
+//   lin   [LinLayout::kWords][stride]   (sequential path only)
 //         transition out of the slot: F (N*N), c (N), Q' (s(N))
 //         measurement at the slot:    H (P*N), d (P), R' (s(P)), ytil (P)
-//   felem [FilterOp::kElemWords][stride], filt [N + s(N)][stride]
-//   selem [SmootherOp::kElemWords][stride]
 // Slot flags: bit 0 = first slot of a track (x_0), bit 1 = last slot (x_T).
 #pragma once
 
-#include "elements.hpp"
-#include "operators.hpp"
+#include "fused.hpp"
 
 namespace pks {
-
-enum : unsigned { kSlotFirst = 1u, kSlotLast = 2u };
-
-template <int N, int P>
-struct LinLayout {
-  static constexpr int kF = 0;
-  static constexpr int kc = kF + N * N;
-  static constexpr int kQ = kc + N;
-  static constexpr int kH = kQ + sym_size<N>();
-  static constexpr int kd = kH + P * N;
-  static constexpr int kR = kd + P;
-  static constexpr int ky = kR + sym_size<P>();
-  static constexpr int kWords = ky + P;
-};
 
 struct SlotArgs {
   int64_t S;
@@ -44,9 +27,7 @@ struct SlotArgs {
   const void* yslot;
   const void* traj;     // current iterate
   void* lin;
-  void* felem;
   void* filt;
-  void* selem;
   void* traj_out;
   unsigned long long* delta_bits;  // [ntracks + 1]; last entry = max over tracks
   SigmaRule rule;
@@ -91,77 +72,6 @@ __global__ __launch_bounds__(kSlotBlock) void k_linearize(SlotArgs a) {
   }
 }
 
-template <int N, int P, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_filter_elements(SlotArgs a) {
-  using LL = LinLayout<N, P>;
-  using Op = FilterOp<N, R>;
-  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
-  if (s >= a.S) return;
-  const unsigned fl = a.flags[s];
-  const size_t st = a.stride;
-  const R* lin = static_cast<const R*>(a.lin);
-  typename Op::Elem e;
-  if (fl & kSlotFirst) {
-    // prior element (A = 0, b = m0, C = P0, eta = 0, J = 0)
-    const int tr = a.track[s];
-    set_zero<N>(e.A);
-    set_zero<N>(e.eta);
-    set_zero<N>(e.J);
-    ld_vec<N>(static_cast<const R*>(a.m0), a.tstride, tr, e.b);
-    ld_sym<N>(static_cast<const R*>(a.P0), a.tstride, tr, e.C);
-  } else {
-    R F[N][N], c[N], Qp[N][N], H[P][N], d[P], Rp[P][P], yt[P];
-    ld_mat<N, N>(lin + LL::kF * st, st, s - 1, F);
-    ld_vec<N>(lin + LL::kc * st, st, s - 1, c);
-    ld_sym<N>(lin + LL::kQ * st, st, s - 1, Qp);
-    ld_mat<P, N>(lin + LL::kH * st, st, s, H);
-    ld_vec<P>(lin + LL::kd * st, st, s, d);
-    ld_sym<P>(lin + LL::kR * st, st, s, Rp);
-    ld_vec<P>(lin + LL::ky * st, st, s, yt);
-    const bool ok = filter_element<N, P, R>(F, c, Qp, H, d, Rp, yt, e.A, e.b, e.C, e.eta, e.J);
-    if (!ok) e.b[0] = quiet_nan<R>();
-  }
-  Op::store(static_cast<R*>(a.felem), st, s, e);
-}
-
-template <int N, int P, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_smoother_elements(SlotArgs a) {
-  using LL = LinLayout<N, P>;
-  using Op = SmootherOp<N, R>;
-  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
-  if (s >= a.S) return;
-  const unsigned fl = a.flags[s];
-  const size_t st = a.stride;
-  const R* filt = static_cast<const R*>(a.filt);
-  typename Op::Elem e;
-  R xf[N], Pf[N][N];
-  ld_vec<N>(filt, st, s, xf);
-  ld_sym<N>(filt + N * st, st, s, Pf);
-  if (fl & kSlotLast) {
-    // end element (E = 0, g = x*, L = P*)
-    set_zero<N>(e.E);
-    PKS_UNROLL for (int i = 0; i < N; ++i) {
-      e.g[i] = xf[i];
-      PKS_UNROLL for (int j = 0; j < N; ++j) e.L[i][j] = Pf[i][j];
-    }
-  } else {
-    const R* lin = static_cast<const R*>(a.lin);
-    R F[N][N], c[N], Qp[N][N];
-    ld_mat<N, N>(lin + LL::kF * st, st, s, F);
-    ld_vec<N>(lin + LL::kc * st, st, s, c);
-    ld_sym<N>(lin + LL::kQ * st, st, s, Qp);
-    const bool ok = smoother_element<N, R>(xf, Pf, F, c, Qp, e.E, e.g, e.L);
-    if (!ok) e.g[0] = quiet_nan<R>();
-  }
-  Op::store(static_cast<R*>(a.selem), st, s, e);
-}
-
-// Non-negative doubles (and NaN) order like their bit patterns as unsigned.
-PKS_DEV unsigned long long order_bits(double v) {
-  const double a = (v == v) ? v : __builtin_nan("");
-  return static_cast<unsigned long long>(__double_as_longlong(a));
-}
-
 // Per-track and global max |xbar_new - xbar_old| (NaN wins).  A block whose
 // slots all belong to one track reduces in LDS and issues one global atomic.
 template <int N, typename R>
@@ -198,7 +108,12 @@ __global__ __launch_bounds__(kSlotBlock) void k_delta(SlotArgs a) {
   }
 }
 
-__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+static __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static __global__ void k_fill_u32(unsigned int* p, int64_t n, unsigned int v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }

@@ -1,14 +1,7 @@
-// Host runtime and C ABI of the parallel iterated smoother (include/smoother.h).
-//
-// One handle owns a device memory plan for a batch of tracks laid out slot by
-// slot (tracks concatenated) and queues every iteration on the caller's HIP
-// stream:
-//   linearise -> filtering elements -> prefix scan (eq. 15) -> smoothing
-//   elements -> suffix scan (eq. 19) -> per-track convergence statistic.
-// Tracks need no segmentation in the scans: the prior element that opens each
-// track has A = 0, eta = J = 0, and the end element that closes it has E = 0,
-// so no prefix or suffix leaks across a track boundary (the parts that do
-// cross -- A, eta, J of a filtering prefix -- never reach the outputs).
+// C ABI of the parallel iterated smoother (include/smoother.h): host-side
+// validation of the problem, handle lifetime and error reporting.  The device
+// memory plan and the kernel sequence live in the engines (engine.hpp), one
+// translation unit per model and precision.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,20 +15,11 @@
 #include <vector>
 
 #include "smoother.h"
-#include "scan.hpp"
-#include "slot_kernels.hpp"
+#include "engine_base.hpp"
 
 namespace pks {
 
-constexpr int kScanB = 64;        // lanes per scan tile (one wavefront)
-constexpr int kLevelK = 2;        // positions per lane below the top level
-constexpr int kTopMaxK = 8;       // the top level is one tile of <= kScanB * kTopMaxK positions
-
 static thread_local std::string g_init_error;
-
-static std::string hip_msg(hipError_t e, const char* what) {
-  return std::string(what) + ": " + hipGetErrorString(e);
-}
 
 // ---------------------------------------------------------------------------
 // Host-side validation helpers (double precision, plain loops).
@@ -72,456 +56,11 @@ static bool all_finite(const double* p, size_t n) {
   return true;
 }
 
-struct ScanLevel {
-  int64_t m;
-  int K;
-  int64_t tiles;
-  void* lane_excl = nullptr;   // [elem words][tiles*B]
-  void* tile_agg = nullptr;    // [elem words][tiles]
-  void* tile_carry = nullptr;  // [carry words][tiles]
-};
-
-static std::vector<ScanLevel> plan_levels(int64_t S) {
-  std::vector<ScanLevel> lv;
-  int64_t m = S;
-  while (m > int64_t(kScanB) * kTopMaxK) {
-    ScanLevel L;
-    L.m = m;
-    L.K = kLevelK;
-    L.tiles = (m + int64_t(kScanB) * kLevelK - 1) / (int64_t(kScanB) * kLevelK);
-    lv.push_back(L);
-    m = L.tiles;
-  }
-  ScanLevel top;
-  top.m = m;
-  top.K = int((m + kScanB - 1) / kScanB);
-  top.tiles = 1;
-  lv.push_back(top);
-  return lv;
-}
-
-// ---------------------------------------------------------------------------
-// Engine: everything that depends on the model, dimensions and precision.
-// ---------------------------------------------------------------------------
-class EngineBase {
- public:
-  virtual ~EngineBase() { release(); }
-  virtual sm_status setup(const sm_problem& pb, hipStream_t stream) = 0;
-  virtual sm_status iterate(int k) = 0;
-  virtual sm_status result_host(double* mean, double* cov) = 0;
-  virtual sm_status result_device(void* mean, void* cov) = 0;
-
-  sm_status track_deltas(double* out) {
-    std::vector<unsigned long long> bits(ntracks + 1);
-    hipError_t e = hipMemcpyAsync(bits.data(), delta_bits, sizeof(unsigned long long) * (ntracks + 1),
-                                  hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "copy of the convergence statistic"));
-    for (int i = 0; i <= ntracks; ++i) std::memcpy(&out[i], &bits[i], sizeof(double));
-    return SM_OK;
-  }
-
-  // Per-launch HIP events (only while profiling).
-  struct ProfRec {
-    const char* name;
-    hipEvent_t a, b;
-    int64_t positions;
-  };
-
-  template <class F>
-  void timed(const char* name, int64_t positions, F&& launch) {
-    if (!profiling) {
-      launch();
-      return;
-    }
-    ProfRec r{name, nullptr, nullptr, positions};
-    (void)hipEventCreate(&r.a);
-    (void)hipEventCreate(&r.b);
-    (void)hipEventRecord(r.a, stream);
-    launch();
-    (void)hipEventRecord(r.b, stream);
-    prof.push_back(r);
-  }
-
-  sm_status profile(int k, sm_kernel_time* out, int cap_out, int* n_out) {
-    prof.clear();
-    profiling = true;
-    sm_status st = iterate(k);
-    profiling = false;
-    hipError_t e = hipStreamSynchronize(stream);
-    std::vector<sm_kernel_time> acc;
-    for (ProfRec& r : prof) {
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
-      auto it = std::find_if(acc.begin(), acc.end(),
-                             [&](const sm_kernel_time& t) { return std::strcmp(t.name, r.name) == 0; });
-      if (it == acc.end()) {
-        sm_kernel_time t{};
-        std::snprintf(t.name, sizeof(t.name), "%s", r.name);
-        acc.push_back(t);
-        it = acc.end() - 1;
-      }
-      it->launches += 1;
-      it->total_ms += ms;
-      it->positions += r.positions;
-    }
-    prof.clear();
-    if (st != SM_OK) return st;
-    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "profiling events"));
-    const int n = std::min<int>(cap_out, int(acc.size()));
-    for (int i = 0; i < n; ++i) out[i] = acc[i];
-    if (n_out) *n_out = n;
-    return SM_OK;
-  }
-
-  sm_status fail(sm_status st, const std::string& msg) {
-    err = msg;
-    return st;
-  }
-
-  hipError_t dalloc(void** p, size_t bytes) {
-    *p = nullptr;
-    if (bytes == 0) return hipSuccess;
-    if (cap > 0 && int64_t(device_bytes + bytes) > cap) return hipErrorOutOfMemory;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e == hipSuccess) {
-      allocs.push_back(*p);
-      device_bytes += bytes;
-    } else {
-      *p = nullptr;
-    }
-    return e;
-  }
-
-  void release() {
-    for (void* p : allocs) (void)hipFree(p);
-    allocs.clear();
-    device_bytes = 0;
-  }
-
-  std::string err;
-  int64_t S = 0;
-  size_t stride = 0;
-  int ntracks = 0;
-  int n_iter = 0;
-  int iters = 0;
-  int64_t cap = 0;
-  size_t device_bytes = 0;
-  hipStream_t stream = nullptr;
-  unsigned long long* delta_bits = nullptr;
-  std::vector<void*> allocs;
-  bool profiling = false;
-  std::vector<ProfRec> prof;
-};
-
-template <class Model, typename R>
-class Engine final : public EngineBase {
- public:
-  static constexpr int N = Model::N, P = Model::P;
-  static constexpr int kSN = sym_size<N>();
-  static constexpr int kTrajW = N + kSN;
-  using FOp = FilterOp<N, R>;
-  using SOp = SmootherOp<N, R>;
-  using LL = LinLayout<N, P>;
-
-  sm_status setup(const sm_problem& pb, hipStream_t st) override {
-    stream = st;
-    cap = pb.max_device_bytes;
-    ntracks = pb.n_tracks;
-    n_iter = pb.n_iter;
-    lin_ = pb.lin;
-    seq_ = pb.scan == SM_SCAN_SEQUENTIAL;
-    rule_.alpha = pb.ut_alpha;
-    rule_.kappa = pb.ut_kappa;
-    // slot map
-    slot_off_.resize(ntracks + 1);
-    for (int i = 0; i <= ntracks; ++i) slot_off_[i] = pb.offsets[i] + i;
-    S = slot_off_[ntracks];
-    stride = size_t((S + 63) / 64 * 64);
-    std::vector<unsigned char> flags(S, 0);
-    std::vector<int> track(S, 0);
-    for (int i = 0; i < ntracks; ++i) {
-      for (int64_t s = slot_off_[i]; s < slot_off_[i + 1]; ++s) track[s] = i;
-      flags[slot_off_[i]] |= kSlotFirst;
-      flags[slot_off_[i + 1] - 1] |= kSlotLast;
-    }
-    // host copies in the compute precision
-    std::vector<R> prm(pb.params, pb.params + pb.n_params);
-    std::vector<R> Q(pb.Q, pb.Q + N * N), Rm(pb.R, pb.R + P * P);
-    std::vector<R> m0(size_t(N) * ntracks), P0(size_t(kSN) * ntracks);
-    for (int t = 0; t < ntracks; ++t) {
-      for (int i = 0; i < N; ++i) m0[size_t(i) * ntracks + t] = R(pb.m0[size_t(t) * N + i]);
-      for (int i = 0; i < N; ++i)
-        for (int j = i; j < N; ++j)
-          P0[size_t(sym_index<N>(i, j)) * ntracks + t] = R(pb.P0[(size_t(t) * N + i) * N + j]);
-    }
-    std::vector<R> yslot(size_t(P) * stride, R(0));
-    for (int t = 0; t < ntracks; ++t)
-      for (int64_t k = 1; k < slot_off_[t + 1] - slot_off_[t]; ++k) {
-        const int64_t s = slot_off_[t] + k, row = pb.offsets[t] + k - 1;
-        for (int i = 0; i < P; ++i) yslot[size_t(i) * stride + s] = R(pb.y[row * P + i]);
-      }
-    levels_ = plan_levels(S);
-    // device plan
-    hipError_t e = hipSuccess;
-    auto A = [&](void** p, size_t bytes) {
-      if (e == hipSuccess) e = dalloc(p, bytes);
-    };
-    A(&d_params_, sizeof(R) * std::max<size_t>(prm.size(), 1));
-    A(&d_Q_, sizeof(R) * N * N);
-    A(&d_R_, sizeof(R) * P * P);
-    A(&d_m0_, sizeof(R) * m0.size());
-    A(&d_P0_, sizeof(R) * P0.size());
-    A(reinterpret_cast<void**>(&d_flags_), S);
-    A(reinterpret_cast<void**>(&d_track_), sizeof(int) * S);
-    A(reinterpret_cast<void**>(&d_slot_off_), sizeof(int64_t) * (ntracks + 1));
-    A(&d_y_, sizeof(R) * yslot.size());
-    A(&d_traj_[0], sizeof(R) * kTrajW * stride);
-    A(&d_traj_[1], sizeof(R) * kTrajW * stride);
-    A(&d_lin_, sizeof(R) * LL::kWords * stride);
-    A(&d_filt_, sizeof(R) * kTrajW * stride);
-    A(reinterpret_cast<void**>(&delta_bits), sizeof(unsigned long long) * (ntracks + 1));
-    if (!seq_) {
-      // smoothing elements reuse the filtering-element buffer (dead after the prefix scan)
-      A(&d_felem_, sizeof(R) * FOp::kElemWords * stride);
-      for (size_t l = 0; l + 1 < levels_.size(); ++l) {
-        ScanLevel& L = levels_[l];
-        A(&L.lane_excl, sizeof(R) * FOp::kElemWords * L.tiles * kScanB);
-        A(&L.tile_agg, sizeof(R) * FOp::kElemWords * L.tiles);
-        A(&L.tile_carry, sizeof(R) * FOp::kCarryWords * L.tiles);
-      }
-    }
-    if (e != hipSuccess)
-      return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE,
-                  hip_msg(e, "device allocation") + " (plan needs more than is available or allowed)");
-    auto H2D = [&](void* dst, const void* src, size_t bytes) {
-      if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
-    };
-    H2D(d_params_, prm.data(), sizeof(R) * prm.size());
-    H2D(d_Q_, Q.data(), sizeof(R) * Q.size());
-    H2D(d_R_, Rm.data(), sizeof(R) * Rm.size());
-    H2D(d_m0_, m0.data(), sizeof(R) * m0.size());
-    H2D(d_P0_, P0.data(), sizeof(R) * P0.size());
-    H2D(d_flags_, flags.data(), S);
-    H2D(d_track_, track.data(), sizeof(int) * S);
-    H2D(d_slot_off_, slot_off_.data(), sizeof(int64_t) * (ntracks + 1));
-    H2D(d_y_, yslot.data(), sizeof(R) * yslot.size());
-    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "upload of the problem"));
-    const int64_t grid = (S + kSlotBlock - 1) / kSlotBlock;
-    SlotArgs a = args(0);
-    if (pb.init_mean) {
-      // caller trajectory: pack on the device from staging copies
-      std::vector<R> mean(pb.init_mean, pb.init_mean + size_t(S) * N);
-      std::vector<R> cov(size_t(S) * N * N);
-      for (int64_t s = 0; s < S; ++s)
-        for (int i = 0; i < N * N; ++i)
-          cov[size_t(s) * N * N + i] = R(pb.init_cov ? pb.init_cov[size_t(s) * N * N + i]
-                                                     : pb.P0[size_t(track[s]) * N * N + i]);
-      void *dm = nullptr, *dc = nullptr;
-      e = hipMalloc(&dm, sizeof(R) * mean.size());
-      if (e == hipSuccess) e = hipMalloc(&dc, sizeof(R) * cov.size());
-      H2D(dm, mean.data(), sizeof(R) * mean.size());
-      H2D(dc, cov.data(), sizeof(R) * cov.size());
-      if (e == hipSuccess)
-        hipLaunchKernelGGL((k_pack<N, R>), dim3(grid), dim3(kSlotBlock), 0, stream, S, stride,
-                           static_cast<const R*>(dm), static_cast<const R*>(dc), static_cast<R*>(d_traj_[0]));
-      if (e == hipSuccess) e = hipGetLastError();
-      if (e == hipSuccess) e = hipStreamSynchronize(stream);
-      if (dm) (void)hipFree(dm);
-      if (dc) (void)hipFree(dc);
-      if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "upload of the initial trajectory"));
-    } else {
-      hipLaunchKernelGGL((k_broadcast_prior<N, R>), dim3(grid), dim3(kSlotBlock), 0, stream, a,
-                         static_cast<R*>(d_traj_[0]));
-    }
-    hipLaunchKernelGGL(k_fill_u64, dim3((ntracks + 256) / 256), dim3(256), 0, stream, delta_bits,
-                       int64_t(ntracks + 1), 0ull);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "initial trajectory"));
-    cur_ = 0;
-    return SM_OK;
-  }
-
-  SlotArgs args(int cur) const {
-    SlotArgs a;
-    a.S = S;
-    a.stride = stride;
-    a.flags = d_flags_;
-    a.track = d_track_;
-    a.params = d_params_;
-    a.Q = d_Q_;
-    a.R = d_R_;
-    a.m0 = d_m0_;
-    a.P0 = d_P0_;
-    a.tstride = size_t(ntracks);
-    a.yslot = d_y_;
-    a.traj = d_traj_[cur];
-    a.lin = d_lin_;
-    a.felem = d_felem_;
-    a.filt = d_filt_;
-    a.selem = d_felem_;
-    a.traj_out = d_traj_[cur ^ 1];
-    a.delta_bits = delta_bits;
-    a.rule = rule_;
-    return a;
-  }
-
-  template <class Op>
-  void run_scan(const void* elems, bool reverse, void* out, const char* const (&names)[3]) {
-    const size_t lds = sizeof(R) * Op::kElemWords * kScanB;
-    const int L = int(levels_.size());
-    for (int l = 0; l + 1 < L; ++l) {
-      const ScanLevel& lv = levels_[l];
-      ScanArgs a{};
-      a.elems = l == 0 ? elems : levels_[l - 1].tile_agg;
-      a.estride = l == 0 ? stride : size_t(levels_[l - 1].tiles);
-      a.m = lv.m;
-      a.reverse = (l == 0 && reverse) ? 1 : 0;
-      a.K = lv.K;
-      a.lane_excl = lv.lane_excl;
-      a.lstride = size_t(lv.tiles) * kScanB;
-      a.tile_agg = lv.tile_agg;
-      a.tstride = size_t(lv.tiles);
-      timed(names[0], lv.m, [&] {
-        hipLaunchKernelGGL((k_scan_up<Op, kScanB, R>), dim3(lv.tiles), dim3(kScanB), lds, stream, a);
-      });
-    }
-    {
-      const ScanLevel& top = levels_[L - 1];
-      ScanArgs a{};
-      a.elems = L == 1 ? elems : levels_[L - 2].tile_agg;
-      a.estride = L == 1 ? stride : size_t(levels_[L - 2].tiles);
-      a.m = top.m;
-      a.reverse = (L == 1 && reverse) ? 1 : 0;
-      a.K = top.K;
-      a.out = L == 1 ? out : levels_[L - 2].tile_carry;
-      a.ostride = L == 1 ? stride : size_t(levels_[L - 2].tiles);
-      timed(names[1], top.m, [&] {
-        hipLaunchKernelGGL((k_scan_single<Op, kScanB, R>), dim3(1), dim3(kScanB), lds, stream, a);
-      });
-    }
-    for (int l = L - 2; l >= 0; --l) {
-      const ScanLevel& lv = levels_[l];
-      ScanArgs a{};
-      a.elems = l == 0 ? elems : levels_[l - 1].tile_agg;
-      a.estride = l == 0 ? stride : size_t(levels_[l - 1].tiles);
-      a.m = lv.m;
-      a.reverse = (l == 0 && reverse) ? 1 : 0;
-      a.K = lv.K;
-      a.lane_excl = lv.lane_excl;
-      a.lstride = size_t(lv.tiles) * kScanB;
-      a.tile_carry = lv.tile_carry;
-      a.cstride = size_t(lv.tiles);
-      a.out = l == 0 ? out : levels_[l - 1].tile_carry;
-      a.ostride = l == 0 ? stride : size_t(levels_[l - 1].tiles);
-      timed(names[2], lv.m, [&] {
-        hipLaunchKernelGGL((k_scan_down<Op, kScanB, R>), dim3(lv.tiles), dim3(kScanB), 0, stream, a);
-      });
-    }
-  }
-
-  void launch_linearize(const SlotArgs& a, dim3 grid) {
-    switch (lin_) {
-      case SM_LIN_TAYLOR:
-        hipLaunchKernelGGL((k_linearize<Model, kTaylor, R>), grid, dim3(kSlotBlock), 0, stream, a);
-        break;
-      case SM_LIN_CUBATURE:
-        hipLaunchKernelGGL((k_linearize<Model, kCubature, R>), grid, dim3(kSlotBlock), 0, stream, a);
-        break;
-      default:
-        hipLaunchKernelGGL((k_linearize<Model, kUnscented, R>), grid, dim3(kSlotBlock), 0, stream, a);
-        break;
-    }
-  }
-
-  sm_status iterate(int k) override {
-    static const char* const kFilterNames[3] = {"scan_up_filter", "scan_top_filter", "scan_down_filter"};
-    static const char* const kSmootherNames[3] = {"scan_up_smoother", "scan_top_smoother", "scan_down_smoother"};
-    const dim3 grid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
-    for (int it = 0; it < k; ++it) {
-      const SlotArgs a = args(cur_);
-      timed("reset_delta", ntracks + 1, [&] {
-        hipLaunchKernelGGL(k_fill_u64, dim3((ntracks + 256) / 256), dim3(256), 0, stream, delta_bits,
-                           int64_t(ntracks + 1), 0ull);
-      });
-      timed("linearize", S, [&] { launch_linearize(a, grid); });
-      if (seq_) {
-        timed("sequential", S, [&] {
-          hipLaunchKernelGGL((k_sequential<N, P, R>), dim3((ntracks + 63) / 64), dim3(64), 0, stream, a,
-                             d_slot_off_, ntracks);
-        });
-      } else {
-        timed("filter_elements", S, [&] {
-          hipLaunchKernelGGL((k_filter_elements<N, P, R>), grid, dim3(kSlotBlock), 0, stream, a);
-        });
-        run_scan<FOp>(d_felem_, false, d_filt_, kFilterNames);
-        timed("smoother_elements", S, [&] {
-          hipLaunchKernelGGL((k_smoother_elements<N, P, R>), grid, dim3(kSlotBlock), 0, stream, a);
-        });
-        run_scan<SOp>(d_felem_, true, d_traj_[cur_ ^ 1], kSmootherNames);
-      }
-      timed("delta", S, [&] { hipLaunchKernelGGL((k_delta<N, R>), grid, dim3(kSlotBlock), 0, stream, a); });
-      cur_ ^= 1;
-      ++iters;
-    }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "kernel launch"));
-    return SM_OK;
-  }
-
-  sm_status result_host(double* mean, double* cov) override {
-    std::vector<R> h(size_t(kTrajW) * stride);
-    hipError_t e = hipMemcpyAsync(h.data(), d_traj_[cur_], sizeof(R) * h.size(), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "copy of the result"));
-    for (int64_t s = 0; s < S; ++s) {
-      if (mean)
-        for (int i = 0; i < N; ++i) mean[size_t(s) * N + i] = double(h[size_t(i) * stride + s]);
-      if (cov)
-        for (int i = 0; i < N; ++i)
-          for (int j = 0; j < N; ++j)
-            cov[(size_t(s) * N + i) * N + j] = double(h[size_t(N + sym_index<N>(i, j)) * stride + s]);
-    }
-    return SM_OK;
-  }
-
-  sm_status result_device(void* mean, void* cov) override {
-    const dim3 grid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
-    hipLaunchKernelGGL((k_unpack<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride,
-                       static_cast<const R*>(d_traj_[cur_]), static_cast<R*>(mean), static_cast<R*>(cov));
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "result kernel"));
-    return SM_OK;
-  }
-
- private:
-  int lin_ = 0;
-  bool seq_ = false;
-  SigmaRule rule_{1.0, 1.0};
-  int cur_ = 0;
-  std::vector<int64_t> slot_off_;
-  std::vector<ScanLevel> levels_;
-  void *d_params_ = nullptr, *d_Q_ = nullptr, *d_R_ = nullptr, *d_m0_ = nullptr, *d_P0_ = nullptr;
-  unsigned char* d_flags_ = nullptr;
-  int* d_track_ = nullptr;
-  int64_t* d_slot_off_ = nullptr;
-  void *d_y_ = nullptr, *d_traj_[2] = {nullptr, nullptr}, *d_lin_ = nullptr, *d_filt_ = nullptr;
-  void* d_felem_ = nullptr;
-};
-
-// Compiled (model, nx, ny) combinations.
-template <typename R>
-static EngineBase* make_engine_t(int model, int nx, int ny) {
-  if (model == SM_MODEL_CT_BEARINGS) {
-    if (nx == 5 && ny == 2) return new Engine<CtBearings<5, 2, R>, R>();
-  } else if (model == SM_MODEL_LINEAR) {
-    if (nx == 1 && ny == 1) return new Engine<LinearModel<1, 1, R>, R>();
-    if (nx == 3 && ny == 2) return new Engine<LinearModel<3, 2, R>, R>();
-    if (nx == 5 && ny == 2) return new Engine<LinearModel<5, 2, R>, R>();
-  }
+static EngineBase* make_engine(int model, int precision, int nx, int ny) {
+  if (model == SM_MODEL_CT_BEARINGS)
+    return precision == SM_FP64 ? make_engine_ct_f64(nx, ny) : make_engine_ct_f32(nx, ny);
+  if (model == SM_MODEL_LINEAR)
+    return precision == SM_FP64 ? make_engine_linear_f64(nx, ny) : make_engine_linear_f32(nx, ny);
   return nullptr;
 }
 
@@ -573,6 +112,8 @@ static std::string validate(const sm_problem* pb) {
   if (pb->precision != SM_FP64 && pb->precision != SM_FP32) return "unknown precision";
   if (pb->scan != SM_SCAN_PARALLEL && pb->scan != SM_SCAN_SEQUENTIAL) return "unknown scan mode";
   if (pb->max_device_bytes < 0) return "max_device_bytes must be >= 0";
+  if (pb->tile_lanes != 0 && pb->tile_lanes != 64 && pb->tile_lanes != 256) return "tile_lanes must be 0, 64 or 256";
+  if (pb->lane_slots < 0 || pb->lane_slots > 8) return "lane_slots must be in 0..8";
   const int64_t S = nmeas + pb->n_tracks;
   if (pb->init_cov && !pb->init_mean) return "init_cov given without init_mean";
   if (pb->init_mean && !all_finite(pb->init_mean, size_t(S) * n)) return "init_mean must be finite";
@@ -618,9 +159,7 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
       g_init_error = msg;
       return SM_EINVAL;
     }
-    std::unique_ptr<pks::EngineBase> eng(pb->precision == SM_FP64
-                                             ? pks::make_engine_t<double>(pb->model, pb->nx, pb->ny)
-                                             : pks::make_engine_t<float>(pb->model, pb->nx, pb->ny));
+    std::unique_ptr<pks::EngineBase> eng(pks::make_engine(pb->model, pb->precision, pb->nx, pb->ny));
     if (!eng) {
       g_init_error = "no kernel for this configuration";
       return SM_EINVAL;
@@ -736,6 +275,14 @@ sm_status smoother_info(smoother_t h, int64_t* n_slots, int32_t* n_tracks, int64
   if (n_slots) *n_slots = h->eng->S;
   if (n_tracks) *n_tracks = h->eng->ntracks;
   if (device_bytes) *device_bytes = int64_t(h->eng->device_bytes);
+  return SM_OK;
+}
+
+sm_status smoother_schedule(smoother_t h, int32_t* tile_lanes, int32_t* lane_slots, int64_t* tiles) {
+  if (!h || !h->eng) return SM_ESTATE;
+  if (tile_lanes) *tile_lanes = h->eng->sched_lanes;
+  if (lane_slots) *lane_slots = h->eng->sched_slots;
+  if (tiles) *tiles = h->eng->sched_tiles;
   return SM_OK;
 }
 

@@ -90,15 +90,15 @@ def test_c2_single_iteration(B, T, lin):
         assert_parity(mean, cov, one, what=f"C2 T={T} {lin} iteration {start + 1}")
 
 
-def test_three_level_scan(B):
-    """More than 64*2*64*2 slots: two recursion levels below the top tile."""
+def test_long_tracks(B):
+    """Long single tracks (automatic schedule)."""
     pb = wl.ct_bearings(20000, seed=7)
     mean, cov, one = single_iteration_case(B, pb, "taylor", 0)
-    assert_parity(mean, cov, one, what="T=20000 (2 levels)")
+    assert_parity(mean, cov, one, what="T=20000")
     p2 = wl.linear_gaussian(1, 1, 70000, seed=4)
     ref = oracle.smoother(p2, 1, "taylor")
     mean, cov, _, _ = run_gpu(B, p2, 1)
-    assert_parity(mean, cov, ref, what="linear T=70000 (3 levels)")
+    assert_parity(mean, cov, ref, what="linear T=70000")
 
 
 def test_sequential_mode_matches_oracle(B):
@@ -161,3 +161,27 @@ def test_fp32_variant(B):
     ep = oracle.cov_error(cov, ref["cov"])
     print(f"FP32 C1: e_m={em:.3e} e_P={ep:.3e}", flush=True)
     assert em < 1e-4 and ep < 1e-3
+
+
+@pytest.mark.parametrize("lanes,slots", [(64, 1), (64, 2), (64, 3), (256, 1), (256, 2), (256, 4), (256, 8)])
+@pytest.mark.parametrize("T", [1, 5, 200, 3000])
+def test_schedules(B, lanes, slots, T):
+    """Every (lanes per tile, slots per lane) gives the oracle's result,
+    including partially filled and padded tiles."""
+    pb = wl.config_c2(T) if T > 1 else wl.ct_bearings(1, seed=5)
+    ref = oracle.smoother(pb, 2, "cubature")
+    mean, cov, _, _ = run_gpu(B, pb, 2, "cubature", tile_lanes=lanes, lane_slots=slots)
+    assert_parity(mean, cov, ref, what=f"T={T} lanes={lanes} slots={slots}")
+
+
+def test_multilevel_tile_scan(B):
+    """More tile aggregates than one block scans: the generic multi-level scan
+    runs between the fused kernels (64 lanes x 1 slot -> 1094 tiles)."""
+    p2 = wl.linear_gaussian(1, 1, 70000, seed=4)
+    ref = oracle.smoother(p2, 1, "taylor")
+    with B.Smoother(p2, n_iter=1, tile_lanes=64, lane_slots=1) as sm:
+        lanes, slots, tiles = sm.schedule()
+        assert tiles > 64 * 8
+        sm.iterate(0)
+        mean, cov = sm.result()
+    assert_parity(mean, cov, ref, what="linear T=70000, 1094 tiles")
