@@ -60,6 +60,31 @@ def algorithmic_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: 
     return words * word
 
 
+def kernel_sources_sha256() -> str:
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2102_00514_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(csrc, "*.h*")) + glob.glob(os.path.join(csrc, "*.hip"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when there is none for this kernel/workload or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh).get(key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("csrc_sha256") != kernel_sources_sha256():
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(pb, lin: str, budget_s: float) -> dict:
     """The oracle, untuned, on one host core: repeated full iterations of the same
     workload until about budget_s seconds of CPU time have been spent."""
@@ -88,6 +113,8 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain copy kernel of 256 MiB in, 256 MiB out (counter calibration)")
     ap.add_argument("--tile-lanes", type=int, default=0, help="scan schedule override (64 or 256)")
     ap.add_argument("--lane-slots", type=int, default=0, help="scan schedule override (1..8)")
     args = ap.parse_args()
@@ -103,6 +130,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # a plain elementwise copy with known traffic, for scaling hardware byte counters
+        src = torch.full((32 * 2 ** 20,), 1.0, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 B read, 268435456 B written by one elementwise kernel")
+        del src, dst
     pb = wl.config_c2(args.T)
     T = int(pb.offsets[1])
     stream = torch.cuda.current_stream()
@@ -150,8 +186,10 @@ def main():
     avg_launch_s = dom[3] * 1e-3 / dom[2]
     bytes_per_launch = dom[5] * dom[4] / dom[2]
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = measured_traffic(f"{dom[1]}|T={T}|{args.lin}|{args.precision}")
     roofline = {"bound": "hbm", "kernel": dom[1], "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                "traffic": None if traffic is None else int(traffic),
                 "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": int(bytes_per_launch)}
     sm.close()
 
