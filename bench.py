@@ -51,6 +51,7 @@ def algorithmic_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: 
         # reverse carries, new trajectory in place, convergence statistic (reads old means)
         "backward_down": se + se / K + n + car,
         "tiles_up_filter": fe + fe / 2, "tiles_top_filter": fe + car, "tiles_down_filter": fe + fe / 2 + car,
+        # (per tile aggregate: read once, write its carry)
         "tiles_up_smoother": se + se / 2, "tiles_top_smoother": se + car, "tiles_down_smoother": se + se / 2 + car,
         "linearize": xin + p + lin_words,
         "sequential": lin_words + 2 * car,

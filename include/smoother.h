@@ -96,11 +96,13 @@ typedef struct {
   int64_t max_device_bytes;       /* 0 = no cap; otherwise SM_ENOMEM if the plan needs more */
   int32_t tile_lanes;             /* scan schedule: lanes per tile (64 or 256; 0 = auto) */
   int32_t lane_slots;             /* scan schedule: consecutive slots per lane (1..8; 0 = auto) */
+  int32_t use_graph;              /* 1: iterations of the parallel path are replayed from a HIP graph
+                                     captured on the first call; 0: launched one kernel at a time */
 } sm_problem;
 
 /* Fills *pb with defaults: n_tracks = 1, n_iter = 10, lin = SM_LIN_TAYLOR,
  * ut_alpha = 1, ut_beta = 0, ut_kappa = 1, FP64, parallel scan, no init, no cap,
- * automatic scan schedule. */
+ * automatic scan schedule, HIP-graph replay. */
 void smoother_problem_defaults(sm_problem* pb);
 
 /* Validates the problem on the host (dimensions supported by the compiled

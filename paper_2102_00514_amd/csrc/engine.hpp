@@ -4,11 +4,13 @@
 // One handle owns a plan for a batch of tracks laid out slot by slot (tracks
 // concatenated, padded to whole tiles) and queues every iteration on the
 // caller's HIP stream as three fused kernels (fused.hpp):
-//   linearise + filtering elements + forward up-sweep  [+ top scan, last block]
-//   forward down-sweep + smoothing elements + reverse up-sweep  [+ top scan]
+//   linearise + filtering elements + forward up-sweep
+//   single-block scan of the tile aggregates
+//   forward down-sweep + smoothing elements + reverse up-sweep
+//   single-block scan of the reverse tile aggregates
 //   reverse down-sweep + convergence statistic.
 // When the tile aggregates do not fit one block, they are scanned by the
-// generic multi-level kernels of scan.hpp between the fused kernels.
+// generic multi-level kernels of scan.hpp instead.
 // Tracks need no segmentation in the scans: the prior element that opens each
 // track has A = 0, eta = J = 0, and the end element that closes it has E = 0,
 // so no prefix or suffix leaks across a track boundary (the parts that do
@@ -25,7 +27,8 @@ namespace pks {
 
 constexpr int kScanB = 64;        // lanes per scan tile (one wavefront)
 constexpr int kLevelK = 2;        // positions per lane below the top level
-constexpr int kTopMaxK = 8;       // a single block scans at most B * kTopMaxK tile aggregates
+constexpr int kTopMaxK = 8;       // a single block scans at most kTopB * kTopMaxK tile aggregates
+constexpr int kTopB = 256;        // lanes of the single-block scan of the tile aggregates
 
 struct ScanLevel {
   int64_t m;
@@ -96,6 +99,7 @@ class Engine final : public EngineBase {
     n_iter = pb.n_iter;
     lin_ = pb.lin;
     seq_ = pb.scan == SM_SCAN_SEQUENTIAL;
+    use_graph_ = pb.use_graph != 0 && !seq_;
     rule_.alpha = pb.ut_alpha;
     rule_.kappa = pb.ut_kappa;
     slot_off_.resize(ntracks + 1);
@@ -106,7 +110,7 @@ class Engine final : public EngineBase {
     tiles_ = (S + per_tile - 1) / per_tile;
     const int64_t S_pad = tiles_ * per_tile;
     stride = size_t((S_pad + 63) / 64 * 64);
-    top_in_kernel_ = tiles_ <= int64_t(sched_.B) * kTopMaxK;
+    top_single_ = tiles_ <= int64_t(kTopB) * kTopMaxK;
     sched_lanes = sched_.B;
     sched_slots = sched_.K;
     sched_tiles = tiles_;
@@ -170,8 +174,7 @@ class Engine final : public EngineBase {
       A(&lx_s_, sizeof(R) * SOp::kElemWords * lanes);
       A(&ta_s_, sizeof(R) * SOp::kElemWords * tiles_);
       A(&tc_s_, sizeof(R) * SOp::kCarryWords * tiles_);
-      A(reinterpret_cast<void**>(&tickets_), sizeof(unsigned int) * 2);
-      if (!top_in_kernel_) {
+      if (!top_single_) {
         // generic multi-level scan of the tile aggregates
         levels_ = plan_levels(tiles_);
         for (size_t l = 0; l + 1 < levels_.size(); ++l) {
@@ -228,8 +231,6 @@ class Engine final : public EngineBase {
     }
     hipLaunchKernelGGL(k_fill_u64, dim3((ntracks + 256) / 256), dim3(256), 0, stream, delta_bits,
                        int64_t(ntracks + 1), 0ull);
-    if (tickets_)
-      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, tickets_, int64_t(2), 0u);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "initial trajectory"));
@@ -254,7 +255,14 @@ class Engine final : public EngineBase {
 
   hipError_t set_lds_limits() {
     if (seq_) return hipSuccess;
-    return sched_.B == 64 ? set_lds_limits_b<64>() : set_lds_limits_b<256>();
+    hipError_t e = sched_.B == 64 ? set_lds_limits_b<64>() : set_lds_limits_b<256>();
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_single<FOp, kTopB, R>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(R) * FOp::kElemWords * kTopB));
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_single<SOp, kTopB, R>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(R) * SOp::kElemWords * kTopB));
+    return e;
   }
 
   SlotArgs slot_args(int cur) const {
@@ -285,7 +293,6 @@ class Engine final : public EngineBase {
     a.stride = stride;
     a.K = sched_.K;
     a.tiles = tiles_;
-    a.top_in_kernel = top_in_kernel_ ? 1 : 0;
     a.ntracks = ntracks;
     a.flags = d_flags_;
     a.track = d_track_;
@@ -306,7 +313,6 @@ class Engine final : public EngineBase {
     a.lx_s = lx_s_;
     a.ta_s = ta_s_;
     a.tc_s = tc_s_;
-    a.tickets = tickets_;
     a.delta_bits = delta_bits;
     a.rule = rule_;
     return a;
@@ -364,6 +370,26 @@ class Engine final : public EngineBase {
     }
   }
 
+  // Tile aggregates -> inclusive tile carries: one 256-lane block when they fit,
+  // the generic multi-level scan otherwise.
+  template <class Op>
+  void scan_tiles(void* agg, void* carry, const char* const (&names)[3]) {
+    if (!top_single_) {
+      run_scan<Op>(agg, tiles_, carry, names);
+      return;
+    }
+    ScanArgs a{};
+    a.elems = agg;
+    a.estride = size_t(tiles_);
+    a.m = tiles_;
+    a.out = carry;
+    a.ostride = size_t(tiles_);
+    timed(names[1], tiles_, [&] {
+      hipLaunchKernelGGL((k_scan_single<Op, kTopB, R>), dim3(1), dim3(kTopB), sizeof(R) * Op::kElemWords * kTopB,
+                         stream, a);
+    });
+  }
+
   template <int B>
   void launch_iteration(const FusedArgs& a) {
     static const char* const kFilterNames[3] = {"tiles_up_filter", "tiles_top_filter", "tiles_down_filter"};
@@ -382,11 +408,11 @@ class Engine final : public EngineBase {
         hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R>), grid, block, lds_filter(), stream, a);
       });
     }
-    if (!top_in_kernel_) run_scan<FOp>(ta_f_, tiles_, tc_f_, kFilterNames);
+    scan_tiles<FOp>(ta_f_, tc_f_, kFilterNames);
     timed("forward_down_backward_up", S, [&] {
       hipLaunchKernelGGL((k_forward_down_backward_up<Model, B, R>), grid, block, lds_smoother(), stream, a);
     });
-    if (!top_in_kernel_) run_scan<SOp>(ta_s_, tiles_, tc_s_, kSmootherNames);
+    scan_tiles<SOp>(ta_s_, tc_s_, kSmootherNames);
     timed("backward_down", S, [&] {
       hipLaunchKernelGGL((k_backward_down<Model, B, R>), grid, block, 0, stream, a);
     });
@@ -422,16 +448,54 @@ class Engine final : public EngineBase {
         });
         timed("delta", S, [&] { hipLaunchKernelGGL((k_delta<N, R>), grid, dim3(kSlotBlock), 0, stream, a); });
         cur_ ^= 1;
+      } else if (use_graph_ && !profiling) {
+        if (!graph_exec_) {
+          const hipError_t ge = capture_iteration();
+          if (ge != hipSuccess) return fail(SM_EDEVICE, hip_msg(ge, "capture of the iteration graph"));
+        }
+        const hipError_t le = hipGraphLaunch(graph_exec_, stream);
+        if (le != hipSuccess) return fail(SM_EDEVICE, hip_msg(le, "graph launch"));
       } else {
-        const FusedArgs a = fused_args();
-        if (sched_.B == 64) launch_iteration<64>(a);
-        else launch_iteration<256>(a);
+        launch_parallel_iteration();
       }
       ++iters;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "kernel launch"));
     return SM_OK;
+  }
+
+  void launch_parallel_iteration() {
+    const FusedArgs a = fused_args();
+    if (sched_.B == 64) launch_iteration<64>(a);
+    else launch_iteration<256>(a);
+  }
+
+  // Records one iteration on a private stream (capture is not allowed on the
+  // legacy default stream) and instantiates it; the kernels update the
+  // trajectory in place and reset their own counters, so the same graph is
+  // replayed for every iteration on the handle's stream.
+  hipError_t capture_iteration() {
+    hipError_t e = hipSuccess;
+    if (!capture_stream_) e = hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipStream_t user = stream;
+    stream = capture_stream_;
+    e = hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      launch_parallel_iteration();
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(capture_stream_, &g);
+      if (e == hipSuccess) e = hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    stream = user;
+    return e;
+  }
+
+  ~Engine() override {
+    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+    if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
   }
 
   sm_status result_host(double* mean, double* cov) override {
@@ -462,11 +526,14 @@ class Engine final : public EngineBase {
  private:
   int lin_ = 0;
   bool seq_ = false;
+  bool use_graph_ = false;
+  hipGraphExec_t graph_exec_ = nullptr;
+  hipStream_t capture_stream_ = nullptr;
   SigmaRule rule_{1.0, 1.0};
   int cur_ = 0;
   Schedule sched_;
   int64_t tiles_ = 0;
-  bool top_in_kernel_ = true;
+  bool top_single_ = true;
   std::vector<int64_t> slot_off_;
   std::vector<ScanLevel> levels_;
   void *d_params_ = nullptr, *d_Q_ = nullptr, *d_R_ = nullptr, *d_m0_ = nullptr, *d_P0_ = nullptr;
@@ -477,7 +544,6 @@ class Engine final : public EngineBase {
   void *d_lin_ = nullptr, *d_filt_ = nullptr;  // sequential path
   void *d_trans_ = nullptr, *d_felem_ = nullptr, *d_selem_ = nullptr;
   void *lx_f_ = nullptr, *ta_f_ = nullptr, *tc_f_ = nullptr, *lx_s_ = nullptr, *ta_s_ = nullptr, *tc_s_ = nullptr;
-  unsigned int* tickets_ = nullptr;
 };
 
 }  // namespace pks

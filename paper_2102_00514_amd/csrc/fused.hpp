@@ -5,16 +5,17 @@
 //                   sigma-point regression read from a separate pass), fold
 //                   each lane's K elements,
 //                   Kogge-Stone over the lanes (eq. 15) -> lane exclusive
-//                   prefixes and the tile aggregate; the last block scans the
-//                   tile aggregates.
+//                   prefixes and the tile aggregate.
 //   k_forward_down_backward_up
 //                   apply the tile and lane carries to every slot -> filtered
 //                   x*_k, P*_k; build the smoothing element (eq. 16-18); fold
 //                   and ladder them in reverse slot order (eq. 19) -> reverse
-//                   lane prefixes and tile aggregates; the last block scans the
-//                   reverse tile aggregates.
+//                   lane prefixes and tile aggregates.
 //   k_backward_down apply the reverse carries -> smoothed xbar_k, Pbar_k,
 //                   written in place, and the convergence statistic.
+//
+// Between them the tile aggregates are scanned into tile carries by a
+// single-block scan (or the multi-level scan of scan.hpp for many tiles).
 //
 // The slot range is padded to tiles * B * K with single-slot dummy tracks
 // (flags first|last, prior element (0, 0, I, 0, 0), end element (0, 0, I));
@@ -37,7 +38,6 @@ struct FusedArgs {
   size_t stride;        // row stride of every slot array (>= padded slots)
   int K;                // slots per lane
   int64_t tiles;        // tiles of B*K slots
-  int top_in_kernel;    // 1: the last block scans the tile aggregates
   int ntracks;
   const unsigned char* flags;
   const int* track;
@@ -54,7 +54,6 @@ struct FusedArgs {
   void* filt;           // optional [N + s(N)][stride]  x*, P*
   void *lx_f, *ta_f, *tc_f;  // forward lane exclusives [words][tiles*B], tile aggregates, tile carries
   void *lx_s, *ta_s, *tc_s;  // same for the reverse scan, indexed by reverse tile
-  unsigned int* tickets;     // [2] last-block tickets
   unsigned long long* delta_bits;  // [ntracks + 1]; entry ntracks = max over tracks
   SigmaRule rule;
 };
@@ -161,15 +160,20 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
   if (tile == 0)
     for (int i = lane; i <= a.ntracks; i += B) a.delta_bits[i] = 0ull;
   R* felem = static_cast<R*>(a.felem);
-  // build and store all K elements first, then fold them back from memory: the
-  // running aggregate is never live while a slot is linearised
-  for (int j = 0; j < a.K; ++j) {
-    typename Op::Elem e;
-    build_filter_element<Model, SRC, R>(a, base + j, e);
-    Op::store(felem, a.stride, base + j, e);
-  }
   typename Op::Elem acc;
-  Op::load(felem, a.stride, base, acc);
+  if (a.K == 1) {
+    build_filter_element<Model, SRC, R>(a, base, acc);
+    Op::store(felem, a.stride, base, acc);
+  } else {
+    // build and store all K elements first, then fold them back from memory:
+    // the running aggregate is never live while a slot is linearised
+    for (int j = 0; j < a.K; ++j) {
+      typename Op::Elem e;
+      build_filter_element<Model, SRC, R>(a, base + j, e);
+      Op::store(felem, a.stride, base + j, e);
+    }
+    Op::load(felem, a.stride, base, acc);
+  }
   for (int j = 1; j < a.K; ++j) {
     typename Op::Elem e, r;
     Op::load(felem, a.stride, base + j, e);
@@ -183,9 +187,6 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
     Op::store(static_cast<R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
   }
   if (lane == B - 1) Op::store(static_cast<R*>(a.ta_f), size_t(a.tiles), tile, acc);
-  if (a.top_in_kernel)
-    last_block_scan<Op, B, R>(lds, lane, &a.tickets[0], a.tiles, static_cast<const R*>(a.ta_f),
-                              static_cast<R*>(a.tc_f));
 }
 
 template <class Model, int B, typename R>
@@ -272,9 +273,6 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
     SOp::store(static_cast<R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, ex);
   }
   if (rl == B - 1) SOp::store(static_cast<R*>(a.ta_s), size_t(a.tiles), rt, sacc);
-  if (a.top_in_kernel)
-    last_block_scan<SOp, B, R>(lds, lane, &a.tickets[1], a.tiles, static_cast<const R*>(a.ta_s),
-                               static_cast<R*>(a.tc_s));
 }
 
 PKS_DEV unsigned long long order_bits(double v) {

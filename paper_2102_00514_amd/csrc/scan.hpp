@@ -199,23 +199,4 @@ __global__ __launch_bounds__(B) void k_scan_single(ScanArgs a) {
                        a.m, a.reverse, static_cast<R*>(a.out), a.ostride);
 }
 
-// The block that finishes last (atomic ticket) scans the tile aggregates of
-// the launch.  No block ever waits for another, so there is no dependence on
-// how many blocks are resident.  Writers release their aggregates with a
-// device-scope fence before taking a ticket; the last block acquires with a
-// device-scope fence before reading them, and resets the ticket for the next
-// launch.
-template <class Op, int B, typename R>
-PKS_DEV void last_block_scan(R* lds, int lane, unsigned int* ticket, int64_t tiles, const R* agg, R* carry) {
-  __shared__ unsigned int s_ticket;
-  __threadfence();
-  __syncthreads();
-  if (lane == 0) s_ticket = atomicAdd(ticket, 1u);
-  __syncthreads();
-  if (s_ticket != unsigned(tiles - 1)) return;
-  __threadfence();
-  block_scan<Op, B, R>(lds, lane, agg, size_t(tiles), tiles, 0, carry, size_t(tiles));
-  if (lane == 0) *ticket = 0u;
-}
-
 }  // namespace pks

@@ -114,6 +114,7 @@ static std::string validate(const sm_problem* pb) {
   if (pb->max_device_bytes < 0) return "max_device_bytes must be >= 0";
   if (pb->tile_lanes != 0 && pb->tile_lanes != 64 && pb->tile_lanes != 256) return "tile_lanes must be 0, 64 or 256";
   if (pb->lane_slots < 0 || pb->lane_slots > 8) return "lane_slots must be in 0..8";
+  if (pb->use_graph != 0 && pb->use_graph != 1) return "use_graph must be 0 or 1";
   const int64_t S = nmeas + pb->n_tracks;
   if (pb->init_cov && !pb->init_mean) return "init_cov given without init_mean";
   if (pb->init_mean && !all_finite(pb->init_mean, size_t(S) * n)) return "init_mean must be finite";
@@ -145,6 +146,7 @@ void smoother_problem_defaults(sm_problem* pb) {
   pb->ut_kappa = 1.0;
   pb->precision = SM_FP64;
   pb->scan = SM_SCAN_PARALLEL;
+  pb->use_graph = 1;
 }
 
 sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out) {

@@ -202,28 +202,42 @@ def ct_batch(n_tracks: int, t_min: int, t_max: int, seed_tag: int = 3,
     Track i uses ``default_rng([seed_tag, i])``: its length T_i ~ U{t_min..t_max},
     its true initial state (uniform position, unit speed with uniform heading,
     turn rate ~ U(-1, 1)), then the process and measurement noise.  The prior
-    mean is the true initial state with the turn rate set to zero, P0 = I."""
+    mean is the true initial state with the turn rate set to zero, P0 = I.
+    The tracks are propagated together, one time step for all live tracks at a
+    time."""
     sensors = np.asarray(sensors, dtype=np.float64)
     ny = sensors.shape[0]
     Q = ct_process_noise()
     Lq = np.linalg.cholesky(Q)
     R = CT_R_STD ** 2 * np.eye(ny)
     lengths = np.empty(n_tracks, dtype=np.int64)
-    m0 = np.empty((n_tracks, 5))
-    ys, truths = [], []
+    x0 = np.empty((n_tracks, 5))
+    procs, meass = [], []
     for i in range(n_tracks):
         rng = np.random.default_rng([seed_tag, i])
         T = int(rng.integers(t_min, t_max + 1))
-        x0 = _random_ct_state(rng)
-        proc = rng.standard_normal((T, 5))
-        meas = rng.standard_normal((T, ny))
-        xs, y = _simulate_ct(x0, T, Lq, proc, meas, sensors, np.zeros(ny), CT_DT, CT_R_STD)
+        x0[i] = _random_ct_state(rng)
+        procs.append(rng.standard_normal((T, 5)))
+        meass.append(rng.standard_normal((T, ny)))
         lengths[i] = T
-        m0[i] = x0
-        m0[i, 4] = 0.0
-        ys.append(y)
-        truths.append(xs)
+    tmax = int(lengths.max())
+    states = np.empty((tmax + 1, n_tracks, 5))
+    states[0] = x0
+    noise = np.zeros((tmax, n_tracks, 5))
+    for i in range(n_tracks):
+        noise[:lengths[i], i] = procs[i] @ Lq.T
+    for k in range(1, tmax + 1):
+        states[k] = _ct_propagate(states[k - 1], CT_DT) + noise[k - 1]
     offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    ys, truths = [], []
+    for i in range(n_tracks):
+        T = int(lengths[i])
+        xs = states[:T + 1, i]
+        ang = np.arctan2(xs[1:, 1:2] - sensors[:, 1], xs[1:, 0:1] - sensors[:, 0])
+        ys.append(wrap_angle(ang + CT_R_STD * meass[i]))
+        truths.append(xs)
+    m0 = x0.copy()
+    m0[:, 4] = 0.0
     P0 = np.broadcast_to(np.eye(5), (n_tracks, 5, 5)).copy()
     return Problem(5, ny, MODEL_CT_BEARINGS, ct_params(sensors), Q, R, m0, P0,
                    np.concatenate(ys), offsets, np.concatenate(truths),
