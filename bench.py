@@ -62,11 +62,15 @@ def algorithmic_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: 
 
 
 def kernel_sources_sha256() -> str:
+    """Hash of the smoother's kernel sources (the warm-start network's own
+    sources, nn_* and warmstart*, do not define any smoother kernel)."""
     import glob
     import hashlib
     csrc = os.path.join(ROOT, "paper_2102_00514_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(csrc, "*.h*")) + glob.glob(os.path.join(csrc, "*.hip"))):
+    files = glob.glob(os.path.join(csrc, "*.h*")) + glob.glob(os.path.join(csrc, "*.hip"))
+    files = [f for f in files if not os.path.basename(f).startswith(("nn_", "warmstart"))]
+    for f in sorted(files):
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -196,15 +196,20 @@ def _random_ct_state(rng) -> np.ndarray:
 
 
 def ct_batch(n_tracks: int, t_min: int, t_max: int, seed_tag: int = 3,
-             sensors=CT_SENSORS) -> Problem:
+             sensors=CT_SENSORS, first: int = 0, initial_state=None, prior_mean=None) -> Problem:
     """Ragged batch of independent coordinated-turn tracks.
 
-    Track i uses ``default_rng([seed_tag, i])``: its length T_i ~ U{t_min..t_max},
+    Track i uses ``default_rng([seed_tag, i])``: its length T_i ~ U{t_min..t_max}
+    (no draw when t_min == t_max),
     its true initial state (uniform position, unit speed with uniform heading,
     turn rate ~ U(-1, 1)), then the process and measurement noise.  The prior
     mean is the true initial state with the turn rate set to zero, P0 = I.
     The tracks are propagated together, one time step for all live tracks at a
-    time."""
+    time.
+
+    ``first`` offsets the track index in the seed (tracks first..first+n-1);
+    ``initial_state(rng)`` replaces the true-initial-state draw and
+    ``prior_mean(x0)`` the prior rule."""
     sensors = np.asarray(sensors, dtype=np.float64)
     ny = sensors.shape[0]
     Q = ct_process_noise()
@@ -214,9 +219,9 @@ def ct_batch(n_tracks: int, t_min: int, t_max: int, seed_tag: int = 3,
     x0 = np.empty((n_tracks, 5))
     procs, meass = [], []
     for i in range(n_tracks):
-        rng = np.random.default_rng([seed_tag, i])
-        T = int(rng.integers(t_min, t_max + 1))
-        x0[i] = _random_ct_state(rng)
+        rng = np.random.default_rng([seed_tag, first + i])
+        T = t_min if t_min == t_max else int(rng.integers(t_min, t_max + 1))
+        x0[i] = (initial_state or _random_ct_state)(rng)
         procs.append(rng.standard_normal((T, 5)))
         meass.append(rng.standard_normal((T, ny)))
         lengths[i] = T
@@ -236,12 +241,39 @@ def ct_batch(n_tracks: int, t_min: int, t_max: int, seed_tag: int = 3,
         ang = np.arctan2(xs[1:, 1:2] - sensors[:, 1], xs[1:, 0:1] - sensors[:, 0])
         ys.append(wrap_angle(ang + CT_R_STD * meass[i]))
         truths.append(xs)
-    m0 = x0.copy()
-    m0[:, 4] = 0.0
+    if prior_mean is None:
+        m0 = x0.copy()
+        m0[:, 4] = 0.0
+    else:
+        m0 = np.stack([prior_mean(x) for x in x0])
     P0 = np.broadcast_to(np.eye(5), (n_tracks, 5, 5)).copy()
     return Problem(5, ny, MODEL_CT_BEARINGS, ct_params(sensors), Q, R, m0, P0,
                    np.concatenate(ys), offsets, np.concatenate(truths),
                    f"ct_batch({n_tracks},[{t_min},{t_max}])")
+
+
+C4_T = 4096
+C4_HELD_OUT_BASE = 10 ** 6
+
+
+def _c4_initial_state(rng) -> np.ndarray:
+    x0 = np.array(CT_M0, dtype=np.float64)
+    x0[4] = rng.uniform(-1.0, 1.0)
+    return x0
+
+
+def config_c4(first: int, count: int, held_out: bool = False, T: int = C4_T) -> Problem:
+    """Warm-start workload: tracks of T=4096 steps that all start from the
+    experiment's initial position and velocity with a turn rate ~ U(-1, 1).
+    Track i draws from ``default_rng([4, i])`` (training) or
+    ``default_rng([4, 10^6 + i])`` (held out): the turn rate, then the process
+    and measurement noise.  The prior is the single-track prior (turn rate 0,
+    P0 = I) for every track."""
+    base = C4_HELD_OUT_BASE if held_out else 0
+    pb = ct_batch(count, T, T, seed_tag=4, first=base + first, initial_state=_c4_initial_state,
+                  prior_mean=lambda x0: np.array(CT_M0, dtype=np.float64))
+    pb.name = f"c4({'held-out' if held_out else 'train'} {first}..{first + count - 1}, T={T})"
+    return pb
 
 
 def config_c3(n_tracks: int = 4096, t_min: int = 100, t_max: int = 8192) -> Problem:
