@@ -134,6 +134,20 @@ sm_status smoother_result(smoother_t h, double* mean, double* cov);
  * stream without a host wait. */
 sm_status smoother_result_device(smoother_t h, void* d_mean, void* d_cov);
 
+/* Replaces the current trajectory -- the linearisation points of the next
+ * iteration (Section 3) -- with caller-owned device data, queued on the
+ * handle's stream without a host wait: means d_mean [S*nx] in the handle's
+ * precision (double for SM_FP64, float for SM_FP32); covariances from d_cov
+ * [S*nx*nx] (symmetrised), else the host matrix cov_const [nx*nx] (double,
+ * symmetric positive definite) at every slot, else each track's P0.  Giving
+ * both d_cov and cov_const is SM_EINVAL.  The iteration count restarts at 0
+ * and the per-track deltas are cleared.  The device data are not inspected: a
+ * non-finite value surfaces as SM_ENUMERIC from the next smoother_iterate
+ * that asks for the delta.  Used to start from a learned initial trajectory
+ * (warmstart.h, ws_trajectory). */
+sm_status smoother_set_trajectory_device(smoother_t h, const void* d_mean, const void* d_cov,
+                                         const double* cov_const);
+
 /* Per-track maximum |xbar^(i) - xbar^(i-1)| of the last iteration, host
  * [n_tracks]; waits for the stream. */
 sm_status smoother_track_deltas(smoother_t h, double* deltas);

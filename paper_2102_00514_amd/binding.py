@@ -27,7 +27,8 @@ SCAN = {"parallel": 0, "sequential": 1}
 
 EXPORTS = ("smoother_problem_defaults", "smoother_init", "smoother_iterate", "smoother_result",
            "smoother_result_device", "smoother_track_deltas", "smoother_info", "smoother_last_error",
-           "smoother_destroy", "smoother_version", "smoother_profile", "smoother_schedule")
+           "smoother_destroy", "smoother_version", "smoother_profile", "smoother_schedule",
+           "smoother_set_trajectory_device")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -63,6 +64,16 @@ class SmootherError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built (python -m paper_2102_00514_amd.build)")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (soname
+    # libamdhip64.so.7) and requests it by the unversioned name, so if this
+    # library were loaded first, PyTorch would map a second copy of the HIP and
+    # HSA runtimes next to ours and ours would find no device.  Loading PyTorch
+    # first lets this library's libamdhip64.so.7 dependency resolve to the
+    # runtime PyTorch already holds.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     lib.smoother_problem_defaults.argtypes = [ctypes.POINTER(sm_problem)]
@@ -90,6 +101,8 @@ def _load():
     lib.smoother_schedule.restype = ctypes.c_int
     lib.smoother_version.argtypes = []
     lib.smoother_version.restype = ctypes.c_char_p
+    lib.smoother_set_trajectory_device.argtypes = [vp, vp, vp, _dp]
+    lib.smoother_set_trajectory_device.restype = ctypes.c_int
     return lib
 
 
@@ -192,6 +205,14 @@ def smoother_result_device(h: int, mean_ptr: int, cov_ptr: int) -> None:
     _check(h, _lib.smoother_result_device(h, ctypes.c_void_p(mean_ptr), ctypes.c_void_p(cov_ptr)))
 
 
+def smoother_set_trajectory_device(h: int, mean_ptr: int, cov_ptr: int = 0, cov_const=None) -> None:
+    """Next linearisation trajectory from device memory: means at mean_ptr,
+    covariances at cov_ptr, else the constant host matrix cov_const, else P0."""
+    cc = None if cov_const is None else _f64(cov_const)
+    _check(h, _lib.smoother_set_trajectory_device(h, ctypes.c_void_p(mean_ptr), ctypes.c_void_p(cov_ptr or 0),
+                                                  None if cc is None else cc.ctypes.data_as(_dp)))
+
+
 def smoother_track_deltas(h: int) -> np.ndarray:
     _, T, _ = smoother_info(h)
     out = np.empty(T)
@@ -242,6 +263,9 @@ class Smoother:
 
     def track_deltas(self):
         return smoother_track_deltas(self.h)
+
+    def set_trajectory_device(self, mean_ptr: int, cov_ptr: int = 0, cov_const=None):
+        smoother_set_trajectory_device(self.h, mean_ptr, cov_ptr, cov_const)
 
     def info(self):
         return smoother_info(self.h)

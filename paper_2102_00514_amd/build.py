@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 UNITS = ["smoother.hip", "engine_ct_f64.hip", "engine_ct_f32.hip", "engine_linear_f64.hip",
-         "engine_linear_f32.hip"]
+         "engine_linear_f32.hip", "warmstart.hip"]
 LIB = os.path.join(PKG, "libsmoother.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -30,7 +30,7 @@ HIP_FLAGS = [
 
 def sources():
     return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".hip", ".hpp"))] + \
-        [os.path.join(ROOT, "include", "smoother.h")]
+        [os.path.join(ROOT, "include", "smoother.h"), os.path.join(ROOT, "include", "warmstart.h")]
 
 
 def build(verbose: bool = False, extra=(), jobs: int = 8) -> str:

@@ -523,6 +523,31 @@ class Engine final : public EngineBase {
     return SM_OK;
   }
 
+  sm_status set_trajectory_device(const void* mean, const void* cov, const double* cov_const) override {
+    const dim3 grid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
+    R* traj = static_cast<R*>(d_traj_[cur_]);
+    const R* m = static_cast<const R*>(mean);
+    if (cov) {
+      hipLaunchKernelGGL((k_pack<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, static_cast<const R*>(cov),
+                         traj);
+    } else if (cov_const) {
+      SymConst<N, R> c;
+      for (int i = 0; i < N; ++i)
+        for (int j = i; j < N; ++j)
+          c.v[sym_index<N>(i, j)] = R(0.5 * (cov_const[i * N + j] + cov_const[j * N + i]));
+      hipLaunchKernelGGL((k_pack_const<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, c, traj);
+    } else {
+      hipLaunchKernelGGL((k_broadcast_prior<N, R>), grid, dim3(kSlotBlock), 0, stream, slot_args(cur_), traj);
+      hipLaunchKernelGGL((k_set_mean<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, traj);
+    }
+    hipLaunchKernelGGL(k_fill_u64, dim3((ntracks + 256) / 256), dim3(256), 0, stream, delta_bits,
+                       int64_t(ntracks + 1), 0ull);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "trajectory kernels"));
+    iters = 0;
+    return SM_OK;
+  }
+
  private:
   int lin_ = 0;
   bool seq_ = false;

@@ -27,6 +27,7 @@ class EngineBase {
   virtual sm_status iterate(int k) = 0;
   virtual sm_status result_host(double* mean, double* cov) = 0;
   virtual sm_status result_device(void* mean, void* cov) = 0;
+  virtual sm_status set_trajectory_device(const void* mean, const void* cov, const double* cov_const) = 0;
 
   sm_status track_deltas(double* out) {
     std::vector<unsigned long long> bits(ntracks + 1);

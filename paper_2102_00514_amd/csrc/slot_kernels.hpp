@@ -153,6 +153,31 @@ __global__ __launch_bounds__(kSlotBlock) void k_pack(int64_t S, size_t stride, c
       traj[(N + sym_index<N>(i, j)) * stride + s] = R(0.5) * (cov[(s * N + i) * N + j] + cov[(s * N + j) * N + i]);
 }
 
+// A covariance shared by every slot, upper-packed in sym_index order (passed by value).
+template <int N, typename R>
+struct SymConst {
+  R v[sym_size<N>()];
+};
+
+// Caller means [S][N] (device) -> packed trajectory; the covariance of every
+// slot is the constant c.
+template <int N, typename R>
+__global__ __launch_bounds__(kSlotBlock) void k_pack_const(int64_t S, size_t stride, const R* mean, SymConst<N, R> c,
+                                                           R* traj) {
+  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  if (s >= S) return;
+  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[s * N + i];
+  PKS_UNROLL for (int i = 0; i < sym_size<N>(); ++i) traj[(N + i) * stride + s] = c.v[i];
+}
+
+// Caller means [S][N] (device) -> the mean rows of the packed trajectory only.
+template <int N, typename R>
+__global__ __launch_bounds__(kSlotBlock) void k_set_mean(int64_t S, size_t stride, const R* mean, R* traj) {
+  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  if (s >= S) return;
+  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[s * N + i];
+}
+
 // ---------------------------------------------------------------------------
 // Sequential comparison path: one lane per track runs the Kalman filter and
 // the RTS smoother over the same linearised model (the recursions the scans

@@ -129,6 +129,7 @@ static std::string validate(const sm_problem* pb) {
 struct smoother {
   std::unique_ptr<pks::EngineBase> eng;
   std::string err;
+  int nx = 0;
 };
 
 using pks::g_init_error;
@@ -173,6 +174,7 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
     }
     smoother* h = new smoother();
     h->eng = std::move(eng);
+    h->nx = pb->nx;
     *out = h;
     g_init_error.clear();
     return SM_OK;
@@ -233,6 +235,39 @@ sm_status smoother_result_device(smoother_t h, void* d_mean, void* d_cov) {
   const sm_status st = h->eng->result_device(d_mean, d_cov);
   if (st != SM_OK) h->err = h->eng->err;
   return st;
+}
+
+sm_status smoother_set_trajectory_device(smoother_t h, const void* d_mean, const void* d_cov,
+                                         const double* cov_const) {
+  if (!h || !h->eng) return SM_ESTATE;
+  if (!d_mean) {
+    h->err = "d_mean is NULL";
+    return SM_EINVAL;
+  }
+  if (d_cov && cov_const) {
+    h->err = "give d_cov or cov_const, not both";
+    return SM_EINVAL;
+  }
+  if (cov_const) {
+    const int n = h->nx;
+    for (int i = 0; i < n * n; ++i)
+      if (!std::isfinite(cov_const[i])) {
+        h->err = "cov_const must be finite";
+        return SM_EINVAL;
+      }
+    if (!pks::host_spd(cov_const, n)) {
+      h->err = "cov_const must be symmetric positive definite";
+      return SM_EINVAL;
+    }
+  }
+  try {
+    const sm_status st = h->eng->set_trajectory_device(d_mean, d_cov, cov_const);
+    if (st != SM_OK) h->err = h->eng->err;
+    return st;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return SM_EDEVICE;
+  }
 }
 
 sm_status smoother_track_deltas(smoother_t h, double* deltas) {

@@ -124,3 +124,56 @@ def test_null_handle_calls_are_state_errors():
     assert lib.smoother_result(None, None, None) == B.SM_ESTATE
     assert lib.smoother_track_deltas(None, None) == B.SM_ESTATE
     lib.smoother_destroy(None)   # NULL-safe
+
+
+WS_HEADER = os.path.join(os.path.dirname(HEADER), "warmstart.h")
+
+
+def test_warmstart_symbols_and_config_layout():
+    from paper_2102_00514_amd import warmstart as W
+    text = re.sub(r"/\*.*?\*/", "", open(WS_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(ws_\w+)\s*\(", text)))
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(W.WS_EXPORTS)
+    body = text[text.index("typedef struct {"):text.index("} ws_config;")]
+    assert re.findall(r"(\w+)\s*;", body) == [f for f, _ in W.ws_config._fields_]
+    body = text[text.index("} ws_config;"):text.index("} ws_adam;")]
+    body = body[body.index("{") + 1:]
+    assert re.findall(r"(\w+)\s*[;,]", body) == [f for f, _ in W.ws_adam._fields_]
+
+
+def test_warmstart_param_count_and_config_validation():
+    from paper_2102_00514_amd import warmstart as W
+    from oracle import nn as onn
+    assert W.param_count(W.config()) == onn.n_params() == 201876
+    for cfgd in (dict(window=16, patch=4, width=16, hidden=2), dict(hidden=0), dict(width=64, hidden=6)):
+        c = W.config(**cfgd)
+        assert W.param_count(c) == onn.n_params(dict(onn.DEFAULT, **cfgd))
+    for bad in (dict(patch=3), dict(window=24, patch=4), dict(hidden=13), dict(max_batch=0), dict(nx=0)):
+        c = W.config(**bad)
+        assert W.param_count(c) == 0
+        h = ctypes.c_void_p()
+        st = W._lib.ws_create(ctypes.byref(c), None, ctypes.byref(h))   # validated before any device call
+        assert st == W.WS_EINVAL and not h.value
+        assert W._lib.ws_last_error(None)
+
+
+def test_warmstart_null_handles():
+    from paper_2102_00514_amd import warmstart as W
+    assert W._lib.ws_set_tracks(None, None, 0, None) == W.WS_ESTATE
+    assert W._lib.ws_trajectory(None, None, None) == W.WS_ESTATE
+    W._lib.ws_destroy(None)
+    assert B.lib().smoother_set_trajectory_device(None, None, None, None) == B.SM_ESTATE
+
+
+def test_one_hip_runtime_in_the_process():
+    """The library and PyTorch share a single HIP / HSA runtime (two copies in
+    one process leave one of them without a device)."""
+    import torch  # noqa: F401
+    B.lib()
+    maps = open("/proc/self/maps").read().split("\n")
+    for name in ("libamdhip64", "libhsa-runtime64"):
+        paths = {ln.split()[-1] for ln in maps if name in ln}
+        assert len(paths) == 1, (name, paths)
