@@ -107,6 +107,47 @@ def cpu_baseline(pb, lin: str, budget_s: float) -> dict:
             "sample": f"T={T}, {iters} iterations from the prior broadcast ({dt:.1f} s, 1 thread)"}
 
 
+def binding_autotune(pb, stream, lin):
+    from paper_2102_00514_amd import binding
+    lanes, slots, _ = binding.smoother_autotune(pb, stream=stream, iters=5, lin=lin)
+    return lanes, slots
+
+
+def warm_start_section(weights: str, n_batch: int, n_single: int, lin: str = "taylor") -> dict:
+    """Time to converge (trajectory change < 1e-6) from the prior broadcast vs
+    from the learned initial trajectory, on held-out warm-start tracks
+    (T = 4096): one batch of n_batch tracks in one handle, and n_single tracks
+    one handle at a time (latency of a single track, best of 5 runs each)."""
+    import numpy as np
+    import torch
+    from paper_2102_00514_amd import warmstart as W
+    from paper_2102_00514_amd import workloads as wl
+    stream = torch.cuda.current_stream().cuda_stream
+    net, cov, meta = W.load(weights, stream=stream)
+    pb = wl.config_c4(0, n_batch, held_out=True)
+    sched_batch = binding_autotune(pb, stream, lin)
+    sched_single = binding_autotune(pb.track(0), stream, lin)
+    W.time_to_converge(net, cov, pb.track(0), lin, schedule=sched_single)   # warm-up (kernels, allocator)
+    batch = W._public(W.time_to_converge(net, cov, pb, lin, schedule=sched_batch))
+    rows = {"plain": [], "learned": []}
+    for i in range(n_single):
+        r = W.time_to_converge(net, cov, pb.track(i), lin, repeats=5, schedule=sched_single)
+        for k in rows:
+            rows[k].append((r[k]["ms_to_converge"], r[k]["iters_mean"]))
+    single = {"tracks": n_single}
+    for k, v in rows.items():
+        ms = np.array([a if a is not None else np.nan for a, _ in v])
+        single[k] = {"ms_median": float(np.nanmedian(ms)), "ms_mean": float(np.nanmean(ms)),
+                     "iters_median": float(np.median([b for _, b in v])),
+                     "converged": float(np.mean(np.isfinite(ms)))}
+    single["speedup_median"] = single["plain"]["ms_median"] / single["learned"]["ms_median"]
+    net.close()
+    return {"weights": os.path.relpath(weights, ROOT), "lin": lin, "tol": 1e-6, "max_iter": 50, "T": wl.C4_T,
+            "schedules": {"batch": list(sched_batch), "single_track": list(sched_single)},
+            "trained_on": {k: meta.get(k) for k in ("tracks", "kept", "windows", "epochs", "train_s")},
+            "batch": dict(batch, tracks=n_batch), "single_track": single}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +163,12 @@ def main():
                     help="also run one plain copy kernel of 256 MiB in, 256 MiB out (counter calibration)")
     ap.add_argument("--tile-lanes", type=int, default=0, help="scan schedule override (64 or 256)")
     ap.add_argument("--lane-slots", type=int, default=0, help="scan schedule override (1..8)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default schedule instead of the autotuner's")
+    ap.add_argument("--warm-start-weights", default=os.path.join(ROOT, "paper_2102_00514_amd", "weights",
+                                                                 "warmstart_ieks.npz"))
+    ap.add_argument("--warm-start-tracks", type=int, default=512, help="held-out tracks in the batch comparison")
+    ap.add_argument("--warm-start-single", type=int, default=32, help="held-out tracks timed one at a time")
+    ap.add_argument("--no-warm-start", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -148,6 +195,13 @@ def main():
     T = int(pb.offsets[1])
     stream = torch.cuda.current_stream()
     total_iters = args.warmup + args.steps + args.profile_iters
+    tuned = None
+    if not args.tile_lanes and not args.lane_slots and not args.no_autotune:
+        lanes_t, slots_t, ms_t = binding.smoother_autotune(pb, stream=stream.cuda_stream, iters=10, lin=args.lin,
+                                                           precision=args.precision)
+        tuned = {"tile_lanes": lanes_t, "lane_slots": slots_t, "ms_per_iter": round(ms_t, 6)}
+        log(f"autotuned schedule: {lanes_t} lanes x {slots_t} slots ({ms_t * 1e3:.1f} us/iteration)")
+        args.tile_lanes, args.lane_slots = lanes_t, slots_t
     sm = binding.Smoother(pb, stream=stream.cuda_stream, n_iter=total_iters, lin=args.lin,
                           precision=args.precision, tile_lanes=args.tile_lanes, lane_slots=args.lane_slots)
     S, _, dev_bytes = sm.info()
@@ -198,6 +252,15 @@ def main():
                 "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": int(bytes_per_launch)}
     sm.close()
 
+    warm = None
+    if not args.no_warm_start and os.path.exists(args.warm_start_weights):
+        warm = warm_start_section(args.warm_start_weights, args.warm_start_tracks, args.warm_start_single)
+        log(f"time to converge (1e-6), held-out batch of {args.warm_start_tracks}: "
+            f"plain {warm['batch']['plain']['iters_mean']:.2f} iterations (mean), "
+            f"learned {warm['batch']['learned']['iters_mean']:.2f}; single track median "
+            f"{warm['single_track']['plain']['ms_median']:.3f} ms plain vs "
+            f"{warm['single_track']['learned']['ms_median']:.3f} ms learned")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(pb, args.lin, args.cpu_seconds)
@@ -212,9 +275,11 @@ def main():
                                f"{'IEKS (Taylor)' if args.lin == 'taylor' else args.lin + ' SLR'}, "
                                f"one iteration per step",
                    "T": T, "nx": pb.nx, "ny": pb.ny, "lin": args.lin, "parallelism": "time-axis scan, 1 GPU",
-                   "schedule": {"tiles": tiles, "lanes_per_tile": lanes, "slots_per_lane": slots}},
+                   "schedule": {"tiles": tiles, "lanes_per_tile": lanes, "slots_per_lane": slots,
+                                "autotuned": tuned}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "warm_start": warm,
     }
     print(json.dumps(out), flush=True)
 

@@ -24,6 +24,18 @@
  *                         atan2(py - sy, px - sx) of block `target`.
  *                         Bearing innovations are wrapped to [-pi, pi) around
  *                         h(xbar_k) of the current linearisation point.
+ *                         Supported: nx = 5 with ny = 2; and, with the Taylor
+ *                         linearisation, k = nx / 5 stacked targets
+ *                         (2 <= k <= 16) with two sensors per target and Q, R,
+ *                         P0 (and init_cov) without terms between different
+ *                         targets (|A_ij| <= 1e-12 sqrt(A_ii A_jj); smaller
+ *                         terms are dropped).  Such targets do not interact,
+ *                         the covariances stay block-diagonal, and the library
+ *                         smooths each target as its own block (exact up to
+ *                         rounding); off-block covariance outputs are zero.
+ *                         (Sigma-point rules couple stacked targets through
+ *                         their regression residuals and are not accepted for
+ *                         stacked states.)
  *
  * Conventions shared by every call:
  *   - Status: every call returns sm_status and never aborts or throws across the
@@ -113,6 +125,18 @@ void smoother_problem_defaults(sm_problem* pb);
  * why (the message is available from smoother_last_error(NULL)). */
 sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out);
 
+/* Scan-schedule autotuner: for every candidate schedule (tile_lanes 64 or
+ * 256, lane_slots 1, 2, 4 or 8) builds a handle for *pb on hip_stream, runs
+ * one warm-up iteration and then `iters` timed iterations (HIP events around
+ * the graph replays), releases the handle, and returns the fastest schedule in
+ * *tile_lanes / *lane_slots and its time per iteration in *ms_per_iter
+ * (nullable).  pb->tile_lanes, lane_slots and n_iter are ignored; the result
+ * is meant for the same fields of the problem given to smoother_init.
+ * Candidates that fail (e.g. over max_device_bytes) are skipped; if none runs,
+ * the last failure is returned.  Messages go to smoother_last_error(NULL). */
+sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iters, int32_t* tile_lanes,
+                            int32_t* lane_slots, double* ms_per_iter);
+
 /* Runs `k` more iterations (k <= 0: the iterations left up to n_iter).  Each
  * iteration re-linearises around the current trajectory (Section 3), builds the
  * filtering elements (eq. 13-14) and combines them with a prefix scan
@@ -123,6 +147,19 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
  * iters_done_out (nullable) receives the total number of iterations so far.
  * Returns SM_ENUMERIC when max_delta_out was requested and is not finite. */
 sm_status smoother_iterate(smoother_t h, int32_t k, double* max_delta_out, int32_t* iters_done_out);
+
+/* Iteration driver with the convergence rule: runs iterations (as
+ * smoother_iterate) until every track's trajectory change
+ * max_{k,j} |xbar_k,j^(i) - xbar_k,j^(i-1)| has been below tol at least once,
+ * or max_iter iterations have run in this call.  Waits for each iteration's
+ * per-track deltas (one small copy through pinned host memory), so it returns
+ * as soon as the last track has converged.  *iters_run (nullable) receives the
+ * iterations run; track_iters (nullable, host [n_tracks]) the 1-based
+ * iteration of this call at which each track first fell below tol, 0 if it
+ * did not.  Returns SM_EINVAL for tol <= 0 or max_iter < 1, SM_ENUMERIC when a
+ * delta is not finite (outputs hold the iterations run until then). */
+sm_status smoother_iterate_until(smoother_t h, double tol, int32_t max_iter, int32_t* iters_run,
+                                 int32_t* track_iters);
 
 /* Waits for the handle's stream and copies the current trajectory to host
  * buffers: mean [S*nx], cov [S*nx*nx] (full symmetric matrices); either may be

@@ -28,7 +28,7 @@ SCAN = {"parallel": 0, "sequential": 1}
 EXPORTS = ("smoother_problem_defaults", "smoother_init", "smoother_iterate", "smoother_result",
            "smoother_result_device", "smoother_track_deltas", "smoother_info", "smoother_last_error",
            "smoother_destroy", "smoother_version", "smoother_profile", "smoother_schedule",
-           "smoother_set_trajectory_device")
+           "smoother_set_trajectory_device", "smoother_iterate_until", "smoother_autotune")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -103,6 +103,12 @@ def _load():
     lib.smoother_version.restype = ctypes.c_char_p
     lib.smoother_set_trajectory_device.argtypes = [vp, vp, vp, _dp]
     lib.smoother_set_trajectory_device.restype = ctypes.c_int
+    lib.smoother_iterate_until.argtypes = [vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32)]
+    lib.smoother_iterate_until.restype = ctypes.c_int
+    lib.smoother_autotune.argtypes = [ctypes.POINTER(sm_problem), vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32), _dp]
+    lib.smoother_autotune.restype = ctypes.c_int
     return lib
 
 
@@ -174,6 +180,17 @@ def smoother_init(pb: Problem, stream: Optional[int] = None, **kw) -> int:
     return h.value
 
 
+def smoother_autotune(pb: Problem, stream: Optional[int] = None, iters: int = 5, **kw):
+    """Fastest scan schedule for this problem: (tile_lanes, lane_slots, ms per iteration)."""
+    s, _keep = make_problem(pb, **kw)
+    B, K, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    st = _lib.smoother_autotune(ctypes.byref(s), ctypes.c_void_p(stream or 0), iters, ctypes.byref(B),
+                                ctypes.byref(K), ctypes.byref(ms))
+    if st != SM_OK:
+        raise SmootherError(st, smoother_last_error(None))
+    return B.value, K.value, ms.value
+
+
 def smoother_iterate(h: int, k: int = 0, want_delta: bool = True):
     """Runs k iterations (k <= 0: up to n_iter).  Returns (max_delta or None, iterations done)."""
     d = ctypes.c_double(0.0)
@@ -183,6 +200,21 @@ def smoother_iterate(h: int, k: int = 0, want_delta: bool = True):
         return float("nan"), it.value
     _check(h, st)
     return (d.value if want_delta else None), it.value
+
+
+def smoother_iterate_until(h: int, tol: float, max_iter: int):
+    """Iterates until every track's trajectory change has been below tol once
+    (or max_iter iterations).  Returns (iterations run, per-track first
+    converged iteration, 0 = not converged, numerics ok)."""
+    _, T, _ = smoother_info(h)
+    run = ctypes.c_int32(0)
+    first = np.zeros(T, dtype=np.int32)
+    st = _lib.smoother_iterate_until(h, tol, max_iter, ctypes.byref(run),
+                                     first.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if st == SM_ENUMERIC:
+        return run.value, first, False
+    _check(h, st)
+    return run.value, first, True
 
 
 def smoother_info(h: int):
@@ -263,6 +295,9 @@ class Smoother:
 
     def track_deltas(self):
         return smoother_track_deltas(self.h)
+
+    def iterate_until(self, tol: float, max_iter: int):
+        return smoother_iterate_until(self.h, tol, max_iter)
 
     def set_trajectory_device(self, mean_ptr: int, cov_ptr: int = 0, cov_const=None):
         smoother_set_trajectory_device(self.h, mean_ptr, cov_ptr, cov_const)

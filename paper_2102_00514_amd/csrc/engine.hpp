@@ -219,7 +219,8 @@ class Engine final : public EngineBase {
       H2D(dc, cov.data(), sizeof(R) * cov.size());
       if (e == hipSuccess)
         hipLaunchKernelGGL((k_pack<N, R>), dim3(grid), dim3(kSlotBlock), 0, stream, S, stride,
-                           static_cast<const R*>(dm), static_cast<const R*>(dc), static_cast<R*>(d_traj_[0]));
+                           static_cast<const R*>(dm), static_cast<const R*>(dc), Place{N, 0},
+                           static_cast<R*>(d_traj_[0]));
       if (e == hipSuccess) e = hipGetLastError();
       if (e == hipSuccess) e = hipStreamSynchronize(stream);
       if (dm) (void)hipFree(dm);
@@ -514,31 +515,41 @@ class Engine final : public EngineBase {
     return SM_OK;
   }
 
-  sm_status result_device(void* mean, void* cov) override {
+  sm_status result_device(void* mean, void* cov) override { return result_device_placed(mean, cov, N, 0); }
+
+  sm_status result_device_placed(void* mean, void* cov, int ld, int off) override {
     const dim3 grid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
     hipLaunchKernelGGL((k_unpack<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride,
-                       static_cast<const R*>(d_traj_[cur_]), static_cast<R*>(mean), static_cast<R*>(cov));
+                       static_cast<const R*>(d_traj_[cur_]), static_cast<R*>(mean), static_cast<R*>(cov),
+                       Place{ld, off});
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "result kernel"));
     return SM_OK;
   }
 
   sm_status set_trajectory_device(const void* mean, const void* cov, const double* cov_const) override {
+    return set_trajectory_placed(mean, cov, cov_const, N, 0);
+  }
+
+  // cov_const, when used, is this engine's N x N block (row-major).
+  sm_status set_trajectory_placed(const void* mean, const void* cov, const double* cov_const, int ld,
+                                  int off) override {
     const dim3 grid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
     R* traj = static_cast<R*>(d_traj_[cur_]);
     const R* m = static_cast<const R*>(mean);
+    const Place pl{ld, off};
     if (cov) {
       hipLaunchKernelGGL((k_pack<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, static_cast<const R*>(cov),
-                         traj);
+                         pl, traj);
     } else if (cov_const) {
       SymConst<N, R> c;
       for (int i = 0; i < N; ++i)
         for (int j = i; j < N; ++j)
           c.v[sym_index<N>(i, j)] = R(0.5 * (cov_const[i * N + j] + cov_const[j * N + i]));
-      hipLaunchKernelGGL((k_pack_const<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, c, traj);
+      hipLaunchKernelGGL((k_pack_const<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, pl, c, traj);
     } else {
       hipLaunchKernelGGL((k_broadcast_prior<N, R>), grid, dim3(kSlotBlock), 0, stream, slot_args(cur_), traj);
-      hipLaunchKernelGGL((k_set_mean<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, traj);
+      hipLaunchKernelGGL((k_set_mean<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, pl, traj);
     }
     hipLaunchKernelGGL(k_fill_u64, dim3((ntracks + 256) / 256), dim3(256), 0, stream, delta_bits,
                        int64_t(ntracks + 1), 0ull);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
@@ -28,14 +29,51 @@ class EngineBase {
   virtual sm_status result_host(double* mean, double* cov) = 0;
   virtual sm_status result_device(void* mean, void* cov) = 0;
   virtual sm_status set_trajectory_device(const void* mean, const void* cov, const double* cov_const) = 0;
+  // The same with the engine's states placed at column off of a caller state
+  // of dimension ld (block decomposition of a larger state).
+  virtual sm_status result_device_placed(void*, void*, int, int) { return fail(SM_ESTATE, "not supported"); }
+  virtual sm_status set_trajectory_placed(const void*, const void*, const double*, int, int) {
+    return fail(SM_ESTATE, "not supported");
+  }
 
-  sm_status track_deltas(double* out) {
-    std::vector<unsigned long long> bits(ntracks + 1);
-    hipError_t e = hipMemcpyAsync(bits.data(), delta_bits, sizeof(unsigned long long) * (ntracks + 1),
-                                  hipMemcpyDeviceToHost, stream);
+  // Per-track deltas (and their maximum, entry ntracks) of the last iteration,
+  // read through a pinned host buffer.
+  virtual sm_status track_deltas(double* out) {
+    hipError_t e = hipSuccess;
+    if (!h_delta) e = hipHostMalloc(reinterpret_cast<void**>(&h_delta), sizeof(unsigned long long) * (ntracks + 1),
+                                    hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h_delta, delta_bits, sizeof(unsigned long long) * (ntracks + 1), hipMemcpyDeviceToHost,
+                         stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "copy of the convergence statistic"));
-    for (int i = 0; i <= ntracks; ++i) std::memcpy(&out[i], &bits[i], sizeof(double));
+    for (int i = 0; i <= ntracks; ++i) std::memcpy(&out[i], &h_delta[i], sizeof(double));
+    return SM_OK;
+  }
+
+  // Iterations until every track's delta has been below tol once, or max_iter
+  // iterations.  first[i] = iteration (1-based, this call) at which track i
+  // first fell below tol, 0 if it did not.
+  sm_status iterate_until(double tol, int max_iter, int* run, int32_t* first) {
+    std::vector<double> d(ntracks + 1);
+    int left = ntracks;
+    for (int i = 0; i < ntracks; ++i) first[i] = 0;
+    *run = 0;
+    bool finite = true;
+    while (*run < max_iter && left > 0) {
+      sm_status st = iterate(1);
+      if (st == SM_OK) st = track_deltas(d.data());
+      if (st != SM_OK) return st;
+      *run += 1;
+      for (int i = 0; i < ntracks; ++i) {
+        if (!std::isfinite(d[i])) finite = false;
+        if (first[i] == 0 && d[i] < tol) {
+          first[i] = *run;
+          --left;
+        }
+      }
+      if (!finite) return fail(SM_ENUMERIC, "non-finite iterate");
+    }
     return SM_OK;
   }
 
@@ -61,7 +99,7 @@ class EngineBase {
     prof.push_back(r);
   }
 
-  sm_status profile(int k, sm_kernel_time* out, int cap_out, int* n_out) {
+  virtual sm_status profile(int k, sm_kernel_time* out, int cap_out, int* n_out) {
     prof.clear();
     profiling = true;
     sm_status st = iterate(k);
@@ -117,6 +155,8 @@ class EngineBase {
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
     device_bytes = 0;
+    if (h_delta) (void)hipHostFree(h_delta);
+    h_delta = nullptr;
   }
 
   std::string err;
@@ -131,6 +171,7 @@ class EngineBase {
   size_t device_bytes = 0;
   hipStream_t stream = nullptr;
   unsigned long long* delta_bits = nullptr;
+  unsigned long long* h_delta = nullptr;   // pinned host copy of delta_bits
   std::vector<void*> allocs;
   bool profiling = false;
   std::vector<ProfRec> prof;

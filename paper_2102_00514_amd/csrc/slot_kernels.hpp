@@ -131,26 +131,38 @@ __global__ __launch_bounds__(kSlotBlock) void k_broadcast_prior(SlotArgs a, R* t
   PKS_UNROLL for (int i = 0; i < W - N; ++i) traj[(N + i) * a.stride + s] = P0[i * a.tstride + tr];
 }
 
-// Packed device trajectory -> caller layout: mean [S][N], cov [S][N][N].
+// Placement of an N-state block inside a caller's state of dimension ld:
+// mean[s * ld + off + i], cov[(s * ld + off + i) * ld + off + j].
+struct Place {
+  int ld, off;
+};
+
+// Packed device trajectory -> caller layout: mean [S][ld], cov [S][ld][ld].
 template <int N, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_unpack(int64_t S, size_t stride, const R* traj, R* mean, R* cov) {
+__global__ __launch_bounds__(kSlotBlock) void k_unpack(int64_t S, size_t stride, const R* traj, R* mean, R* cov,
+                                                       Place pl) {
   const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
   if (s >= S) return;
-  if (mean) PKS_UNROLL for (int i = 0; i < N; ++i) mean[s * N + i] = traj[i * stride + s];
+  const int64_t row = s * pl.ld + pl.off;
+  if (mean) PKS_UNROLL for (int i = 0; i < N; ++i) mean[row + i] = traj[i * stride + s];
   if (cov)
     PKS_UNROLL for (int i = 0; i < N; ++i)
-      PKS_UNROLL for (int j = 0; j < N; ++j) cov[(s * N + i) * N + j] = traj[(N + sym_index<N>(i, j)) * stride + s];
+      PKS_UNROLL for (int j = 0; j < N; ++j)
+        cov[(row + i) * pl.ld + pl.off + j] = traj[(N + sym_index<N>(i, j)) * stride + s];
 }
 
 // Caller layout -> packed device trajectory (initial trajectory given by the caller).
 template <int N, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_pack(int64_t S, size_t stride, const R* mean, const R* cov, R* traj) {
+__global__ __launch_bounds__(kSlotBlock) void k_pack(int64_t S, size_t stride, const R* mean, const R* cov, Place pl,
+                                                     R* traj) {
   const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
   if (s >= S) return;
-  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[s * N + i];
+  const int64_t row = s * pl.ld + pl.off;
+  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[row + i];
   PKS_UNROLL for (int i = 0; i < N; ++i)
     PKS_UNROLL for (int j = i; j < N; ++j)
-      traj[(N + sym_index<N>(i, j)) * stride + s] = R(0.5) * (cov[(s * N + i) * N + j] + cov[(s * N + j) * N + i]);
+      traj[(N + sym_index<N>(i, j)) * stride + s] =
+          R(0.5) * (cov[(row + i) * pl.ld + pl.off + j] + cov[(row + j) * pl.ld + pl.off + i]);
 }
 
 // A covariance shared by every slot, upper-packed in sym_index order (passed by value).
@@ -159,23 +171,23 @@ struct SymConst {
   R v[sym_size<N>()];
 };
 
-// Caller means [S][N] (device) -> packed trajectory; the covariance of every
-// slot is the constant c.
+// Caller means (device, placed by pl) -> packed trajectory; the covariance of
+// every slot is the constant c.
 template <int N, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_pack_const(int64_t S, size_t stride, const R* mean, SymConst<N, R> c,
-                                                           R* traj) {
+__global__ __launch_bounds__(kSlotBlock) void k_pack_const(int64_t S, size_t stride, const R* mean, Place pl,
+                                                           SymConst<N, R> c, R* traj) {
   const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
   if (s >= S) return;
-  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[s * N + i];
+  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[s * pl.ld + pl.off + i];
   PKS_UNROLL for (int i = 0; i < sym_size<N>(); ++i) traj[(N + i) * stride + s] = c.v[i];
 }
 
-// Caller means [S][N] (device) -> the mean rows of the packed trajectory only.
+// Caller means (device, placed by pl) -> the mean rows of the packed trajectory only.
 template <int N, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_set_mean(int64_t S, size_t stride, const R* mean, R* traj) {
+__global__ __launch_bounds__(kSlotBlock) void k_set_mean(int64_t S, size_t stride, const R* mean, Place pl, R* traj) {
   const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
   if (s >= S) return;
-  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[s * N + i];
+  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[s * pl.ld + pl.off + i];
 }
 
 // ---------------------------------------------------------------------------

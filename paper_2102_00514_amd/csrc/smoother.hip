@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "smoother.h"
+#include "block_engine.hpp"
 #include "engine_base.hpp"
 
 namespace pks {
@@ -56,7 +57,7 @@ static bool all_finite(const double* p, size_t n) {
   return true;
 }
 
-static EngineBase* make_engine(int model, int precision, int nx, int ny) {
+static EngineBase* make_dense_engine(int model, int precision, int nx, int ny) {
   if (model == SM_MODEL_CT_BEARINGS)
     return precision == SM_FP64 ? make_engine_ct_f64(nx, ny) : make_engine_ct_f32(nx, ny);
   if (model == SM_MODEL_LINEAR)
@@ -64,10 +65,40 @@ static EngineBase* make_engine(int model, int precision, int nx, int ny) {
   return nullptr;
 }
 
+constexpr int kMaxTargets = 16;   // coordinated-turn blocks in one stacked state
+
+static bool stacked(int model, int nx) { return model == SM_MODEL_CT_BEARINGS && nx > 5 && nx % 5 == 0; }
+
+static EngineBase* make_engine(int model, int precision, int nx, int ny) {
+  if (stacked(model, nx)) {
+    BlockEngine* e = new BlockEngine(&make_dense_engine);
+    e->set_precision_word(precision == SM_FP64 ? sizeof(double) : sizeof(float));
+    return e;
+  }
+  return make_dense_engine(model, precision, nx, ny);
+}
+
 static bool supported(int model, int nx, int ny) {
-  if (model == SM_MODEL_CT_BEARINGS) return nx == 5 && ny == 2;
+  if (model == SM_MODEL_CT_BEARINGS) {
+    if (nx == 5) return ny == 2;
+    // stacked targets: two sensors per target, blocks run on the (5, 2) kernels
+    return stacked(model, nx) && nx / 5 <= kMaxTargets && ny == 2 * (nx / 5);
+  }
   if (model == SM_MODEL_LINEAR) return (nx == 1 && ny == 1) || (nx == 3 && ny == 2) || (nx == 5 && ny == 2);
   return false;
+}
+
+// Entries of the symmetric n x n matrix A between different blocks (block(i)
+// gives the block of index i) are zero up to rounding: |A_ij| <= 1e-12
+// sqrt(A_ii A_jj).  Such entries are dropped by the block decomposition.
+template <class F>
+static bool block_diagonal(const double* A, int n, F block) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (block(i) != block(j) &&
+          !(std::fabs(A[i * n + j]) <= 1e-12 * std::sqrt(std::fabs(A[i * n + i] * A[j * n + j]))))
+        return false;
+  return true;
 }
 
 static std::string validate(const sm_problem* pb) {
@@ -121,6 +152,26 @@ static std::string validate(const sm_problem* pb) {
   if (pb->init_cov)
     for (int64_t s = 0; s < S; ++s)
       if (!host_spd(pb->init_cov + size_t(s) * n * n, n)) return "init_cov must be SPD at every slot";
+  if (stacked(pb->model, n)) {
+    // the targets must not interact for the block decomposition to be exact
+    if (pb->lin != SM_LIN_TAYLOR)
+      return "stacked targets: only the Taylor (IEKS) linearisation keeps the targets separate";
+    const int k = n / 5;
+    std::vector<int> per(k, 0);
+    for (int s = 0; s < p; ++s) per[int(pb->params[3 + 3 * s])] += 1;
+    for (int b = 0; b < k; ++b)
+      if (per[b] != 2) return "stacked targets: every target needs exactly two sensors";
+    auto sblk = [](int i) { return i / 5; };
+    auto mblk = [&](int s) { return int(pb->params[3 + 3 * s]); };
+    if (!block_diagonal(pb->Q, n, sblk)) return "stacked targets: Q must be block-diagonal";
+    if (!block_diagonal(pb->R, p, mblk)) return "stacked targets: R must not couple sensors of different targets";
+    for (int t = 0; t < pb->n_tracks; ++t)
+      if (!block_diagonal(pb->P0 + size_t(t) * n * n, n, sblk)) return "stacked targets: P0 must be block-diagonal";
+    if (pb->init_cov)
+      for (int64_t s = 0; s < S; ++s)
+        if (!block_diagonal(pb->init_cov + size_t(s) * n * n, n, sblk))
+          return "stacked targets: init_cov must be block-diagonal";
+  }
   return std::string();
 }
 
@@ -130,6 +181,7 @@ struct smoother {
   std::unique_ptr<pks::EngineBase> eng;
   std::string err;
   int nx = 0;
+  bool stacked = false;   // stacked targets run as separate blocks
 };
 
 using pks::g_init_error;
@@ -175,7 +227,97 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
     smoother* h = new smoother();
     h->eng = std::move(eng);
     h->nx = pb->nx;
+    h->stacked = pks::stacked(pb->model, pb->nx);
     *out = h;
+    g_init_error.clear();
+    return SM_OK;
+  } catch (const std::bad_alloc&) {
+    g_init_error = "host allocation failed";
+    return SM_ENOMEM;
+  } catch (...) {
+    g_init_error = "unexpected host exception";
+    return SM_EDEVICE;
+  }
+}
+
+sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iters, int32_t* tile_lanes,
+                            int32_t* lane_slots, double* ms_per_iter) {
+  try {
+    if (!pb || !tile_lanes || !lane_slots || iters < 1) {
+      g_init_error = "autotune needs a problem, output pointers and iters >= 1";
+      return SM_EINVAL;
+    }
+    const std::string msg = pks::validate(pb);
+    if (!msg.empty()) {
+      g_init_error = msg;
+      return SM_EINVAL;
+    }
+    if (pb->scan != SM_SCAN_PARALLEL) {
+      g_init_error = "autotune applies to the parallel scan";
+      return SM_EINVAL;
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t he = hipEventCreate(&a);
+    if (he == hipSuccess) he = hipEventCreate(&b);
+    if (he != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      g_init_error = pks::hip_msg(he, "autotune events");
+      return SM_EDEVICE;
+    }
+    double best = -1.0;
+    int best_b = 0, best_k = 0;
+    sm_status last = SM_OK;
+    std::string last_err;
+    for (const int lanes : {64, 256}) {
+      for (const int slots : {1, 2, 4, 8}) {
+        sm_problem q = *pb;
+        q.tile_lanes = lanes;
+        q.lane_slots = slots;
+        q.n_iter = iters + 1;
+        std::unique_ptr<pks::EngineBase> eng(pks::make_engine(q.model, q.precision, q.nx, q.ny));
+        if (!eng) {
+          last = SM_EINVAL;
+          last_err = "no kernel for this configuration";
+          continue;
+        }
+        sm_status st = eng->setup(q, stream);
+        if (st == SM_OK) st = eng->iterate(1);                  // warm-up (and graph capture)
+        float ms = 0.f;
+        if (st == SM_OK) {
+          he = hipEventRecord(a, stream);
+          if (he == hipSuccess) st = eng->iterate(iters);
+          if (he == hipSuccess && st == SM_OK) he = hipEventRecord(b, stream);
+          if (he == hipSuccess && st == SM_OK) he = hipEventSynchronize(b);
+          if (he == hipSuccess && st == SM_OK) he = hipEventElapsedTime(&ms, a, b);
+          if (he != hipSuccess) {
+            st = SM_EDEVICE;
+            eng->err = pks::hip_msg(he, "autotune timing");
+          }
+        }
+        (void)hipStreamSynchronize(stream);   // nothing of this candidate in flight when it is released
+        if (st != SM_OK) {            // e.g. a schedule that does not fit the memory cap
+          last = st;
+          last_err = eng->err;
+          continue;
+        }
+        const double per = double(ms) / iters;
+        if (best < 0.0 || per < best) {
+          best = per;
+          best_b = lanes;
+          best_k = slots;
+        }
+      }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (best < 0.0) {
+      g_init_error = "no schedule could run: " + last_err;
+      return last == SM_OK ? SM_EDEVICE : last;
+    }
+    *tile_lanes = best_b;
+    *lane_slots = best_k;
+    if (ms_per_iter) *ms_per_iter = best;
     g_init_error.clear();
     return SM_OK;
   } catch (const std::bad_alloc&) {
@@ -212,6 +354,28 @@ sm_status smoother_iterate(smoother_t h, int32_t k, double* max_delta_out, int32
       }
     }
     return SM_OK;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return SM_EDEVICE;
+  }
+}
+
+sm_status smoother_iterate_until(smoother_t h, double tol, int32_t max_iter, int32_t* iters_run,
+                                 int32_t* track_iters) {
+  if (!h || !h->eng) return SM_ESTATE;
+  if (!(tol > 0.0) || max_iter < 1) {
+    h->err = "iterate_until needs tol > 0 and max_iter >= 1";
+    return SM_EINVAL;
+  }
+  try {
+    pks::EngineBase& e = *h->eng;
+    std::vector<int32_t> first(e.ntracks);
+    int run = 0;
+    const sm_status st = e.iterate_until(tol, max_iter, &run, first.data());
+    if (iters_run) *iters_run = run;
+    if (track_iters) std::memcpy(track_iters, first.data(), sizeof(int32_t) * e.ntracks);
+    if (st != SM_OK) h->err = e.err;
+    return st;
   } catch (...) {
     h->err = "unexpected host exception";
     return SM_EDEVICE;
@@ -257,6 +421,10 @@ sm_status smoother_set_trajectory_device(smoother_t h, const void* d_mean, const
       }
     if (!pks::host_spd(cov_const, n)) {
       h->err = "cov_const must be symmetric positive definite";
+      return SM_EINVAL;
+    }
+    if (h->stacked && !pks::block_diagonal(cov_const, n, [](int i) { return i / 5; })) {
+      h->err = "stacked targets: cov_const must be block-diagonal";
       return SM_EINVAL;
     }
   }

@@ -226,44 +226,34 @@ def _torch():
 
 def smooth_until_converged(pb: wl.Problem, stream: int, lin: str = "taylor", max_iter: int = 50,
                            tol: float = 1e-6, net: Optional["WarmStartNet"] = None, d_y=None, cov_const=None,
-                           keep_mean: bool = True) -> dict:
-    """Runs the smoother on a batch until every track's trajectory change is
-    below tol or max_iter iterations have run.  With ``net`` the first
-    trajectory comes from the network (measurements d_y already on the device).
-    Returns per-track iterations to converge (max_iter + 1 = not converged),
-    the wall time of the whole run, and the final means on the device."""
+                           keep_mean: bool = True, schedule=(0, 0)) -> dict:
+    """Runs the smoother on a batch until every track's trajectory change has
+    been below tol once, or max_iter iterations (smoother_iterate_until).
+    With ``net`` the first trajectory comes from the network (measurements d_y
+    already on the device, tracks planned with ``net.set_tracks``).  Returns
+    per-track iterations to converge (max_iter + 1 = not converged), the wall
+    time from the first trajectory to the return of the driver, and the final
+    means on the device.  ``schedule`` = (tile_lanes, lane_slots), 0 = automatic."""
     torch = _torch()
-    t0 = time.perf_counter()
-    sm = binding.Smoother(pb, stream=stream, n_iter=max_iter, lin=lin)
+    sm = binding.Smoother(pb, stream=stream, n_iter=max_iter, lin=lin, tile_lanes=schedule[0],
+                          lane_slots=schedule[1])
     S, ntr, _ = sm.info()
-    t_setup = time.perf_counter() - t0
     torch.cuda.synchronize()
-    iters = np.full(ntr, max_iter + 1, dtype=np.int64)
     start = time.perf_counter()
     mean0 = None
     if net is not None:
         mean0 = torch.empty((S, pb.nx), dtype=torch.float64, device="cuda")
         net.trajectory(d_y.data_ptr(), mean0.data_ptr())
         sm.set_trajectory_device(mean0.data_ptr(), 0, cov_const)
-    done = 0
-    for it in range(1, max_iter + 1):
-        sm.iterate(1, want_delta=False)
-        d = sm.track_deltas()
-        newly = (d < tol) & (iters > max_iter)
-        iters[newly] = it
-        done = it
-        if np.all(iters <= max_iter):
-            break
-    torch.cuda.synchronize()
+    run, first, finite = sm.iterate_until(tol, max_iter)
     wall = time.perf_counter() - start
-    out = {"iters": iters, "wall_s": wall, "iterations_run": done, "setup_s": t_setup}
+    iters = np.where(first > 0, first, max_iter + 1).astype(np.int64)
+    out = {"iters": iters, "wall_s": wall, "iterations_run": run, "finite": finite}
     if keep_mean:
         mean = torch.empty((S, pb.nx), dtype=torch.float64, device="cuda")
         sm.result_device(mean.data_ptr(), 0)
         torch.cuda.synchronize()
         out["mean"] = mean
-    if mean0 is not None:
-        out["mean0"] = mean0
     sm.close()
     return out
 
@@ -395,32 +385,39 @@ def load(path: str, stream: Optional[int] = None, max_batch: Optional[int] = Non
 
 
 def time_to_converge(net: WarmStartNet, cov: np.ndarray, pb: wl.Problem, lin: str = "taylor",
-                     max_iter: int = 50, tol: float = 1e-6, repeats: int = 1) -> dict:
-    """Plain (prior broadcast) vs learned first trajectory on the same tracks:
-    iterations per track to reach tol, wall time until every track has
-    converged (or max_iter), and the distance of the learned run's converged
-    means to the plain run's (the plain smoother is the reference)."""
+                     max_iter: int = 50, tol: float = 1e-6, repeats: int = 1, schedule=(0, 0)) -> dict:
+    """Plain (prior broadcast) vs learned first trajectory on the same tracks.
+
+    A first run of each start gives the iterations per track to reach tol
+    (max_iter + 1 = not converged) and the converged means; ``ms_to_converge``
+    is then the best of ``repeats`` timed runs capped at the iteration where
+    the last converging track converged (the learned runs include the
+    network's inference and the hand-over of its trajectory).  The distance of
+    the learned run's converged means to the plain run's is reported per track
+    (the plain smoother is the reference)."""
     torch = _torch()
     stream = torch.cuda.current_stream().cuda_stream
     d_y = torch.from_numpy(np.ascontiguousarray(pb.y)).cuda()
     net.set_tracks(pb.offsets)
     res = {}
     for name, kw in (("plain", {}), ("learned", {"net": net, "d_y": d_y, "cov_const": cov})):
-        runs = [smooth_until_converged(pb, stream, lin, max_iter, tol, **kw) for _ in range(repeats)]
-        r = runs[-1]
+        kw["schedule"] = schedule
+        r = smooth_until_converged(pb, stream, lin, max_iter, tol, **kw)
         conv = r["iters"] <= max_iter
-        res[name] = {"iters_mean": float(np.mean(np.minimum(r["iters"], max_iter))),
-                     "iters_median": float(np.median(r["iters"])), "iters_max": int(r["iters"].max()),
-                     "converged": float(conv.mean()), "iterations_run": r["iterations_run"],
-                     "wall_ms": 1e3 * min(x["wall_s"] for x in runs), "_mean": r["mean"], "_iters": r["iters"]}
-        if "mean0" in r:
-            res[name]["_mean0"] = r["mean0"]
+        kmax = int(r["iters"][conv].max()) if conv.any() else None
+        timed = [smooth_until_converged(pb, stream, lin, kmax, tol, keep_mean=False, **kw)["wall_s"]
+                 for _ in range(repeats)] if kmax else []
+        res[name] = {"iters_mean": float(np.mean(r["iters"])), "iters_median": float(np.median(r["iters"])),
+                     "iters_max_converged": kmax, "converged": float(conv.mean()),
+                     "ms_to_converge": 1e3 * min(timed) if timed else None,
+                     "ms_to_cap": 1e3 * r["wall_s"], "_mean": r["mean"], "_iters": r["iters"]}
     both = (res["plain"]["_iters"] <= max_iter) & (res["learned"]["_iters"] <= max_iter)
     so = pb.slot_offsets()
     diff = (res["learned"]["_mean"] - res["plain"]["_mean"]).abs().amax(dim=1).cpu().numpy()
     per_track = np.array([diff[so[i]:so[i + 1]].max() for i in range(pb.n_tracks)])
-    res["distance_to_plain"] = {"max_over_tracks_converged_by_both": float(per_track[both].max()) if both.any() else None,
-                                "tracks_within_1e-4": float(np.mean(per_track[both] < 1e-4)) if both.any() else None}
+    res["distance_to_plain"] = {
+        "max_over_tracks_converged_by_both": float(per_track[both].max()) if both.any() else None,
+        "tracks_within_1e-4": float(np.mean(per_track[both] < 1e-4)) if both.any() else None}
     return res
 
 

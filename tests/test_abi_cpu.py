@@ -177,3 +177,29 @@ def test_one_hip_runtime_in_the_process():
     for name in ("libamdhip64", "libhsa-runtime64"):
         paths = {ln.split()[-1] for ln in maps if name in ln}
         assert len(paths) == 1, (name, paths)
+
+
+def test_autotune_validates_on_the_host():
+    with pytest.raises(B.SmootherError) as ei:
+        B.smoother_autotune(wl.config_c1(), iters=2, lin="unscented", ut_kappa=-5.0)
+    assert ei.value.status == B.SM_EINVAL
+    with pytest.raises(B.SmootherError) as ei:
+        B.smoother_autotune(wl.config_c1(), iters=0)
+    assert ei.value.status == B.SM_EINVAL
+
+
+def test_stacked_targets_validation():
+    pb = wl.config_c5_single(20)
+    bad_q = pb.Q.copy()
+    bad_q[0, 7] = bad_q[7, 0] = 1e-6               # couples targets 0 and 1
+    pb_q = wl.Problem(**{**pb.__dict__, "Q": bad_q})
+    _expect_einval(pb_q, "Q must be block-diagonal")
+    bad_r = pb.R.copy()
+    bad_r[0, 2] = bad_r[2, 0] = 1e-4                # sensors 0 and 2 watch different targets
+    _expect_einval(wl.Problem(**{**pb.__dict__, "R": bad_r}), "R must not couple")
+    prm = pb.params.copy()
+    prm[3 + 3 * 2] = 0.0                            # three sensors on target 0, one on target 1
+    _expect_einval(wl.Problem(**{**pb.__dict__, "params": prm}), "exactly two sensors")
+    bad_p0 = pb.P0.copy()
+    bad_p0[0, 19, 0] = bad_p0[0, 0, 19] = 0.1
+    _expect_einval(wl.Problem(**{**pb.__dict__, "P0": bad_p0}), "P0 must be block-diagonal")

@@ -209,3 +209,103 @@ def test_graph_replays_match_eager(B, lin):
     finally:
         g.close()
         e.close()
+
+
+def test_iterate_until_matches_manual_loop(B):
+    """The native convergence driver stops where a host loop over
+    smoother_iterate + smoother_track_deltas would, per track."""
+    pb = wl.concat_tracks([wl.config_c1(), wl.ct_batch(5, 50, 400, seed_tag=17), wl.ct_bearings(3, seed=2)])
+    tol, cap = 1e-6, 12
+    with B.Smoother(pb, n_iter=cap) as sm:
+        first = np.zeros(pb.n_tracks, dtype=np.int32)
+        for it in range(1, cap + 1):
+            sm.iterate(1, want_delta=False)
+            d = sm.track_deltas()
+            first[(first == 0) & (d < tol)] = it
+            if np.all(first > 0):
+                break
+        ref_mean, _ = sm.result()
+        ref_run = it
+    with B.Smoother(pb, n_iter=cap) as sm:
+        run, got, ok = sm.iterate_until(tol, cap)
+        mean, _ = sm.result()
+    assert ok and run == ref_run
+    np.testing.assert_array_equal(got, first)
+    assert np.array_equal(mean, ref_mean)
+    with B.Smoother(pb, n_iter=cap) as sm:
+        run, got, ok = sm.iterate_until(1e-300, 3)       # nothing converges: the cap ends the run
+        assert ok and run == 3 and np.all(got == 0)
+        with pytest.raises(B.SmootherError) as ei:
+            sm.iterate_until(0.0, 3)
+        assert ei.value.status == B.SM_EINVAL
+
+
+def test_autotune_picks_a_valid_schedule(B):
+    pb = wl.config_c2(3000)
+    lanes, slots, ms = B.smoother_autotune(pb, iters=3, lin="cubature")
+    assert lanes in (64, 256) and slots in (1, 2, 4, 8) and ms > 0
+    ref = oracle.smoother(pb, 2, "cubature")
+    mean, cov, _, _ = run_gpu(B, pb, 2, "cubature", tile_lanes=lanes, lane_slots=slots)
+    assert_parity(mean, cov, ref, what=f"autotuned {lanes}x{slots}")
+    with pytest.raises(B.SmootherError):          # no schedule fits in 1 MB
+        B.smoother_autotune(pb, iters=1, max_device_bytes=1 << 20)
+
+
+def _block_diag_only(c, k=4):
+    """Drops the rounding-level terms between targets of a stacked covariance."""
+    out = np.zeros_like(c)
+    for b in range(k):
+        sl = slice(5 * b, 5 * b + 5)
+        out[..., sl, sl] = c[..., sl, sl]
+    return out
+
+
+def test_stacked_targets_match_dense_oracle(B):
+    """Four stacked targets (nx = 20, eight sensors), IEKS: the library's
+    per-target blocks against the oracle's dense 20-dimensional smoother, one
+    iteration from a common input trajectory (iterations 1 and 3)."""
+    lin = "taylor"
+    pb = wl.config_c5_single(300)
+    ref = oracle.smoother(pb, 3, lin, history=True)
+    for start in (0, 2):
+        im = None if start == 0 else ref["hist_mean"][start - 1]
+        ic = None if start == 0 else _block_diag_only(ref["hist_cov"][start - 1])
+        one = {"mean": ref["hist_mean"][start], "cov": ref["hist_cov"][start]}
+        mean, cov, _, _ = run_gpu(B, pb, 1, lin, init_mean=im, init_cov=ic)
+        assert_parity(mean, cov, one, what=f"stacked n=20 T=300 {lin} iteration {start + 1}")
+        off = cov - _block_diag_only(cov)
+        assert np.all(off == 0.0)
+
+
+def test_stacked_ragged_batch_and_device_paths(B):
+    import torch
+    sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (8, 2))
+    parts = [wl.stacked_ct(T, np.random.default_rng([55, T]), sensors=sensors) for T in (1, 40, 257)]
+    pb = wl.concat_tracks(parts, "stacked batch")
+    M = 2
+    mean, cov, _, deltas = run_gpu(B, pb, M, "taylor")
+    so = pb.slot_offsets()
+    for i in range(pb.n_tracks):
+        ref = oracle.smoother(pb.track(i), M, "taylor")
+        sl = slice(so[i], so[i + 1])
+        assert_parity(mean[sl], cov[sl], ref, what=f"stacked track {i} T={pb.lengths[i]}")
+        assert abs(deltas[i] - ref["deltas"][-1]) <= 1e-6 * ref["deltas"][-1] + 1e-12
+    S = pb.n_slots
+    with B.Smoother(pb, n_iter=M, lin="taylor") as sm:
+        sm.iterate(0)
+        hm, hc = sm.result()
+        dm = torch.full((S, 20), float("nan"), dtype=torch.float64, device="cuda")
+        dc = torch.full((S, 20, 20), float("nan"), dtype=torch.float64, device="cuda")
+        sm.result_device(dm.data_ptr(), dc.data_ptr())
+        torch.cuda.synchronize()
+        assert np.array_equal(dm.cpu().numpy(), hm) and np.array_equal(dc.cpu().numpy(), hc)
+        # restart from the device copy with a block-diagonal constant covariance
+        cconst = np.kron(np.eye(4), wl.random_spd(np.random.default_rng(3), 5, scale=0.3))
+        sm.set_trajectory_device(dm.data_ptr(), 0, cconst)
+        sm.iterate(1)
+        gm, gc = sm.result()
+    init_cov = np.broadcast_to(cconst, (S, 20, 20))
+    with B.Smoother(pb, n_iter=1, lin="taylor", init_mean=hm, init_cov=init_cov) as ref:
+        ref.iterate(1)
+        rm, rc = ref.result()
+    assert np.array_equal(gm, rm) and np.array_equal(gc, rc)

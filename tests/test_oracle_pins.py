@@ -247,6 +247,51 @@ def test_stacked_ieks_equals_independent_targets(orc):
         assert np.max(np.abs(r["cov"][:, sl][:, :, off])) < 1e-14
 
 
+@pytest.mark.parametrize("lin,kw", [("cubature", {}), ("unscented", {"kappa": 1.0})])
+def test_stacked_sigma_points_couple_targets(orc, lin, kw):
+    """Sigma points of a stacked 20-dimensional state that move one target act
+    on the others as centre points, so block b's regression mean zbar_b differs
+    from h_b(xbar_b) by d_b and the residual covariance gains -d_b d_c^T
+    between targets b != c; the regression matrix stays block-diagonal.  The
+    points are rebuilt here from their definition (lower Cholesky factor,
+    spread sqrt(n + lambda)) to check the oracle's 20-dimensional rule."""
+    pb = wl.config_c5_single(T=4)
+    n, p = 20, 8
+    x = pb.truth[2].copy()
+    x[4::5] = [0.5, -0.7, 0.9, 0.3]
+    P = np.diag(np.linspace(0.2, 0.8, n))
+    G, g, Om = orc.linearize(pb.model, pb.params, n, p, lin, "h", x, P, **kw)
+    if lin == "cubature":
+        spread, w0, wj = np.sqrt(n), 0.0, 1.0 / (2 * n)
+    else:
+        lam = 1.0 * (n + kw["kappa"]) - n
+        spread, w0, wj = np.sqrt(n + lam), lam / (n + lam), 1.0 / (2 * (n + lam))
+    L = np.linalg.cholesky(P)
+    X = [x] + [x + spread * L[:, j] for j in range(n)] + [x - spread * L[:, j] for j in range(n)]
+    W = np.array([w0] + [wj] * (2 * n))
+    sens = pb.params[1:].reshape(-1, 3)
+
+    def h(z):
+        out = np.empty(p)
+        for s in range(p):
+            t = int(sens[s, 2])
+            out[s] = np.arctan2(z[5 * t + 1] - sens[s, 1], z[5 * t] - sens[s, 0])
+        return out
+    hc = h(x)
+    Z = np.array([hc + wl.wrap_angle(h(z) - hc) for z in X])
+    zbar = W @ Z
+    d = hc - zbar
+    tgt = sens[:, 2].astype(int)
+    for s in range(p):
+        for r in range(p):
+            if tgt[s] != tgt[r]:
+                assert Om[s, r] == pytest.approx(-d[s] * d[r], rel=1e-9, abs=1e-18)
+    assert np.max(np.abs(Om[np.ix_(tgt == 0, tgt == 1)])) > 1e-6      # the coupling is real
+    for s in range(p):
+        off = np.delete(np.arange(n), np.arange(5 * tgt[s], 5 * tgt[s] + 5))
+        assert np.max(np.abs(G[s, off])) < 1e-12
+
+
 # ---------------------------------------------------------------------------------------
 # Pin 8 -- the oracle's own rounding error (double vs long double).
 # ---------------------------------------------------------------------------------------
