@@ -33,9 +33,11 @@
  *                         the covariances stay block-diagonal, and the library
  *                         smooths each target as its own block (exact up to
  *                         rounding); off-block covariance outputs are zero.
- *                         (Sigma-point rules couple stacked targets through
- *                         their regression residuals and are not accepted for
- *                         stacked states.)
+ *                         Sigma-point rules couple stacked targets through
+ *                         their regression residuals; with them, four targets
+ *                         and eight sensors (nx = 20, ny = 8, FP64, any SPD Q,
+ *                         R, P0) run on an engine of the full state in which
+ *                         one wavefront cooperates on each element.
  *
  * Conventions shared by every call:
  *   - Status: every call returns sm_status and never aborts or throws across the

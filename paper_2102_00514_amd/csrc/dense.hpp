@@ -1,0 +1,881 @@
+// Wavefront-cooperative form of the method for larger states (n = 20): one
+// 64-lane workgroup owns one element at a time, with its N x N matrices in
+// LDS, and the scans run as a hierarchy of chunk folds (Section 4, eq. 15 and
+// eq. 19 evaluated as in operators.hpp; elements as in elements.hpp).
+//
+// HBM records are slot-major (all words of one slot contiguous), so a wave
+// reads or writes one record with contiguous lanes.  Symmetric matrices are
+// stored upper-packed (sym_index order) in HBM and full in LDS.
+#pragma once
+
+#include "elements.hpp"
+#include "slot_kernels.hpp"
+
+namespace pks {
+namespace dn {
+
+constexpr int kWave = 64;
+
+template <int N>
+constexpr int ld() { return N + 1; }           // LDS row length (odd: spreads banks)
+template <int N>
+constexpr int mat_words() { return N * ld<N>(); }
+
+PKS_DEV int lane() { return int(threadIdx.x); }
+PKS_DEV void wsync() { __syncthreads(); }     // workgroups are a single wave
+
+// ---------------------------------------------------------------------------
+// Wave-wide matrix routines on LDS operands (leading dimension ld<LDN>()).
+// Each ends with a barrier, so its results are visible to every lane.
+// ---------------------------------------------------------------------------
+
+// C = C0 + sgn * op(A) op(B), op(A) M x K, op(B) K x NC.  C may alias C0 but
+// not A or B.  C0 may be null (zero).
+template <int LDN, int M, int K, int NC, bool TA, bool TB, typename R>
+PKS_DEV void mm(const R* A, const R* B, const R* C0, R sgn, R* C) {
+  constexpr int L = ld<LDN>();
+  for (int e = lane(); e < M * NC; e += kWave) {
+    const int i = e / NC, j = e - i * NC;
+    R s = R(0);
+    PKS_UNROLL for (int k = 0; k < K; ++k) {
+      const R a = TA ? A[k * L + i] : A[i * L + k];
+      const R b = TB ? B[j * L + k] : B[k * L + j];
+      s = fma(a, b, s);
+    }
+    C[i * L + j] = (C0 ? C0[i * L + j] : R(0)) + sgn * s;
+  }
+  wsync();
+}
+
+// y = y0 + sgn * op(A) x, op(A) M x K.  y may alias y0 but not x.
+template <int LDN, int M, int K, bool TA, typename R>
+PKS_DEV void mv(const R* A, const R* x, const R* y0, R sgn, R* y) {
+  constexpr int L = ld<LDN>();
+  for (int i = lane(); i < M; i += kWave) {
+    R s = R(0);
+    PKS_UNROLL for (int k = 0; k < K; ++k) s = fma(TA ? A[k * L + i] : A[i * L + k], x[k], s);
+    y[i] = (y0 ? y0[i] : R(0)) + sgn * s;
+  }
+  wsync();
+}
+
+// In-place lower Cholesky factor (true diagonal); the upper triangle is
+// cleared.  *ok (LDS) is cleared when a pivot is not positive; the factor then
+// holds NaN, which reaches the convergence statistic.
+template <int LDN, int N, typename R>
+PKS_DEV void chol(R* A, int* ok) {
+  constexpr int L = ld<LDN>();
+  for (int j = 0; j < N; ++j) {
+    if (lane() == 0) {
+      R s = A[j * L + j];
+      for (int t = 0; t < j; ++t) s -= A[j * L + t] * A[j * L + t];
+      if (!(s > R(0))) *ok = 0;
+      A[j * L + j] = sqrt(s);
+    }
+    wsync();
+    const R inv = R(1) / A[j * L + j];
+    for (int i = j + 1 + lane(); i < N; i += kWave) {
+      R s = A[i * L + j];
+      for (int t = 0; t < j; ++t) s -= A[i * L + t] * A[j * L + t];
+      A[i * L + j] = s * inv;
+    }
+    wsync();
+  }
+  for (int e = lane(); e < N * N; e += kWave) {
+    const int i = e / N, j = e - i * N;
+    if (j > i) A[i * L + j] = R(0);
+  }
+  wsync();
+}
+
+// B <- Lc^-1 B (forward substitution), Lc N x N lower, B N x NC; lane per column.
+template <int LDN, int N, int NC, typename R>
+PKS_DEV void fwd(const R* Lc, R* B) {
+  constexpr int L = ld<LDN>();
+  for (int c = lane(); c < NC; c += kWave) {
+    for (int i = 0; i < N; ++i) {
+      R s = B[i * L + c];
+      for (int t = 0; t < i; ++t) s -= Lc[i * L + t] * B[t * L + c];
+      B[i * L + c] = s / Lc[i * L + i];
+    }
+  }
+  wsync();
+}
+
+// B <- Lc^-T B (back substitution).
+template <int LDN, int N, int NC, typename R>
+PKS_DEV void bwd(const R* Lc, R* B) {
+  constexpr int L = ld<LDN>();
+  for (int c = lane(); c < NC; c += kWave) {
+    for (int i = N - 1; i >= 0; --i) {
+      R s = B[i * L + c];
+      for (int t = i + 1; t < N; ++t) s -= Lc[t * L + i] * B[t * L + c];
+      B[i * L + c] = s / Lc[i * L + i];
+    }
+  }
+  wsync();
+}
+
+// x <- Lc^-1 x for one vector (lane 0; N is small).
+template <int LDN, int N, typename R>
+PKS_DEV void fwd_vec(const R* Lc, R* x) {
+  constexpr int L = ld<LDN>();
+  if (lane() == 0)
+    for (int i = 0; i < N; ++i) {
+      R s = x[i];
+      for (int t = 0; t < i; ++t) s -= Lc[i * L + t] * x[t];
+      x[i] = s / Lc[i * L + i];
+    }
+  wsync();
+}
+
+// A <- (A + A^T) / 2
+template <int LDN, int N, typename R>
+PKS_DEV void symmetrize(R* A) {
+  constexpr int L = ld<LDN>();
+  for (int e = lane(); e < N * N; e += kWave) {
+    const int i = e / N, j = e - i * N;
+    if (j > i) {
+      const R v = R(0.5) * (A[i * L + j] + A[j * L + i]);
+      A[i * L + j] = v;
+      A[j * L + i] = v;
+    }
+  }
+  wsync();
+}
+
+template <int LDN, int M, int NC, bool TR, typename R>
+PKS_DEV void copy(const R* A, R* B) {   // B = op(A), M x NC
+  constexpr int L = ld<LDN>();
+  for (int e = lane(); e < M * NC; e += kWave) {
+    const int i = e / NC, j = e - i * NC;
+    B[i * L + j] = TR ? A[j * L + i] : A[i * L + j];
+  }
+  wsync();
+}
+
+template <int LDN, int M, int NC, typename R>
+PKS_DEV void zero(R* A) {
+  constexpr int L = ld<LDN>();
+  for (int e = lane(); e < M * NC; e += kWave) A[(e / NC) * L + e % NC] = R(0);
+  wsync();
+}
+
+template <int N, typename R>
+PKS_DEV void vcopy(const R* x, R* y) {
+  for (int i = lane(); i < N; i += kWave) y[i] = x[i];
+  wsync();
+}
+
+// --- HBM <-> LDS ------------------------------------------------------------
+template <int LDN, int M, int NC, typename R>
+PKS_DEV void ld_full(const R* g, R* A) {
+  constexpr int L = ld<LDN>();
+  for (int e = lane(); e < M * NC; e += kWave) A[(e / NC) * L + e % NC] = g[e];
+}
+template <int LDN, int M, int NC, typename R>
+PKS_DEV void st_full(const R* A, R* g) {
+  constexpr int L = ld<LDN>();
+  for (int e = lane(); e < M * NC; e += kWave) g[e] = A[(e / NC) * L + e % NC];
+}
+template <int LDN, int N, typename R>
+PKS_DEV void ld_symm(const R* g, R* A) {
+  constexpr int L = ld<LDN>();
+  for (int e = lane(); e < N * N; e += kWave) {
+    const int i = e / N, j = e - i * N;
+    A[i * L + j] = g[sym_index<N>(i, j)];
+  }
+}
+template <int LDN, int N, typename R>
+PKS_DEV void st_symm(const R* A, R* g) {
+  constexpr int L = ld<LDN>();
+  for (int e = lane(); e < N * N; e += kWave) {
+    const int i = e / N, j = e - i * N;
+    if (j >= i) g[sym_index<N>(i, j)] = A[i * L + j];
+  }
+}
+template <int N, typename R>
+PKS_DEV void ld_v(const R* g, R* x) {
+  for (int i = lane(); i < N; i += kWave) x[i] = g[i];
+}
+template <int N, typename R>
+PKS_DEV void st_v(const R* x, R* g) {
+  for (int i = lane(); i < N; i += kWave) g[i] = x[i];
+}
+
+// ---------------------------------------------------------------------------
+// Record layouts (words of one slot, contiguous in HBM).
+// ---------------------------------------------------------------------------
+template <int N, int P>
+struct Layout {
+  static constexpr int kS = sym_size<N>(), kSP = sym_size<P>();
+  static constexpr int kTraj = N + kS;                     // mean, cov
+  static constexpr int kTrans = N * N + N + kS;            // F, c, Q'
+  static constexpr int kHlin = P * N + P + kSP + P;        // H, d, R', ytilde
+  static constexpr int kFElem = N * N + 2 * N + 2 * kS;    // A, b, C, eta, J
+  static constexpr int kSElem = N * N + N + kS;            // E, g, L
+  static constexpr int kCarry = N + kS;                    // (b, C) or (g, L)
+  static_assert(kSElem <= kFElem, "smoothing elements reuse the filtering element records");
+};
+
+// LDS work area of one wave.
+template <int N, typename R>
+struct Work {
+  static constexpr int MW = mat_words<N>();
+  R m[9][MW];      // nine N x N matrices (names per kernel)
+  R v[8][N];       // vectors
+  int ok;
+};
+
+// --- the filtering operator (eq. 15), symmetric pivot-free form ------------
+// l <- l (x) r with l = (lA, lb, lC, le, lJ), r = (rA, rb, rC, re, rJ);
+// T1..T3 scratch.  Same algebra as FilterOp::combine.
+template <int N, typename R>
+PKS_DEV void combine_f(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, const R* rb, const R* rC, const R* re,
+                       const R* rJ, R* T1, R* T2, R* T3, R* v1, R* v2, int* ok) {
+  copy<N, N, N, false>(lC, T1);
+  chol<N, N>(T1, ok);                                   // U
+  mm<N, N, N, N, false, false>(rJ, T1, (const R*)nullptr, R(1), T2);     // J U
+  mm<N, N, N, N, true, false>(T1, T2, (const R*)nullptr, R(1), T3);      // U^T J U
+  for (int i = lane(); i < N; i += kWave) T3[i * ld<N>() + i] += R(1);  // G
+  wsync();
+  chol<N, N>(T3, ok);                                   // Lg
+  copy<N, N, N, true>(T1, T2);                          // U^T
+  fwd<N, N, N>(T3, T2);                                 // W = Lg^-1 U^T
+  mm<N, N, N, N, true, false>(T2, T2, (const R*)nullptr, R(1), T1);      // M = W^T W
+  mm<N, N, N, N, false, false>(rJ, lA, (const R*)nullptr, R(1), T3);     // Y = J A_i
+  mm<N, N, N, N, false, false>(T1, T3, (const R*)nullptr, R(1), T2);     // Z = M Y
+  mv<N, N, N, false>(rJ, lb, re, R(-1), v1);            // v = eta_j - J b_i
+  mv<N, N, N, false>(T1, v1, (const R*)nullptr, R(1), v2);               // u = M v
+  // J_ij = A_i^T Y - Y^T Z + J_i ; eta_ij = A_i^T v - Y^T u + eta_i
+  mm<N, N, N, N, true, false>(lA, T3, lJ, R(1), lJ);
+  mm<N, N, N, N, true, false>(T3, T2, lJ, R(-1), lJ);
+  mv<N, N, N, true>(lA, v1, le, R(1), le);
+  mv<N, N, N, true>(T3, v2, le, R(-1), le);
+  symmetrize<N, N>(lJ);
+  // b_ij = A_j (b_i + u) + b_j
+  for (int i = lane(); i < N; i += kWave) v1[i] = lb[i] + v2[i];
+  wsync();
+  mv<N, N, N, false>(rA, v1, rb, R(1), lb);
+  // C_ij = A_j M A_j^T + C_j
+  mm<N, N, N, N, false, false>(rA, T1, (const R*)nullptr, R(1), T3);
+  mm<N, N, N, N, false, true>(T3, rA, rC, R(1), lC);
+  symmetrize<N, N>(lC);
+  // A_ij = A_j (A_i - Z)
+  for (int e = lane(); e < N * N; e += kWave) {
+    const int i = e / N, j = e - i * N;
+    T2[i * ld<N>() + j] = lA[i * ld<N>() + j] - T2[i * ld<N>() + j];
+  }
+  wsync();
+  mm<N, N, N, N, false, false>(rA, T2, (const R*)nullptr, R(1), lA);
+}
+
+// Carry (b, C) (x) r: the filtered mean and covariance after element r.
+template <int N, typename R>
+PKS_DEV void apply_f(R* cb, R* cC, const R* rA, const R* rb, const R* rC, const R* re, const R* rJ, R* T1, R* T2,
+                     R* T3, R* v1, R* v2, int* ok) {
+  copy<N, N, N, false>(cC, T1);
+  chol<N, N>(T1, ok);
+  mm<N, N, N, N, false, false>(rJ, T1, (const R*)nullptr, R(1), T2);
+  mm<N, N, N, N, true, false>(T1, T2, (const R*)nullptr, R(1), T3);
+  for (int i = lane(); i < N; i += kWave) T3[i * ld<N>() + i] += R(1);
+  wsync();
+  chol<N, N>(T3, ok);
+  copy<N, N, N, true>(T1, T2);
+  fwd<N, N, N>(T3, T2);
+  mm<N, N, N, N, true, false>(T2, T2, (const R*)nullptr, R(1), T1);      // M
+  mv<N, N, N, false>(rJ, cb, re, R(-1), v1);            // v
+  mv<N, N, N, false>(T1, v1, (const R*)nullptr, R(1), v2);               // u
+  for (int i = lane(); i < N; i += kWave) v1[i] = cb[i] + v2[i];
+  wsync();
+  mv<N, N, N, false>(rA, v1, rb, R(1), cb);
+  mm<N, N, N, N, false, false>(rA, T1, (const R*)nullptr, R(1), T3);
+  mm<N, N, N, N, false, true>(T3, rA, rC, R(1), cC);
+  symmetrize<N, N>(cC);
+}
+
+// --- the smoothing operator (eq. 19) ------------------------------------------
+// l <- l (x) r in the paper's order (l earlier in time): (E_l E_r, E_l g_r + g_l, E_l L_r E_l^T + L_l).
+template <int N, typename R>
+PKS_DEV void combine_s(R* lE, R* lg, R* lL, const R* rE, const R* rg, const R* rL, R* T1, R* T2, R* v1) {
+  mm<N, N, N, N, false, false>(lE, rL, (const R*)nullptr, R(1), T1);
+  mm<N, N, N, N, false, true>(T1, lE, lL, R(1), lL);
+  symmetrize<N, N>(lL);
+  mv<N, N, N, false>(lE, rg, (const R*)nullptr, R(1), v1);
+  mm<N, N, N, N, false, false>(lE, rE, (const R*)nullptr, R(1), T2);
+  copy<N, N, N, false>(T2, lE);
+  for (int i = lane(); i < N; i += kWave) lg[i] += v1[i];
+  wsync();
+}
+
+// r (x) carry (g, L): the smoothed mean and covariance before the carry.
+template <int N, typename R>
+PKS_DEV void apply_s(const R* rE, const R* rg, const R* rL, R* cg, R* cL, R* T1, R* v1) {
+  mm<N, N, N, N, false, false>(rE, cL, (const R*)nullptr, R(1), T1);
+  mm<N, N, N, N, false, true>(T1, rE, rL, R(1), cL);
+  symmetrize<N, N>(cL);
+  mv<N, N, N, false>(rE, cg, rg, R(1), v1);
+  vcopy<N>(v1, cg);
+}
+
+// --- statistical linear regression (eq. 7-9) of g: R^N -> R^Q at (xbar, Pbar)
+// with the symmetric sigma-point set of elements.hpp (slr): one sigma point
+// per lane.  Inputs xbar (LDS vector) and Pbar (LDS matrix, destroyed: it
+// becomes its Cholesky factor).  Outputs G (Q x N, LDS), off = zbar - G xbar,
+// Lam (Q x Q), zc = g(xbar).  Zp, Zm, D: N x Q scratch; zbar: Q vector.
+template <int N, int Q, bool kAngular, typename R, class Eval>
+PKS_DEV void slr(int lin, SigmaRule rule, const R* xbar, R* Pbar, Eval eval, R* G, R* off, R* Lam, R* zc, R* Zp,
+                 R* Zm, R* D, R* zbar, int* ok) {
+  static_assert(2 * N <= kWave, "one sigma point per lane");
+  constexpr int L = ld<N>();
+  chol<N, N>(Pbar, ok);
+  R gamma, w0, wj;
+  sigma_weights<N, R>(lin, rule, gamma, w0, wj);
+  if (lane() == 0) {
+    R x[N], z[Q];
+    PKS_UNROLL for (int i = 0; i < N; ++i) x[i] = xbar[i];
+    eval(x, z);
+    PKS_UNROLL for (int q = 0; q < Q; ++q) zc[q] = z[q];
+  }
+  wsync();
+  if (lane() < 2 * N) {
+    const int j = lane() < N ? lane() : lane() - N;
+    const R sg = lane() < N ? gamma : -gamma;
+    R x[N], z[Q];
+    PKS_UNROLL for (int i = 0; i < N; ++i) x[i] = xbar[i] + sg * Pbar[i * L + j];
+    eval(x, z);
+    R* out = lane() < N ? Zp : Zm;
+    PKS_UNROLL for (int q = 0; q < Q; ++q) {
+      R v = z[q];
+      if constexpr (kAngular) v = zc[q] + wrap_pi<R>(v - zc[q]);
+      out[j * L + q] = v;
+    }
+  }
+  wsync();
+  for (int q = lane(); q < Q; q += kWave) {
+    R s = R(0);
+    for (int j = 0; j < N; ++j) s += Zp[j * L + q] + Zm[j * L + q];
+    zbar[q] = w0 * zc[q] + wj * s;
+  }
+  wsync();
+  const R wg = wj * gamma;
+  for (int e = lane(); e < N * Q; e += kWave) {
+    const int j = e / Q, q = e - j * Q;
+    D[j * L + q] = wg * (Zp[j * L + q] - Zm[j * L + q]);
+  }
+  // Lambda = Phi - D^T D, Phi = sum_j w_j (Z_j - zbar)(Z_j - zbar)^T
+  for (int e = lane(); e < Q * Q; e += kWave) {
+    const int a = e / Q, b = e - a * Q;
+    if (b < a) continue;
+    R s = R(0);
+    for (int j = 0; j < N; ++j)
+      s += (Zp[j * L + a] - zbar[a]) * (Zp[j * L + b] - zbar[b]) + (Zm[j * L + a] - zbar[a]) * (Zm[j * L + b] - zbar[b]);
+    s = s * wj + w0 * (zc[a] - zbar[a]) * (zc[b] - zbar[b]);
+    Lam[a * L + b] = s;
+  }
+  wsync();
+  for (int e = lane(); e < Q * Q; e += kWave) {
+    const int a = e / Q, b = e - a * Q;
+    if (b < a) continue;
+    R s = Lam[a * L + b];
+    for (int j = 0; j < N; ++j) s -= D[j * L + a] * D[j * L + b];
+    Lam[a * L + b] = s;
+    Lam[b * L + a] = s;
+  }
+  wsync();
+  bwd<N, N, Q>(Pbar, D);                    // G^T = L^-T D
+  copy<N, Q, N, true>(D, G);
+  for (int q = lane(); q < Q; q += kWave) {
+    R s = zbar[q];
+    for (int i = 0; i < N; ++i) s -= G[q * L + i] * xbar[i];
+    off[q] = s;
+  }
+  wsync();
+}
+
+// ---------------------------------------------------------------------------
+// Kernel arguments.
+// ---------------------------------------------------------------------------
+struct DnArgs {
+  int64_t S;
+  int ntracks;
+  int lin;
+  SigmaRule rule;
+  const unsigned char* flags;   // kSlotFirst / kSlotLast per slot
+  const int* track;             // track of each slot
+  const void* params;
+  const void* Q;                // N x N full
+  const void* Rm;               // P x P full
+  const void* m0;               // [track][N]
+  const void* P0;               // [track][N][N] full
+  const void* y;                // [slot][P] (slot 0 of a track unused)
+  void* traj;                   // [slot][kTraj]
+  void* trans;                  // [slot][kTrans]
+  void* hlin;                   // [slot][kHlin]
+  void* elem;                   // [slot][kFElem]; smoothing elements reuse it
+  unsigned long long* delta_bits;
+};
+
+struct DnLevel {
+  const void* in;    // aggregates of this level (count n)
+  void* out;         // aggregates of the next level (count ceil(n / fan))
+  void* carry_out;   // exclusive carries of this level's elements (count n)
+  const void* carry_in;  // exclusive carries of the next level's chunks
+  int64_t n;
+  int fan;
+};
+
+template <class Model, typename R>
+struct Dense {
+  static constexpr int N = Model::N, P = Model::P;
+  using Lay = Layout<N, P>;
+  using W = Work<N, R>;
+  static constexpr int MW = W::MW;
+
+  // element a_s into (A, b, C, eta, J) in the given LDS buffers
+  static PKS_DEV void build_element(const DnArgs& a, int64_t s, W& w, R* A, R* b, R* C, R* e, R* J) {
+    const unsigned fl = a.flags[s];
+    if (fl & kSlotFirst) {
+      const int tr = a.track[s];
+      zero<N, N, N>(A);
+      zero<N, N, N>(J);
+      ld_v<N>(static_cast<const R*>(a.m0) + size_t(tr) * N, b);
+      ld_full<N, N, N>(static_cast<const R*>(a.P0) + size_t(tr) * N * N, C);
+      for (int i = lane(); i < N; i += kWave) e[i] = R(0);
+      wsync();
+      return;
+    }
+    // transition out of slot s - 1, measurement at slot s
+    const R* tr = static_cast<const R*>(a.trans) + size_t(s - 1) * Lay::kTrans;
+    const R* hl = static_cast<const R*>(a.hlin) + size_t(s) * Lay::kHlin;
+    R* F = w.m[6];
+    R* Qp = w.m[7];
+    R* H = w.m[8];
+    R* c = w.v[4];
+    R* d = w.v[5];
+    R* yt = w.v[6];
+    R* Sx = J;          // P x P scratch (J is written last)
+    ld_full<N, N, N>(tr, F);
+    ld_v<N>(tr + N * N, c);
+    ld_symm<N, N>(tr + N * N + N, Qp);
+    ld_full<N, P, N>(hl, H);
+    ld_v<P>(hl + P * N, d);
+    ld_symm<N, P>(hl + P * N + P, Sx);
+    ld_v<P>(hl + P * N + P + Lay::kSP, yt);
+    wsync();
+    R* HQ = C;          // P x N
+    R* HF = A;          // P x N  (A is formed from F and the scratch at the end)
+    mm<N, P, N, N, false, false>(H, Qp, (const R*)nullptr, R(1), HQ);
+    mm<N, P, N, N, false, false>(H, F, (const R*)nullptr, R(1), HF);
+    mm<N, P, N, P, false, true>(HQ, H, Sx, R(1), Sx);                      // S = H Q' H^T + R'
+    chol<N, P>(Sx, &w.ok);
+    mv<N, P, N, false>(H, c, yt, R(-1), yt);                                // w = y - H c - d
+    for (int i = lane(); i < P; i += kWave) yt[i] -= d[i];
+    wsync();
+    fwd<N, P, N>(Sx, HQ);                                                   // Zs = Ls^-1 H Q'
+    fwd<N, P, N>(Sx, HF);                                                   // Ys = Ls^-1 H F
+    fwd_vec<N, P>(Sx, yt);                                                  // ws = Ls^-1 w
+    mv<N, N, P, true>(HQ, yt, c, R(1), b);                                  // b = c + Zs^T ws
+    mv<N, N, P, true>(HF, yt, (const R*)nullptr, R(1), e);                  // eta = Ys^T ws
+    mm<N, N, P, N, true, false>(HQ, HF, F, R(-1), H);                       // A = F - Zs^T Ys  (into H)
+    mm<N, N, P, N, true, false>(HQ, HQ, Qp, R(-1), F);                      // C = Q' - Zs^T Zs (into F)
+    mm<N, N, P, N, true, false>(HF, HF, (const R*)nullptr, R(1), Qp);       // J = Ys^T Ys (into Qp)
+    copy<N, N, N, false>(H, A);
+    copy<N, N, N, false>(F, C);
+    copy<N, N, N, false>(Qp, J);
+    symmetrize<N, N>(C);
+    symmetrize<N, N>(J);
+  }
+
+  static PKS_DEV void store_felem(const R* A, const R* b, const R* C, const R* e, const R* J, R* g) {
+    st_full<N, N, N>(A, g);
+    st_v<N>(b, g + N * N);
+    st_symm<N, N>(C, g + N * N + N);
+    st_v<N>(e, g + N * N + N + Lay::kS);
+    st_symm<N, N>(J, g + N * N + 2 * N + Lay::kS);
+  }
+  static PKS_DEV void load_felem(const R* g, R* A, R* b, R* C, R* e, R* J) {
+    ld_full<N, N, N>(g, A);
+    ld_v<N>(g + N * N, b);
+    ld_symm<N, N>(g + N * N + N, C);
+    ld_v<N>(g + N * N + N + Lay::kS, e);
+    ld_symm<N, N>(g + N * N + 2 * N + Lay::kS, J);
+    wsync();
+  }
+  static PKS_DEV void store_selem(const R* E, const R* g_, const R* Lm, R* g) {
+    st_full<N, N, N>(E, g);
+    st_v<N>(g_, g + N * N);
+    st_symm<N, N>(Lm, g + N * N + N);
+  }
+  static PKS_DEV void load_selem(const R* g, R* E, R* g_, R* Lm) {
+    ld_full<N, N, N>(g, E);
+    ld_v<N>(g + N * N, g_);
+    ld_symm<N, N>(g + N * N + N, Lm);
+    wsync();
+  }
+  static PKS_DEV void store_carry(const R* x, const R* Pm, R* g) {
+    st_v<N>(x, g);
+    st_symm<N, N>(Pm, g + N);
+  }
+  static PKS_DEV void load_carry(const R* g, R* x, R* Pm) {
+    ld_v<N>(g, x);
+    ld_symm<N, N>(g + N, Pm);
+    wsync();
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Kernels.  Every workgroup is one wave (64 lanes).
+// ---------------------------------------------------------------------------
+
+// Linearisation of f (all but the last slot of a track) and h (all but the
+// first) at the current trajectory; one slot per workgroup.
+template <class Model, typename R>
+__global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
+  using D = Dense<Model, R>;
+  constexpr int N = D::N, P = D::P;
+  using Lay = typename D::Lay;
+  __shared__ typename D::W w;
+  const int64_t s = blockIdx.x;
+  if (s >= a.S) return;
+  if (lane() == 0) w.ok = 1;
+  const Model md{static_cast<const R*>(a.params)};
+  const unsigned fl = a.flags[s];
+  const R* tj = static_cast<const R*>(a.traj) + size_t(s) * Lay::kTraj;
+  R* xbar = w.v[0];
+  ld_v<N>(tj, xbar);
+  wsync();
+  if (!(fl & kSlotLast)) {
+    ld_symm<N, N>(tj + N, w.m[0]);
+    wsync();
+    R* G = w.m[1];
+    R* Lam = w.m[2];
+    slr<N, N, false, R>(a.lin, a.rule, xbar, w.m[0], [&](const R(&x)[N], R(&z)[N]) { md.f(x, z); }, G, w.v[1],
+                        Lam, w.v[2], w.m[3], w.m[4], w.m[5], w.v[3], &w.ok);
+    R* out = static_cast<R*>(a.trans) + size_t(s) * Lay::kTrans;
+    const R* Qm = static_cast<const R*>(a.Q);
+    constexpr int L = ld<N>();
+    for (int e = lane(); e < N * N; e += kWave) Lam[(e / N) * L + e % N] += Qm[e];
+    wsync();
+    st_full<N, N, N>(G, out);
+    st_v<N>(w.v[1], out + N * N);
+    st_symm<N, N>(Lam, out + N * N + N);
+    wsync();                      // the stores have read LDS before it is reused
+  }
+  if (!(fl & kSlotFirst)) {
+    ld_symm<N, N>(tj + N, w.m[0]);
+    wsync();
+    R* H = w.m[1];
+    R* Om = w.m[2];
+    R* hc = w.v[2];
+    slr<N, P, Model::kAngular, R>(a.lin, a.rule, xbar, w.m[0], [&](const R(&x)[N], R(&z)[P]) { md.h(x, z); }, H,
+                                  w.v[1], Om, hc, w.m[3], w.m[4], w.m[5], w.v[3], &w.ok);
+    R* out = static_cast<R*>(a.hlin) + size_t(s) * Lay::kHlin;
+    const R* Rm = static_cast<const R*>(a.Rm);
+    const R* y = static_cast<const R*>(a.y) + size_t(s) * P;
+    constexpr int L = ld<N>();
+    for (int e = lane(); e < P * P; e += kWave) Om[(e / P) * L + e % P] += Rm[e];
+    for (int i = lane(); i < P; i += kWave)
+      out[P * N + P + Lay::kSP + i] = Model::kAngular ? hc[i] + wrap_pi<R>(y[i] - hc[i]) : y[i];
+    wsync();
+    st_full<N, P, N>(H, out);
+    st_v<P>(w.v[1], out + P * N);
+    st_symm<N, P>(Om, out + P * N + P);
+  }
+}
+
+// Level 0 of the filtering scan: build the elements of `fan` consecutive
+// slots, store them, and fold them into the chunk aggregate.
+template <class Model, typename R>
+__global__ __launch_bounds__(kWave) void k_dn_forward_up(DnArgs a, int fan, void* agg_out) {
+  using D = Dense<Model, R>;
+  constexpr int N = D::N;
+  using Lay = typename D::Lay;
+  __shared__ typename D::W w;
+  if (lane() == 0) w.ok = 1;
+  const int64_t s0 = int64_t(blockIdx.x) * fan;
+  const int64_t s1 = min(s0 + fan, a.S);
+  R *lA = w.m[0], *lC = w.m[1], *lJ = w.m[2], *rA = w.m[3], *rC = w.m[4], *rJ = w.m[5];
+  R *lb = w.v[0], *le = w.v[1], *rb = w.v[2], *re = w.v[3];
+  for (int64_t s = s0; s < s1; ++s) {
+    R* A = s == s0 ? lA : rA;
+    R* C = s == s0 ? lC : rC;
+    R* J = s == s0 ? lJ : rJ;
+    R* b = s == s0 ? lb : rb;
+    R* e = s == s0 ? le : re;
+    D::build_element(a, s, w, A, b, C, e, J);
+    D::store_felem(A, b, C, e, J, static_cast<R*>(a.elem) + size_t(s) * Lay::kFElem);
+    if (s > s0)
+      combine_f<N, R>(lA, lb, lC, le, lJ, rA, rb, rC, re, rJ, w.m[6], w.m[7], w.m[8], w.v[4], w.v[5], &w.ok);
+  }
+  D::store_felem(lA, lb, lC, le, lJ, static_cast<R*>(agg_out) + size_t(blockIdx.x) * Lay::kFElem);
+}
+
+// Up-sweep of a scan level: fold `fan` consecutive aggregates.  FILT selects
+// the operator (filtering: records of kFElem words; smoothing: kSElem).
+template <class Model, bool FILT, typename R>
+__global__ __launch_bounds__(kWave) void k_dn_scan_up(DnArgs a, DnLevel lv) {
+  using D = Dense<Model, R>;
+  constexpr int N = D::N;
+  using Lay = typename D::Lay;
+  constexpr int RW = FILT ? Lay::kFElem : Lay::kSElem;
+  __shared__ typename D::W w;
+  if (lane() == 0) w.ok = 1;
+  const int64_t i0 = int64_t(blockIdx.x) * lv.fan;
+  const int64_t i1 = min(i0 + lv.fan, lv.n);
+  const R* in = static_cast<const R*>(lv.in);
+  R* out = static_cast<R*>(lv.out) + size_t(blockIdx.x) * RW;
+  if (FILT) {
+    D::load_felem(in + size_t(i0) * RW, w.m[0], w.v[0], w.m[1], w.v[1], w.m[2]);
+    for (int64_t i = i0 + 1; i < i1; ++i) {
+      D::load_felem(in + size_t(i) * RW, w.m[3], w.v[2], w.m[4], w.v[3], w.m[5]);
+      combine_f<N, R>(w.m[0], w.v[0], w.m[1], w.v[1], w.m[2], w.m[3], w.v[2], w.m[4], w.v[3], w.m[5], w.m[6],
+                      w.m[7], w.m[8], w.v[4], w.v[5], &w.ok);
+    }
+    D::store_felem(w.m[0], w.v[0], w.m[1], w.v[1], w.m[2], out);
+  } else {
+    D::load_selem(in + size_t(i0) * RW, w.m[0], w.v[0], w.m[1]);
+    for (int64_t i = i0 + 1; i < i1; ++i) {
+      D::load_selem(in + size_t(i) * RW, w.m[2], w.v[1], w.m[3]);
+      combine_s<N, R>(w.m[0], w.v[0], w.m[1], w.m[2], w.v[1], w.m[3], w.m[4], w.m[5], w.v[2]);
+    }
+    D::store_selem(w.m[0], w.v[0], w.m[1], out);
+  }
+}
+
+// Down-sweep of a scan level: exclusive carries of the `fan` aggregates of one
+// chunk from the chunk's own exclusive carry.  Filtering runs forward (the
+// first element overall has no carry: it starts at a prior element);
+// smoothing runs backward (the last element overall has none: it ends at a
+// last slot).
+template <class Model, bool FILT, typename R>
+__global__ __launch_bounds__(kWave) void k_dn_scan_down(DnArgs a, DnLevel lv) {
+  using D = Dense<Model, R>;
+  constexpr int N = D::N;
+  using Lay = typename D::Lay;
+  constexpr int RW = FILT ? Lay::kFElem : Lay::kSElem;
+  __shared__ typename D::W w;
+  if (lane() == 0) w.ok = 1;
+  const int64_t c = blockIdx.x;
+  const int64_t i0 = c * lv.fan;
+  const int64_t i1 = min(i0 + lv.fan, lv.n);
+  const int64_t nchunks = (lv.n + lv.fan - 1) / lv.fan;
+  const R* in = static_cast<const R*>(lv.in);
+  R* cout = static_cast<R*>(lv.carry_out);
+  R *cx = w.v[6], *cP = w.m[8];
+  R *rA = w.m[0], *rC = w.m[1], *rJ = w.m[2], *rb = w.v[0], *re = w.v[1];
+  bool have = FILT ? c > 0 : c < nchunks - 1;
+  if (have) D::load_carry(static_cast<const R*>(lv.carry_in) + size_t(c) * Lay::kCarry, cx, cP);
+  for (int64_t k = 0; k < i1 - i0; ++k) {
+    const int64_t i = FILT ? i0 + k : i1 - 1 - k;
+    if (have) {
+      D::store_carry(cx, cP, cout + size_t(i) * Lay::kCarry);
+      wsync();
+    }
+    if (FILT) {
+      D::load_felem(in + size_t(i) * RW, rA, rb, rC, re, rJ);
+      if (have) {
+        apply_f<N, R>(cx, cP, rA, rb, rC, re, rJ, w.m[3], w.m[4], w.m[5], w.v[2], w.v[3], &w.ok);
+      } else {
+        vcopy<N>(rb, cx);
+        copy<N, N, N, false>(rC, cP);
+      }
+    } else {
+      D::load_selem(in + size_t(i) * RW, rA, rb, rC);
+      if (have) {
+        apply_s<N, R>(rA, rb, rC, cx, cP, w.m[3], w.v[2]);
+      } else {
+        vcopy<N>(rb, cx);
+        copy<N, N, N, false>(rC, cP);
+      }
+    }
+    have = true;
+  }
+}
+
+// Level 0 down-sweep of the filtering scan and level 0 up-sweep of the
+// smoothing scan: filtered x*, P* of every slot of the chunk, its smoothing
+// element (eq. 17-18, stored over the filtering element) and the chunk's
+// smoothing aggregate.
+template <class Model, typename R>
+__global__ __launch_bounds__(kWave) void k_dn_forward_down_backward_up(DnArgs a, int fan, const void* carry_in,
+                                                                       void* sagg_out) {
+  using D = Dense<Model, R>;
+  constexpr int N = D::N;
+  using Lay = typename D::Lay;
+  constexpr int L = ld<N>();
+  __shared__ typename D::W w;
+  if (lane() == 0) w.ok = 1;
+  const int64_t c = blockIdx.x;
+  const int64_t s0 = c * fan;
+  const int64_t s1 = min(s0 + fan, a.S);
+  R *cx = w.v[6], *cP = w.m[8];                       // filtered mean / covariance (carry)
+  R *rA = w.m[0], *rC = w.m[1], *rJ = w.m[2], *rb = w.v[0], *re = w.v[1];
+  R *sE = w.m[6], *sL = w.m[7], *sg = w.v[7];          // smoothing aggregate
+  bool have = c > 0;
+  if (have) D::load_carry(static_cast<const R*>(carry_in) + size_t(c) * Lay::kCarry, cx, cP);
+  for (int64_t s = s0; s < s1; ++s) {
+    R* rec = static_cast<R*>(a.elem) + size_t(s) * Lay::kFElem;
+    D::load_felem(rec, rA, rb, rC, re, rJ);
+    if (have) {
+      apply_f<N, R>(cx, cP, rA, rb, rC, re, rJ, w.m[3], w.m[4], w.m[5], w.v[2], w.v[3], &w.ok);
+    } else {
+      vcopy<N>(rb, cx);
+      copy<N, N, N, false>(rC, cP);
+    }
+    have = true;
+    // smoothing element of slot s into (eE, eg, eL) = (rA, rb, rC)
+    R *eE = rA, *eg = rb, *eL = rC;
+    if (a.flags[s] & kSlotLast) {
+      zero<N, N, N>(eE);
+      vcopy<N>(cx, eg);
+      copy<N, N, N, false>(cP, eL);
+    } else {
+      const R* tr = static_cast<const R*>(a.trans) + size_t(s) * Lay::kTrans;
+      R *F = w.m[2], *FP = w.m[3], *Pp = w.m[4], *V = w.m[3];
+      R *r = w.v[2], *t = w.v[3];
+      ld_full<N, N, N>(tr, F);
+      ld_symm<N, N>(tr + N * N + N, Pp);
+      ld_v<N>(tr + N * N, r);
+      wsync();
+      mm<N, N, N, N, false, false>(F, cP, (const R*)nullptr, R(1), FP);   // F P*
+      mm<N, N, N, N, false, true>(FP, F, Pp, R(1), Pp);                  // F P* F^T + Q'
+      symmetrize<N, N>(Pp);
+      mv<N, N, N, false>(F, cx, r, R(1), t);                              // F x* + c
+      chol<N, N>(Pp, &w.ok);
+      fwd<N, N, N>(Pp, V);                                                // V = Lp^-1 F P*
+      fwd_vec<N, N>(Pp, t);
+      mm<N, N, N, N, true, false>(V, V, cP, R(-1), eL);                   // L_s = P* - V^T V
+      symmetrize<N, N>(eL);
+      mv<N, N, N, true>(V, t, cx, R(-1), eg);                             // g = x* - V^T Lp^-1 (F x* + c)
+      bwd<N, N, N>(Pp, V);                                                // E^T = Lp^-T V
+      copy<N, N, N, true>(V, eE);
+    }
+    D::store_selem(eE, eg, eL, rec);
+    if (s == s0) {
+      copy<N, N, N, false>(eE, sE);
+      copy<N, N, N, false>(eL, sL);
+      vcopy<N>(eg, sg);
+    } else {
+      combine_s<N, R>(sE, sg, sL, eE, eg, eL, w.m[3], w.m[4], w.v[2]);
+    }
+  }
+  (void)L;
+  D::store_selem(sE, sg, sL, static_cast<R*>(sagg_out) + size_t(c) * Lay::kSElem);
+}
+
+// Level 0 down-sweep of the smoothing scan: the new trajectory (eq. 19) and the
+// per-track largest change of the means.
+template <class Model, typename R>
+__global__ __launch_bounds__(kWave) void k_dn_backward_down(DnArgs a, int fan, const void* carry_in) {
+  using D = Dense<Model, R>;
+  constexpr int N = D::N;
+  using Lay = typename D::Lay;
+  __shared__ typename D::W w;
+  __shared__ R dmax[kWave];
+  if (lane() == 0) w.ok = 1;
+  const int64_t c = blockIdx.x;
+  const int64_t s0 = c * fan;
+  const int64_t s1 = min(s0 + fan, a.S);
+  const int64_t nchunks = (a.S + fan - 1) / fan;
+  R *cx = w.v[6], *cP = w.m[8];
+  R *rE = w.m[0], *rL = w.m[1], *rg = w.v[0];
+  bool have = c < nchunks - 1;
+  if (have) D::load_carry(static_cast<const R*>(carry_in) + size_t(c) * Lay::kCarry, cx, cP);
+  for (int64_t k = 0; k < s1 - s0; ++k) {
+    const int64_t s = s1 - 1 - k;
+    D::load_selem(static_cast<const R*>(a.elem) + size_t(s) * Lay::kFElem, rE, rg, rL);
+    if (have) {
+      apply_s<N, R>(rE, rg, rL, cx, cP, w.m[2], w.v[2]);
+    } else {
+      vcopy<N>(rg, cx);
+      copy<N, N, N, false>(rL, cP);
+    }
+    have = true;
+    R* tj = static_cast<R*>(a.traj) + size_t(s) * Lay::kTraj;
+    R m = R(0);
+    bool nan = false;
+    if (lane() < N) {
+      const R d = fabs(cx[lane()] - tj[lane()]);
+      nan = !(d == d);
+      m = d;
+    }
+    dmax[lane()] = nan ? R(-1) : m;
+    wsync();
+    D::store_carry(cx, cP, tj);
+    if (lane() == 0) {
+      R mx = R(0);
+      bool bad = false;
+      for (int i = 0; i < N; ++i) {
+        bad = bad || dmax[i] < R(0);
+        mx = dmax[i] > mx ? dmax[i] : mx;
+      }
+      const unsigned long long bits = order_bits(bad ? __builtin_nan("") : double(mx));
+      atomicMax(&a.delta_bits[a.track[s]], bits);
+      atomicMax(&a.delta_bits[a.ntracks], bits);
+    }
+    wsync();
+  }
+}
+
+// Prior broadcast of the initial trajectory: (m0, P0) of the slot's track.
+template <int N, typename R>
+__global__ void k_dn_prior(int64_t S, const int* track, const R* m0, const R* P0, R* traj) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  constexpr int TW = N + sym_size<N>();
+  if (e >= S * TW) return;
+  const int64_t s = e / TW;
+  const int k = int(e - s * TW);
+  const int tr = track[s];
+  if (k < N) {
+    traj[e] = m0[size_t(tr) * N + k];
+  } else {
+    int i = 0, rem = k - N;
+    while (rem >= N - i) {
+      rem -= N - i;
+      ++i;
+    }
+    traj[e] = P0[(size_t(tr) * N + i) * N + i + rem];
+  }
+}
+
+// Caller layout <-> slot records: mean [S][N], cov [S][N][N].
+template <int N, typename R>
+__global__ void k_dn_unpack(int64_t S, const R* traj, R* mean, R* cov) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= S * N * N) return;
+  const int64_t s = e / (N * N);
+  const int r = int(e - s * N * N), i = r / N, j = r - i * N;
+  const R* t = traj + size_t(s) * (N + sym_size<N>());
+  if (cov) cov[e] = t[N + sym_index<N>(i, j)];
+  if (mean && j == 0) mean[s * N + i] = t[i];
+}
+
+template <int N, typename R>
+__global__ void k_dn_pack(int64_t S, const R* mean, const R* cov, SymConst<N, R> cc, int use_const, const int* track,
+                          const R* P0, R* traj) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  constexpr int TW = N + sym_size<N>();
+  if (e >= S * TW) return;
+  const int64_t s = e / TW;
+  const int k = int(e - s * TW);
+  if (k < N) {
+    traj[e] = mean[s * N + k];
+    return;
+  }
+  int i = 0, rem = k - N;
+  while (rem >= N - i) {
+    rem -= N - i;
+    ++i;
+  }
+  const int j = i + rem;
+  if (cov)
+    traj[e] = R(0.5) * (cov[(s * N + i) * N + j] + cov[(s * N + j) * N + i]);
+  else if (use_const)
+    traj[e] = cc.v[k - N];
+  else
+    traj[e] = P0[(size_t(track[s]) * N + i) * N + j];
+}
+
+}  // namespace dn
+}  // namespace pks

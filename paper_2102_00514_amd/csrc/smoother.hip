@@ -69,8 +69,12 @@ constexpr int kMaxTargets = 16;   // coordinated-turn blocks in one stacked stat
 
 static bool stacked(int model, int nx) { return model == SM_MODEL_CT_BEARINGS && nx > 5 && nx % 5 == 0; }
 
-static EngineBase* make_engine(int model, int precision, int nx, int ny) {
+// Stacked targets: the Taylor linearisation runs each target as its own block;
+// sigma-point rules couple the targets and run on the wavefront-cooperative
+// engine of the full state.
+static EngineBase* make_engine(int model, int precision, int nx, int ny, int lin) {
   if (stacked(model, nx)) {
+    if (lin != SM_LIN_TAYLOR) return precision == SM_FP64 ? make_engine_dense_ct_f64(nx, ny) : nullptr;
     BlockEngine* e = new BlockEngine(&make_dense_engine);
     e->set_precision_word(precision == SM_FP64 ? sizeof(double) : sizeof(float));
     return e;
@@ -78,11 +82,14 @@ static EngineBase* make_engine(int model, int precision, int nx, int ny) {
   return make_dense_engine(model, precision, nx, ny);
 }
 
-static bool supported(int model, int nx, int ny) {
+static bool supported(int model, int nx, int ny, int lin, int precision) {
   if (model == SM_MODEL_CT_BEARINGS) {
     if (nx == 5) return ny == 2;
-    // stacked targets: two sensors per target, blocks run on the (5, 2) kernels
-    return stacked(model, nx) && nx / 5 <= kMaxTargets && ny == 2 * (nx / 5);
+    if (!stacked(model, nx)) return false;
+    // sigma points: the compiled full-state engine (four targets, eight sensors, FP64)
+    if (lin != SM_LIN_TAYLOR) return nx == 20 && ny == 8 && precision == SM_FP64;
+    // Taylor: two sensors per target, blocks run on the (5, 2) kernels
+    return nx / 5 <= kMaxTargets && ny == 2 * (nx / 5);
   }
   if (model == SM_MODEL_LINEAR) return (nx == 1 && ny == 1) || (nx == 3 && ny == 2) || (nx == 5 && ny == 2);
   return false;
@@ -104,9 +111,10 @@ static bool block_diagonal(const double* A, int n, F block) {
 static std::string validate(const sm_problem* pb) {
   if (!pb) return "problem is NULL";
   if (pb->model != SM_MODEL_LINEAR && pb->model != SM_MODEL_CT_BEARINGS) return "unknown model";
-  if (!supported(pb->model, pb->nx, pb->ny))
-    return "unsupported (model, nx, ny) = (" + std::to_string(pb->model) + ", " + std::to_string(pb->nx) + ", " +
-           std::to_string(pb->ny) + ")";
+  if (!supported(pb->model, pb->nx, pb->ny, pb->lin, pb->precision))
+    return "unsupported (model, nx, ny, linearisation, precision) = (" + std::to_string(pb->model) + ", " +
+           std::to_string(pb->nx) + ", " + std::to_string(pb->ny) + ", " + std::to_string(pb->lin) + ", " +
+           std::to_string(pb->precision) + ")";
   const int n = pb->nx, p = pb->ny;
   if (pb->n_tracks < 1) return "n_tracks must be >= 1";
   if (!pb->offsets) return "offsets is NULL";
@@ -152,10 +160,8 @@ static std::string validate(const sm_problem* pb) {
   if (pb->init_cov)
     for (int64_t s = 0; s < S; ++s)
       if (!host_spd(pb->init_cov + size_t(s) * n * n, n)) return "init_cov must be SPD at every slot";
-  if (stacked(pb->model, n)) {
+  if (stacked(pb->model, n) && pb->lin == SM_LIN_TAYLOR) {
     // the targets must not interact for the block decomposition to be exact
-    if (pb->lin != SM_LIN_TAYLOR)
-      return "stacked targets: only the Taylor (IEKS) linearisation keeps the targets separate";
     const int k = n / 5;
     std::vector<int> per(k, 0);
     for (int s = 0; s < p; ++s) per[int(pb->params[3 + 3 * s])] += 1;
@@ -181,7 +187,7 @@ struct smoother {
   std::unique_ptr<pks::EngineBase> eng;
   std::string err;
   int nx = 0;
-  bool stacked = false;   // stacked targets run as separate blocks
+  bool blocks = false;    // stacked targets run as separate blocks
 };
 
 using pks::g_init_error;
@@ -214,7 +220,7 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
       g_init_error = msg;
       return SM_EINVAL;
     }
-    std::unique_ptr<pks::EngineBase> eng(pks::make_engine(pb->model, pb->precision, pb->nx, pb->ny));
+    std::unique_ptr<pks::EngineBase> eng(pks::make_engine(pb->model, pb->precision, pb->nx, pb->ny, pb->lin));
     if (!eng) {
       g_init_error = "no kernel for this configuration";
       return SM_EINVAL;
@@ -227,7 +233,7 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
     smoother* h = new smoother();
     h->eng = std::move(eng);
     h->nx = pb->nx;
-    h->stacked = pks::stacked(pb->model, pb->nx);
+    h->blocks = pks::stacked(pb->model, pb->nx) && pb->lin == SM_LIN_TAYLOR;
     *out = h;
     g_init_error.clear();
     return SM_OK;
@@ -275,7 +281,7 @@ sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iter
         q.tile_lanes = lanes;
         q.lane_slots = slots;
         q.n_iter = iters + 1;
-        std::unique_ptr<pks::EngineBase> eng(pks::make_engine(q.model, q.precision, q.nx, q.ny));
+        std::unique_ptr<pks::EngineBase> eng(pks::make_engine(q.model, q.precision, q.nx, q.ny, q.lin));
         if (!eng) {
           last = SM_EINVAL;
           last_err = "no kernel for this configuration";
@@ -423,7 +429,7 @@ sm_status smoother_set_trajectory_device(smoother_t h, const void* d_mean, const
       h->err = "cov_const must be symmetric positive definite";
       return SM_EINVAL;
     }
-    if (h->stacked && !pks::block_diagonal(cov_const, n, [](int i) { return i / 5; })) {
+    if (h->blocks && !pks::block_diagonal(cov_const, n, [](int i) { return i / 5; })) {
       h->err = "stacked targets: cov_const must be block-diagonal";
       return SM_EINVAL;
     }

@@ -203,3 +203,11 @@ def test_stacked_targets_validation():
     bad_p0 = pb.P0.copy()
     bad_p0[0, 19, 0] = bad_p0[0, 0, 19] = 0.1
     _expect_einval(wl.Problem(**{**pb.__dict__, "P0": bad_p0}), "P0 must be block-diagonal")
+
+
+def test_dense_stacked_scope():
+    pb = wl.config_c5_single(10)
+    _expect_einval(pb, "unsupported", lin="unscented", precision="f32")     # full-state engine is FP64
+    sensors = np.random.default_rng(1).uniform(-2, 2, (6, 2))
+    pb3 = wl.stacked_ct(10, np.random.default_rng(2), sensors=sensors, n_targets=3, n_sensors=6)
+    _expect_einval(pb3, "unsupported", lin="cubature")                      # only (20, 8) is compiled

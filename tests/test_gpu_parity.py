@@ -309,3 +309,58 @@ def test_stacked_ragged_batch_and_device_paths(B):
         ref.iterate(1)
         rm, rc = ref.result()
     assert np.array_equal(gm, rm) and np.array_equal(gc, rc)
+
+
+@pytest.mark.parametrize("lin", ["unscented", "cubature"])
+def test_dense_stacked_sigma_points_match_oracle(B, lin):
+    """Four stacked targets with sigma points (nx = 20, 41 / 40 points): the
+    wavefront-cooperative engine against the oracle's dense smoother, one
+    iteration from a common input trajectory (iterations 1 and 3), T = 300
+    (several scan levels)."""
+    pb = wl.config_c5_single(300)
+    for start in (0, 2):
+        mean, cov, one = single_iteration_case(B, pb, lin, start)
+        assert_parity(mean, cov, one, what=f"dense n=20 T=300 {lin} iteration {start + 1}")
+
+
+@pytest.mark.parametrize("slots", [1, 2, 8])
+def test_dense_schedules_and_ragged_batch(B, slots):
+    sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (8, 2))
+    parts = [wl.stacked_ct(T, np.random.default_rng([56, T]), sensors=sensors) for T in (1, 9, 70)]
+    pb = wl.concat_tracks(parts, "stacked batch")
+    M = 2
+    mean, cov, _, deltas = run_gpu(B, pb, M, "unscented", lane_slots=slots)
+    so = pb.slot_offsets()
+    for i in range(pb.n_tracks):
+        ref = oracle.smoother(pb.track(i), M, "unscented")
+        sl = slice(so[i], so[i + 1])
+        assert_parity(mean[sl], cov[sl], ref, what=f"dense slots={slots} track {i} T={pb.lengths[i]}")
+        assert abs(deltas[i] - ref["deltas"][-1]) <= 1e-6 * ref["deltas"][-1] + 1e-12
+
+
+def test_dense_device_paths_and_graph(B):
+    import torch
+    pb = wl.config_c5_single(150)
+    S = pb.n_slots
+    with B.Smoother(pb, n_iter=3, lin="unscented", use_graph=True) as g, \
+            B.Smoother(pb, n_iter=3, lin="unscented", use_graph=False) as e:
+        for _ in range(3):
+            dg, _ = g.iterate(1)
+            de, _ = e.iterate(1)
+            assert dg == de
+        gm, gc = g.result()
+        em, ec = e.result()
+        assert np.array_equal(gm, em) and np.array_equal(gc, ec)
+        dm = torch.empty((S, 20), dtype=torch.float64, device="cuda")
+        dc = torch.empty((S, 20, 20), dtype=torch.float64, device="cuda")
+        g.result_device(dm.data_ptr(), dc.data_ptr())
+        torch.cuda.synchronize()
+        assert np.array_equal(dm.cpu().numpy(), gm) and np.array_equal(dc.cpu().numpy(), gc)
+        cconst = wl.random_spd(np.random.default_rng(8), 20, scale=0.3)
+        g.set_trajectory_device(dm.data_ptr(), 0, cconst)
+        g.iterate(1)
+        sm_m, sm_c = g.result()
+    with B.Smoother(pb, n_iter=1, lin="unscented", init_mean=gm, init_cov=np.broadcast_to(cconst, (S, 20, 20))) as r:
+        r.iterate(1)
+        rm, rc = r.result()
+    assert np.array_equal(sm_m, rm) and np.array_equal(sm_c, rc)
