@@ -9,6 +9,14 @@ suffix-scan them, and reduce the convergence statistic.  Inputs are resident
 on the GPU before timing starts.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--lin taylor|cubature|unscented]
+                    [--workload c2|c3|c5|c2sweep]
+
+Other workloads (one JSON line each): c3, 4096 ragged tracks with T_i ~ U{100..8192}
+(cubature; steps = sum of T_i per iteration); c5, four stacked targets (nx = 20,
+eight bearings, T = 2^16, unscented) on the wavefront-cooperative engine, whose
+roofline is FP64 arithmetic; c2sweep, T = 2^10..2^15 on the GPU parallel and
+sequential paths (FP64 and FP32) and the CPU oracle.  The learned warm-start
+comparison runs with c2.
 
 Prints one JSON line on stdout; details go to stderr.
 """
@@ -25,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "smoothed steps/sec per iteration at T=2^15 FP64; time-to-converge learned vs plain"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
 def log(*a):
@@ -61,17 +70,44 @@ def algorithmic_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: 
     return words * word
 
 
+# Floating-point operations per position of the wavefront-cooperative (n = 20)
+# kernels, counted from their dense 20 x 20 products (2 N^3 each), Cholesky
+# factorisations (N^3 / 3), triangular solves with N right-hand sides (N^3) and
+# the sigma-point statistics; vector and O(N^2) terms are left out.
+def dense_flops_per_position(kernel: str, n: int, p: int) -> float:
+    mm, ch, sv = 2 * n ** 3, n ** 3 / 3, n ** 3
+    m = 2 * n + 1                                   # sigma points
+    f_lin = ch + 2 * m * n * n + 2 * n ** 3 + sv    # Phi, D^T D, G
+    h_lin = 2 * m * p * p + 2 * n * p * p + n * n * p
+    element = 2 * (2 * p * n * n) + 2 * p * p * n + 3 * (2 * n * n * p) + 2 * p * p * n
+    combine_f = 10 * mm + 2 * ch + sv
+    apply_f = 5 * mm + 2 * ch + sv
+    combine_s, apply_s = 3 * mm, 2 * mm
+    smoother_element = 3 * mm + ch + 2 * sv
+    return {
+        "dn_linearize": f_lin + h_lin,
+        "dn_forward_up": element + combine_f,
+        "dn_forward_down_backward_up": apply_f + smoother_element + combine_s,
+        "dn_backward_down": apply_s,
+        "scan_up_filter": combine_f, "scan_down_filter": apply_f,
+        "scan_up_smoother": combine_s, "scan_down_smoother": apply_s,
+        "reset_delta": 0.0,
+    }[kernel]
+
+
+# Sources of the n = 5 kernels whose HBM traffic is recorded in profiles/
+# (the kernels, their device functions and their launch configuration).
+TRAFFIC_SOURCES = ("fused.hpp", "elements.hpp", "operators.hpp", "linalg.hpp", "models.hpp", "scan.hpp",
+                   "slot_kernels.hpp", "engine.hpp", "engine_ct_f64.hip")
+
+
 def kernel_sources_sha256() -> str:
-    """Hash of the smoother's kernel sources (the warm-start network's own
-    sources, nn_* and warmstart*, do not define any smoother kernel)."""
-    import glob
+    """Hash of the sources that define the n = 5 kernels and their launches."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2102_00514_amd", "csrc")
     h = hashlib.sha256()
-    files = glob.glob(os.path.join(csrc, "*.h*")) + glob.glob(os.path.join(csrc, "*.hip"))
-    files = [f for f in files if not os.path.basename(f).startswith(("nn_", "warmstart"))]
-    for f in sorted(files):
-        with open(f, "rb") as fh:
+    for f in sorted(TRAFFIC_SOURCES):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -91,20 +127,40 @@ def measured_traffic(key: str):
 
 
 def cpu_baseline(pb, lin: str, budget_s: float) -> dict:
-    """The oracle, untuned, on one host core: repeated full iterations of the same
-    workload until about budget_s seconds of CPU time have been spent."""
+    """The oracle, untuned, on one host core, on a bounded sample of the same
+    workload: one iteration from the prior broadcast per track, track after
+    track (a single track repeats; a track longer than the budget allows is
+    cut to a prefix), until about budget_s seconds have been spent."""
     import oracle
-    T = int(pb.offsets[1])
     t0 = time.perf_counter()
-    iters = 0
+    steps = iters = 0
+    i = 0
+    first = pb.track(0)
+    T0 = int(first.offsets[1])
+    # one-iteration cost probe on a short prefix decides whether the full track fits
+    probe_T = min(T0, 256)
+    tp = time.perf_counter()
+    oracle.smoother(first.prefix(probe_T) if probe_T < T0 else first, 1, lin, filtered=False)
+    per_step = (time.perf_counter() - tp) / probe_T
+    cut = T0 if per_step * T0 <= budget_s else max(probe_T, int(budget_s / 3 / per_step))
+    t0 = time.perf_counter()
     while True:
-        oracle.smoother(pb, 1, lin, filtered=False)
+        tr = pb.track(i % pb.n_tracks)
+        T = int(tr.offsets[1])
+        if T > cut:
+            tr, T = tr.prefix(cut), cut
+        oracle.smoother(tr, 1, lin, filtered=False)
+        steps += T
         iters += 1
+        i += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": T * iters / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"T={T}, {iters} iterations from the prior broadcast ({dt:.1f} s, 1 thread)"}
+    what = (f"{iters} single-iteration runs over tracks 0..{min(i, pb.n_tracks) - 1}" if pb.n_tracks > 1
+            else f"{iters} iterations")
+    return {"value": steps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what}, {steps} steps{' (prefixes of T=' + str(cut) + ')' if cut < T0 else ''}, "
+                      f"from the prior broadcast ({dt:.1f} s, 1 thread)"}
 
 
 def binding_autotune(pb, stream, lin):
@@ -148,13 +204,72 @@ def warm_start_section(weights: str, n_batch: int, n_single: int, lin: str = "ta
             "batch": dict(batch, tracks=n_batch), "single_track": single}
 
 
+def c2_sweep(args) -> None:
+    """T = 2^10..2^15 (prefixes of the seed-0 track): ms per iteration of the
+    GPU parallel path (Taylor and cubature, FP64; Taylor FP32), of the GPU
+    sequential path (one lane runs the Kalman filter and RTS smoother), and
+    of the CPU oracle (one thread, Taylor), each at its autotuned schedule.
+    Prints one JSON line whose value is the parallel FP64 Taylor rate at the
+    longest T."""
+    import torch
+    from paper_2102_00514_amd import binding
+    from paper_2102_00514_amd import workloads as wl
+    import oracle
+    stream = torch.cuda.current_stream()
+    rows = []
+    cases = [("taylor", "f64", "parallel"), ("cubature", "f64", "parallel"), ("taylor", "f32", "parallel"),
+             ("taylor", "f64", "sequential"), ("cubature", "f64", "sequential")]
+    for e in range(10, 16):
+        T = 2 ** e
+        pb = wl.config_c2(T)
+        row = {"T": T}
+        for lin, prec, scan in cases:
+            kw = dict(lin=lin, precision=prec, scan=scan)
+            if scan == "parallel":
+                lanes, slots, _ = binding.smoother_autotune(pb, stream=stream.cuda_stream, iters=5, **kw)
+                kw.update(tile_lanes=lanes, lane_slots=slots)
+            with binding.Smoother(pb, stream=stream.cuda_stream, n_iter=1000, **kw) as sm:
+                sm.iterate(3, want_delta=False)
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                k = 20 if scan == "parallel" else 3
+                torch.cuda.synchronize()
+                a.record(stream)
+                sm.iterate(k, want_delta=False)
+                b.record(stream)
+                torch.cuda.synchronize()
+                row[f"{scan}_{lin}_{prec}_ms"] = round(a.elapsed_time(b) / k, 4)
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            oracle.smoother(pb, 1, "taylor", filtered=False)
+            reps += 1
+            if time.perf_counter() - t0 > 0.5:
+                break
+        row["cpu_oracle_taylor_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+        log(json.dumps(row))
+        rows.append(row)
+    top = rows[-1]
+    ms = top["parallel_taylor_f64_ms"]
+    print(json.dumps({
+        "metric": METRIC, "value": round(top["T"] / (ms * 1e-3), 1), "unit": "steps/s", "n_gpus": 1,
+        "steps": 20, "warmup": 3, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "coordinated-turn + 2 bearings, T = 2^10..2^15 prefixes of one track; "
+                               "GPU parallel / GPU sequential / CPU oracle (1 thread)", "parallelism": "1 GPU"},
+        "sweep": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--T", type=int, default=2 ** 15)
-    ap.add_argument("--lin", default="taylor", choices=["taylor", "cubature", "unscented"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "c2sweep"],
+                    help="c2: one track, T=2^15 (default); c3: 4096 ragged tracks; c5: four stacked targets, T=2^16")
+    ap.add_argument("--T", type=int, default=0, help="track length (c2: 2^15, c5: 2^16)")
+    ap.add_argument("--lin", default=None, choices=["taylor", "cubature", "unscented"],
+                    help="default: taylor (c2), cubature (c3), unscented (c5)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--profile-iters", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -191,13 +306,30 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 268435456 B read, 268435456 B written by one elementwise kernel")
         del src, dst
-    pb = wl.config_c2(args.T)
-    T = int(pb.offsets[1])
+    if args.workload == "c2sweep":
+        c2_sweep(args)
+        return
+    if args.lin is None:
+        args.lin = {"c2": "taylor", "c3": "cubature", "c5": "unscented"}[args.workload]
+    if args.workload == "c2":
+        pb = wl.config_c2(args.T or 2 ** 15)
+        desc = f"coordinated-turn + 2 bearings, T={int(pb.offsets[1])}, single track"
+    elif args.workload == "c3":
+        pb = wl.config_c3()
+        desc = "4096 coordinated-turn tracks, T_i ~ U{100..8192}, 2 bearings, one ragged batch"
+    else:
+        pb = wl.config_c5_single(args.T or 2 ** 16)
+        desc = f"4 stacked coordinated-turn targets (nx=20), 8 bearings, T={int(pb.offsets[1])}, single track"
+    T = int(pb.offsets[-1])            # smoothed steps per iteration (all tracks)
+    dense = pb.nx == 20 and args.lin != "taylor"
+    if args.workload != "c2":
+        args.no_warm_start = True
     stream = torch.cuda.current_stream()
     total_iters = args.warmup + args.steps + args.profile_iters
     tuned = None
     if not args.tile_lanes and not args.lane_slots and not args.no_autotune:
-        lanes_t, slots_t, ms_t = binding.smoother_autotune(pb, stream=stream.cuda_stream, iters=10, lin=args.lin,
+        lanes_t, slots_t, ms_t = binding.smoother_autotune(pb, stream=stream.cuda_stream,
+                                                           iters=10 if pb.n_slots < 2 ** 20 else 2, lin=args.lin,
                                                            precision=args.precision)
         tuned = {"tile_lanes": lanes_t, "lane_slots": slots_t, "ms_per_iter": round(ms_t, 6)}
         log(f"autotuned schedule: {lanes_t} lanes x {slots_t} slots ({ms_t * 1e3:.1f} us/iteration)")
@@ -206,7 +338,7 @@ def main():
                           precision=args.precision, tile_lanes=args.tile_lanes, lane_slots=args.lane_slots)
     S, _, dev_bytes = sm.info()
     lanes, slots, tiles = sm.schedule()
-    log(f"workload: T={T} slots={S} lin={args.lin} precision={args.precision} device_bytes={dev_bytes} "
+    log(f"workload {args.workload}: steps={T} slots={S} lin={args.lin} precision={args.precision} device_bytes={dev_bytes} "
         f"schedule: {tiles} tiles x {lanes} lanes x {slots} slots")
 
     sm.iterate(args.warmup, want_delta=False)
@@ -232,24 +364,36 @@ def main():
     rows = []
     for name, (launches, tot_ms, positions) in prof.items():
         per_iter_us = tot_ms * 1e3 / args.profile_iters
-        bpp = algorithmic_bytes_per_position(name, pb.nx, pb.ny, args.lin, word, slots)
-        gbs = (bpp * positions) / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
-        rows.append((per_iter_us, name, launches, tot_ms, positions, bpp, gbs))
+        if dense:      # per position: floating-point operations
+            upp = dense_flops_per_position(name, pb.nx, pb.ny)
+            rate = upp * positions / (tot_ms * 1e-3) / 1e12 if tot_ms > 0 else 0.0
+        else:          # per position: bytes
+            upp = algorithmic_bytes_per_position(name, pb.nx, pb.ny, args.lin, word, slots)
+            rate = upp * positions / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+        rows.append((per_iter_us, name, launches, tot_ms, positions, upp, rate))
     rows.sort(reverse=True)
-    log(f"{'kernel':22s} {'us/iter':>9s} {'launches':>8s} {'avg us':>8s} {'B/pos':>7s} {'GB/s':>8s}")
-    for per_iter_us, name, launches, tot_ms, positions, bpp, gbs in rows:
-        log(f"{name:22s} {per_iter_us:9.2f} {launches:8d} {tot_ms * 1e3 / launches:8.2f} {bpp:7.0f} {gbs:8.1f}")
+    unit_pp, unit_rate = ("flop/pos", "TFLOP/s") if dense else ("B/pos", "GB/s")
+    log(f"{'kernel':28s} {'us/iter':>9s} {'launches':>8s} {'avg us':>9s} {unit_pp:>9s} {unit_rate:>8s}")
+    for per_iter_us, name, launches, tot_ms, positions, upp, rate in rows:
+        log(f"{name:28s} {per_iter_us:9.2f} {launches:8d} {tot_ms * 1e3 / launches:9.2f} {upp:9.0f} {rate:8.2f}")
     sum_us = sum(r[0] for r in rows)
     log(f"sum of kernel time per iteration: {sum_us:.1f} us (vs {ms_per_step * 1e3:.1f} us end to end)")
     dom = rows[0]
     avg_launch_s = dom[3] * 1e-3 / dom[2]
-    bytes_per_launch = dom[5] * dom[4] / dom[2]
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(f"{dom[1]}|T={T}|{args.lin}|{args.precision}")
-    roofline = {"bound": "hbm", "kernel": dom[1], "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                "traffic": None if traffic is None else int(traffic),
-                "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": int(bytes_per_launch)}
+    units_per_launch = dom[5] * dom[4] / dom[2]
+    if dense:
+        achieved = units_per_launch / avg_launch_s / 1e12
+        roofline = {"bound": "alu", "kernel": dom[1], "achieved": round(achieved, 4),
+                    "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 6), "traffic": None,
+                    "avg_launch_us": round(avg_launch_s * 1e6, 3), "flops_per_launch": int(units_per_launch)}
+    else:
+        achieved = units_per_launch / avg_launch_s / 1e9
+        traffic = measured_traffic(f"{dom[1]}|T={T}|{args.lin}|{args.precision}")
+        roofline = {"bound": "hbm", "kernel": dom[1], "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                    "traffic": None if traffic is None else int(traffic),
+                    "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": int(units_per_launch)}
     sm.close()
 
     warm = None
@@ -271,10 +415,11 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 6),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": f"coordinated-turn + 2 bearings, T={T} ({S} slots), single track, "
+        "config": {"workload": f"{desc} ({S} slots), "
                                f"{'IEKS (Taylor)' if args.lin == 'taylor' else args.lin + ' SLR'}, "
                                f"one iteration per step",
-                   "T": T, "nx": pb.nx, "ny": pb.ny, "lin": args.lin, "parallelism": "time-axis scan, 1 GPU",
+                   "T": T, "tracks": pb.n_tracks, "nx": pb.nx, "ny": pb.ny, "lin": args.lin,
+                   "parallelism": "time-axis scan, 1 GPU",
                    "schedule": {"tiles": tiles, "lanes_per_tile": lanes, "slots_per_lane": slots,
                                 "autotuned": tuned}},
         "roofline": roofline,

@@ -30,19 +30,36 @@ PKS_DEV void wsync() { __syncthreads(); }     // workgroups are a single wave
 // ---------------------------------------------------------------------------
 
 // C = C0 + sgn * op(A) op(B), op(A) M x K, op(B) K x NC.  C may alias C0 but
-// not A or B.  C0 may be null (zero).
+// not A or B.  C0 may be null (zero).  Each lane computes a 2 x 4 block of C,
+// so every LDS word it loads feeds two or four multiply-adds.
 template <int LDN, int M, int K, int NC, bool TA, bool TB, typename R>
 PKS_DEV void mm(const R* A, const R* B, const R* C0, R sgn, R* C) {
   constexpr int L = ld<LDN>();
-  for (int e = lane(); e < M * NC; e += kWave) {
-    const int i = e / NC, j = e - i * NC;
-    R s = R(0);
-    PKS_UNROLL for (int k = 0; k < K; ++k) {
-      const R a = TA ? A[k * L + i] : A[i * L + k];
-      const R b = TB ? B[j * L + k] : B[k * L + j];
-      s = fma(a, b, s);
+  constexpr int TR = 2, TC = 4;
+  constexpr int MR = (M + TR - 1) / TR, MC = (NC + TC - 1) / TC;
+  for (int t = lane(); t < MR * MC; t += kWave) {
+    const int i0 = (t / MC) * TR, j0 = (t % MC) * TC;
+    R acc[TR][TC];
+    PKS_UNROLL for (int r = 0; r < TR; ++r) PKS_UNROLL for (int c = 0; c < TC; ++c) acc[r][c] = R(0);
+#pragma unroll 4
+    for (int k = 0; k < K; ++k) {
+      R a[TR], b[TC];
+      PKS_UNROLL for (int r = 0; r < TR; ++r) {
+        const int i = i0 + r;
+        a[r] = (M % TR == 0 || i < M) ? (TA ? A[k * L + i] : A[i * L + k]) : R(0);
+      }
+      PKS_UNROLL for (int c = 0; c < TC; ++c) {
+        const int j = j0 + c;
+        b[c] = (NC % TC == 0 || j < NC) ? (TB ? B[j * L + k] : B[k * L + j]) : R(0);
+      }
+      PKS_UNROLL for (int r = 0; r < TR; ++r) PKS_UNROLL for (int c = 0; c < TC; ++c)
+        acc[r][c] = fma(a[r], b[c], acc[r][c]);
     }
-    C[i * L + j] = (C0 ? C0[i * L + j] : R(0)) + sgn * s;
+    PKS_UNROLL for (int r = 0; r < TR; ++r) PKS_UNROLL for (int c = 0; c < TC; ++c) {
+      const int i = i0 + r, j = j0 + c;
+      if ((M % TR == 0 || i < M) && (NC % TC == 0 || j < NC))
+        C[i * L + j] = (C0 ? C0[i * L + j] : R(0)) + sgn * acc[r][c];
+    }
   }
   wsync();
 }
@@ -59,45 +76,61 @@ PKS_DEV void mv(const R* A, const R* x, const R* y0, R sgn, R* y) {
   wsync();
 }
 
+// Value of x in lane `src` (uniform), as a double.
+PKS_DEV double lane_value(double x, int src) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(int(v & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane(int(v >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // In-place lower Cholesky factor (true diagonal); the upper triangle is
 // cleared.  *ok (LDS) is cleared when a pivot is not positive; the factor then
-// holds NaN, which reaches the convergence statistic.
+// holds NaN, which reaches the convergence statistic.  Lane i keeps row i in
+// registers; column j takes the finished entries of row j from lane j with
+// cross-lane reads, so the whole factorisation touches LDS twice.
 template <int LDN, int N, typename R>
 PKS_DEV void chol(R* A, int* ok) {
+  static_assert(N <= kWave, "one row per lane");
   constexpr int L = ld<LDN>();
-  for (int j = 0; j < N; ++j) {
-    if (lane() == 0) {
-      R s = A[j * L + j];
-      for (int t = 0; t < j; ++t) s -= A[j * L + t] * A[j * L + t];
-      if (!(s > R(0))) *ok = 0;
-      A[j * L + j] = sqrt(s);
+  const int i = lane();
+  R row[N];
+  PKS_UNROLL for (int k = 0; k < N; ++k) row[k] = i < N ? A[i * L + k] : R(0);
+  bool good = true;
+  PKS_UNROLL for (int j = 0; j < N; ++j) {
+    R s0 = row[j], s1 = R(0);
+    PKS_UNROLL for (int t = 0; t < j; ++t) {
+      const R ljt = lane_value(row[t], j);
+      if (t & 1) s1 = fma(-row[t], ljt, s1);
+      else s0 = fma(-row[t], ljt, s0);
     }
-    wsync();
-    const R inv = R(1) / A[j * L + j];
-    for (int i = j + 1 + lane(); i < N; i += kWave) {
-      R s = A[i * L + j];
-      for (int t = 0; t < j; ++t) s -= A[i * L + t] * A[j * L + t];
-      A[i * L + j] = s * inv;
-    }
-    wsync();
+    const R s = s0 + s1;
+    const R d = lane_value(s, j);               // pivot of column j
+    good = good && d > R(0);
+    const R sd = sqrt(d);
+    row[j] = i == j ? sd : (i > j ? s / sd : R(0));
   }
-  for (int e = lane(); e < N * N; e += kWave) {
-    const int i = e / N, j = e - i * N;
-    if (j > i) A[i * L + j] = R(0);
+  if (i < N) {
+    PKS_UNROLL for (int k = 0; k < N; ++k) A[i * L + k] = k <= i ? row[k] : R(0);
   }
+  if (i == 0 && !good) *ok = 0;
   wsync();
 }
 
-// B <- Lc^-1 B (forward substitution), Lc N x N lower, B N x NC; lane per column.
+// B <- Lc^-1 B (forward substitution), Lc N x N lower, B N x NC; lane per
+// column, the column kept in registers.
 template <int LDN, int N, int NC, typename R>
 PKS_DEV void fwd(const R* Lc, R* B) {
   constexpr int L = ld<LDN>();
   for (int c = lane(); c < NC; c += kWave) {
-    for (int i = 0; i < N; ++i) {
-      R s = B[i * L + c];
-      for (int t = 0; t < i; ++t) s -= Lc[i * L + t] * B[t * L + c];
-      B[i * L + c] = s / Lc[i * L + i];
+    R x[N];
+    PKS_UNROLL for (int i = 0; i < N; ++i) x[i] = B[i * L + c];
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      R s = x[i];
+      PKS_UNROLL for (int t = 0; t < i; ++t) s = fma(-Lc[i * L + t], x[t], s);
+      x[i] = s / Lc[i * L + i];
     }
+    PKS_UNROLL for (int i = 0; i < N; ++i) B[i * L + c] = x[i];
   }
   wsync();
 }
@@ -107,25 +140,32 @@ template <int LDN, int N, int NC, typename R>
 PKS_DEV void bwd(const R* Lc, R* B) {
   constexpr int L = ld<LDN>();
   for (int c = lane(); c < NC; c += kWave) {
-    for (int i = N - 1; i >= 0; --i) {
-      R s = B[i * L + c];
-      for (int t = i + 1; t < N; ++t) s -= Lc[t * L + i] * B[t * L + c];
-      B[i * L + c] = s / Lc[i * L + i];
+    R x[N];
+    PKS_UNROLL for (int i = 0; i < N; ++i) x[i] = B[i * L + c];
+    PKS_UNROLL for (int i = N - 1; i >= 0; --i) {
+      R s = x[i];
+      PKS_UNROLL for (int t = i + 1; t < N; ++t) s = fma(-Lc[t * L + i], x[t], s);
+      x[i] = s / Lc[i * L + i];
     }
+    PKS_UNROLL for (int i = 0; i < N; ++i) B[i * L + c] = x[i];
   }
   wsync();
 }
 
-// x <- Lc^-1 x for one vector (lane 0; N is small).
+// x <- Lc^-1 x for one vector (lane 0, in registers).
 template <int LDN, int N, typename R>
 PKS_DEV void fwd_vec(const R* Lc, R* x) {
   constexpr int L = ld<LDN>();
-  if (lane() == 0)
-    for (int i = 0; i < N; ++i) {
-      R s = x[i];
-      for (int t = 0; t < i; ++t) s -= Lc[i * L + t] * x[t];
-      x[i] = s / Lc[i * L + i];
+  if (lane() == 0) {
+    R y[N];
+    PKS_UNROLL for (int i = 0; i < N; ++i) y[i] = x[i];
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      R s = y[i];
+      PKS_UNROLL for (int t = 0; t < i; ++t) s = fma(-Lc[i * L + t], y[t], s);
+      y[i] = s / Lc[i * L + i];
     }
+    PKS_UNROLL for (int i = 0; i < N; ++i) x[i] = y[i];
+  }
   wsync();
 }
 
@@ -218,11 +258,12 @@ struct Layout {
   static_assert(kSElem <= kFElem, "smoothing elements reuse the filtering element records");
 };
 
-// LDS work area of one wave.
-template <int N, typename R>
+// LDS work area of one wave: NM matrices of N x N (names per kernel), sized
+// per kernel so that light kernels keep more waves resident.
+template <int N, typename R, int NM>
 struct Work {
   static constexpr int MW = mat_words<N>();
-  R m[9][MW];      // nine N x N matrices (names per kernel)
+  R m[NM][MW];
   R v[8][N];       // vectors
   int ok;
 };
@@ -429,8 +470,9 @@ template <class Model, typename R>
 struct Dense {
   static constexpr int N = Model::N, P = Model::P;
   using Lay = Layout<N, P>;
-  using W = Work<N, R>;
-  static constexpr int MW = W::MW;
+  using W = Work<N, R, 9>;
+  template <int NM>
+  using WorkN = Work<N, R, NM>;
 
   // element a_s into (A, b, C, eta, J) in the given LDS buffers
   static PKS_DEV void build_element(const DnArgs& a, int64_t s, W& w, R* A, R* b, R* C, R* e, R* J) {
@@ -535,7 +577,7 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
   using D = Dense<Model, R>;
   constexpr int N = D::N, P = D::P;
   using Lay = typename D::Lay;
-  __shared__ typename D::W w;
+  __shared__ typename D::template WorkN<6> w;
   const int64_t s = blockIdx.x;
   if (s >= a.S) return;
   if (lane() == 0) w.ok = 1;
@@ -619,7 +661,7 @@ __global__ __launch_bounds__(kWave) void k_dn_scan_up(DnArgs a, DnLevel lv) {
   constexpr int N = D::N;
   using Lay = typename D::Lay;
   constexpr int RW = FILT ? Lay::kFElem : Lay::kSElem;
-  __shared__ typename D::W w;
+  __shared__ typename D::template WorkN<FILT ? 9 : 6> w;
   if (lane() == 0) w.ok = 1;
   const int64_t i0 = int64_t(blockIdx.x) * lv.fan;
   const int64_t i1 = min(i0 + lv.fan, lv.n);
@@ -654,7 +696,7 @@ __global__ __launch_bounds__(kWave) void k_dn_scan_down(DnArgs a, DnLevel lv) {
   constexpr int N = D::N;
   using Lay = typename D::Lay;
   constexpr int RW = FILT ? Lay::kFElem : Lay::kSElem;
-  __shared__ typename D::W w;
+  __shared__ typename D::template WorkN<7> w;
   if (lane() == 0) w.ok = 1;
   const int64_t c = blockIdx.x;
   const int64_t i0 = c * lv.fan;
@@ -662,7 +704,7 @@ __global__ __launch_bounds__(kWave) void k_dn_scan_down(DnArgs a, DnLevel lv) {
   const int64_t nchunks = (lv.n + lv.fan - 1) / lv.fan;
   const R* in = static_cast<const R*>(lv.in);
   R* cout = static_cast<R*>(lv.carry_out);
-  R *cx = w.v[6], *cP = w.m[8];
+  R *cx = w.v[6], *cP = w.m[6];
   R *rA = w.m[0], *rC = w.m[1], *rJ = w.m[2], *rb = w.v[0], *re = w.v[1];
   bool have = FILT ? c > 0 : c < nchunks - 1;
   if (have) D::load_carry(static_cast<const R*>(lv.carry_in) + size_t(c) * Lay::kCarry, cx, cP);
@@ -771,17 +813,24 @@ __global__ __launch_bounds__(kWave) void k_dn_backward_down(DnArgs a, int fan, c
   using D = Dense<Model, R>;
   constexpr int N = D::N;
   using Lay = typename D::Lay;
-  __shared__ typename D::W w;
+  __shared__ typename D::template WorkN<4> w;
   __shared__ R dmax[kWave];
   if (lane() == 0) w.ok = 1;
   const int64_t c = blockIdx.x;
   const int64_t s0 = c * fan;
   const int64_t s1 = min(s0 + fan, a.S);
   const int64_t nchunks = (a.S + fan - 1) / fan;
-  R *cx = w.v[6], *cP = w.m[8];
+  R *cx = w.v[6], *cP = w.m[3];
   R *rE = w.m[0], *rL = w.m[1], *rg = w.v[0];
   bool have = c < nchunks - 1;
   if (have) D::load_carry(static_cast<const R*>(carry_in) + size_t(c) * Lay::kCarry, cx, cP);
+  // running largest change of the current track segment of this chunk (lane 0);
+  // published once per segment, and only when it exceeds the stored value
+  int seg_track = -1;
+  unsigned long long seg_bits = 0ull, all_bits = 0ull;
+  auto publish = [&](unsigned long long* p, unsigned long long v) {
+    if (v > *static_cast<volatile unsigned long long*>(p)) atomicMax(p, v);
+  };
   for (int64_t k = 0; k < s1 - s0; ++k) {
     const int64_t s = s1 - 1 - k;
     D::load_selem(static_cast<const R*>(a.elem) + size_t(s) * Lay::kFElem, rE, rg, rL);
@@ -811,10 +860,20 @@ __global__ __launch_bounds__(kWave) void k_dn_backward_down(DnArgs a, int fan, c
         mx = dmax[i] > mx ? dmax[i] : mx;
       }
       const unsigned long long bits = order_bits(bad ? __builtin_nan("") : double(mx));
-      atomicMax(&a.delta_bits[a.track[s]], bits);
-      atomicMax(&a.delta_bits[a.ntracks], bits);
+      const int tr = a.track[s];
+      if (tr != seg_track) {
+        if (seg_track >= 0) publish(&a.delta_bits[seg_track], seg_bits);
+        seg_track = tr;
+        seg_bits = 0ull;
+      }
+      seg_bits = bits > seg_bits ? bits : seg_bits;
+      all_bits = bits > all_bits ? bits : all_bits;
     }
     wsync();
+  }
+  if (lane() == 0 && seg_track >= 0) {
+    publish(&a.delta_bits[seg_track], seg_bits);
+    publish(&a.delta_bits[a.ntracks], all_bits);
   }
 }
 
