@@ -239,8 +239,9 @@ class Engine final : public EngineBase {
     return SM_OK;
   }
 
-  size_t lds_filter() const { return sizeof(R) * FOp::kElemWords * sched_.B; }
-  size_t lds_smoother() const { return sizeof(R) * SOp::kElemWords * sched_.B; }
+  // the ladders keep one element per wavefront in LDS
+  size_t lds_filter() const { return sizeof(R) * FOp::kElemWords * (sched_.B / 64); }
+  size_t lds_smoother() const { return sizeof(R) * SOp::kElemWords * (sched_.B / 64); }
 
   template <int B>
   hipError_t set_lds_limits_b() {
@@ -259,10 +260,10 @@ class Engine final : public EngineBase {
     hipError_t e = sched_.B == 64 ? set_lds_limits_b<64>() : set_lds_limits_b<256>();
     if (e == hipSuccess)
       e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_single<FOp, kTopB, R>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(R) * FOp::kElemWords * kTopB));
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(R) * FOp::kElemWords * (kTopB / 64)));
     if (e == hipSuccess)
       e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_single<SOp, kTopB, R>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(R) * SOp::kElemWords * kTopB));
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(R) * SOp::kElemWords * (kTopB / 64)));
     return e;
   }
 
@@ -322,7 +323,7 @@ class Engine final : public EngineBase {
   // Generic multi-level scan of `m` elements stored in scan order (tile aggregates).
   template <class Op>
   void run_scan(const void* elems, int64_t m, void* out, const char* const (&names)[3]) {
-    const size_t lds = sizeof(R) * Op::kElemWords * kScanB;
+    const size_t lds = sizeof(R) * Op::kElemWords * (kScanB / 64);
     const int L = int(levels_.size());
     for (int l = 0; l + 1 < L; ++l) {
       const ScanLevel& lv = levels_[l];
@@ -386,7 +387,7 @@ class Engine final : public EngineBase {
     a.out = carry;
     a.ostride = size_t(tiles_);
     timed(names[1], tiles_, [&] {
-      hipLaunchKernelGGL((k_scan_single<Op, kTopB, R>), dim3(1), dim3(kTopB), sizeof(R) * Op::kElemWords * kTopB,
+      hipLaunchKernelGGL((k_scan_single<Op, kTopB, R>), dim3(1), dim3(kTopB), sizeof(R) * Op::kElemWords * (kTopB / 64),
                          stream, a);
     });
   }

@@ -180,12 +180,10 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
     Op::combine(acc, e, r);
     acc = r;
   }
-  block_ladder<Op, B, R>(lds, lane, true, acc);
-  if (lane > 0) {
-    typename Op::Elem ex;
-    Op::load(lds, B, lane - 1, ex);
-    Op::store(static_cast<R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
-  }
+  typename Op::Elem ex;
+  bool has_ex;
+  block_ladder<Op, B, true, R>(lds, acc, ex, has_ex);
+  if (has_ex) Op::store(static_cast<R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
   if (lane == B - 1) Op::store(static_cast<R*>(a.ta_f), size_t(a.tiles), tile, acc);
 }
 
@@ -263,15 +261,12 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
       sacc = r;
     }
   }
-  __syncthreads();  // the forward carries above read no LDS, but the ladder reuses it
   const int rl = B - 1 - lane;
   const int64_t rt = a.tiles - 1 - tile;
-  block_ladder<SOp, B, R>(lds, rl, true, sacc);
-  if (rl > 0) {
-    typename SOp::Elem ex;
-    SOp::load(lds, B, rl - 1, ex);
-    SOp::store(static_cast<R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, ex);
-  }
+  typename SOp::Elem ex;
+  bool has_ex;
+  block_ladder<SOp, B, false, R>(lds, sacc, ex, has_ex);
+  if (has_ex) SOp::store(static_cast<R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, ex);
   if (rl == B - 1) SOp::store(static_cast<R*>(a.ta_s), size_t(a.tiles), rt, sacc);
 }
 

@@ -68,6 +68,20 @@ struct FilterOp {
     st_vec<N>(p, st, i, c.b);
     st_sym<N>(p + N * st, st, i, c.C);
   }
+  // o = e of lane src of this wavefront; every lane must take part.  The
+  // symmetric blocks move their upper triangles only.
+  static PKS_DEV void shfl(const Elem& e, int src, Elem& o) {
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      o.b[i] = __shfl(e.b[i], src);
+      o.eta[i] = __shfl(e.eta[i], src);
+      PKS_UNROLL for (int j = 0; j < N; ++j) o.A[i][j] = __shfl(e.A[i][j], src);
+      PKS_UNROLL for (int j = i; j < N; ++j) {
+        o.C[i][j] = o.C[j][i] = __shfl(e.C[i][j], src);
+        o.J[i][j] = o.J[j][i] = __shfl(e.J[i][j], src);
+      }
+    }
+  }
+
   // A carry-form element (prior element or a prefix from one): take (b, C).
   static PKS_DEV void to_carry(const Elem& e, Carry& c) {
     PKS_UNROLL for (int i = 0; i < N; ++i) {
@@ -202,6 +216,13 @@ struct SmootherOp {
   static PKS_DEV void store(R* p, size_t st, size_t i, const Carry& c) {
     st_vec<N>(p, st, i, c.g);
     st_sym<N>(p + N * st, st, i, c.L);
+  }
+  static PKS_DEV void shfl(const Elem& e, int src, Elem& o) {
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      o.g[i] = __shfl(e.g[i], src);
+      PKS_UNROLL for (int j = 0; j < N; ++j) o.E[i][j] = __shfl(e.E[i][j], src);
+      PKS_UNROLL for (int j = i; j < N; ++j) o.L[i][j] = o.L[j][i] = __shfl(e.L[i][j], src);
+    }
   }
   static PKS_DEV void to_carry(const Elem& e, Carry& c) {
     PKS_UNROLL for (int i = 0; i < N; ++i) {

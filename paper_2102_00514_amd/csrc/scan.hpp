@@ -35,26 +35,55 @@ struct ScanArgs {
   size_t ostride;
 };
 
-// Kogge-Stone over the lanes of a block.  On entry v holds the lane aggregate
-// (valid lanes only); on exit v holds the inclusive prefix over lanes 0..lane
-// and the LDS rows hold the same values.
-template <class Op, int B, typename R>
-PKS_DEV void block_ladder(R* lds, int lane, bool valid, typename Op::Elem& v) {
-  if (valid) Op::store(lds, B, lane, v);
-  __syncthreads();
-  PKS_UNROLL for (int d = 1; d < B; d <<= 1) {
-    typename Op::Elem left, res;
-    const bool act = valid && lane >= d;
-    if (act) {
-      Op::load(lds, B, lane - d, left);
-      Op::combine(left, v, res);
+// Inclusive scan of the B lane values of a block.  Scan position q = lane
+// (FWD) or B-1-lane (reverse).  Inside a wavefront the Kogge-Stone steps move
+// elements with cross-lane shuffles (no LDS, no barriers); across wavefronts
+// (B > 64) only each wavefront's total goes through LDS: lds holds B/64
+// elements, entry-major with row stride B/64.  On exit v is the inclusive
+// prefix at q and, when has_ex (q > 0), ex the exclusive one.  Invalid lanes
+// must form a suffix of the scan order: no valid lane reads their values.
+template <class Op, int B, bool FWD, typename R>
+PKS_DEV void block_ladder(R* lds, typename Op::Elem& v, typename Op::Elem& ex, bool& has_ex) {
+  constexpr int NW = B / 64;
+  static_assert(B % 64 == 0, "whole wavefronts");
+  const int pl = int(threadIdx.x), wl = pl & 63, w = pl >> 6;
+  const int qw = FWD ? wl : 63 - wl;        // scan position inside the wavefront
+  const int qwave = FWD ? w : NW - 1 - w;   // scan position of the wavefront
+  PKS_UNROLL for (int d = 1; d < 64; d <<= 1) {
+    typename Op::Elem left;
+    const int src = FWD ? (wl >= d ? wl - d : wl) : (wl + d < 64 ? wl + d : wl);
+    Op::shfl(v, src, left);
+    if (qw >= d) {
+      typename Op::Elem r;
+      Op::combine(left, v, r);
+      v = r;
     }
+  }
+  typename Op::Elem wp;   // total of the wavefronts before this one (qwave > 0)
+  if constexpr (NW > 1) {
+    if (qw == 63) Op::store(lds, NW, qwave, v);
     __syncthreads();
-    if (act) {
-      v = res;
-      Op::store(lds, B, lane, v);
+    if (qwave > 0) {
+      Op::load(lds, NW, 0, wp);
+      for (int k = 1; k < qwave; ++k) {
+        typename Op::Elem t, r;
+        Op::load(lds, NW, k, t);
+        Op::combine(wp, t, r);
+        wp = r;
+      }
+      typename Op::Elem r;
+      Op::combine(wp, v, r);
+      v = r;
     }
-    __syncthreads();
+  }
+  const int src = FWD ? (wl > 0 ? wl - 1 : wl) : (wl < 63 ? wl + 1 : wl);
+  Op::shfl(v, src, ex);
+  has_ex = qw > 0;
+  if constexpr (NW > 1) {
+    if (qw == 0 && qwave > 0) {
+      ex = wp;
+      has_ex = true;
+    }
   }
 }
 
@@ -67,7 +96,7 @@ __global__ __launch_bounds__(B) void k_scan_up(ScanArgs a) {
   const int64_t tile = blockIdx.x;
   const int64_t first = (tile * B + lane) * a.K;
   const bool valid = first < a.m;
-  typename Op::Elem v;
+  typename Op::Elem v{};   // invalid lanes feed the ladder zeros
   if (valid) {
     const int64_t idx0 = a.reverse ? a.m - 1 - first : first;
     Op::load(E, a.estride, idx0, v);
@@ -80,13 +109,11 @@ __global__ __launch_bounds__(B) void k_scan_up(ScanArgs a) {
       v = r;
     }
   }
-  block_ladder<Op, B, R>(lds, lane, valid, v);
+  typename Op::Elem ex;
+  bool has_ex;
+  block_ladder<Op, B, true, R>(lds, v, ex, has_ex);
   R* LX = static_cast<R*>(a.lane_excl);
-  if (valid && lane > 0) {
-    typename Op::Elem ex;
-    Op::load(lds, B, lane - 1, ex);
-    Op::store(LX, a.lstride, tile * B + lane, ex);
-  }
+  if (valid && has_ex) Op::store(LX, a.lstride, tile * B + lane, ex);
   // last valid lane of the tile publishes the tile aggregate
   const int64_t rem = a.m - tile * B * (int64_t)a.K;
   const int64_t nvalid = (rem + a.K - 1) / a.K;
@@ -151,7 +178,7 @@ PKS_DEV void block_scan(R* lds, int lane, const R* E, size_t estride, int64_t m,
   const int K = int((m + B - 1) / B);
   const int64_t first = (int64_t)lane * K;
   const bool valid = first < m;
-  typename Op::Elem v;
+  typename Op::Elem v{};   // invalid lanes feed the ladder zeros
   if (valid) {
     Op::load(E, estride, reverse ? m - 1 - first : first, v);
     for (int j = 1; j < K; ++j) {
@@ -163,13 +190,13 @@ PKS_DEV void block_scan(R* lds, int lane, const R* E, size_t estride, int64_t m,
       v = r;
     }
   }
-  block_ladder<Op, B, R>(lds, lane, valid, v);
+  typename Op::Elem ex;
+  bool has_ex;
+  block_ladder<Op, B, true, R>(lds, v, ex, has_ex);
   if (!valid) return;
   typename Op::Carry c;
   bool have = false;
-  if (lane > 0) {
-    typename Op::Elem ex;
-    Op::load(lds, B, lane - 1, ex);
+  if (has_ex) {
     Op::to_carry(ex, c);
     have = true;
   }
