@@ -89,8 +89,11 @@ def _check(rc, what):
 
 def smoother(pb, M: int, lin: str = "taylor", alpha: float = 1.0, beta: float = 0.0,
              kappa: float = 1.0, init_mean=None, init_cov=None, precision: str = "f64",
-             history: bool = False, filtered: bool = True) -> dict:
+             history: bool = False, filtered: bool = True, lm_lambda: float = 0.0) -> dict:
     """Iterated smoother on a single-track ``workloads.Problem``.
+
+    lm_lambda > 0: Levenberg-Marquardt damping, each iteration observes the
+    previous iterate as a pseudo-measurement with covariance I / lm_lambda.
 
     Returns mean [T+1, nx], cov [T+1, nx, nx], filt_mean/filt_cov (last
     iteration's filter), deltas [M] and, with ``history``, every iterate."""
@@ -115,7 +118,8 @@ def smoother(pb, M: int, lin: str = "taylor", alpha: float = 1.0, beta: float = 
         ctypes.c_double(alpha), ctypes.c_double(beta), ctypes.c_double(kappa),
         _ptr(im), _ptr(ic), _ptr(out["mean"]), _ptr(out["cov"]),
         _ptr(out.get("filt_mean")), _ptr(out.get("filt_cov")),
-        _ptr(out.get("hist_mean")), _ptr(out.get("hist_cov")), _ptr(out["deltas"]))
+        _ptr(out.get("hist_mean")), _ptr(out.get("hist_cov")), _ptr(out["deltas"]),
+        ctypes.c_double(lm_lambda))
     _check(rc, "orc_smoother")
     out["deltas"] = out["deltas"][:M]
     return out

@@ -430,11 +430,39 @@ typedef struct {
     real *yt;             /* slots 1..T (index k-1): unwrapped measurement */
 } linpass_t;
 
-static int kf_rts(const linpass_t *lp, const real *m0, const real *P0,
+/*
+ * Levenberg-Marquardt damping of the Gauss-Newton step (Section 3 remark on
+ * IEKS as Gauss-Newton and its Levenberg-Marquardt extension): the previous
+ * iterate xbar_k is observed as a pseudo-measurement z = x_k + v,
+ * v ~ N(0, I / lam), which adds (lam / 2) |x_k - xbar_k|^2 to the MAP
+ * objective of every slot.  Kalman update of (m, P) with H = I, R = I / lam.
+ */
+static int lm_update(int n, real *m, real *P, const real *z, real lam) {
+    real S[NMAX * NMAX], L[NMAX * NMAX], Kt[NMAX * NMAX], KP[NMAX * NMAX];
+    memcpy(S, P, sizeof(real) * n * n);
+    for (int i = 0; i < n; ++i) S[i * n + i] += 1 / lam;
+    if (chol(n, S, L)) return ORC_ENUMERIC;
+    memcpy(Kt, P, sizeof(real) * n * n);          /* K^T = S^-1 P (P symmetric) */
+    chol_solve(n, L, Kt, n);
+    real e[NMAX];
+    for (int i = 0; i < n; ++i) e[i] = z[i] - m[i];
+    for (int i = 0; i < n; ++i) {
+        real s = m[i];
+        for (int j = 0; j < n; ++j) s += Kt[j * n + i] * e[j];
+        m[i] = s;
+    }
+    mtm(n, n, n, Kt, P, KP);                      /* K P = (S^-1 P)^T P */
+    for (int i = 0; i < n * n; ++i) P[i] -= KP[i];
+    symmetrize(n, P);
+    return ORC_OK;
+}
+
+static int kf_rts(const linpass_t *lp, const real *m0, const real *P0, real lam, const real *xbar,
                   real *xf, real *Pf, real *xs, real *Ps) {
     int n = lp->n, p = lp->p, T = lp->T;
     memcpy(xf, m0, sizeof(real) * n);
     memcpy(Pf, P0, sizeof(real) * n * n);
+    if (lam > 0 && lm_update(n, xf, Pf, xbar, lam)) return ORC_ENUMERIC;
     real mp[NMAX], Pp[NMAX * NMAX], tmp[NMAX * NMAX], S[NMAX * NMAX], L[NMAX * NMAX];
     real PHt[NMAX * NMAX], K[NMAX * NMAX], v[NMAX], Hm[NMAX], KS[NMAX * NMAX], KSK[NMAX * NMAX];
     for (int k = 1; k <= T; ++k) {
@@ -470,6 +498,7 @@ static int kf_rts(const linpass_t *lp, const real *m0, const real *P0,
         mm(n, p, n, KS, K, KSK);                  /* K S K^T */
         for (int i = 0; i < n * n; ++i) Pk[i] = Pp[i] - KSK[i];
         symmetrize(n, Pk);
+        if (lam > 0 && lm_update(n, mk, Pk, xbar + k * n, lam)) return ORC_ENUMERIC;
     }
     memcpy(xs + T * n, xf + T * n, sizeof(real) * n);
     memcpy(Ps + T * n * n, Pf + T * n * n, sizeof(real) * n * n);
@@ -556,6 +585,7 @@ static int linearize_traj(const model_t *md, int lin, real alpha, real kappa, co
  *   filt_mean, filt_cov (same shapes)     filtered result of the last iteration;
  *   hist_mean [M][T+1][nx], hist_cov [M][T+1][nx][nx]  every iterate;
  *   deltas [M]   max_k,j |xbar^(i) - xbar^(i-1)|.
+ * lm_lambda > 0 damps every iteration by the pseudo-measurement of lm_update.
  * Returns 0, 1 (invalid argument) or 4 (a Cholesky factorisation failed).
  */
 int SFX(orc_smoother)(int nx, int ny, int T, int model, const double *params, int n_params,
@@ -563,10 +593,10 @@ int SFX(orc_smoother)(int nx, int ny, int T, int model, const double *params, in
                       const double *y, int M, int lin, double alpha, double beta, double kappa,
                       const double *init_mean, const double *init_cov,
                       double *mean, double *cov, double *filt_mean, double *filt_cov,
-                      double *hist_mean, double *hist_cov, double *deltas) {
+                      double *hist_mean, double *hist_cov, double *deltas, double lm_lambda) {
     (void)beta;
     model_t md;
-    if (T < 0 || M < 0 || lin < 0 || lin > 2) return ORC_EINVAL;
+    if (T < 0 || M < 0 || lin < 0 || lin > 2 || !(lm_lambda >= 0)) return ORC_EINVAL;
     int rc = model_setup(&md, model, params, n_params, nx, ny);
     if (rc) return rc;
     int n = nx, p = ny;
@@ -594,7 +624,7 @@ int SFX(orc_smoother)(int nx, int ny, int T, int model, const double *params, in
     for (int it = 0; it < M; ++it) {
         rc = linearize_traj(&md, lin, (real)alpha, (real)kappa, Qr, Rr, yy, xb, Pb, &lp);
         if (rc) goto done;
-        rc = kf_rts(&lp, m0r, P0r, xf, Pf, xs, Ps);
+        rc = kf_rts(&lp, m0r, P0r, (real)lm_lambda, xb, xf, Pf, xs, Ps);
         if (rc) goto done;
         real dmax = 0;
         for (size_t i = 0; i < S * n; ++i) {
@@ -722,7 +752,7 @@ int SFX(orc_kf_rts)(int nx, int ny, int T, const double *F, const double *c, con
     load(lp.F, F, T * n * n); load(lp.c, c, T * n); load(lp.Qp, Qp, T * n * n);
     load(lp.H, H, T * p * n); load(lp.d, d, T * p); load(lp.Rp, Rp, T * p * p); load(lp.yt, yt, T * p);
     load(m0r, m0, n); load(P0r, P0, n * n);
-    rc = kf_rts(&lp, m0r, P0r, a, b, e, f);
+    rc = kf_rts(&lp, m0r, P0r, 0, NULL, a, b, e, f);
     if (rc) goto done;
     store(xf, a, (int)(S * n)); store(Pf, b, (int)(S * n * n));
     store(xs, e, (int)(S * n)); store(Ps, f, (int)(S * n * n));

@@ -128,11 +128,13 @@ def map_residual(pb, f, h, angular):
     return r
 
 
-def gauss_newton(pb, f, h, angular, x_init, iters):
-    """Dense Gauss-Newton on the MAP objective over x_{0:T}.
+def gauss_newton(pb, f, h, angular, x_init, iters, lam=0.0):
+    """Dense Gauss-Newton on the MAP objective over x_{0:T}; with lam > 0 each
+    step is Levenberg-Marquardt damped: the rows sqrt(lam) (x - x_lin) are
+    appended to the linearised residual.
 
     Returns the list of iterates and, for each step, the marginal covariances
-    (diagonal blocks of (J^T J)^-1 at the linearisation point)."""
+    (diagonal blocks of (J^T J + lam I)^-1 at the linearisation point)."""
     n = pb.nx
     T = int(pb.offsets[1])
     r = map_residual(pb, f, h, angular)
@@ -141,6 +143,9 @@ def gauss_newton(pb, f, h, angular, x_init, iters):
     for _ in range(iters):
         J = cs_jacobian(r, x)
         res = r(x)
+        if lam > 0:
+            J = np.vstack([J, np.sqrt(lam) * np.eye(x.size)])
+            res = np.concatenate([res, np.zeros(x.size)])
         step, *_ = np.linalg.lstsq(J, -res, rcond=None)
         x = x + step
         Qf, Rf = np.linalg.qr(J)

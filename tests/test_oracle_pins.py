@@ -293,6 +293,39 @@ def test_stacked_sigma_points_couple_targets(orc, lin, kw):
 
 
 # ---------------------------------------------------------------------------------------
+# Levenberg-Marquardt damping: the damped IEKS iterates equal damped dense Gauss-Newton,
+# vanish into the IEKS as lam -> 0, and share its fixed point.
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [0.5, 20.0])
+def test_lm_iterates_equal_damped_gauss_newton(orc, lam):
+    T, M = 8, 4
+    pb = wl.ct_bearings(T, seed=3)
+    f, h = ph.ct_model_funcs(pb)
+    x_init = np.broadcast_to(pb.m0[0], (T + 1, 5)).copy()
+    xs, covs = ph.gauss_newton(pb, f, h, True, x_init, M, lam=lam)
+    r = orc.smoother(pb, M, "taylor", history=True, lm_lambda=lam)
+    for i in range(M):
+        assert orc.mean_error(r["hist_mean"][i], xs[i]) < 1e-9, i
+        assert orc.cov_error(r["hist_cov"][i], covs[i]) < 1e-8, i
+
+
+def test_lm_small_lambda_is_ieks(orc):
+    pb = wl.config_c1()
+    a = orc.smoother(pb, 5, "cubature")
+    b = orc.smoother(pb, 5, "cubature", lm_lambda=1e-13)
+    assert orc.mean_error(a["mean"], b["mean"]) < 1e-9
+    assert orc.cov_error(a["cov"], b["cov"]) < 1e-9
+
+
+def test_lm_fixed_point_is_the_ieks_fixed_point(orc):
+    pb = wl.config_c1()
+    plain = orc.smoother(pb, 40, "taylor")
+    damped = orc.smoother(pb, 120, "taylor", lm_lambda=0.1)
+    assert plain["deltas"][-1] < 1e-10 and damped["deltas"][-1] < 1e-10
+    assert orc.mean_error(damped["mean"], plain["mean"]) < 1e-8
+
+
+# ---------------------------------------------------------------------------------------
 # Pin 8 -- the oracle's own rounding error (double vs long double).
 # ---------------------------------------------------------------------------------------
 @pytest.mark.parametrize("lin", ["taylor", "cubature"])
