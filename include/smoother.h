@@ -112,11 +112,18 @@ typedef struct {
   int32_t lane_slots;             /* scan schedule: consecutive slots per lane (1..8; 0 = auto) */
   int32_t use_graph;              /* 1: iterations of the parallel path are replayed from a HIP graph
                                      captured on the first call; 0: launched one kernel at a time */
+  double lm_lambda;               /* Levenberg-Marquardt damping (Section 3, damped Gauss-Newton
+                                     extension): >= 0, finite; 0 = the undamped iterated smoother.
+                                     Each iteration also observes every state x_k of every track
+                                     through x_k + r, r ~ N(0, I/lm_lambda), with the previous
+                                     iterate xbar_k as the value: this adds (lm_lambda/2)|x_k - xbar_k|^2
+                                     to the objective.  Fixed points are those of the undamped
+                                     smoother.  Every engine and scan mode supports it. */
 } sm_problem;
 
 /* Fills *pb with defaults: n_tracks = 1, n_iter = 10, lin = SM_LIN_TAYLOR,
  * ut_alpha = 1, ut_beta = 0, ut_kappa = 1, FP64, parallel scan, no init, no cap,
- * automatic scan schedule, HIP-graph replay. */
+ * automatic scan schedule, HIP-graph replay, no damping. */
 void smoother_problem_defaults(sm_problem* pb);
 
 /* Validates the problem on the host (dimensions supported by the compiled

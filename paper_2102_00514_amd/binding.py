@@ -47,6 +47,7 @@ class sm_problem(ctypes.Structure):
         ("max_device_bytes", ctypes.c_int64),
         ("tile_lanes", ctypes.c_int32), ("lane_slots", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
+        ("lm_lambda", ctypes.c_double),
     ]
 
 
@@ -135,7 +136,7 @@ def smoother_last_error(h=None) -> str:
 def make_problem(pb: Problem, n_iter: int = 10, lin: str = "taylor", precision: str = "f64",
                  scan: str = "parallel", init_mean=None, init_cov=None, ut_alpha=1.0, ut_beta=0.0,
                  ut_kappa=1.0, max_device_bytes: int = 0, tile_lanes: int = 0, lane_slots: int = 0,
-                 use_graph: bool = True):
+                 use_graph: bool = True, lm_lambda: float = 0.0):
     """sm_problem for a workloads.Problem; returns (struct, keep-alive arrays)."""
     s = sm_problem()
     _lib.smoother_problem_defaults(ctypes.byref(s))
@@ -166,6 +167,7 @@ def make_problem(pb: Problem, n_iter: int = 10, lin: str = "taylor", precision: 
     s.max_device_bytes = max_device_bytes
     s.tile_lanes, s.lane_slots = tile_lanes, lane_slots
     s.use_graph = int(bool(use_graph))
+    s.lm_lambda = lm_lambda
     return s, keep
 
 

@@ -455,6 +455,7 @@ struct DnArgs {
   void* hlin;                   // [slot][kHlin]
   void* elem;                   // [slot][kFElem]; smoothing elements reuse it
   unsigned long long* delta_bits;
+  double lm;                    // Levenberg-Marquardt damping lambda (0 = undamped)
 };
 
 struct DnLevel {
@@ -485,6 +486,7 @@ struct Dense {
       ld_full<N, N, N>(static_cast<const R*>(a.P0) + size_t(tr) * N * N, C);
       for (int i = lane(); i < N; i += kWave) e[i] = R(0);
       wsync();
+      if (a.lm > 0.0) lm_damp(a, s, w, A, b, C, e, J);
       return;
     }
     // transition out of slot s - 1, measurement at slot s
@@ -525,6 +527,43 @@ struct Dense {
     copy<N, N, N, false>(H, A);
     copy<N, N, N, false>(F, C);
     copy<N, N, N, false>(Qp, J);
+    symmetrize<N, N>(C);
+    symmetrize<N, N>(J);
+    if (a.lm > 0.0) lm_damp(a, s, w, A, b, C, e, J);
+  }
+
+  // Levenberg-Marquardt damping of the element of slot s (Section 3, damped
+  // Gauss-Newton extension): the previous iterate xbar_s is observed through
+  // x_s with noise covariance I/lambda.  With G = I + lambda C = L L^T,
+  // Z = L^-1 C, V = L^-1 A, v = L^-1 (xbar - b):
+  //   A -= lambda Z^T V,  b += lambda Z^T v,  C -= lambda Z^T Z,
+  //   J += lambda V^T V,  eta += lambda V^T v.
+  // Scratch: w.m[6..8], w.v[4] (free once the element is built).
+  static PKS_DEV void lm_damp(const DnArgs& a, int64_t s, W& w, R* A, R* b, R* C, R* e, R* J) {
+    constexpr int L = ld<N>();
+    const R lam = R(a.lm);
+    const R* xbar = static_cast<const R*>(a.traj) + size_t(s) * Lay::kTraj;
+    R* G = w.m[6];
+    R* Z = w.m[7];
+    R* V = w.m[8];
+    R* v = w.v[4];
+    for (int t = lane(); t < N * N; t += kWave) {
+      const int i = t / N, j = t - i * N;
+      G[i * L + j] = lam * C[i * L + j] + (i == j ? R(1) : R(0));
+      Z[i * L + j] = C[i * L + j];
+      V[i * L + j] = A[i * L + j];
+    }
+    for (int i = lane(); i < N; i += kWave) v[i] = xbar[i] - b[i];
+    wsync();
+    chol<N, N>(G, &w.ok);
+    fwd<N, N, N>(G, Z);
+    fwd<N, N, N>(G, V);
+    fwd_vec<N, N>(G, v);
+    mv<N, N, N, true>(Z, v, b, lam, b);
+    mv<N, N, N, true>(V, v, e, lam, e);
+    mm<N, N, N, N, true, false>(Z, V, A, -lam, A);
+    mm<N, N, N, N, true, false>(Z, Z, C, -lam, C);
+    mm<N, N, N, N, true, false>(V, V, J, lam, J);
     symmetrize<N, N>(C);
     symmetrize<N, N>(J);
   }

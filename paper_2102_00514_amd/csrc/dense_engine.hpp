@@ -30,6 +30,7 @@ class DenseEngine final : public EngineBase {
     ntracks = pb.n_tracks;
     n_iter = pb.n_iter;
     lin_ = pb.lin;
+    lm_ = pb.lm_lambda;
     rule_.alpha = pb.ut_alpha;
     rule_.kappa = pb.ut_kappa;
     use_graph_ = pb.use_graph != 0;
@@ -137,6 +138,7 @@ class DenseEngine final : public EngineBase {
     a.ntracks = ntracks;
     a.lin = lin_;
     a.rule = rule_;
+    a.lm = lm_;
     a.flags = d_flags_;
     a.track = d_track_;
     a.params = d_params_;
@@ -291,6 +293,7 @@ class DenseEngine final : public EngineBase {
  private:
   int lin_ = 0;
   SigmaRule rule_{1.0, 1.0};
+  double lm_ = 0.0;
   bool use_graph_ = false;
   int fan0_ = kFan;
   hipGraphExec_t graph_exec_ = nullptr;

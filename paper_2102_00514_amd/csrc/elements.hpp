@@ -222,6 +222,91 @@ PKS_DEV bool filter_element(const R (&F)[N][N], const R (&c)[N], const R (&Qp)[N
 }
 
 // ---------------------------------------------------------------------------
+// Levenberg-Marquardt damping (Section 3, the damped Gauss-Newton extension of
+// the iterated smoother): the previous iterate xbar_k is observed at slot k
+// through x_k plus noise of covariance I/lambda.  That measurement is
+// independent of y_k given x_k, so it is a second update of the filtering
+// element.  With G = I + lambda C = L L^T, Z = L^-1 C, W = L^-1 A and
+// v = L^-1 (xbar - b), the gain is K = C (C + I/lambda)^-1 = lambda Z^T L^-1 and
+//   A -= lambda Z^T W,  b += lambda Z^T v,  C -= lambda Z^T Z,
+//   J += lambda W^T W,  eta += lambda W^T v.
+// Returns false if G is not positive definite.
+// ---------------------------------------------------------------------------
+template <int N, typename R>
+PKS_DEV bool lm_damp_element(R lam, const R (&xbar)[N], R (&A)[N][N], R (&b)[N], R (&C)[N][N], R (&eta)[N],
+                             R (&J)[N][N]) {
+  R G[N][N], Z[N][N], W[N][N], v[N];
+  PKS_UNROLL for (int i = 0; i < N; ++i) {
+    v[i] = xbar[i] - b[i];
+    PKS_UNROLL for (int j = 0; j < N; ++j) {
+      G[i][j] = lam * C[i][j] + (i == j ? R(1) : R(0));
+      Z[i][j] = C[i][j];
+      W[i][j] = A[i][j];
+    }
+  }
+  const bool ok = chol_inplace<N>(G);
+  chol_fwd<N, N>(G, Z);
+  chol_fwd<N, N>(G, W);
+  chol_fwd_vec<N>(G, v);
+  PKS_UNROLL for (int i = 0; i < N; ++i) {
+    R sb = R(0), se = R(0);
+    PKS_UNROLL for (int t = 0; t < N; ++t) {
+      sb += Z[t][i] * v[t];
+      se += W[t][i] * v[t];
+    }
+    b[i] += lam * sb;
+    eta[i] += lam * se;
+    PKS_UNROLL for (int j = 0; j < N; ++j) {
+      R sa = R(0);
+      PKS_UNROLL for (int t = 0; t < N; ++t) sa += Z[t][i] * W[t][j];
+      A[i][j] -= lam * sa;
+    }
+    PKS_UNROLL for (int j = i; j < N; ++j) {
+      R sc = R(0), sj = R(0);
+      PKS_UNROLL for (int t = 0; t < N; ++t) {
+        sc += Z[t][i] * Z[t][j];
+        sj += W[t][i] * W[t][j];
+      }
+      C[i][j] -= lam * sc;
+      C[j][i] = C[i][j];
+      J[i][j] += lam * sj;
+      J[j][i] = J[i][j];
+    }
+  }
+  return ok;
+}
+
+// The same damping update applied to filtered moments (m, P) of the
+// sequential Kalman filter: m += lambda Z^T v, P -= lambda Z^T Z with
+// G = I + lambda P = L L^T, Z = L^-1 P, v = L^-1 (xbar - m).
+template <int N, typename R>
+PKS_DEV bool lm_damp_moments(R lam, const R (&xbar)[N], R (&m)[N], R (&P)[N][N]) {
+  R G[N][N], Z[N][N], v[N];
+  PKS_UNROLL for (int i = 0; i < N; ++i) {
+    v[i] = xbar[i] - m[i];
+    PKS_UNROLL for (int j = 0; j < N; ++j) {
+      G[i][j] = lam * P[i][j] + (i == j ? R(1) : R(0));
+      Z[i][j] = P[i][j];
+    }
+  }
+  const bool ok = chol_inplace<N>(G);
+  chol_fwd<N, N>(G, Z);
+  chol_fwd_vec<N>(G, v);
+  PKS_UNROLL for (int i = 0; i < N; ++i) {
+    R sb = R(0);
+    PKS_UNROLL for (int t = 0; t < N; ++t) sb += Z[t][i] * v[t];
+    m[i] += lam * sb;
+    PKS_UNROLL for (int j = i; j < N; ++j) {
+      R sc = R(0);
+      PKS_UNROLL for (int t = 0; t < N; ++t) sc += Z[t][i] * Z[t][j];
+      P[i][j] -= lam * sc;
+      P[j][i] = P[i][j];
+    }
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
 // Smoothing element (E, g, L) (eq. 17) from the filtered x*, P* at slot k and
 // the surrogate transition (F, c, Q') out of slot k.  With
 // F P* F^T + Q' = L L^T and V = L^-1 F P*:

@@ -100,6 +100,7 @@ class Engine final : public EngineBase {
     lin_ = pb.lin;
     seq_ = pb.scan == SM_SCAN_SEQUENTIAL;
     use_graph_ = pb.use_graph != 0 && !seq_;
+    lm_ = pb.lm_lambda;
     rule_.alpha = pb.ut_alpha;
     rule_.kappa = pb.ut_kappa;
     slot_off_.resize(ntracks + 1);
@@ -286,6 +287,7 @@ class Engine final : public EngineBase {
     a.traj_out = d_traj_[cur ^ 1];
     a.delta_bits = delta_bits;
     a.rule = rule_;
+    a.lm = lm_;
     return a;
   }
 
@@ -317,6 +319,7 @@ class Engine final : public EngineBase {
     a.tc_s = tc_s_;
     a.delta_bits = delta_bits;
     a.rule = rule_;
+    a.lm = lm_;
     return a;
   }
 
@@ -567,6 +570,7 @@ class Engine final : public EngineBase {
   hipGraphExec_t graph_exec_ = nullptr;
   hipStream_t capture_stream_ = nullptr;
   SigmaRule rule_{1.0, 1.0};
+  double lm_ = 0.0;
   int cur_ = 0;
   Schedule sched_;
   int64_t tiles_ = 0;

@@ -56,6 +56,7 @@ struct FusedArgs {
   void *lx_s, *ta_s, *tc_s;  // same for the reverse scan, indexed by reverse tile
   unsigned long long* delta_bits;  // [ntracks + 1]; entry ntracks = max over tracks
   SigmaRule rule;
+  double lm;            // Levenberg-Marquardt damping lambda (0 = undamped)
 };
 
 // Linearisation arrays written by the separate linearisation pass: transition
@@ -84,6 +85,17 @@ enum LinSource : int {
   kStoredLin = 1      // read from the arrays a separate linearisation pass wrote (sigma-point SLR)
 };
 
+// Levenberg-Marquardt damping of the element of real slot s towards the
+// previous iterate stored in traj (the linearisation point of this iteration).
+template <int N, typename R>
+PKS_DEV bool lm_damp_slot(const FusedArgs& a, int64_t s, typename FilterOp<N, R>::Elem& e) {
+  R xb[N];
+  ld_vec<N>(static_cast<const R*>(a.traj), a.stride, s, xb);
+  const bool ok = lm_damp_element<N, R>(R(a.lm), xb, e.A, e.b, e.C, e.eta, e.J);
+  if (!ok) e.b[0] = quiet_nan<R>();
+  return ok;
+}
+
 // Filtering element of slot s.
 template <class Model, int SRC, typename R>
 PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename FilterOp<Model::N, R>::Elem& e) {
@@ -99,6 +111,7 @@ PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename Filter
       const int tr = a.track[s];
       ld_vec<N>(static_cast<const R*>(a.m0), size_t(a.ntracks), tr, e.b);
       ld_sym<N>(static_cast<const R*>(a.P0), size_t(a.ntracks), tr, e.C);
+      if (a.lm > 0.0) lm_damp_slot<N, R>(a, s, e);
     } else {
       set_zero<N>(e.b);
       set_zero<N>(e.C);
@@ -144,7 +157,8 @@ PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename Filter
       linearize_h<Model, R>(md, kTaylor, a.rule, Rm, x, Px, y, H, d, Rp, yt);
     }
   }
-  const bool ok = filter_element<N, P, R>(F, c, Qp, H, d, Rp, yt, e.A, e.b, e.C, e.eta, e.J);
+  bool ok = filter_element<N, P, R>(F, c, Qp, H, d, Rp, yt, e.A, e.b, e.C, e.eta, e.J);
+  if (a.lm > 0.0) ok = lm_damp_slot<N, R>(a, s, e) && ok;
   if (!ok) e.b[0] = quiet_nan<R>();
 }
 

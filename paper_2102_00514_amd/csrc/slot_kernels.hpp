@@ -31,6 +31,7 @@ struct SlotArgs {
   void* traj_out;
   unsigned long long* delta_bits;  // [ntracks + 1]; last entry = max over tracks
   SigmaRule rule;
+  double lm;            // Levenberg-Marquardt damping lambda (0 = undamped)
 };
 
 constexpr int kSlotBlock = 256;
@@ -208,6 +209,12 @@ __global__ __launch_bounds__(64) void k_sequential(SlotArgs a, const int64_t* sl
   R m[N], Pm[N][N];
   ld_vec<N>(static_cast<const R*>(a.m0), a.tstride, tr, m);
   ld_sym<N>(static_cast<const R*>(a.P0), a.tstride, tr, Pm);
+  const R* traj = static_cast<const R*>(a.traj);
+  if (a.lm > 0.0) {
+    R xb[N];
+    ld_vec<N>(traj, st, s0, xb);
+    if (!lm_damp_moments<N, R>(R(a.lm), xb, m, Pm)) m[0] = quiet_nan<R>();
+  }
   st_vec<N>(filt, st, s0, m);
   st_sym<N>(filt + N * st, st, s0, Pm);
   for (int64_t s = s0 + 1; s < s1; ++s) {
@@ -252,6 +259,11 @@ __global__ __launch_bounds__(64) void k_sequential(SlotArgs a, const int64_t* sl
         Pm[i][j] = q;
         Pm[j][i] = q;
       }
+    }
+    if (a.lm > 0.0) {
+      R xb[N];
+      ld_vec<N>(traj, st, s, xb);
+      if (!lm_damp_moments<N, R>(R(a.lm), xb, m, Pm)) m[0] = quiet_nan<R>();
     }
     st_vec<N>(filt, st, s, m);
     st_sym<N>(filt + N * st, st, s, Pm);

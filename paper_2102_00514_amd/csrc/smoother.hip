@@ -154,6 +154,7 @@ static std::string validate(const sm_problem* pb) {
   if (pb->tile_lanes != 0 && pb->tile_lanes != 64 && pb->tile_lanes != 256) return "tile_lanes must be 0, 64 or 256";
   if (pb->lane_slots < 0 || pb->lane_slots > 8) return "lane_slots must be in 0..8";
   if (pb->use_graph != 0 && pb->use_graph != 1) return "use_graph must be 0 or 1";
+  if (!(pb->lm_lambda >= 0.0) || !std::isfinite(pb->lm_lambda)) return "lm_lambda must be finite and >= 0";
   const int64_t S = nmeas + pb->n_tracks;
   if (pb->init_cov && !pb->init_mean) return "init_cov given without init_mean";
   if (pb->init_mean && !all_finite(pb->init_mean, size_t(S) * n)) return "init_mean must be finite";

@@ -211,3 +211,8 @@ def test_dense_stacked_scope():
     sensors = np.random.default_rng(1).uniform(-2, 2, (6, 2))
     pb3 = wl.stacked_ct(10, np.random.default_rng(2), sensors=sensors, n_targets=3, n_sensors=6)
     _expect_einval(pb3, "unsupported", lin="cubature")                      # only (20, 8) is compiled
+
+
+def test_rejects_bad_lm_lambda():
+    for bad in (-0.5, float("nan"), float("inf")):
+        _expect_einval(_c1(), "lm_lambda", lm_lambda=bad)
