@@ -268,3 +268,75 @@ def cov_error(P_test, P_ref):
     """max_k ||P_test_k - P_ref_k||_F / ||P_ref_k||_F."""
     d = np.linalg.norm(np.asarray(P_test) - P_ref, axis=(-2, -1))
     return float(np.max(d / np.linalg.norm(P_ref, axis=(-2, -1))))
+
+
+def map_cost(pb, x, precision: str = "f64") -> float:
+    """MAP objective J(x_{0:T}) of a single-track problem (Section 3: the
+    function whose Gauss-Newton iterations are the iterated extended smoother):
+    prior, transition and measurement residuals weighted by P0^-1, Q^-1, R^-1,
+    bearing residuals wrapped to [-pi, pi)."""
+    assert pb.n_tracks == 1, "the oracle runs one track at a time"
+    nx, ny = pb.nx, pb.ny
+    T = int(pb.offsets[1])
+    x = _arr(x, (T + 1, nx))
+    params = _arr(pb.params)
+    out = ctypes.c_double()
+    rc = _fn("orc_map_cost", precision)(nx, ny, T, int(pb.model), _ptr(params), int(params.size),
+                                         *[_ptr(_arr(a)) for a in (pb.Q, pb.R, pb.m0[0], pb.P0[0], pb.y)],
+                                         _ptr(x), ctypes.byref(out))
+    _check(rc, "orc_map_cost")
+    return out.value
+
+
+LM_LAMBDA_MAX = 1e16
+
+
+def lm_adaptive(pb, lam0: float = 1e-2, nu: float = 10.0, tol: float = 1e-6, max_iter: int = 50,
+                accept_rtol: float = 1e-12, init_mean=None, init_cov=None, stop: bool = True) -> dict:
+    """Levenberg-Marquardt iterated extended smoother with Marquardt's damping
+    schedule, one track.
+
+    Every iteration is one damped pass (``smoother(..., M=1, lm_lambda=lam)``)
+    from the current iterate.  The step is taken when it does not raise the MAP
+    objective by more than accept_rtol |J| (rounding of J), and then lam /= nu;
+    otherwise the iterate is kept and lam = min(lam * nu, LM_LAMBDA_MAX).  The
+    track has converged at the first taken step whose largest change is below
+    tol while lam (the value the step used) is at most lam0.  With ``stop`` the
+    loop ends there, otherwise it runs max_iter iterations.
+
+    Returns mean, cov, first (1-based iteration of convergence, 0 if none),
+    iters, and per iteration: lam (used), cost (after the decision), taken,
+    delta (of the damped pass), cost_new (of the damped pass's result)."""
+    nx = pb.nx
+    T = int(pb.offsets[1])
+    S = T + 1
+    xb = np.broadcast_to(pb.m0[0], (S, nx)).copy() if init_mean is None else _arr(init_mean, (S, nx)).copy()
+    Pb = np.broadcast_to(pb.P0[0], (S, nx, nx)).copy() if init_cov is None else _arr(init_cov, (S, nx, nx)).copy()
+    J = map_cost(pb, xb)
+    lam = lam0
+    hist = {"lam": [], "cost": [], "taken": [], "delta": [], "cost_new": []}
+    first = 0
+    it = 0
+    while it < max_iter:
+        it += 1
+        r = smoother(pb, 1, "taylor", init_mean=xb, init_cov=Pb, lm_lambda=lam, filtered=False)
+        Jn = map_cost(pb, r["mean"])
+        d = float(r["deltas"][0])
+        taken = bool(Jn <= J + accept_rtol * abs(J))
+        hist["lam"].append(lam)
+        hist["delta"].append(d)
+        hist["cost_new"].append(Jn)
+        hist["taken"].append(taken)
+        if taken:
+            if first == 0 and d < tol and lam <= lam0:
+                first = it
+            xb, Pb, J = r["mean"], r["cov"], Jn
+            lam = lam / nu
+        else:
+            lam = min(lam * nu, LM_LAMBDA_MAX)
+        hist["cost"].append(J)
+        if stop and first:
+            break
+    out = {"mean": xb, "cov": Pb, "first": first, "iters": it, "final_cost": J}
+    out.update({k: np.array(v) for k, v in hist.items()})
+    return out

@@ -648,6 +648,60 @@ done:
     return rc;
 }
 
+/*
+ * MAP objective of the trajectory x = x_{0:T} (Section 3: the iterated
+ * extended smoother is Gauss-Newton on it, and its Levenberg-Marquardt
+ * extension decides on it whether a damped step is taken):
+ *   J(x) = 1/2 |x_0 - m0|^2_{P0^-1}
+ *        + sum_{k=1..T} 1/2 |x_k - f(x_{k-1})|^2_{Q^-1} + 1/2 |y_k - h(x_k)|^2_{R^-1},
+ * with |v|^2_{A^-1} = v^T A^-1 v.  For bearing measurements the residual
+ * y_k - h(x_k) is taken modulo 2 pi in [-pi, pi), the same unwrapping the
+ * linearisation uses.  x is [T+1][nx]; *cost receives J.
+ * Returns 0, 1 (invalid argument) or 4 (P0, Q or R not positive definite).
+ */
+int SFX(orc_map_cost)(int nx, int ny, int T, int model, const double *params, int n_params,
+                      const double *Q, const double *R, const double *m0, const double *P0,
+                      const double *y, const double *x, double *cost) {
+    model_t md;
+    if (T < 0 || !x || !cost) return ORC_EINVAL;
+    int rc = model_setup(&md, model, params, n_params, nx, ny);
+    if (rc) return rc;
+    int n = nx, p = ny;
+    real A[NMAX * NMAX], LQ[NMAX * NMAX], LR[NMAX * NMAX], L0[NMAX * NMAX];
+    load(A, Q, n * n);
+    if (chol(n, A, LQ)) return ORC_ENUMERIC;
+    load(A, R, p * p);
+    if (chol(p, A, LR)) return ORC_ENUMERIC;
+    load(A, P0, n * n);
+    if (chol(n, A, L0)) return ORC_ENUMERIC;
+    real xp[NMAX], xk[NMAX], fx[NMAX], hx[NMAX], r[NMAX], z[NMAX];
+    real total = 0;
+    load(xk, x, n);
+    for (int i = 0; i < n; ++i) r[i] = xk[i] - (real)m0[i];
+    memcpy(z, r, sizeof(real) * n);
+    chol_solve(n, L0, z, 1);
+    for (int i = 0; i < n; ++i) total += r[i] * z[i] / 2;
+    for (int k = 1; k <= T; ++k) {
+        memcpy(xp, xk, sizeof(real) * n);
+        load(xk, x + (size_t)k * n, n);
+        model_f(&md, xp, fx, NULL);
+        for (int i = 0; i < n; ++i) r[i] = xk[i] - fx[i];
+        memcpy(z, r, sizeof(real) * n);
+        chol_solve(n, LQ, z, 1);
+        for (int i = 0; i < n; ++i) total += r[i] * z[i] / 2;
+        model_h(&md, xk, hx, NULL);
+        for (int i = 0; i < p; ++i) {
+            r[i] = (real)y[(size_t)(k - 1) * p + i] - hx[i];
+            if (model_angular_y(&md)) r[i] = wrap_angle(r[i]);
+        }
+        memcpy(z, r, sizeof(real) * p);
+        chol_solve(p, LR, z, 1);
+        for (int i = 0; i < p; ++i) total += r[i] * z[i] / 2;
+    }
+    *cost = (double)total;
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Exported: model evaluation, sigma points, single-slot linearisation.        */
 /* ------------------------------------------------------------------------ */

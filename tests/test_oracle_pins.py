@@ -326,6 +326,118 @@ def test_lm_fixed_point_is_the_ieks_fixed_point(orc):
 
 
 # ---------------------------------------------------------------------------------------
+# The MAP objective (Section 3: the IEKS is Gauss-Newton on it).  Pinned to an independent
+# whitened-residual implementation, to the negative log joint density of a linear model
+# evaluated by scipy, and to the periodicity of bearings.
+# ---------------------------------------------------------------------------------------
+def test_map_cost_is_half_squared_whitened_residual(orc):
+    pb = wl.config_c1().prefix(30)
+    f, h = ph.ct_model_funcs(pb)
+    res = ph.map_residual(pb, f, h, True)
+    rng = np.random.default_rng(0)
+    ieks = orc.smoother(pb, 15, "taylor")["mean"]
+    for x in (np.broadcast_to(pb.m0[0], (31, 5)).copy(), ieks, ieks + 0.05 * rng.standard_normal(ieks.shape)):
+        r = res(x.ravel())
+        ref = 0.5 * float(r @ r)
+        assert abs(orc.map_cost(pb, x) - ref) <= 1e-10 * ref
+
+
+def test_map_cost_linear_is_negative_log_joint_density(orc):
+    from scipy.stats import multivariate_normal
+    n, p, T = 2, 1, 4
+    pb = wl.linear_gaussian(n, p, T, seed=3)
+    prm = pb.params
+    F = prm[:n * n].reshape(n, n)
+    c = prm[n * n:n * n + n]
+    H = prm[n * n + n:n * n + n + p * n].reshape(p, n)
+    d = prm[n * n + n + p * n:]
+    # z = (x_0..x_T, y_1..y_T) = mu + A eps with eps standard normal: the joint Gaussian.
+    nz, ne = (T + 1) * n + T * p, (T + 1) * n + T * p
+    A = np.zeros((nz, ne))
+    mu = np.zeros(nz)
+    L0, Lq, Lr = (np.linalg.cholesky(M) for M in (pb.P0[0], pb.Q, pb.R))
+    xs = slice(0, n)
+    mu[xs] = pb.m0[0]
+    A[xs, 0:n] = L0
+    for k in range(1, T + 1):
+        cur, prev = slice(k * n, (k + 1) * n), slice((k - 1) * n, k * n)
+        mu[cur] = F @ mu[prev] + c
+        A[cur] = F @ A[prev]
+        A[cur, k * n:(k + 1) * n] += Lq
+    for k in range(1, T + 1):
+        row = slice((T + 1) * n + (k - 1) * p, (T + 1) * n + k * p)
+        mu[row] = H @ mu[k * n:(k + 1) * n] + d
+        A[row] = H @ A[k * n:(k + 1) * n]
+        A[row, (T + 1) * n + (k - 1) * p:(T + 1) * n + k * p] += Lr
+    dist = multivariate_normal(mu, A @ A.T)
+    const = 0.5 * (np.linalg.slogdet(2 * np.pi * pb.P0[0])[1] + T * np.linalg.slogdet(2 * np.pi * pb.Q)[1]
+                   + T * np.linalg.slogdet(2 * np.pi * pb.R)[1])
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        x = rng.standard_normal((T + 1, n))
+        z = np.concatenate([x.ravel(), pb.y.ravel()])
+        assert abs(orc.map_cost(pb, x) - (-dist.logpdf(z) - const)) < 1e-9 * (1 + abs(dist.logpdf(z)))
+
+
+def test_map_cost_minimised_by_linear_smoother(orc):
+    pb = wl.linear_gaussian(3, 2, 40, seed=5)
+    x = orc.smoother(pb, 1, "taylor")["mean"]
+    J = orc.map_cost(pb, x)
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        assert orc.map_cost(pb, x + 1e-3 * rng.standard_normal(x.shape)) > J
+
+
+def test_map_cost_bearings_are_periodic(orc):
+    pb = wl.config_c1()
+    x = orc.smoother(pb, 10, "taylor")["mean"]
+    q = pb.prefix(100)
+    q.y = pb.y.copy()
+    q.y[5, 0] += 2 * np.pi
+    q.y[40, 1] -= 4 * np.pi
+    a, b = orc.map_cost(pb, x), orc.map_cost(q, x)
+    assert abs(a - b) < 1e-10 * a
+
+
+def _fd_gradient(orc, pb, x, idx, h=1e-5):
+    g = []
+    for i in idx:
+        xp, xm = x.ravel().copy(), x.ravel().copy()
+        xp[i] += h
+        xm[i] -= h
+        g.append((orc.map_cost(pb, xp) - orc.map_cost(pb, xm)) / (2 * h))
+    return np.array(g)
+
+
+# ---------------------------------------------------------------------------------------
+# Levenberg-Marquardt with Marquardt's damping schedule: it only takes steps that do not
+# raise the objective, reaches the IEKS fixed point where the IEKS converges, and reaches a
+# stationary point of the objective on a track where undamped Gauss-Newton diverges.
+# ---------------------------------------------------------------------------------------
+def test_lm_adaptive_reaches_the_ieks_fixed_point(orc):
+    pb = wl.config_c1()
+    plain = orc.smoother(pb, 60, "taylor")
+    lm = orc.lm_adaptive(pb, tol=1e-10, max_iter=200)
+    assert lm["first"] > 0
+    assert orc.mean_error(lm["mean"], plain["mean"]) < 1e-8
+    c = np.concatenate([[orc.map_cost(pb, np.broadcast_to(pb.m0[0], (101, 5)))], lm["cost"]])
+    assert np.all(c[1:] <= c[:-1] * (1 + 1e-12))
+
+
+def test_lm_adaptive_converges_where_gauss_newton_diverges(orc):
+    pb = wl.config_c4(147, 1, held_out=True)
+    plain = orc.smoother(pb, 100, "taylor", filtered=False)
+    assert plain["deltas"][-1] > 1.0                      # undamped iterations still jump
+    lm = orc.lm_adaptive(pb, tol=1e-9, max_iter=100)
+    assert lm["first"] > 0
+    idx = np.random.default_rng(0).choice(lm["mean"].size, 120, replace=False)
+    g = _fd_gradient(orc, pb, lm["mean"], idx)
+    g0 = _fd_gradient(orc, pb, np.broadcast_to(pb.m0[0], lm["mean"].shape), idx)
+    assert np.max(np.abs(g)) < 1e-9 * np.max(np.abs(g0))
+    assert lm["final_cost"] < orc.map_cost(pb, plain["mean"])
+
+
+# ---------------------------------------------------------------------------------------
 # Pin 8 -- the oracle's own rounding error (double vs long double).
 # ---------------------------------------------------------------------------------------
 @pytest.mark.parametrize("lin", ["taylor", "cubature"])
