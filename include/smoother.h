@@ -170,6 +170,40 @@ sm_status smoother_iterate(smoother_t h, int32_t k, double* max_delta_out, int32
 sm_status smoother_iterate_until(smoother_t h, double tol, int32_t max_iter, int32_t* iters_run,
                                  int32_t* track_iters);
 
+/* MAP objective of the current trajectory of every track (Section 3: the
+ * function whose Gauss-Newton iterations are the iterated extended smoother):
+ *   J(x_{0:T}) = 1/2 |x_0 - m0|^2_{P0^-1}
+ *              + sum_{k=1..T} 1/2 |x_k - f(x_{k-1})|^2_{Q^-1} + 1/2 |y_k - h(x_k)|^2_{R^-1},
+ * bearing residuals y_k - h(x_k) taken modulo 2 pi in [-pi, pi).  Waits for
+ * the handle's stream; track_cost is host [n_tracks].  Evaluated in the
+ * handle's precision per slot and summed per track in double, in a fixed
+ * order.  SM_EINVAL for the nx = 20 sigma-point engine (not built there) or a
+ * NULL track_cost. */
+sm_status smoother_objective(smoother_t h, double* track_cost);
+
+/* Levenberg-Marquardt iterations (Section 3, the damped Gauss-Newton
+ * extension of the iterated extended smoother) with Marquardt's damping
+ * schedule, every track on its own: each iteration is one pass damped by
+ * the track's lambda (the previous iterate observed with covariance
+ * I/lambda, as lm_lambda does); the pass is kept when the track's objective
+ * (smoother_objective) does not rise by more than 1e-12 |J| (1e-6 for SM_FP32,
+ * the rounding of J), and lambda is divided by nu; otherwise the track's
+ * trajectory is put back and lambda = min(lambda * nu, 1e16).  lambda starts
+ * at lambda0 for every track.  A track has converged at the first kept pass
+ * whose largest change max_{k,j} |xbar^(i) - xbar^(i-1)| is below tol while
+ * its lambda is at most lambda0.  Runs until every track has converged or
+ * max_iter passes; rejected passes count.  *iters_run (nullable) receives the
+ * passes run, track_iters (nullable, host [n_tracks]) the 1-based pass of
+ * convergence (0 = none), track_cost (nullable, host [n_tracks]) the final
+ * objective.  The problem's lm_lambda is not used during the call and is used
+ * again by later calls of smoother_iterate.  Covariances are those of the last
+ * kept damped pass; one more smoother_iterate with lm_lambda = 0 gives the
+ * undamped ones at the result.  Needs the Taylor linearisation (SM_EINVAL
+ * otherwise, or for invalid arguments: lambda0 > 0 and nu > 1 finite, tol > 0,
+ * max_iter >= 1).  Waits for the stream twice per pass. */
+sm_status smoother_iterate_lm(smoother_t h, double lambda0, double nu, double tol, int32_t max_iter,
+                              int32_t* iters_run, int32_t* track_iters, double* track_cost);
+
 /* Waits for the handle's stream and copies the current trajectory to host
  * buffers: mean [S*nx], cov [S*nx*nx] (full symmetric matrices); either may be
  * NULL.  S = sum(T_i + 1), slots of track 0 first. */

@@ -28,7 +28,8 @@ SCAN = {"parallel": 0, "sequential": 1}
 EXPORTS = ("smoother_problem_defaults", "smoother_init", "smoother_iterate", "smoother_result",
            "smoother_result_device", "smoother_track_deltas", "smoother_info", "smoother_last_error",
            "smoother_destroy", "smoother_version", "smoother_profile", "smoother_schedule",
-           "smoother_set_trajectory_device", "smoother_iterate_until", "smoother_autotune")
+           "smoother_set_trajectory_device", "smoother_iterate_until", "smoother_autotune",
+           "smoother_objective", "smoother_iterate_lm")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -110,6 +111,11 @@ def _load():
     lib.smoother_autotune.argtypes = [ctypes.POINTER(sm_problem), vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), _dp]
     lib.smoother_autotune.restype = ctypes.c_int
+    lib.smoother_objective.argtypes = [vp, _dp]
+    lib.smoother_objective.restype = ctypes.c_int
+    lib.smoother_iterate_lm.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _dp]
+    lib.smoother_iterate_lm.restype = ctypes.c_int
     return lib
 
 
@@ -219,6 +225,28 @@ def smoother_iterate_until(h: int, tol: float, max_iter: int):
     return run.value, first, True
 
 
+def smoother_objective(h: int) -> np.ndarray:
+    """MAP objective of the current trajectory, per track."""
+    _, T, _ = smoother_info(h)
+    out = np.empty(T)
+    _check(h, _lib.smoother_objective(h, out.ctypes.data_as(_dp)))
+    return out
+
+
+def smoother_iterate_lm(h: int, lambda0: float = 1e-2, nu: float = 10.0, tol: float = 1e-6, max_iter: int = 50):
+    """Levenberg-Marquardt passes with Marquardt's damping schedule until every
+    track has converged (or max_iter).  Returns (passes run, per-track pass of
+    convergence (0 = none), per-track final objective)."""
+    _, T, _ = smoother_info(h)
+    run = ctypes.c_int32(0)
+    first = np.zeros(T, dtype=np.int32)
+    cost = np.empty(T)
+    _check(h, _lib.smoother_iterate_lm(h, lambda0, nu, tol, max_iter, ctypes.byref(run),
+                                       first.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       cost.ctypes.data_as(_dp)))
+    return run.value, first, cost
+
+
 def smoother_info(h: int):
     S, T, B = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
     _check(h, _lib.smoother_info(h, ctypes.byref(S), ctypes.byref(T), ctypes.byref(B)))
@@ -300,6 +328,12 @@ class Smoother:
 
     def iterate_until(self, tol: float, max_iter: int):
         return smoother_iterate_until(self.h, tol, max_iter)
+
+    def objective(self):
+        return smoother_objective(self.h)
+
+    def iterate_lm(self, lambda0: float = 1e-2, nu: float = 10.0, tol: float = 1e-6, max_iter: int = 50):
+        return smoother_iterate_lm(self.h, lambda0, nu, tol, max_iter)
 
     def set_trajectory_device(self, mean_ptr: int, cov_ptr: int = 0, cov_const=None):
         smoother_set_trajectory_device(self.h, mean_ptr, cov_ptr, cov_const)

@@ -197,9 +197,41 @@ class BlockEngine final : public EngineBase {
     return SM_OK;
   }
 
+  // The objective of the stacked state is the sum of the blocks' objectives;
+  // one damping value per track acts on every block (I/lambda is
+  // block-diagonal), so the blocks take or reject their steps together.
+  sm_status objective(double* out) override {
+    std::vector<double> c(ntracks);
+    std::fill(out, out + ntracks, 0.0);
+    for (auto& b : blocks_) {
+      const sm_status s = b->objective(c.data());
+      if (s != SM_OK) return fail(s, b->err);
+      for (int i = 0; i < ntracks; ++i) out[i] += c[i];
+    }
+    return SM_OK;
+  }
+
+  sm_status lm_mode(bool on) override { return each([&](EngineBase& b) { return b.lm_mode(on); }); }
+  sm_status lm_set_lambda(const double* lam) override {
+    return each([&](EngineBase& b) { return b.lm_set_lambda(lam); });
+  }
+  sm_status lm_save() override { return each([](EngineBase& b) { return b.lm_save(); }); }
+  sm_status lm_restore(const unsigned char* reject) override {
+    return each([&](EngineBase& b) { return b.lm_restore(reject); });
+  }
+
   void set_precision_word(size_t w) { word_ = w; }
 
  private:
+  template <class F>
+  sm_status each(F&& f) {
+    for (auto& b : blocks_) {
+      const sm_status s = f(*b);
+      if (s != SM_OK) return fail(s, b->err);
+    }
+    return SM_OK;
+  }
+
   size_t precision_word() const { return word_; }
 
   EngineFactory make_;

@@ -20,6 +20,7 @@
 #include <memory>
 
 #include "engine_base.hpp"
+#include "objective.hpp"
 #include "scan.hpp"
 #include "slot_kernels.hpp"
 
@@ -131,6 +132,19 @@ class Engine final : public EngineBase {
         for (int j = i; j < N; ++j)
           P0[size_t(sym_index<N>(i, j)) * ntracks + t] = R(pb.P0[(size_t(t) * N + i) * N + j]);
     }
+    // whitening matrices of Q, R and each P0 for the MAP objective
+    std::vector<double> w(size_t(N) * N);
+    std::vector<R> wq(size_t(N) * N), wr(size_t(P) * P), wp0(size_t(ntracks) * N * N);
+    if (!whitening(pb.Q, N, w.data())) return fail(SM_EINVAL, "Q is not positive definite");
+    std::copy(w.begin(), w.end(), wq.begin());
+    w.resize(size_t(P) * P);
+    if (!whitening(pb.R, P, w.data())) return fail(SM_EINVAL, "R is not positive definite");
+    std::copy(w.begin(), w.end(), wr.begin());
+    w.resize(size_t(N) * N);
+    for (int t = 0; t < ntracks; ++t) {
+      if (!whitening(pb.P0 + size_t(t) * N * N, N, w.data())) return fail(SM_EINVAL, "P0 is not positive definite");
+      std::copy(w.begin(), w.end(), wp0.begin() + size_t(t) * N * N);
+    }
     std::vector<R> yslot(size_t(P) * stride, R(0));
     for (int t = 0; t < ntracks; ++t)
       for (int64_t k = 1; k < slot_off_[t + 1] - slot_off_[t]; ++k) {
@@ -151,6 +165,9 @@ class Engine final : public EngineBase {
     A(reinterpret_cast<void**>(&d_track_), sizeof(int) * S);
     A(reinterpret_cast<void**>(&d_slot_off_), sizeof(int64_t) * (ntracks + 1));
     A(&d_y_, sizeof(R) * yslot.size());
+    A(&d_wq_, sizeof(R) * wq.size());
+    A(&d_wr_, sizeof(R) * wr.size());
+    A(&d_wp0_, sizeof(R) * wp0.size());
     A(&d_traj_[0], sizeof(R) * kTrajW * stride);
     A(reinterpret_cast<void**>(&delta_bits), sizeof(unsigned long long) * (ntracks + 1));
     if (seq_) {
@@ -203,6 +220,9 @@ class Engine final : public EngineBase {
     H2D(d_track_, track.data(), sizeof(int) * S);
     H2D(d_slot_off_, slot_off_.data(), sizeof(int64_t) * (ntracks + 1));
     H2D(d_y_, yslot.data(), sizeof(R) * yslot.size());
+    H2D(d_wq_, wq.data(), sizeof(R) * wq.size());
+    H2D(d_wr_, wr.data(), sizeof(R) * wr.size());
+    H2D(d_wp0_, wp0.data(), sizeof(R) * wp0.size());
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "upload of the problem"));
     const int64_t grid = (S + kSlotBlock - 1) / kSlotBlock;
     const SlotArgs a = slot_args(0);
@@ -288,6 +308,7 @@ class Engine final : public EngineBase {
     a.delta_bits = delta_bits;
     a.rule = rule_;
     a.lm = lm_;
+    a.lm_track = lm_track_;
     return a;
   }
 
@@ -320,6 +341,7 @@ class Engine final : public EngineBase {
     a.delta_bits = delta_bits;
     a.rule = rule_;
     a.lm = lm_;
+    a.lm_track = lm_track_;
     return a;
   }
 
@@ -501,6 +523,111 @@ class Engine final : public EngineBase {
   ~Engine() override {
     if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
     if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
+    for (void* p : pinned_) (void)hipHostFree(p);
+  }
+
+  // ---- MAP objective and Levenberg-Marquardt hooks ------------------------
+  hipError_t pinned_alloc(void** p, size_t bytes) {
+    const hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) pinned_.push_back(*p);
+    return e;
+  }
+
+  sm_status objective(double* out) override {
+    hipError_t e = hipSuccess;
+    if (!d_slot_cost_) {
+      e = dalloc(reinterpret_cast<void**>(&d_slot_cost_), sizeof(double) * S);
+      if (e == hipSuccess) e = dalloc(reinterpret_cast<void**>(&d_cost_), sizeof(double) * ntracks);
+      if (e == hipSuccess) e = pinned_alloc(reinterpret_cast<void**>(&h_cost_), sizeof(double) * ntracks);
+      if (e != hipSuccess) {
+        d_slot_cost_ = nullptr;
+        return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE, hip_msg(e, "objective buffers"));
+      }
+    }
+    CostArgs a{};
+    a.S = S;
+    a.stride = stride;
+    a.ntracks = ntracks;
+    a.flags = d_flags_;
+    a.track = d_track_;
+    a.params = d_params_;
+    a.m0 = d_m0_;
+    a.yslot = d_y_;
+    a.traj = d_traj_[cur_];
+    a.wq = d_wq_;
+    a.wr = d_wr_;
+    a.wp0 = d_wp0_;
+    a.slot_cost = d_slot_cost_;
+    hipLaunchKernelGGL((k_objective_slots<Model, R>), dim3(unsigned((S + kSlotBlock - 1) / kSlotBlock)),
+                       dim3(kSlotBlock), 0, stream, a);
+    hipLaunchKernelGGL(k_objective_tracks, dim3(unsigned(ntracks)), dim3(kTrackSumB), 0, stream,
+                       static_cast<const double*>(d_slot_cost_), static_cast<const int64_t*>(d_slot_off_), d_cost_);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h_cost_, d_cost_, sizeof(double) * ntracks, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "objective"));
+    std::memcpy(out, h_cost_, sizeof(double) * ntracks);
+    return SM_OK;
+  }
+
+  sm_status lm_mode(bool on) override {
+    if (on && lin_ != SM_LIN_TAYLOR)
+      return fail(SM_EINVAL, "adaptive damping needs the Taylor linearisation (sigma-point iterations minimise "
+                             "no fixed objective)");
+    if (on && !d_lam_) {
+      hipError_t e = dalloc(reinterpret_cast<void**>(&d_lam_), sizeof(double) * ntracks);
+      if (e == hipSuccess) e = dalloc(&d_saved_, sizeof(R) * kTrajW * stride);
+      if (e == hipSuccess) e = dalloc(reinterpret_cast<void**>(&d_reject_), ntracks);
+      if (e == hipSuccess) e = pinned_alloc(reinterpret_cast<void**>(&h_lam_), sizeof(double) * ntracks);
+      if (e == hipSuccess) e = pinned_alloc(reinterpret_cast<void**>(&h_reject_), ntracks);
+      if (e != hipSuccess) {
+        d_lam_ = nullptr;
+        return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE, hip_msg(e, "damping buffers"));
+      }
+    }
+    double* want = on ? d_lam_ : nullptr;
+    if (want != lm_track_) {
+      lm_track_ = want;
+      // the captured iteration holds the kernel arguments: capture again
+      if (graph_exec_) {
+        const hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "stream before a new capture"));
+        (void)hipGraphExecDestroy(graph_exec_);
+        graph_exec_ = nullptr;
+      }
+    }
+    return SM_OK;
+  }
+
+  sm_status lm_set_lambda(const double* lam) override {
+    if (!lm_track_) return fail(SM_ESTATE, "adaptive damping is off");
+    std::memcpy(h_lam_, lam, sizeof(double) * ntracks);
+    const hipError_t e = hipMemcpyAsync(d_lam_, h_lam_, sizeof(double) * ntracks, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "damping upload"));
+    return SM_OK;
+  }
+
+  sm_status lm_save() override {
+    if (!lm_track_) return fail(SM_ESTATE, "adaptive damping is off");
+    const hipError_t e =
+        hipMemcpyAsync(d_saved_, d_traj_[cur_], sizeof(R) * kTrajW * stride, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "trajectory save"));
+    return SM_OK;
+  }
+
+  sm_status lm_restore(const unsigned char* reject) override {
+    if (!lm_track_) return fail(SM_ESTATE, "adaptive damping is off");
+    std::memcpy(h_reject_, reject, ntracks);
+    hipError_t e = hipMemcpyAsync(d_reject_, h_reject_, ntracks, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL((k_restore_tracks<R>), dim3(unsigned((S + kSlotBlock - 1) / kSlotBlock)), dim3(kSlotBlock),
+                         0, stream, S, stride, kTrajW, static_cast<const int*>(d_track_),
+                         static_cast<const unsigned char*>(d_reject_), static_cast<const R*>(d_saved_),
+                         static_cast<R*>(d_traj_[cur_]));
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "trajectory restore"));
+    return SM_OK;
   }
 
   sm_status result_host(double* mean, double* cov) override {
@@ -571,6 +698,7 @@ class Engine final : public EngineBase {
   hipStream_t capture_stream_ = nullptr;
   SigmaRule rule_{1.0, 1.0};
   double lm_ = 0.0;
+  double* lm_track_ = nullptr;          // per-track damping while adaptive damping runs
   int cur_ = 0;
   Schedule sched_;
   int64_t tiles_ = 0;
@@ -583,6 +711,12 @@ class Engine final : public EngineBase {
   int64_t* d_slot_off_ = nullptr;
   void *d_y_ = nullptr, *d_traj_[2] = {nullptr, nullptr};
   void *d_lin_ = nullptr, *d_filt_ = nullptr;  // sequential path
+  void *d_wq_ = nullptr, *d_wr_ = nullptr, *d_wp0_ = nullptr;  // whitening of Q, R, P0
+  double *d_slot_cost_ = nullptr, *d_cost_ = nullptr, *h_cost_ = nullptr;
+  double *d_lam_ = nullptr, *h_lam_ = nullptr;
+  void* d_saved_ = nullptr;
+  unsigned char *d_reject_ = nullptr, *h_reject_ = nullptr;
+  std::vector<void*> pinned_;
   void *d_trans_ = nullptr, *d_felem_ = nullptr, *d_selem_ = nullptr;
   void *lx_f_ = nullptr, *ta_f_ = nullptr, *tc_f_ = nullptr, *lx_s_ = nullptr, *ta_s_ = nullptr, *tc_s_ = nullptr;
 };

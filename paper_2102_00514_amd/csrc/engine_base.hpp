@@ -20,6 +20,33 @@ inline std::string hip_msg(hipError_t e, const char* what) {
   return std::string(what) + ": " + hipGetErrorString(e);
 }
 
+// W = L^-1 for A = L L^T (n x n, row-major, lower triangular), so that
+// r^T A^-1 r = |W r|^2.  Returns false if A is not positive definite.
+inline bool whitening(const double* A, int n, double* W) {
+  std::vector<double> L(size_t(n) * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int t = 0; t < j; ++t) d -= L[j * n + t] * L[j * n + t];
+    if (!(d > 0.0)) return false;
+    L[j * n + j] = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[i * n + j];
+      for (int t = 0; t < j; ++t) v -= L[i * n + t] * L[j * n + t];
+      L[i * n + j] = v / L[j * n + j];
+    }
+  }
+  // columns of W solve L w = e_c by forward substitution
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      double v = i == c ? 1.0 : 0.0;
+      for (int t = c; t < i; ++t) v -= L[i * n + t] * W[t * n + c];
+      W[i * n + c] = i < c ? 0.0 : v / L[i * n + i];
+    }
+  return true;
+}
+
+constexpr double kLmLambdaMax = 1e16;   // cap of the damping schedule
+
 // Everything that depends on the model, dimensions and precision sits behind this interface.
 class EngineBase {
  public:
@@ -75,6 +102,71 @@ class EngineBase {
       if (!finite) return fail(SM_ENUMERIC, "non-finite iterate");
     }
     return SM_OK;
+  }
+
+  // MAP objective (Section 3) of the current trajectory, per track, into a
+  // host buffer; waits for the stream.
+  virtual sm_status objective(double*) {
+    return fail(SM_EINVAL, "the MAP objective is not built for this engine");
+  }
+
+  // Levenberg-Marquardt hooks: per-track damping values replace the problem's
+  // lm_lambda while the mode is on; save/restore keep the trajectory of the
+  // tracks whose damped step is not taken.
+  virtual sm_status lm_mode(bool) { return fail(SM_EINVAL, "adaptive damping is not built for this engine"); }
+  virtual sm_status lm_set_lambda(const double*) { return fail(SM_ESTATE, "adaptive damping is off"); }
+  virtual sm_status lm_save() { return fail(SM_ESTATE, "adaptive damping is off"); }
+  virtual sm_status lm_restore(const unsigned char*) { return fail(SM_ESTATE, "adaptive damping is off"); }
+
+  // Levenberg-Marquardt iterations with Marquardt's schedule, per track: a
+  // damped pass with the track's lambda; the step is kept when the objective
+  // does not rise by more than accept_rtol |J| (then lambda /= nu), otherwise
+  // the trajectory is put back (lambda = min(lambda nu, kLmLambdaMax)).  A track
+  // has converged at the first kept step whose largest change is below tol
+  // while its lambda is at most lam0.  Runs until every track has converged or
+  // max_iter iterations; first[i] as in iterate_until, cost[i] (nullable) the
+  // final objective.
+  sm_status iterate_lm(double lam0, double nu, double tol, int max_iter, double accept_rtol, int* run,
+                       int32_t* first, double* cost) {
+    sm_status st = lm_mode(true);
+    if (st != SM_OK) return st;
+    std::vector<double> lam(ntracks, lam0), J(ntracks), Jn(ntracks), d(ntracks + 1);
+    std::vector<unsigned char> reject(ntracks, 0);
+    for (int i = 0; i < ntracks; ++i) first[i] = 0;
+    *run = 0;
+    int left = ntracks;
+    st = objective(J.data());
+    while (st == SM_OK && *run < max_iter && left > 0) {
+      st = lm_set_lambda(lam.data());
+      if (st == SM_OK) st = lm_save();
+      if (st == SM_OK) st = iterate(1);
+      if (st == SM_OK) st = objective(Jn.data());
+      if (st == SM_OK) st = track_deltas(d.data());
+      if (st != SM_OK) break;
+      *run += 1;
+      bool any = false;
+      for (int i = 0; i < ntracks; ++i) {
+        const bool taken = Jn[i] <= J[i] + accept_rtol * std::fabs(J[i]);
+        reject[i] = taken ? 0 : 1;
+        any = any || !taken;
+        if (taken) {
+          if (first[i] == 0 && d[i] < tol && lam[i] <= lam0) {
+            first[i] = *run;
+            --left;
+          }
+          J[i] = Jn[i];
+          lam[i] /= nu;
+        } else {
+          lam[i] = std::min(lam[i] * nu, kLmLambdaMax);
+        }
+      }
+      if (any) st = lm_restore(reject.data());
+    }
+    const sm_status off = lm_mode(false);
+    if (st == SM_OK) st = off;
+    if (cost)
+      for (int i = 0; i < ntracks; ++i) cost[i] = J[i];
+    return st;
   }
 
   // Per-launch HIP events (only while profiling).

@@ -57,6 +57,7 @@ struct FusedArgs {
   unsigned long long* delta_bits;  // [ntracks + 1]; entry ntracks = max over tracks
   SigmaRule rule;
   double lm;            // Levenberg-Marquardt damping lambda (0 = undamped)
+  const double* lm_track;  // optional [ntracks]: per-track damping, replaces lm
 };
 
 // Linearisation arrays written by the separate linearisation pass: transition
@@ -89,9 +90,11 @@ enum LinSource : int {
 // previous iterate stored in traj (the linearisation point of this iteration).
 template <int N, typename R>
 PKS_DEV bool lm_damp_slot(const FusedArgs& a, int64_t s, typename FilterOp<N, R>::Elem& e) {
+  const double lam = a.lm_track ? a.lm_track[a.track[s]] : a.lm;
+  if (!(lam > 0.0)) return true;
   R xb[N];
   ld_vec<N>(static_cast<const R*>(a.traj), a.stride, s, xb);
-  const bool ok = lm_damp_element<N, R>(R(a.lm), xb, e.A, e.b, e.C, e.eta, e.J);
+  const bool ok = lm_damp_element<N, R>(R(lam), xb, e.A, e.b, e.C, e.eta, e.J);
   if (!ok) e.b[0] = quiet_nan<R>();
   return ok;
 }
@@ -111,7 +114,7 @@ PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename Filter
       const int tr = a.track[s];
       ld_vec<N>(static_cast<const R*>(a.m0), size_t(a.ntracks), tr, e.b);
       ld_sym<N>(static_cast<const R*>(a.P0), size_t(a.ntracks), tr, e.C);
-      if (a.lm > 0.0) lm_damp_slot<N, R>(a, s, e);
+      if (a.lm > 0.0 || a.lm_track) lm_damp_slot<N, R>(a, s, e);
     } else {
       set_zero<N>(e.b);
       set_zero<N>(e.C);
@@ -158,7 +161,7 @@ PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename Filter
     }
   }
   bool ok = filter_element<N, P, R>(F, c, Qp, H, d, Rp, yt, e.A, e.b, e.C, e.eta, e.J);
-  if (a.lm > 0.0) ok = lm_damp_slot<N, R>(a, s, e) && ok;
+  if (a.lm > 0.0 || a.lm_track) ok = lm_damp_slot<N, R>(a, s, e) && ok;
   if (!ok) e.b[0] = quiet_nan<R>();
 }
 

@@ -1,0 +1,109 @@
+// MAP objective of a trajectory and the per-track bookkeeping of
+// Levenberg-Marquardt iterations with a damping schedule.
+//
+// Section 3: the iterated extended smoother is Gauss-Newton on
+//   J(x_{0:T}) = 1/2 |x_0 - m0|^2_{P0^-1}
+//              + sum_k 1/2 |x_k - f(x_{k-1})|^2_{Q^-1} + 1/2 |y_k - h(x_k)|^2_{R^-1},
+// and its Levenberg-Marquardt extension keeps a damped step only when J does
+// not rise.  Bearing residuals are taken modulo 2 pi in [-pi, pi), the same
+// unwrapping the linearisation applies.  The weights come in as whitening
+// matrices W (lower triangular, W A W^T = I for A = Q, R, P0), so each term is
+// 1/2 |W r|^2.
+//
+// Slot s of the batch contributes its prior term (first slot of a track) or
+// its transition and measurement terms; one workgroup per track then sums its
+// slots in a fixed order, so the objective is deterministic.
+#pragma once
+
+#include "slot_kernels.hpp"
+
+namespace pks {
+
+struct CostArgs {
+  int64_t S;
+  size_t stride;
+  int ntracks;
+  const unsigned char* flags;
+  const int* track;
+  const void* params;
+  const void* m0;       // [N][ntracks]
+  const void* yslot;    // [P][stride]
+  const void* traj;     // [N + s(N)][stride], means in the first N rows
+  const void* wq;       // N x N row-major lower triangular
+  const void* wr;       // P x P
+  const void* wp0;      // [ntracks][N][N]
+  double* slot_cost;    // [S]
+};
+
+template <int N, typename R>
+PKS_DEV R half_sq_whitened(const R* W, const R (&r)[N]) {
+  R s = R(0);
+  PKS_UNROLL for (int i = 0; i < N; ++i) {
+    R z = R(0);
+    PKS_UNROLL for (int j = 0; j <= i; ++j) z += W[i * N + j] * r[j];
+    s += z * z;
+  }
+  return R(0.5) * s;
+}
+
+template <class Model, typename R>
+__global__ __launch_bounds__(kSlotBlock) void k_objective_slots(CostArgs a) {
+  constexpr int N = Model::N, P = Model::P;
+  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  if (s >= a.S) return;
+  const R* traj = static_cast<const R*>(a.traj);
+  R x[N], r[N];
+  ld_vec<N>(traj, a.stride, s, x);
+  R c;
+  if (a.flags[s] & kSlotFirst) {
+    const int tr = a.track[s];
+    R m0[N];
+    ld_vec<N>(static_cast<const R*>(a.m0), size_t(a.ntracks), tr, m0);
+    PKS_UNROLL for (int i = 0; i < N; ++i) r[i] = x[i] - m0[i];
+    c = half_sq_whitened<N, R>(static_cast<const R*>(a.wp0) + size_t(tr) * N * N, r);
+  } else {
+    const Model md{static_cast<const R*>(a.params)};
+    R xp[N], fx[N], hx[P], y[P], e[P];
+    ld_vec<N>(traj, a.stride, s - 1, xp);
+    md.f(xp, fx);
+    PKS_UNROLL for (int i = 0; i < N; ++i) r[i] = x[i] - fx[i];
+    c = half_sq_whitened<N, R>(static_cast<const R*>(a.wq), r);
+    md.h(x, hx);
+    ld_vec<P>(static_cast<const R*>(a.yslot), a.stride, s, y);
+    PKS_UNROLL for (int i = 0; i < P; ++i) e[i] = Model::kAngular ? wrap_pi<R>(y[i] - hx[i]) : y[i] - hx[i];
+    c += half_sq_whitened<P, R>(static_cast<const R*>(a.wr), e);
+  }
+  a.slot_cost[s] = double(c);
+}
+
+constexpr int kTrackSumB = 256;
+
+// cost[t] = sum of slot_cost over the slots of track t (one workgroup per track).
+static __global__ __launch_bounds__(kTrackSumB) void k_objective_tracks(const double* slot_cost,
+                                                                        const int64_t* slot_off, double* cost) {
+  __shared__ double red[kTrackSumB];
+  const int t = blockIdx.x;
+  const int64_t lo = slot_off[t], hi = slot_off[t + 1];
+  double s = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kTrackSumB) s += slot_cost[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kTrackSumB / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cost[t] = red[0];
+}
+
+// Puts back the saved trajectory (all `words` rows) at the slots of the tracks
+// whose damped step was not taken.
+template <typename R>
+__global__ __launch_bounds__(kSlotBlock) void k_restore_tracks(int64_t S, size_t stride, int words, const int* track,
+                                                               const unsigned char* reject, const R* saved,
+                                                               R* traj) {
+  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  if (s >= S || !reject[track[s]]) return;
+  for (int w = 0; w < words; ++w) traj[size_t(w) * stride + s] = saved[size_t(w) * stride + s];
+}
+
+}  // namespace pks

@@ -32,6 +32,7 @@ struct SlotArgs {
   unsigned long long* delta_bits;  // [ntracks + 1]; last entry = max over tracks
   SigmaRule rule;
   double lm;            // Levenberg-Marquardt damping lambda (0 = undamped)
+  const double* lm_track;  // optional [ntracks]: per-track damping, replaces lm
 };
 
 constexpr int kSlotBlock = 256;
@@ -210,10 +211,11 @@ __global__ __launch_bounds__(64) void k_sequential(SlotArgs a, const int64_t* sl
   ld_vec<N>(static_cast<const R*>(a.m0), a.tstride, tr, m);
   ld_sym<N>(static_cast<const R*>(a.P0), a.tstride, tr, Pm);
   const R* traj = static_cast<const R*>(a.traj);
-  if (a.lm > 0.0) {
+  const double lam = a.lm_track ? a.lm_track[tr] : a.lm;
+  if (lam > 0.0) {
     R xb[N];
     ld_vec<N>(traj, st, s0, xb);
-    if (!lm_damp_moments<N, R>(R(a.lm), xb, m, Pm)) m[0] = quiet_nan<R>();
+    if (!lm_damp_moments<N, R>(R(lam), xb, m, Pm)) m[0] = quiet_nan<R>();
   }
   st_vec<N>(filt, st, s0, m);
   st_sym<N>(filt + N * st, st, s0, Pm);
@@ -260,10 +262,10 @@ __global__ __launch_bounds__(64) void k_sequential(SlotArgs a, const int64_t* sl
         Pm[j][i] = q;
       }
     }
-    if (a.lm > 0.0) {
+    if (lam > 0.0) {
       R xb[N];
       ld_vec<N>(traj, st, s, xb);
-      if (!lm_damp_moments<N, R>(R(a.lm), xb, m, Pm)) m[0] = quiet_nan<R>();
+      if (!lm_damp_moments<N, R>(R(lam), xb, m, Pm)) m[0] = quiet_nan<R>();
     }
     st_vec<N>(filt, st, s, m);
     st_sym<N>(filt + N * st, st, s, Pm);

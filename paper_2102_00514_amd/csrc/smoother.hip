@@ -188,6 +188,7 @@ struct smoother {
   std::unique_ptr<pks::EngineBase> eng;
   std::string err;
   int nx = 0;
+  int precision = SM_FP64;
   bool blocks = false;    // stacked targets run as separate blocks
 };
 
@@ -234,6 +235,7 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
     smoother* h = new smoother();
     h->eng = std::move(eng);
     h->nx = pb->nx;
+    h->precision = pb->precision;
     h->blocks = pks::stacked(pb->model, pb->nx) && pb->lin == SM_LIN_TAYLOR;
     *out = h;
     g_init_error.clear();
@@ -381,6 +383,49 @@ sm_status smoother_iterate_until(smoother_t h, double tol, int32_t max_iter, int
     const sm_status st = e.iterate_until(tol, max_iter, &run, first.data());
     if (iters_run) *iters_run = run;
     if (track_iters) std::memcpy(track_iters, first.data(), sizeof(int32_t) * e.ntracks);
+    if (st != SM_OK) h->err = e.err;
+    return st;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return SM_EDEVICE;
+  }
+}
+
+sm_status smoother_objective(smoother_t h, double* track_cost) {
+  if (!h || !h->eng) return SM_ESTATE;
+  if (!track_cost) {
+    h->err = "track_cost is NULL";
+    return SM_EINVAL;
+  }
+  try {
+    const sm_status st = h->eng->objective(track_cost);
+    if (st != SM_OK) h->err = h->eng->err;
+    return st;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return SM_EDEVICE;
+  }
+}
+
+sm_status smoother_iterate_lm(smoother_t h, double lambda0, double nu, double tol, int32_t max_iter,
+                              int32_t* iters_run, int32_t* track_iters, double* track_cost) {
+  if (!h || !h->eng) return SM_ESTATE;
+  if (!(lambda0 > 0.0) || !std::isfinite(lambda0) || !(nu > 1.0) || !std::isfinite(nu) || !(tol > 0.0) ||
+      max_iter < 1) {
+    h->err = "iterate_lm needs finite lambda0 > 0, finite nu > 1, tol > 0 and max_iter >= 1";
+    return SM_EINVAL;
+  }
+  try {
+    pks::EngineBase& e = *h->eng;
+    std::vector<int32_t> first(e.ntracks);
+    std::vector<double> cost(e.ntracks);
+    int run = 0;
+    // a kept step may raise the objective by its rounding level at most
+    const double rtol = h->precision == SM_FP64 ? 1e-12 : 1e-6;
+    const sm_status st = e.iterate_lm(lambda0, nu, tol, max_iter, rtol, &run, first.data(), cost.data());
+    if (iters_run) *iters_run = run;
+    if (track_iters) std::memcpy(track_iters, first.data(), sizeof(int32_t) * e.ntracks);
+    if (track_cost) std::memcpy(track_cost, cost.data(), sizeof(double) * e.ntracks);
     if (st != SM_OK) h->err = e.err;
     return st;
   } catch (...) {

@@ -159,3 +159,138 @@ def test_damped_fixed_point_is_undamped_fixed_point(B):
     err = oracle.mean_error(damped, plain)
     print(f"damped vs plain fixed point: {err:.3e}", flush=True)
     assert err < 1e-8
+
+
+# ---------------------------------------------------------------------------------------
+# MAP objective and Levenberg-Marquardt with Marquardt's damping schedule.
+# ---------------------------------------------------------------------------------------
+def _perturbed_batch_init(pb, scale, seed):
+    rng = np.random.default_rng(seed)
+    so = pb.slot_offsets()
+    im = np.concatenate([np.broadcast_to(pb.m0[i], (so[i + 1] - so[i], pb.nx)) for i in range(pb.n_tracks)])
+    return im + scale * rng.standard_normal(im.shape)
+
+
+@pytest.mark.parametrize("kind", ["ct", "linear", "stacked"])
+def test_objective_matches_oracle(B, kind):
+    if kind == "ct":
+        pb = wl.concat_tracks([wl.ct_bearings(T, seed=T) for T in (1, 2, 63, 700)], "ragged")
+    elif kind == "linear":
+        pb = wl.linear_gaussian(3, 2, 300, seed=4, n_tracks=3, t_min=1)
+    else:
+        sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (8, 2))
+        pb = wl.concat_tracks([wl.stacked_ct(T, np.random.default_rng([57, T]), sensors=sensors)
+                               for T in (3, 120)], "stacked batch")
+    im = _perturbed_batch_init(pb, 0.3, 1)
+    with B.Smoother(pb, n_iter=1, init_mean=im) as sm:
+        got = sm.objective()
+    so = pb.slot_offsets()
+    for i in range(pb.n_tracks):
+        ref = oracle.map_cost(pb.track(i), im[so[i]:so[i + 1]])
+        print(f"{kind} track {i}: {got[i]:.15e} vs {ref:.15e}", flush=True)
+        assert abs(got[i] - ref) <= 1e-12 * abs(ref)
+
+
+def test_objective_fp32(B):
+    pb = wl.config_c1()
+    im = _perturbed_batch_init(pb, 0.3, 2)
+    with B.Smoother(pb, n_iter=1, init_mean=im, precision="f32") as sm:
+        got = sm.objective()[0]
+    ref = oracle.map_cost(pb, im)
+    assert abs(got - ref) <= 1e-5 * abs(ref)
+
+
+def _margins_clear(ref, J0, rtol=1e-12):
+    """The oracle's keep/reject decisions are not within rounding of the threshold."""
+    prev = np.concatenate([[J0], ref["cost"][:-1]])
+    m = ref["cost_new"] - (prev + rtol * np.abs(prev))
+    return np.all(np.abs(m) > 1e-14 * np.abs(prev))
+
+
+def test_adaptive_single_track_matches_oracle(B):
+    pb = wl.config_c1()
+    with B.Smoother(pb, n_iter=1) as sm:
+        run, first, cost = sm.iterate_lm(1e-2, 10.0, 1e-9, 200)
+        mean, cov = sm.result()
+    ref = oracle.lm_adaptive(pb, 1e-2, 10.0, 1e-9, 200)
+    J0 = oracle.map_cost(pb, np.broadcast_to(pb.m0[0], mean.shape))
+    assert _margins_clear(ref, J0)
+    print(f"C1 adaptive: gpu run={run} first={first[0]}, oracle {ref['iters']} {ref['first']}", flush=True)
+    assert run == ref["iters"] and first[0] == ref["first"] > 0
+    assert abs(cost[0] - ref["final_cost"]) <= 1e-12 * ref["final_cost"]
+    assert_parity(mean, cov, ref, what="C1 adaptive damping")
+
+
+def test_adaptive_batch_matches_oracle(B):
+    """Held-out warm-start tracks (T = 4096): two where undamped iterations do
+    not converge in 100 passes (145, 147), one slow (38) and two ordinary."""
+    idx = (0, 38, 145, 147, 3)
+    pb = wl.concat_tracks([wl.config_c4(i, 1, held_out=True) for i in idx], "held-out")
+    with B.Smoother(pb, n_iter=1) as sm:
+        run, first, cost = sm.iterate_lm(1e-2, 10.0, 1e-6, 80)
+        mean, cov = sm.result()
+    so = pb.slot_offsets()
+    assert np.all(first > 0)
+    for i in range(pb.n_tracks):
+        tr = pb.track(i)
+        ref = oracle.lm_adaptive(tr, 1e-2, 10.0, 1e-6, run, stop=False)
+        J0 = oracle.map_cost(tr, np.broadcast_to(tr.m0[0], (so[i + 1] - so[i], 5)))
+        assert _margins_clear(ref, J0), i
+        print(f"track {idx[i]}: first gpu {first[i]} oracle {ref['first']}", flush=True)
+        assert first[i] == ref["first"]
+        assert abs(cost[i] - ref["final_cost"]) <= 1e-10 * ref["final_cost"]
+        sl = slice(so[i], so[i + 1])
+        assert_parity(mean[sl], cov[sl], ref, tol=1e-8, what=f"held-out track {idx[i]} adaptive")
+
+
+def test_adaptive_stacked_blocks_match_dense_oracle(B):
+    pb = wl.config_c5_single(200)
+    with B.Smoother(pb, n_iter=1) as sm:
+        run, first, cost = sm.iterate_lm(1e-2, 10.0, 1e-9, 100)
+        mean, cov = sm.result()
+    ref = oracle.lm_adaptive(pb, 1e-2, 10.0, 1e-9, 100)
+    print(f"stacked adaptive: gpu run={run} first={first[0]}, oracle {ref['iters']} {ref['first']}", flush=True)
+    assert run == ref["iters"] and first[0] == ref["first"] > 0
+    assert_parity(mean, _block_diag_only(cov), {"mean": ref["mean"], "cov": _block_diag_only(ref["cov"])},
+                  tol=1e-8, what="stacked adaptive")
+
+
+def test_adaptive_modes_agree_and_plain_pass_follows(B):
+    """Graph replay, eager launches and the sequential path take the same
+    passes; afterwards smoother_iterate runs undamped again."""
+    pb = wl.config_c1()
+    outs = []
+    for kw in ({}, {"use_graph": False}, {"scan": "sequential"}):
+        with B.Smoother(pb, n_iter=1, **kw) as sm:
+            run, first, _ = sm.iterate_lm(1e-2, 10.0, 1e-8, 100)
+            m, c = sm.result()
+            sm.iterate(1)
+            m2, c2 = sm.result()
+        outs.append((run, first[0], m, c, m2, c2))
+    assert outs[0][:2] == outs[1][:2] == outs[2][:2]
+    assert np.array_equal(outs[0][2], outs[1][2]) and np.array_equal(outs[0][4], outs[1][4])
+    assert oracle.mean_error(outs[2][2], outs[0][2]) < 1e-10
+    ref = oracle.smoother(pb, 1, "taylor", init_mean=outs[0][2], init_cov=outs[0][3])
+    assert_parity(outs[0][4], outs[0][5], ref, what="undamped pass after adaptive damping")
+
+
+def test_adaptive_fp32(B):
+    pb = wl.config_c1()
+    with B.Smoother(pb, n_iter=1, precision="f32") as sm:
+        run, first, _ = sm.iterate_lm(1e-2, 10.0, 1e-4, 100)
+        mean, _ = sm.result()
+    ref = oracle.lm_adaptive(pb, 1e-2, 10.0, 1e-9, 200)
+    err = oracle.mean_error(mean, ref["mean"])
+    print(f"FP32 adaptive: run={run} first={first[0]} e_m={err:.3e}", flush=True)
+    assert first[0] > 0 and err < 1e-3
+
+
+def test_adaptive_needs_taylor_and_objective_engine(B):
+    with B.Smoother(wl.config_c1(), n_iter=1, lin="cubature") as sm:
+        with pytest.raises(B.SmootherError, match="Taylor"):
+            sm.iterate_lm()
+    with B.Smoother(wl.config_c5_single(20), n_iter=1, lin="unscented") as sm:
+        with pytest.raises(B.SmootherError, match="not built"):
+            sm.objective()
+        with pytest.raises(B.SmootherError, match="not built"):
+            sm.iterate_lm()
