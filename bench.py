@@ -204,6 +204,49 @@ def warm_start_section(weights: str, n_batch: int, n_single: int, lin: str = "ta
             "batch": dict(batch, tracks=n_batch), "single_track": single}
 
 
+def damping_section(n_batch: int, tol: float = 1e-6, max_iter: int = 50) -> dict:
+    """Undamped iterations vs Levenberg-Marquardt passes with Marquardt's
+    damping schedule (lambda0 = 1e-2, nu = 10), both from the prior broadcast,
+    on the same held-out batch of warm-start tracks (T = 4096) in one handle:
+    tracks converged within max_iter passes, mean passes of the converged
+    tracks, wall time of the whole call, and how the final MAP objectives
+    compare per track."""
+    import time
+
+    import numpy as np
+    import torch
+    from paper_2102_00514_amd import binding as Bn
+    from paper_2102_00514_amd import workloads as wl
+    stream = torch.cuda.current_stream().cuda_stream
+    pb = wl.config_c4(0, n_batch, held_out=True)
+    lanes, slots = binding_autotune(pb, stream, "taylor")
+    with Bn.Smoother(pb, n_iter=1, lin="taylor", stream=stream, tile_lanes=lanes, lane_slots=slots) as sm:
+        sm.iterate_lm(1e-2, 10.0, tol, 2)       # warm-up: kernels, graph capture
+    res = {}
+    for name in ("plain", "lm"):
+        with Bn.Smoother(pb, n_iter=1, lin="taylor", stream=stream, tile_lanes=lanes, lane_slots=slots) as sm:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "plain":
+                run, first, _ = sm.iterate_until(tol, max_iter)
+            else:
+                run, first, cost = sm.iterate_lm(1e-2, 10.0, tol, max_iter)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            if name == "plain":
+                cost = sm.objective()
+        conv = first > 0
+        res[name] = {"converged": float(conv.mean()), "passes_mean_converged": float(first[conv].mean()),
+                     "passes_run": int(run), "ms": round(1e3 * wall, 3), "_cost": cost}
+    lower = res["lm"]["_cost"] <= res["plain"]["_cost"] * (1 + 1e-9)
+    out = {"tracks": n_batch, "T": wl.C4_T, "tol": tol, "max_iter": max_iter, "lambda0": 1e-2, "nu": 10.0,
+           "schedule": [lanes, slots]}
+    for k in ("plain", "lm"):
+        out[k] = {a: b for a, b in res[k].items() if not a.startswith("_")}
+    out["lm_objective_not_above_plain"] = float(lower.mean())
+    return out
+
+
 def c2_sweep(args) -> None:
     """T = 2^10..2^15 (prefixes of the seed-0 track): ms per iteration of the
     GPU parallel path (Taylor and cubature, FP64; Taylor FP32), of the GPU
@@ -284,6 +327,8 @@ def main():
     ap.add_argument("--warm-start-tracks", type=int, default=512, help="held-out tracks in the batch comparison")
     ap.add_argument("--warm-start-single", type=int, default=32, help="held-out tracks timed one at a time")
     ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--no-damping", action="store_true", help="skip the Levenberg-Marquardt comparison")
+    ap.add_argument("--damping-tracks", type=int, default=512, help="held-out tracks in the damping comparison")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -405,6 +450,14 @@ def main():
             f"{warm['single_track']['plain']['ms_median']:.3f} ms plain vs "
             f"{warm['single_track']['learned']['ms_median']:.3f} ms learned")
 
+    damping = None
+    if not args.no_damping:
+        damping = damping_section(args.damping_tracks)
+        log(f"held-out batch of {args.damping_tracks}, prior start: undamped converged "
+            f"{damping['plain']['converged']:.3f} ({damping['plain']['passes_mean_converged']:.2f} passes, "
+            f"{damping['plain']['ms']:.1f} ms), Levenberg-Marquardt {damping['lm']['converged']:.3f} "
+            f"({damping['lm']['passes_mean_converged']:.2f} passes, {damping['lm']['ms']:.1f} ms)")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(pb, args.lin, args.cpu_seconds)
@@ -425,6 +478,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "warm_start": warm,
+        "damping": damping,
     }
     print(json.dumps(out), flush=True)
 
