@@ -340,3 +340,28 @@ def lm_adaptive(pb, lam0: float = 1e-2, nu: float = 10.0, tol: float = 1e-6, max
     out = {"mean": xb, "cov": Pb, "first": first, "iters": it, "final_cost": J}
     out.update({k: np.array(v) for k, v in hist.items()})
     return out
+
+
+def filter_loglik(pb, lin: str = "taylor", alpha: float = 1.0, beta: float = 0.0, kappa: float = 1.0,
+                  init_mean=None, init_cov=None, precision: str = "f64") -> dict:
+    """One filtering pass of a single track linearised at (init_mean, init_cov)
+    (default: the prior broadcast): filt_mean [T+1, nx], filt_cov [T+1, nx, nx]
+    and loglik = log p(y_{1:T}) of the linearised model, the sum of the
+    Gaussian predictive log densities."""
+    assert pb.n_tracks == 1, "the oracle runs one track at a time"
+    nx, ny = pb.nx, pb.ny
+    T = int(pb.offsets[1])
+    S = T + 1
+    out = {"filt_mean": np.empty((S, nx)), "filt_cov": np.empty((S, nx, nx))}
+    params = _arr(pb.params)
+    im = _arr(init_mean, (S, nx)) if init_mean is not None else None
+    ic = _arr(init_cov, (S, nx, nx)) if init_cov is not None else None
+    ll = ctypes.c_double()
+    rc = _fn("orc_filter_loglik", precision)(
+        nx, ny, T, int(pb.model), _ptr(params), int(params.size),
+        *[_ptr(_arr(a)) for a in (pb.Q, pb.R, pb.m0[0], pb.P0[0], pb.y)], LIN[lin],
+        ctypes.c_double(alpha), ctypes.c_double(beta), ctypes.c_double(kappa),
+        _ptr(im), _ptr(ic), _ptr(out["filt_mean"]), _ptr(out["filt_cov"]), ctypes.byref(ll))
+    _check(rc, "orc_filter_loglik")
+    out["loglik"] = ll.value
+    return out

@@ -66,6 +66,7 @@ typedef double real;
 #define RATAN2 atan2
 #define RFLOOR floor
 #define RFABS fabs
+#define RLOG log
 #define RPI 3.14159265358979323846264338327950288
 #else
 typedef long double real;
@@ -76,6 +77,7 @@ typedef long double real;
 #define RATAN2 atan2l
 #define RFLOOR floorl
 #define RFABS fabsl
+#define RLOG logl
 #define RPI 3.14159265358979323846264338327950288L
 #endif
 
@@ -645,6 +647,111 @@ int SFX(orc_smoother)(int nx, int ny, int T, int model, const double *params, in
 done:
     linpass_free(&lp);
     free(xb); free(Pb); free(xf); free(Pf); free(xs); free(Ps); free(yy);
+    return rc;
+}
+
+/*
+ * Kalman filter of one linearised pass with the log marginal likelihood of the
+ * surrogate model (Section 2: the filtering prefix a_1 (x) ... (x) a_k carries
+ * p(x_k | y_{1:k}) and, with the normalising constants, p(y_{1:k})).  By the
+ * chain rule p(y_{1:T}) = prod_k p(y_k | y_{1:k-1}), and each factor is the
+ * Gaussian predictive density N(y_k; H_k m-_k + d_k, H_k P-_k H_k^T + R'_k).
+ */
+static int kf_loglik(const linpass_t *lp, const real *m0, const real *P0, real *xf, real *Pf, real *loglik) {
+    int n = lp->n, p = lp->p, T = lp->T;
+    memcpy(xf, m0, sizeof(real) * n);
+    memcpy(Pf, P0, sizeof(real) * n * n);
+    real ll = 0;
+    real mp[NMAX], Pp[NMAX * NMAX], tmp[NMAX * NMAX], S[NMAX * NMAX], L[NMAX * NMAX];
+    real PHt[NMAX * NMAX], K[NMAX * NMAX], v[NMAX], w[NMAX], Hm[NMAX], KS[NMAX * NMAX], KSK[NMAX * NMAX];
+    for (int k = 1; k <= T; ++k) {
+        const real *F = lp->F + (k - 1) * n * n, *c = lp->c + (k - 1) * n, *Qp = lp->Qp + (k - 1) * n * n;
+        const real *H = lp->H + (k - 1) * p * n, *d = lp->d + (k - 1) * p, *Rp = lp->Rp + (k - 1) * p * p;
+        const real *yk = lp->yt + (k - 1) * p;
+        const real *m = xf + (k - 1) * n, *P = Pf + (k - 1) * n * n;
+        mv(n, n, F, m, mp);
+        for (int i = 0; i < n; ++i) mp[i] += c[i];
+        mm(n, n, n, F, P, tmp);
+        mmt(n, n, n, tmp, F, Pp);
+        for (int i = 0; i < n * n; ++i) Pp[i] += Qp[i];
+        symmetrize(n, Pp);
+        mmt(n, n, p, Pp, H, PHt);
+        mm(p, n, p, H, PHt, S);
+        for (int i = 0; i < p * p; ++i) S[i] += Rp[i];
+        symmetrize(p, S);
+        if (chol(p, S, L)) return ORC_ENUMERIC;
+        mv(p, n, H, mp, Hm);
+        for (int j = 0; j < p; ++j) v[j] = yk[j] - Hm[j] - d[j];
+        /* log N(v; 0, S) = -1/2 (p log 2 pi + log det S + v^T S^-1 v) */
+        memcpy(w, v, sizeof(real) * p);
+        chol_solve(p, L, w, 1);
+        real quad = 0, logdet = 0;
+        for (int j = 0; j < p; ++j) {
+            quad += v[j] * w[j];
+            logdet += 2 * RLOG(L[j * p + j]);
+        }
+        ll -= (p * RLOG(2 * RPI) + logdet + quad) / 2;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < p; ++j) K[j * n + i] = PHt[i * p + j];
+        chol_solve(p, L, K, n);
+        real *mk = xf + k * n, *Pk = Pf + k * n * n;
+        for (int i = 0; i < n; ++i) {
+            real s = mp[i];
+            for (int j = 0; j < p; ++j) s += K[j * n + i] * v[j];
+            mk[i] = s;
+        }
+        mtm(n, p, p, K, S, KS);
+        mm(n, p, n, KS, K, KSK);
+        for (int i = 0; i < n * n; ++i) Pk[i] = Pp[i] - KSK[i];
+        symmetrize(n, Pk);
+    }
+    *loglik = ll;
+    return ORC_OK;
+}
+
+/*
+ * One filtering pass linearised at (xbar, Pbar) over slots 0..T (both NULL =
+ * prior broadcast, as the first iteration of orc_smoother): filtered means
+ * filt_mean [T+1][nx] and covariances filt_cov [T+1][nx][nx] (nullable) and
+ * *loglik = log p(y_{1:T}) of the linearised model (for a linear model, the
+ * exact marginal likelihood).
+ */
+int SFX(orc_filter_loglik)(int nx, int ny, int T, int model, const double *params, int n_params,
+                           const double *Q, const double *R, const double *m0, const double *P0,
+                           const double *y, int lin, double alpha, double beta, double kappa,
+                           const double *xbar, const double *Pbar, double *filt_mean, double *filt_cov,
+                           double *loglik) {
+    (void)beta;
+    model_t md;
+    if (T < 0 || lin < 0 || lin > 2 || !loglik) return ORC_EINVAL;
+    int rc = model_setup(&md, model, params, n_params, nx, ny);
+    if (rc) return rc;
+    int n = nx, p = ny;
+    size_t S = (size_t)T + 1;
+    real *xb = malloc(sizeof(real) * S * n), *Pb = malloc(sizeof(real) * S * n * n);
+    real *xf = malloc(sizeof(real) * S * n), *Pf = malloc(sizeof(real) * S * n * n);
+    real *yy = malloc(sizeof(real) * (T > 0 ? T : 1) * p);
+    real Qr[NMAX * NMAX], Rr[NMAX * NMAX], m0r[NMAX], P0r[NMAX * NMAX], ll = 0;
+    linpass_t lp;
+    rc = linpass_alloc(&lp, n, p, T);
+    if (rc || !xb || !Pb || !xf || !Pf || !yy) { rc = ORC_EINVAL; goto done; }
+    load(Qr, Q, n * n); load(Rr, R, p * p); load(m0r, m0, n); load(P0r, P0, n * n);
+    load(yy, y, T * p);
+    if (xbar) load(xb, xbar, (int)(S * n));
+    else for (size_t k = 0; k < S; ++k) memcpy(xb + k * n, m0r, sizeof(real) * n);
+    if (Pbar) load(Pb, Pbar, (int)(S * n * n));
+    else for (size_t k = 0; k < S; ++k) memcpy(Pb + k * n * n, P0r, sizeof(real) * n * n);
+    rc = linearize_traj(&md, lin, (real)alpha, (real)kappa, Qr, Rr, yy, xb, Pb, &lp);
+    if (rc) goto done;
+    rc = kf_loglik(&lp, m0r, P0r, xf, Pf, &ll);
+    if (rc) goto done;
+    if (filt_mean) store(filt_mean, xf, (int)(S * n));
+    if (filt_cov) store(filt_cov, Pf, (int)(S * n * n));
+    *loglik = (double)ll;
+    rc = ORC_OK;
+done:
+    linpass_free(&lp);
+    free(xb); free(Pb); free(xf); free(Pf); free(yy);
     return rc;
 }
 

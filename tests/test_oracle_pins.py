@@ -438,6 +438,65 @@ def test_lm_adaptive_converges_where_gauss_newton_diverges(orc):
 
 
 # ---------------------------------------------------------------------------------------
+# Marginal likelihood of a filtering pass (Section 2: the filtering prefix carries
+# p(y_{1:k}) with the normalising constants).  Pinned to scipy's log density of the
+# measurements' dense joint Gaussian, for a linear model and for the surrogate linear model
+# of a nonlinear one.
+# ---------------------------------------------------------------------------------------
+def _joint_y(F, c, Q, H, d, R, m0, P0):
+    """Mean and covariance of (y_1..y_T) of x_0 ~ N(m0, P0), x_k = F_k x_{k-1} + c_k + N(0, Q_k),
+    y_k = H_k x_k + d_k + N(0, R_k), by pushing standard normal noise through the model."""
+    T, n = len(F), len(m0)
+    p = H[0].shape[0]
+    ne = (T + 1) * n + T * p
+    Ax = np.zeros((n, ne))
+    Ax[:, :n] = np.linalg.cholesky(P0)
+    mx = np.array(m0, dtype=float)
+    My, Ay = np.zeros(T * p), np.zeros((T * p, ne))
+    for k in range(T):
+        mx = F[k] @ mx + c[k]
+        Ax = F[k] @ Ax
+        Ax[:, (k + 1) * n:(k + 2) * n] += np.linalg.cholesky(Q[k])
+        rows = slice(k * p, (k + 1) * p)
+        My[rows] = H[k] @ mx + d[k]
+        Ay[rows] = H[k] @ Ax
+        Ay[rows, (T + 1) * n + k * p:(T + 1) * n + (k + 1) * p] += np.linalg.cholesky(R[k])
+    return My, Ay @ Ay.T
+
+
+@pytest.mark.parametrize("nx,ny,T,seed", [(3, 2, 12, 1), (1, 1, 30, 2), (5, 2, 8, 3)])
+def test_loglik_linear_is_marginal_density(orc, nx, ny, T, seed):
+    from scipy.stats import multivariate_normal
+    pb = wl.linear_gaussian(nx, ny, T, seed=seed)
+    prm = pb.params
+    F = prm[:nx * nx].reshape(nx, nx)
+    c = prm[nx * nx:nx * nx + nx]
+    H = prm[nx * nx + nx:nx * nx + nx + ny * nx].reshape(ny, nx)
+    d = prm[nx * nx + nx + ny * nx:]
+    mu, Sig = _joint_y([F] * T, [c] * T, [pb.Q] * T, [H] * T, [d] * T, [pb.R] * T, pb.m0[0], pb.P0[0])
+    ref = multivariate_normal(mu, Sig).logpdf(pb.y.ravel())
+    for lin in ("taylor", "cubature"):
+        r = orc.filter_loglik(pb, lin)
+        assert abs(r["loglik"] - ref) < 1e-9 * abs(ref), (lin, r["loglik"], ref)
+
+
+@pytest.mark.parametrize("lin", ["taylor", "unscented"])
+def test_loglik_of_surrogate_model(orc, lin):
+    from scipy.stats import multivariate_normal
+    pb = wl.config_c1().prefix(25)
+    it = orc.smoother(pb, 3, lin)
+    lm = orc.linearize_traj(pb, it["mean"], it["cov"], lin)
+    mu, Sig = _joint_y(lm["F"], lm["c"], lm["Qp"], lm["H"], lm["d"], lm["Rp"], pb.m0[0], pb.P0[0])
+    ref = multivariate_normal(mu, Sig).logpdf(lm["yt"].ravel())
+    r = orc.filter_loglik(pb, lin, init_mean=it["mean"], init_cov=it["cov"])
+    assert abs(r["loglik"] - ref) < 1e-9 * abs(ref)
+    # the filtered marginals are those of the smoother's filter at the same linearisation
+    one = orc.smoother(pb, 1, lin, init_mean=it["mean"], init_cov=it["cov"])
+    assert orc.mean_error(r["filt_mean"], one["filt_mean"]) < 1e-12
+    assert orc.cov_error(r["filt_cov"], one["filt_cov"]) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------
 # Pin 8 -- the oracle's own rounding error (double vs long double).
 # ---------------------------------------------------------------------------------------
 @pytest.mark.parametrize("lin", ["taylor", "cubature"])
