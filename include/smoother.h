@@ -170,6 +170,20 @@ sm_status smoother_iterate(smoother_t h, int32_t k, double* max_delta_out, int32
 sm_status smoother_iterate_until(smoother_t h, double tol, int32_t max_iter, int32_t* iters_run,
                                  int32_t* track_iters);
 
+/* One filtering pass (Section 2: the filter is the prefix of the filtering
+ * elements, eq. 13-15) linearised at the current trajectory as an iteration
+ * would be, without damping, and without the smoothing half.  Outputs (host,
+ * each nullable): filt_mean [S*nx] and filt_cov [S*nx*nx] the filtered moments
+ * x*_k, P*_k of every slot (slot 0 of a track holds m0, P0); track_loglik
+ * [n_tracks] log p(y_{1:T}) of the linearised model, the sum over k of the log
+ * Gaussian predictive density N(ytil_k; H_k m-_k + d_k, S_k) from the filtered
+ * moments of slot k-1 (the normalising constants that eq. 14 leaves out; for a
+ * linear model, the exact log marginal likelihood).  Bearing measurements
+ * enter unwrapped around h(xbar_k), as in the iteration.  The trajectory, the
+ * iteration count and the per-track deltas are unchanged.  Waits for the
+ * stream.  SM_EINVAL for the nx = 20 sigma-point engine (not built there). */
+sm_status smoother_filter(smoother_t h, double* filt_mean, double* filt_cov, double* track_loglik);
+
 /* MAP objective of the current trajectory of every track (Section 3: the
  * function whose Gauss-Newton iterations are the iterated extended smoother):
  *   J(x_{0:T}) = 1/2 |x_0 - m0|^2_{P0^-1}

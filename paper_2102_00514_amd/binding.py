@@ -29,7 +29,7 @@ EXPORTS = ("smoother_problem_defaults", "smoother_init", "smoother_iterate", "sm
            "smoother_result_device", "smoother_track_deltas", "smoother_info", "smoother_last_error",
            "smoother_destroy", "smoother_version", "smoother_profile", "smoother_schedule",
            "smoother_set_trajectory_device", "smoother_iterate_until", "smoother_autotune",
-           "smoother_objective", "smoother_iterate_lm")
+           "smoother_objective", "smoother_iterate_lm", "smoother_filter")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -111,6 +111,8 @@ def _load():
     lib.smoother_autotune.argtypes = [ctypes.POINTER(sm_problem), vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), _dp]
     lib.smoother_autotune.restype = ctypes.c_int
+    lib.smoother_filter.argtypes = [vp, _dp, _dp, _dp]
+    lib.smoother_filter.restype = ctypes.c_int
     lib.smoother_objective.argtypes = [vp, _dp]
     lib.smoother_objective.restype = ctypes.c_int
     lib.smoother_iterate_lm.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
@@ -225,6 +227,18 @@ def smoother_iterate_until(h: int, tol: float, max_iter: int):
     return run.value, first, True
 
 
+def smoother_filter(h: int, nx: int, moments: bool = True):
+    """One filtering pass at the current trajectory: (filtered means [S, nx],
+    covariances [S, nx, nx]) or (None, None), and log p(y_{1:T}) per track."""
+    S, T, _ = smoother_info(h)
+    ll = np.empty(T)
+    mean = np.empty((S, nx)) if moments else None
+    cov = np.empty((S, nx, nx)) if moments else None
+    _check(h, _lib.smoother_filter(h, None if mean is None else mean.ctypes.data_as(_dp),
+                                   None if cov is None else cov.ctypes.data_as(_dp), ll.ctypes.data_as(_dp)))
+    return mean, cov, ll
+
+
 def smoother_objective(h: int) -> np.ndarray:
     """MAP objective of the current trajectory, per track."""
     _, T, _ = smoother_info(h)
@@ -331,6 +345,9 @@ class Smoother:
 
     def objective(self):
         return smoother_objective(self.h)
+
+    def filter(self, moments: bool = True):
+        return smoother_filter(self.h, self.nx, moments)
 
     def iterate_lm(self, lambda0: float = 1e-2, nu: float = 10.0, tol: float = 1e-6, max_iter: int = 50):
         return smoother_iterate_lm(self.h, lambda0, nu, tol, max_iter)

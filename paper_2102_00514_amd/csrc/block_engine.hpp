@@ -211,6 +211,29 @@ class BlockEngine final : public EngineBase {
     return SM_OK;
   }
 
+  // Independent targets: the filtered moments are block-diagonal and the log
+  // likelihood of the stacked measurements is the sum over the blocks.
+  sm_status filter(double* mean, double* cov, double* loglik) override {
+    std::vector<double> m(mean ? size_t(S) * kB : 0), c(cov ? size_t(S) * kB * kB : 0), l(ntracks);
+    if (cov) std::fill(cov, cov + size_t(S) * N_ * N_, 0.0);
+    if (loglik) std::fill(loglik, loglik + ntracks, 0.0);
+    for (int b = 0; b < k_; ++b) {
+      const sm_status s = blocks_[b]->filter(mean ? m.data() : nullptr, cov ? c.data() : nullptr, l.data());
+      if (s != SM_OK) return fail(s, blocks_[b]->err);
+      if (loglik)
+        for (int i = 0; i < ntracks; ++i) loglik[i] += l[i];
+      const int o = b * kB;
+      for (int64_t sl = 0; sl < S; ++sl)
+        for (int i = 0; i < kB; ++i) {
+          if (mean) mean[size_t(sl) * N_ + o + i] = m[size_t(sl) * kB + i];
+          if (cov)
+            for (int j = 0; j < kB; ++j)
+              cov[(size_t(sl) * N_ + o + i) * N_ + o + j] = c[(size_t(sl) * kB + i) * kB + j];
+        }
+    }
+    return SM_OK;
+  }
+
   sm_status lm_mode(bool on) override { return each([&](EngineBase& b) { return b.lm_mode(on); }); }
   sm_status lm_set_lambda(const double* lam) override {
     return each([&](EngineBase& b) { return b.lm_set_lambda(lam); });

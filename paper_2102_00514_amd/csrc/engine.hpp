@@ -533,17 +533,107 @@ class Engine final : public EngineBase {
     return e;
   }
 
-  sm_status objective(double* out) override {
-    hipError_t e = hipSuccess;
-    if (!d_slot_cost_) {
-      e = dalloc(reinterpret_cast<void**>(&d_slot_cost_), sizeof(double) * S);
-      if (e == hipSuccess) e = dalloc(reinterpret_cast<void**>(&d_cost_), sizeof(double) * ntracks);
-      if (e == hipSuccess) e = pinned_alloc(reinterpret_cast<void**>(&h_cost_), sizeof(double) * ntracks);
-      if (e != hipSuccess) {
-        d_slot_cost_ = nullptr;
-        return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE, hip_msg(e, "objective buffers"));
-      }
+  // per-slot and per-track double buffers shared by the objective and the
+  // log-likelihood, allocated on first use
+  sm_status ensure_sums() {
+    if (d_slot_cost_) return SM_OK;
+    hipError_t e = dalloc(reinterpret_cast<void**>(&d_slot_cost_), sizeof(double) * S);
+    if (e == hipSuccess) e = dalloc(reinterpret_cast<void**>(&d_cost_), sizeof(double) * ntracks);
+    if (e == hipSuccess) e = pinned_alloc(reinterpret_cast<void**>(&h_cost_), sizeof(double) * ntracks);
+    if (e != hipSuccess) {
+      d_slot_cost_ = nullptr;
+      return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE, hip_msg(e, "per-track sum buffers"));
     }
+    return SM_OK;
+  }
+
+  // d_cost_ -> host, after the per-slot values have been queued
+  sm_status track_sums_to_host(double* out, const char* what) {
+    hipLaunchKernelGGL(k_track_sums, dim3(unsigned(ntracks)), dim3(kTrackSumB), 0, stream,
+                       static_cast<const double*>(d_slot_cost_), static_cast<const int64_t*>(d_slot_off_), d_cost_);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h_cost_, d_cost_, sizeof(double) * ntracks, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, what));
+    if (out) std::memcpy(out, h_cost_, sizeof(double) * ntracks);
+    return SM_OK;
+  }
+
+  sm_status filter(double* mean, double* cov, double* loglik) override {
+    sm_status st = ensure_sums();
+    if (st != SM_OK) return st;
+    hipError_t e = hipSuccess;
+    if (!d_filt_) e = dalloc(&d_filt_, sizeof(R) * kTrajW * stride);
+    if (e == hipSuccess && !d_delta_spare_)
+      e = dalloc(reinterpret_cast<void**>(&d_delta_spare_), sizeof(unsigned long long) * (ntracks + 1));
+    if (e != hipSuccess) {
+      return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE, hip_msg(e, "filtering pass buffers"));
+    }
+    const dim3 grid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
+    LoglikArgs la{};
+    la.S = S;
+    la.stride = stride;
+    la.flags = d_flags_;
+    la.params = d_params_;
+    la.R = d_R_;
+    la.yslot = d_y_;
+    la.traj = d_traj_[cur_];
+    la.filt = d_filt_;
+    la.rule = rule_;
+    la.slot_ll = d_slot_cost_;
+    if (seq_) {
+      // linearise, filter (the smoothed output goes to the spare trajectory
+      // buffer and is discarded), then the predictive densities
+      SlotArgs a = slot_args(cur_);
+      a.lm = 0.0;
+      a.lm_track = nullptr;
+      launch_linearize(a, grid);
+      hipLaunchKernelGGL((k_sequential<N, P, R>), dim3((ntracks + 63) / 64), dim3(64), 0, stream, a, d_slot_off_,
+                         ntracks);
+      la.trans = d_lin_;
+      la.lin = d_lin_;
+    } else {
+      FusedArgs a = fused_args();
+      a.lm = 0.0;
+      a.lm_track = nullptr;
+      a.filt = d_filt_;
+      a.delta_bits = d_delta_spare_;    // the forward kernel clears its statistic: keep the handle's
+      if (sched_.B == 64) launch_filter_pass<64>(a);
+      else launch_filter_pass<256>(a);
+      la.trans = d_trans_;
+      la.lin = lin_ == SM_LIN_TAYLOR ? nullptr : d_lin_;
+    }
+    hipLaunchKernelGGL((k_loglik_slots<Model, R>), grid, dim3(kSlotBlock), 0, stream, la);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "filtering pass"));
+    st = track_sums_to_host(loglik, "log-likelihood");
+    if (st != SM_OK || (!mean && !cov)) return st;
+    std::vector<R> h(size_t(kTrajW) * stride);
+    e = hipMemcpyAsync(h.data(), d_filt_, sizeof(R) * h.size(), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "copy of the filtered moments"));
+    unpack_host(h, mean, cov);
+    return SM_OK;
+  }
+
+  template <int B>
+  void launch_filter_pass(const FusedArgs& a) {
+    static const char* const kFilterNames[3] = {"tiles_up_filter", "tiles_top_filter", "tiles_down_filter"};
+    const dim3 grid{unsigned(tiles_)}, block{unsigned(B)};
+    if (lin_ == SM_LIN_TAYLOR) {
+      hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R>), grid, block, lds_filter(), stream, a);
+    } else {
+      launch_linearize(slot_args(cur_), dim3(unsigned((S + kSlotBlock - 1) / kSlotBlock)));
+      hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R>), grid, block, lds_filter(), stream, a);
+    }
+    scan_tiles<FOp>(ta_f_, tc_f_, kFilterNames);
+    hipLaunchKernelGGL((k_forward_down_filter<Model, B, R>), grid, block, 0, stream, a);
+  }
+
+  sm_status objective(double* out) override {
+    const sm_status st = ensure_sums();
+    if (st != SM_OK) return st;
+    hipError_t e = hipSuccess;
     CostArgs a{};
     a.S = S;
     a.stride = stride;
@@ -560,14 +650,9 @@ class Engine final : public EngineBase {
     a.slot_cost = d_slot_cost_;
     hipLaunchKernelGGL((k_objective_slots<Model, R>), dim3(unsigned((S + kSlotBlock - 1) / kSlotBlock)),
                        dim3(kSlotBlock), 0, stream, a);
-    hipLaunchKernelGGL(k_objective_tracks, dim3(unsigned(ntracks)), dim3(kTrackSumB), 0, stream,
-                       static_cast<const double*>(d_slot_cost_), static_cast<const int64_t*>(d_slot_off_), d_cost_);
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(h_cost_, d_cost_, sizeof(double) * ntracks, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "objective"));
-    std::memcpy(out, h_cost_, sizeof(double) * ntracks);
-    return SM_OK;
+    return track_sums_to_host(out, "objective");
   }
 
   sm_status lm_mode(bool on) override {
@@ -635,6 +720,12 @@ class Engine final : public EngineBase {
     hipError_t e = hipMemcpyAsync(h.data(), d_traj_[cur_], sizeof(R) * h.size(), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "copy of the result"));
+    unpack_host(h, mean, cov);
+    return SM_OK;
+  }
+
+  // slot-major host arrays (full symmetric covariances) from a [N + s(N)][stride] copy
+  void unpack_host(const std::vector<R>& h, double* mean, double* cov) const {
     for (int64_t s = 0; s < S; ++s) {
       if (mean)
         for (int i = 0; i < N; ++i) mean[size_t(s) * N + i] = double(h[size_t(i) * stride + s]);
@@ -643,7 +734,6 @@ class Engine final : public EngineBase {
           for (int j = 0; j < N; ++j)
             cov[(size_t(s) * N + i) * N + j] = double(h[size_t(N + sym_index<N>(i, j)) * stride + s]);
     }
-    return SM_OK;
   }
 
   sm_status result_device(void* mean, void* cov) override { return result_device_placed(mean, cov, N, 0); }
@@ -716,6 +806,7 @@ class Engine final : public EngineBase {
   double *d_lam_ = nullptr, *h_lam_ = nullptr;
   void* d_saved_ = nullptr;
   unsigned char *d_reject_ = nullptr, *h_reject_ = nullptr;
+  unsigned long long* d_delta_spare_ = nullptr;   // statistic cleared by a filtering pass
   std::vector<void*> pinned_;
   void *d_trans_ = nullptr, *d_felem_ = nullptr, *d_selem_ = nullptr;
   void *lx_f_ = nullptr, *ta_f_ = nullptr, *tc_f_ = nullptr, *lx_s_ = nullptr, *ta_s_ = nullptr, *tc_s_ = nullptr;

@@ -110,6 +110,14 @@ class EngineBase {
     return fail(SM_EINVAL, "the MAP objective is not built for this engine");
   }
 
+  // One filtering pass linearised at the current trajectory, without damping:
+  // filtered moments of every slot (host, nullable) and log p(y_{1:T}) of the
+  // linearised model per track (nullable).  The trajectory, the iteration
+  // count and the per-track deltas are left as they are.
+  virtual sm_status filter(double*, double*, double*) {
+    return fail(SM_EINVAL, "the filtering pass is not built for this engine");
+  }
+
   // Levenberg-Marquardt hooks: per-track damping values replace the problem's
   // lm_lambda while the mode is on; save/restore keep the trajectory of the
   // tracks whose damped step is not taken.

@@ -287,6 +287,49 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
   if (rl == B - 1) SOp::store(static_cast<R*>(a.ta_s), size_t(a.tiles), rt, sacc);
 }
 
+// Filtering pass only: forward down-sweep that stores the filtered moments
+// (x*, P*) of every slot (the prefix of the filtering elements, Section 2).
+template <class Model, int B, typename R>
+__global__ __launch_bounds__(B) void k_forward_down_filter(FusedArgs a) {
+  constexpr int N = Model::N;
+  using FOp = FilterOp<N, R>;
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t base = (tile * B + lane) * a.K;
+  typename FOp::Carry c;
+  bool have = false;
+  if (tile > 0) {
+    FOp::load(static_cast<const R*>(a.tc_f), size_t(a.tiles), tile - 1, c);
+    have = true;
+  }
+  if (lane > 0) {
+    typename FOp::Elem ex;
+    FOp::load(static_cast<const R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
+    if (have) {
+      typename FOp::Carry n;
+      FOp::apply(c, ex, n);
+      c = n;
+    } else {
+      FOp::to_carry(ex, c);
+      have = true;
+    }
+  }
+  for (int j = 0; j < a.K; ++j) {
+    const int64_t s = base + j;
+    typename FOp::Elem e;
+    FOp::load(static_cast<const R*>(a.felem), a.stride, s, e);
+    if (have) {
+      typename FOp::Carry n;
+      FOp::apply(c, e, n);
+      c = n;
+    } else {
+      FOp::to_carry(e, c);
+      have = true;
+    }
+    FOp::store(static_cast<R*>(a.filt), a.stride, s, c);
+  }
+}
+
 PKS_DEV unsigned long long order_bits(double v) {
   // non-negative doubles and NaN order like their bit patterns as unsigned
   return static_cast<unsigned long long>(__double_as_longlong(v == v ? v : __builtin_nan("")));

@@ -79,8 +79,8 @@ __global__ __launch_bounds__(kSlotBlock) void k_objective_slots(CostArgs a) {
 constexpr int kTrackSumB = 256;
 
 // cost[t] = sum of slot_cost over the slots of track t (one workgroup per track).
-static __global__ __launch_bounds__(kTrackSumB) void k_objective_tracks(const double* slot_cost,
-                                                                        const int64_t* slot_off, double* cost) {
+static __global__ __launch_bounds__(kTrackSumB) void k_track_sums(const double* slot_cost, const int64_t* slot_off,
+                                                                  double* cost) {
   __shared__ double red[kTrackSumB];
   const int t = blockIdx.x;
   const int64_t lo = slot_off[t], hi = slot_off[t + 1];
@@ -93,6 +93,96 @@ static __global__ __launch_bounds__(kTrackSumB) void k_objective_tracks(const do
     __syncthreads();
   }
   if (threadIdx.x == 0) cost[t] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Log marginal likelihood of one linearised pass (Section 2: the filtering
+// prefix carries p(y_{1:k}) with its normalising constants).  By the chain
+// rule log p(y_{1:T}) = sum_k log p(y_k | y_{1:k-1}); each term is the
+// Gaussian predictive density of the surrogate model at slot k,
+//   N(ytil_k; H_k m-_k + d_k, S_k),  m-_k = F x*_{k-1} + c,
+//   S_k = H_k (F P*_{k-1} F^T + Q') H_k^T + R'_k,
+// from the filtered moments of slot k-1.  The first slot of a track has no
+// measurement and contributes 0.
+// ---------------------------------------------------------------------------
+struct LoglikArgs {
+  int64_t S;
+  size_t stride;
+  const unsigned char* flags;
+  const void* params;
+  const void* R;        // P x P
+  const void* yslot;    // [P][stride]
+  const void* traj;     // linearisation points (Taylor measurement rows are rebuilt from them)
+  const void* trans;    // transition rows (TransLayout) of each slot
+  const void* lin;      // optional LinLayout rows with the stored measurement linearisation
+  const void* filt;     // [N + s(N)][stride] filtered moments
+  SigmaRule rule;
+  double* slot_ll;      // [S]
+};
+
+template <class Model, typename R>
+__global__ __launch_bounds__(kSlotBlock) void k_loglik_slots(LoglikArgs a) {
+  constexpr int N = Model::N, P = Model::P;
+  using TL = TransLayout<N>;
+  using LL = LinLayout<N, P>;
+  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  if (s >= a.S) return;
+  if (a.flags[s] & kSlotFirst) {
+    a.slot_ll[s] = 0.0;
+    return;
+  }
+  const size_t st = a.stride;
+  R F[N][N], c[N], Qp[N][N], H[P][N], d[P], Rp[P][P], yt[P];
+  const R* tr = static_cast<const R*>(a.trans);
+  ld_mat<N, N>(tr + TL::kF * st, st, s - 1, F);
+  ld_vec<N>(tr + TL::kc * st, st, s - 1, c);
+  ld_sym<N>(tr + TL::kQ * st, st, s - 1, Qp);
+  if (a.lin) {
+    const R* lin = static_cast<const R*>(a.lin);
+    ld_mat<P, N>(lin + LL::kH * st, st, s, H);
+    ld_vec<P>(lin + LL::kd * st, st, s, d);
+    ld_sym<P>(lin + LL::kR * st, st, s, Rp);
+    ld_vec<P>(lin + LL::ky * st, st, s, yt);
+  } else {
+    const Model md{static_cast<const R*>(a.params)};
+    R x[N], Px[N][N], Rm[P][P], y[P];
+    ld_vec<N>(static_cast<const R*>(a.traj), st, s, x);
+    set_zero<N>(Px);
+    const R* Rg = static_cast<const R*>(a.R);
+    PKS_UNROLL for (int i = 0; i < P; ++i) PKS_UNROLL for (int j = 0; j < P; ++j) Rm[i][j] = Rg[i * P + j];
+    ld_vec<P>(static_cast<const R*>(a.yslot), st, s, y);
+    linearize_h<Model, R>(md, kTaylor, a.rule, Rm, x, Px, y, H, d, Rp, yt);
+  }
+  const R* filt = static_cast<const R*>(a.filt);
+  R xf[N], Pf[N][N], mp[N], Pp[N][N];
+  ld_vec<N>(filt, st, s - 1, xf);
+  ld_sym<N>(filt + N * st, st, s - 1, Pf);
+  mat_vec<N, N>(F, xf, mp);
+  PKS_UNROLL for (int i = 0; i < N; ++i) mp[i] += c[i];
+  sandwich_add<N, N>(F, Pf, Qp, Pp);
+  R HP[P][N], Sm[P][P], v[P], diag[P];
+  mat_mul<P, N, N>(H, Pp, HP);
+  PKS_UNROLL for (int i = 0; i < P; ++i)
+    PKS_UNROLL for (int j = i; j < P; ++j) {
+      R sum = Rp[i][j];
+      PKS_UNROLL for (int t = 0; t < N; ++t) sum += HP[i][t] * H[j][t];
+      Sm[i][j] = sum;
+      Sm[j][i] = sum;
+    }
+  const bool ok = chol_inplace<P>(Sm, diag);
+  PKS_UNROLL for (int i = 0; i < P; ++i) {
+    R sum = yt[i] - d[i];
+    PKS_UNROLL for (int t = 0; t < N; ++t) sum -= H[i][t] * mp[t];
+    v[i] = sum;
+  }
+  chol_fwd_vec<P>(Sm, v);
+  double quad = 0.0, logdet = 0.0;
+  PKS_UNROLL for (int i = 0; i < P; ++i) {
+    quad += double(v[i]) * double(v[i]);
+    logdet += 2.0 * log(double(diag[i]));
+  }
+  constexpr double kLog2Pi = 1.8378770664093454836;
+  a.slot_ll[s] = ok ? -0.5 * (P * kLog2Pi + logdet + quad) : __builtin_nan("");
 }
 
 // Puts back the saved trajectory (all `words` rows) at the slots of the tracks

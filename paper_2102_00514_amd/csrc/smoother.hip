@@ -391,6 +391,18 @@ sm_status smoother_iterate_until(smoother_t h, double tol, int32_t max_iter, int
   }
 }
 
+sm_status smoother_filter(smoother_t h, double* filt_mean, double* filt_cov, double* track_loglik) {
+  if (!h || !h->eng) return SM_ESTATE;
+  try {
+    const sm_status st = h->eng->filter(filt_mean, filt_cov, track_loglik);
+    if (st != SM_OK) h->err = h->eng->err;
+    return st;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return SM_EDEVICE;
+  }
+}
+
 sm_status smoother_objective(smoother_t h, double* track_cost) {
   if (!h || !h->eng) return SM_ESTATE;
   if (!track_cost) {

@@ -124,6 +124,7 @@ def test_null_handle_calls_are_state_errors():
     assert lib.smoother_result(None, None, None) == B.SM_ESTATE
     assert lib.smoother_track_deltas(None, None) == B.SM_ESTATE
     assert lib.smoother_objective(None, None) == B.SM_ESTATE
+    assert lib.smoother_filter(None, None, None, None) == B.SM_ESTATE
     assert lib.smoother_iterate_lm(None, 1e-2, 10.0, 1e-6, 10, None, None, None) == B.SM_ESTATE
     lib.smoother_destroy(None)   # NULL-safe
 

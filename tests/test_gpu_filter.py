@@ -1,0 +1,144 @@
+"""GPU parity of the filtering pass with the log marginal likelihood
+(smoother_filter) against the oracle's filter_loglik: filtered moments of every
+slot and log p(y_{1:T}) of the linearised model, per track (Section 2: the
+filtering prefix carries p(x_k | y_{1:k}) and p(y_{1:k})).
+
+Metric and FP64 gate as in test_gpu_parity; the log-likelihood is compared
+relative to its magnitude.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_00514_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2102_00514_amd import binding
+    return binding
+
+
+def assert_filter_parity(mean, cov, ll, ref, tol=TOL64, ll_tol=1e-10, what=""):
+    em = oracle.mean_error(mean, ref["filt_mean"])
+    ep = oracle.cov_error(cov, ref["filt_cov"])
+    el = abs(ll - ref["loglik"]) / max(abs(ref["loglik"]), 1.0)
+    print(f"{what}: e_m={em:.3e} e_P={ep:.3e} e_ll={el:.3e}", flush=True)
+    assert em < tol and ep < tol and el < ll_tol, (what, em, ep, el)
+
+
+@pytest.mark.parametrize("lin", ["taylor", "cubature", "unscented"])
+def test_c1_at_prior_and_after_iterations(B, lin):
+    pb = wl.config_c1()
+    with B.Smoother(pb, n_iter=3, lin=lin) as sm:
+        mean, cov, ll = sm.filter()
+        assert_filter_parity(mean, cov, ll[0], oracle.filter_loglik(pb, lin), what=f"C1 {lin} at the prior")
+        sm.iterate(0)
+        xm, xc = sm.result()
+        mean, cov, ll = sm.filter()
+    ref = oracle.filter_loglik(pb, lin, init_mean=xm, init_cov=xc)
+    assert_filter_parity(mean, cov, ll[0], ref, what=f"C1 {lin} after 3 iterations")
+
+
+@pytest.mark.parametrize("T", [1, 2, 65, 513, 32768])
+def test_lengths_and_c2_size(B, T):
+    pb = wl.config_c2(T) if T > 1 else wl.ct_bearings(1, seed=5)
+    with B.Smoother(pb, n_iter=1) as sm:
+        mean, cov, ll = sm.filter()
+    assert_filter_parity(mean, cov, ll[0], oracle.filter_loglik(pb), what=f"T={T}")
+
+
+@pytest.mark.parametrize("lanes,slots", [(64, 3), (256, 8)])
+def test_schedules(B, lanes, slots):
+    pb = wl.config_c2(3000)
+    with B.Smoother(pb, n_iter=1, lin="cubature", tile_lanes=lanes, lane_slots=slots) as sm:
+        mean, cov, ll = sm.filter()
+    assert_filter_parity(mean, cov, ll[0], oracle.filter_loglik(pb, "cubature"), what=f"{lanes}x{slots}")
+
+
+@pytest.mark.parametrize("scan", ["parallel", "sequential"])
+def test_ragged_linear_batch_is_exact_marginal_likelihood(B, scan):
+    pb = wl.linear_gaussian(3, 2, 400, seed=6, n_tracks=5, t_min=1)
+    with B.Smoother(pb, n_iter=1, scan=scan) as sm:
+        mean, cov, ll = sm.filter()
+    so = pb.slot_offsets()
+    for i in range(pb.n_tracks):
+        ref = oracle.filter_loglik(pb.track(i))
+        sl = slice(so[i], so[i + 1])
+        assert_filter_parity(mean[sl], cov[sl], ll[i], ref, what=f"{scan} linear track {i} T={pb.lengths[i]}")
+
+
+def test_pass_leaves_the_iteration_state(B):
+    pb = wl.config_c1()
+    with B.Smoother(pb, n_iter=2) as a, B.Smoother(pb, n_iter=2) as b:
+        a.iterate(2)
+        b.iterate(2)
+        before = a.result()
+        da = a.track_deltas()
+        a.filter()
+        after = a.result()
+        assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+        assert np.array_equal(da, a.track_deltas())
+        a.iterate(1)
+        b.iterate(1)
+        assert np.array_equal(a.result()[0], b.result()[0])
+        assert np.array_equal(a.result()[1], b.result()[1])
+
+
+def test_stacked_targets_sum_over_blocks(B):
+    pb = wl.config_c5_single(200)
+    with B.Smoother(pb, n_iter=1) as sm:
+        mean, cov, ll = sm.filter()
+    ref = oracle.filter_loglik(pb)
+    blk = np.zeros_like(ref["filt_cov"])
+    for t in range(4):
+        s = slice(5 * t, 5 * t + 5)
+        blk[:, s, s] = ref["filt_cov"][:, s, s]
+    assert_filter_parity(mean, cov, ll[0], {"filt_mean": ref["filt_mean"], "filt_cov": blk,
+                                            "loglik": ref["loglik"]}, what="stacked n=20 blocks")
+
+
+def test_fp32(B):
+    pb = wl.config_c1()
+    with B.Smoother(pb, n_iter=1, precision="f32") as sm:
+        mean, cov, ll = sm.filter()
+    ref = oracle.filter_loglik(pb)
+    em = oracle.mean_error(mean, ref["filt_mean"])
+    el = abs(ll[0] - ref["loglik"]) / abs(ref["loglik"])
+    print(f"FP32 filter: e_m={em:.3e} e_ll={el:.3e}", flush=True)
+    assert em < 1e-4 and el < 1e-4
+
+
+def test_dense_engine_rejects(B):
+    with B.Smoother(wl.config_c5_single(20), n_iter=1, lin="unscented") as sm:
+        with pytest.raises(B.SmootherError, match="not built"):
+            sm.filter()
+
+
+def test_measurement_noise_estimation(B):
+    """Parameter estimation with the marginal likelihood: on a T = 4096
+    coordinated-turn track, smooth to convergence under each candidate R, then
+    one filtering pass at the smoothed trajectory; the log-likelihood peaks at
+    the R the data were simulated with and matches the oracle's."""
+    base = wl.config_c2(4096)
+    scales = (0.5, 0.8, 1.0, 1.25, 2.0)
+    lls = []
+    for sc in scales:
+        pb = base.prefix(4096)
+        pb.R = base.R * sc
+        with B.Smoother(pb, n_iter=1) as sm:
+            run, first, ok = sm.iterate_until(1e-10, 60)
+            assert ok and first[0] > 0
+            xm, xc = sm.result()
+            _, _, ll = sm.filter(moments=False)
+        ref = oracle.filter_loglik(pb, init_mean=xm, init_cov=xc)
+        assert abs(ll[0] - ref["loglik"]) < 1e-9 * abs(ref["loglik"])
+        lls.append(ll[0])
+    print("log-likelihood by R scale:", dict(zip(scales, np.round(lls, 3))), flush=True)
+    assert int(np.argmax(lls)) == scales.index(1.0)
