@@ -439,6 +439,20 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                     "traffic": None if traffic is None else int(traffic),
                     "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": int(units_per_launch)}
+    filter_pass = None
+    if not dense:
+        # filtering pass with the log marginal likelihood at the current
+        # trajectory (host wall per call, including the per-track copy back)
+        for _ in range(3):
+            sm.filter(moments=False)
+        n_f = 20
+        w0 = time.perf_counter()
+        for _ in range(n_f):
+            _, _, ll = sm.filter(moments=False)
+        ms_f = (time.perf_counter() - w0) * 1e3 / n_f
+        filter_pass = {"ms_per_pass": round(ms_f, 4), "loglik_track0": float(ll[0]),
+                       "timing": "host wall per call, log-likelihood copied to the host"}
+        log(f"filtering pass with log-likelihood: {ms_f * 1e3:.1f} us per call")
     sm.close()
 
     warm = None
@@ -479,6 +493,7 @@ def main():
         "cpu_baseline": cpu,
         "warm_start": warm,
         "damping": damping,
+        "filter_pass": filter_pass,
     }
     print(json.dumps(out), flush=True)
 

@@ -75,26 +75,28 @@ PKS_DEV bool slr(int lin, SigmaRule rule, const R (&xbar)[N], const R (&Pbar)[N]
     PKS_UNROLL for (int j = 0; j < N; ++j) s += Zp[j][q] + Zm[j][q];
     g[q] = w0 * zc[q] + wj * s;
   }
-  // Phi = sum_j w_j (Z_j - zbar)(Z_j - zbar)^T, Delta_j = w_j gamma (Z_j^+ - Z_j^-)
-  R Phi[Q][Q];
-  PKS_UNROLL for (int a = 0; a < Q; ++a)
-    PKS_UNROLL for (int b = a; b < Q; ++b) {
-      R s = R(0);
-      PKS_UNROLL for (int j = 0; j < N; ++j)
-        s += (Zp[j][a] - g[a]) * (Zp[j][b] - g[b]) + (Zm[j][a] - g[a]) * (Zm[j][b] - g[b]);
-      s *= wj;
-      s += w0 * (zc[a] - g[a]) * (zc[b] - g[b]);
-      Phi[a][b] = s;
-      Phi[b][a] = s;
-    }
+  // Delta_j = w_j gamma (Z_j^+ - Z_j^-)
   R D[N][Q];
   const R wg = wj * gamma;
   PKS_UNROLL for (int j = 0; j < N; ++j) PKS_UNROLL for (int q = 0; q < Q; ++q) D[j][q] = wg * (Zp[j][q] - Zm[j][q]);
-  // Lambda = Phi - Delta^T Delta
+  // Lambda = Phi - G Pbar G^T = Phi - Delta^T Delta, evaluated as the weighted
+  // sum of outer products of the regression residuals
+  //   r_j^(+/-) = (Z_j^(+/-) - zbar) - G (X_j^(+/-) - xbar) = Z_j^(+/-) - zbar -/+ gamma Delta_j,
+  //   r_0 = zc - zbar (centre point).
+  // The two forms are equal; this one is positive semi-definite by
+  // construction (non-negative weights), where the difference of two nearly
+  // equal matrices can lose definiteness in FP32.
+  PKS_UNROLL for (int j = 0; j < N; ++j)
+    PKS_UNROLL for (int q = 0; q < Q; ++q) {
+      Zp[j][q] = Zp[j][q] - g[q] - gamma * D[j][q];
+      Zm[j][q] = Zm[j][q] - g[q] + gamma * D[j][q];
+    }
   PKS_UNROLL for (int a = 0; a < Q; ++a)
     PKS_UNROLL for (int b = a; b < Q; ++b) {
-      R s = Phi[a][b];
-      PKS_UNROLL for (int j = 0; j < N; ++j) s -= D[j][a] * D[j][b];
+      R s = R(0);
+      PKS_UNROLL for (int j = 0; j < N; ++j) s += Zp[j][a] * Zp[j][b] + Zm[j][a] * Zm[j][b];
+      s *= wj;
+      s += w0 * (zc[a] - g[a]) * (zc[b] - g[b]);
       Lam[a][b] = s;
       Lam[b][a] = s;
     }

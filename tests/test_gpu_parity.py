@@ -153,14 +153,32 @@ def test_result_device_into_torch(B):
     assert np.array_equal(m.cpu().numpy(), hm) and np.array_equal(P.cpu().numpy(), hP)
 
 
-def test_fp32_variant(B):
+@pytest.mark.parametrize("lin", ["taylor", "cubature", "unscented"])
+def test_fp32_variant(B, lin):
     pb = wl.config_c1()
-    ref = oracle.smoother(pb, 10, "taylor")
-    mean, cov, _, _ = run_gpu(B, pb, 10, "taylor", precision="f32")
+    ref = oracle.smoother(pb, 10, lin)
+    mean, cov, _, _ = run_gpu(B, pb, 10, lin, precision="f32")
     em = oracle.mean_error(mean, ref["mean"])
     ep = oracle.cov_error(cov, ref["cov"])
-    print(f"FP32 C1: e_m={em:.3e} e_P={ep:.3e}", flush=True)
+    print(f"FP32 C1 {lin}: e_m={em:.3e} e_P={ep:.3e}", flush=True)
     assert em < 1e-4 and ep < 1e-3
+
+
+@pytest.mark.parametrize("lin", ["taylor", "cubature"])
+def test_fp32_long_track(B, lin):
+    """FP32 at T = 2^15, one iteration from the prior and one from the
+    oracle's fourth iterate, against the FP64 oracle (bar 1e-4 on means and
+    covariances)."""
+    pb = wl.config_c2(2 ** 15)
+    for start in (0, 4):
+        ref = oracle.smoother(pb, start + 1, lin, history=True)
+        im = None if start == 0 else ref["hist_mean"][start - 1]
+        ic = None if start == 0 else ref["hist_cov"][start - 1]
+        mean, cov, _, _ = run_gpu(B, pb, 1, lin, init_mean=im, init_cov=ic, precision="f32")
+        em = oracle.mean_error(mean, ref["hist_mean"][start])
+        ep = oracle.cov_error(cov, ref["hist_cov"][start])
+        print(f"FP32 T=32768 {lin} iteration {start + 1}: e_m={em:.3e} e_P={ep:.3e}", flush=True)
+        assert em < 1e-4 and ep < 1e-4
 
 
 @pytest.mark.parametrize("lanes,slots", [(64, 1), (64, 2), (64, 3), (256, 1), (256, 2), (256, 4), (256, 8)])
