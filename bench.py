@@ -9,12 +9,13 @@ suffix-scan them, and reduce the convergence statistic.  Inputs are resident
 on the GPU before timing starts.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--lin taylor|cubature|unscented]
-                    [--workload c2|c3|c5|c2sweep]
+                    [--workload c2|c3|c5|c5batch|c2sweep]
 
 Other workloads (one JSON line each): c3, 4096 ragged tracks with T_i ~ U{100..8192}
 (cubature; steps = sum of T_i per iteration); c5, four stacked targets (nx = 20,
 eight bearings, T = 2^16, unscented) on the wavefront-cooperative engine, whose
-roofline is FP64 arithmetic; c2sweep, T = 2^10..2^15 on the GPU parallel and
+roofline is FP64 arithmetic; c5batch, 256 such tracks with T_i ~ U{1024..65536}
+in one ragged batch (~8.5e6 slots, ~133 GB of device memory); c2sweep, T = 2^10..2^15 on the GPU parallel and
 sequential paths (FP64 and FP32) and the CPU oracle.  The learned warm-start
 comparison runs with c2.
 
@@ -308,8 +309,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "c2sweep"],
-                    help="c2: one track, T=2^15 (default); c3: 4096 ragged tracks; c5: four stacked targets, T=2^16")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "c5batch", "c2sweep"],
+                    help="c2: one track, T=2^15 (default); c3: 4096 ragged tracks; c5: four stacked targets, "
+                         "T=2^16; c5batch: 256 ragged stacked tracks, T_i in [1024, 2^16]")
     ap.add_argument("--T", type=int, default=0, help="track length (c2: 2^15, c5: 2^16)")
     ap.add_argument("--lin", default=None, choices=["taylor", "cubature", "unscented"],
                     help="default: taylor (c2), cubature (c3), unscented (c5)")
@@ -355,16 +357,20 @@ def main():
         c2_sweep(args)
         return
     if args.lin is None:
-        args.lin = {"c2": "taylor", "c3": "cubature", "c5": "unscented"}[args.workload]
+        args.lin = {"c2": "taylor", "c3": "cubature", "c5": "unscented", "c5batch": "unscented"}[args.workload]
     if args.workload == "c2":
         pb = wl.config_c2(args.T or 2 ** 15)
         desc = f"coordinated-turn + 2 bearings, T={int(pb.offsets[1])}, single track"
     elif args.workload == "c3":
         pb = wl.config_c3()
         desc = "4096 coordinated-turn tracks, T_i ~ U{100..8192}, 2 bearings, one ragged batch"
-    else:
+    elif args.workload == "c5":
         pb = wl.config_c5_single(args.T or 2 ** 16)
         desc = f"4 stacked coordinated-turn targets (nx=20), 8 bearings, T={int(pb.offsets[1])}, single track"
+    else:
+        pb = wl.config_c5_batch()
+        desc = ("256 tracks of 4 stacked coordinated-turn targets (nx=20), 8 bearings, T_i ~ U{1024..65536}, "
+                "one ragged batch")
     T = int(pb.offsets[-1])            # smoothed steps per iteration (all tracks)
     dense = pb.nx == 20 and args.lin != "taylor"
     if args.workload != "c2":

@@ -310,13 +310,44 @@ def config_c5_single(T: int = 2 ** 16) -> Problem:
 
 def config_c5_batch(n_tracks: int = 256, t_min: int = 1024, t_max: int = 2 ** 16) -> Problem:
     """Ragged batch of stacked tracks sharing the single-track sensor layout;
-    track i draws its length and states from ``default_rng([5, 1 + i])``."""
-    sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (8, 2))
-    parts = []
+    track i draws its length and then, as ``stacked_ct``, its states and noises
+    from ``default_rng([5, 1 + i])``.  The tracks are simulated together, one
+    time step for all of them at once (the draws, and so the data, are those
+    of ``stacked_ct`` track by track, up to the rounding of the noise
+    products)."""
+    n_targets, n_sensors = 4, 8
+    sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (n_sensors, 2))
+    targets = np.arange(n_sensors) // (n_sensors // n_targets)
+    nx = 5 * n_targets
+    Q = ct_process_noise(n_targets=n_targets)
+    Lq = np.linalg.cholesky(Q)
+    Ts, x0s, procs, meass = [], [], [], []
     for i in range(n_tracks):
         rng = np.random.default_rng([5, 1 + i])
         T = int(rng.integers(t_min, t_max + 1))
-        parts.append(stacked_ct(T, rng, sensors=sensors))
+        x0s.append(np.concatenate([_random_ct_state(rng) for _ in range(n_targets)]))
+        procs.append(rng.standard_normal((T, nx)) @ Lq.T)
+        meass.append(rng.standard_normal((T, n_sensors)))
+        Ts.append(T)
+    Tmax = max(Ts)
+    noise = np.zeros((Tmax, n_tracks, nx))
+    for i, p in enumerate(procs):
+        noise[:Ts[i], i] = p
+    X = np.empty((Tmax + 1, n_tracks, nx))
+    X[0] = np.stack(x0s)
+    for k in range(1, Tmax + 1):
+        X[k] = _ct_propagate(X[k - 1].reshape(n_tracks, n_targets, 5), CT_DT).reshape(n_tracks, nx) + noise[k - 1]
+    parts = []
+    for i, T in enumerate(Ts):
+        xs = X[:T + 1, i]
+        px, py = xs[1:, 5 * targets], xs[1:, 5 * targets + 1]
+        y = wrap_angle(np.arctan2(py - sensors[:, 1], px - sensors[:, 0]) + CT_R_STD * meass[i])
+        m0 = xs[0].copy()
+        m0[4::5] = 0.0
+        parts.append(Problem(nx, n_sensors, MODEL_CT_BEARINGS, ct_params(sensors, targets), Q,
+                             CT_R_STD ** 2 * np.eye(n_sensors), m0[None], np.eye(nx)[None], y,
+                             np.array([0, T], dtype=np.int64), xs.copy(), f"stacked_ct(T={T})",
+                             {"sensors": sensors}))
     return concat_tracks(parts, f"c5_batch({n_tracks})")
 
 
