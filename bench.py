@@ -375,6 +375,7 @@ def main():
     dense = pb.nx == 20 and args.lin != "taylor"
     if args.workload != "c2":
         args.no_warm_start = True
+        args.no_damping = True
     stream = torch.cuda.current_stream()
     total_iters = args.warmup + args.steps + args.profile_iters
     tuned = None
