@@ -405,13 +405,16 @@ class Engine final : public EngineBase {
       run_scan<Op>(agg, tiles_, carry, names);
       return;
     }
+    // tile t reads the inclusive carry of tiles 0..t-1, so the last tile's
+    // aggregate is never needed: scan tiles_ - 1 positions (none for one tile)
+    if (tiles_ < 2) return;
     ScanArgs a{};
     a.elems = agg;
     a.estride = size_t(tiles_);
-    a.m = tiles_;
+    a.m = tiles_ - 1;
     a.out = carry;
     a.ostride = size_t(tiles_);
-    timed(names[1], tiles_, [&] {
+    timed(names[1], tiles_ - 1, [&] {
       hipLaunchKernelGGL((k_scan_single<Op, kTopB, R>), dim3(1), dim3(kTopB), sizeof(R) * Op::kElemWords * (kTopB / 64),
                          stream, a);
     });

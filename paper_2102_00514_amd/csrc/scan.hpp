@@ -41,29 +41,33 @@ struct ScanArgs {
 // (B > 64) only each wavefront's total goes through LDS: lds holds B/64
 // elements, entry-major with row stride B/64.  On exit v is the inclusive
 // prefix at q and, when has_ex (q > 0), ex the exclusive one.  Invalid lanes
-// must form a suffix of the scan order: no valid lane reads their values.
+// must form a suffix of the scan order: no valid lane reads their values.  A
+// wavefront whose lanes are all invalid passes active = false (wavefront-
+// uniform): it skips its combines and only takes part in the barrier.
 template <class Op, int B, bool FWD, typename R>
-PKS_DEV void block_ladder(R* lds, typename Op::Elem& v, typename Op::Elem& ex, bool& has_ex) {
+PKS_DEV void block_ladder(R* lds, typename Op::Elem& v, typename Op::Elem& ex, bool& has_ex, bool active = true) {
   constexpr int NW = B / 64;
   static_assert(B % 64 == 0, "whole wavefronts");
   const int pl = int(threadIdx.x), wl = pl & 63, w = pl >> 6;
   const int qw = FWD ? wl : 63 - wl;        // scan position inside the wavefront
   const int qwave = FWD ? w : NW - 1 - w;   // scan position of the wavefront
-  PKS_UNROLL for (int d = 1; d < 64; d <<= 1) {
-    typename Op::Elem left;
-    const int src = FWD ? (wl >= d ? wl - d : wl) : (wl + d < 64 ? wl + d : wl);
-    Op::shfl(v, src, left);
-    if (qw >= d) {
-      typename Op::Elem r;
-      Op::combine(left, v, r);
-      v = r;
+  if (active) {
+    PKS_UNROLL for (int d = 1; d < 64; d <<= 1) {
+      typename Op::Elem left;
+      const int src = FWD ? (wl >= d ? wl - d : wl) : (wl + d < 64 ? wl + d : wl);
+      Op::shfl(v, src, left);
+      if (qw >= d) {
+        typename Op::Elem r;
+        Op::combine(left, v, r);
+        v = r;
+      }
     }
   }
   typename Op::Elem wp;   // total of the wavefronts before this one (qwave > 0)
   if constexpr (NW > 1) {
-    if (qw == 63) Op::store(lds, NW, qwave, v);
+    if (active && qw == 63) Op::store(lds, NW, qwave, v);
     __syncthreads();
-    if (qwave > 0) {
+    if (active && qwave > 0) {
       Op::load(lds, NW, 0, wp);
       for (int k = 1; k < qwave; ++k) {
         typename Op::Elem t, r;
@@ -76,6 +80,8 @@ PKS_DEV void block_ladder(R* lds, typename Op::Elem& v, typename Op::Elem& ex, b
       v = r;
     }
   }
+  has_ex = false;
+  if (!active) return;
   const int src = FWD ? (wl > 0 ? wl - 1 : wl) : (wl < 63 ? wl + 1 : wl);
   Op::shfl(v, src, ex);
   has_ex = qw > 0;
@@ -111,7 +117,8 @@ __global__ __launch_bounds__(B) void k_scan_up(ScanArgs a) {
   }
   typename Op::Elem ex;
   bool has_ex;
-  block_ladder<Op, B, true, R>(lds, v, ex, has_ex);
+  const bool wave_active = (tile * B + (lane & ~63)) * a.K < a.m;
+  block_ladder<Op, B, true, R>(lds, v, ex, has_ex, wave_active);
   R* LX = static_cast<R*>(a.lane_excl);
   if (valid && has_ex) Op::store(LX, a.lstride, tile * B + lane, ex);
   // last valid lane of the tile publishes the tile aggregate
@@ -192,7 +199,7 @@ PKS_DEV void block_scan(R* lds, int lane, const R* E, size_t estride, int64_t m,
   }
   typename Op::Elem ex;
   bool has_ex;
-  block_ladder<Op, B, true, R>(lds, v, ex, has_ex);
+  block_ladder<Op, B, true, R>(lds, v, ex, has_ex, int64_t(lane & ~63) * K < m);
   if (!valid) return;
   typename Op::Carry c;
   bool have = false;
