@@ -540,7 +540,11 @@ class Engine final : public EngineBase {
   // log-likelihood, allocated on first use
   sm_status ensure_sums() {
     if (d_slot_cost_) return SM_OK;
+    int64_t longest = 0;
+    for (int t = 0; t < ntracks; ++t) longest = std::max<int64_t>(longest, slot_off_[t + 1] - slot_off_[t]);
+    sum_chunks_ = int((longest + kSumChunk - 1) / kSumChunk);
     hipError_t e = dalloc(reinterpret_cast<void**>(&d_slot_cost_), sizeof(double) * S);
+    if (e == hipSuccess) e = dalloc(reinterpret_cast<void**>(&d_partial_), sizeof(double) * ntracks * sum_chunks_);
     if (e == hipSuccess) e = dalloc(reinterpret_cast<void**>(&d_cost_), sizeof(double) * ntracks);
     if (e == hipSuccess) e = pinned_alloc(reinterpret_cast<void**>(&h_cost_), sizeof(double) * ntracks);
     if (e != hipSuccess) {
@@ -552,8 +556,11 @@ class Engine final : public EngineBase {
 
   // d_cost_ -> host, after the per-slot values have been queued
   sm_status track_sums_to_host(double* out, const char* what) {
-    hipLaunchKernelGGL(k_track_sums, dim3(unsigned(ntracks)), dim3(kTrackSumB), 0, stream,
-                       static_cast<const double*>(d_slot_cost_), static_cast<const int64_t*>(d_slot_off_), d_cost_);
+    hipLaunchKernelGGL(k_track_partials, dim3(unsigned(ntracks), unsigned(sum_chunks_)), dim3(kTrackSumB), 0, stream,
+                       static_cast<const double*>(d_slot_cost_), static_cast<const int64_t*>(d_slot_off_), ntracks,
+                       d_partial_);
+    hipLaunchKernelGGL(k_track_totals, dim3(unsigned((ntracks + kTrackSumB - 1) / kTrackSumB)), dim3(kTrackSumB), 0,
+                       stream, static_cast<const double*>(d_partial_), ntracks, sum_chunks_, d_cost_);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(h_cost_, d_cost_, sizeof(double) * ntracks, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -805,7 +812,8 @@ class Engine final : public EngineBase {
   void *d_y_ = nullptr, *d_traj_[2] = {nullptr, nullptr};
   void *d_lin_ = nullptr, *d_filt_ = nullptr;  // sequential path
   void *d_wq_ = nullptr, *d_wr_ = nullptr, *d_wp0_ = nullptr;  // whitening of Q, R, P0
-  double *d_slot_cost_ = nullptr, *d_cost_ = nullptr, *h_cost_ = nullptr;
+  double *d_slot_cost_ = nullptr, *d_cost_ = nullptr, *h_cost_ = nullptr, *d_partial_ = nullptr;
+  int sum_chunks_ = 1;
   double *d_lam_ = nullptr, *h_lam_ = nullptr;
   void* d_saved_ = nullptr;
   unsigned char *d_reject_ = nullptr, *h_reject_ = nullptr;

@@ -11,8 +11,9 @@
 // 1/2 |W r|^2.
 //
 // Slot s of the batch contributes its prior term (first slot of a track) or
-// its transition and measurement terms; one workgroup per track then sums its
-// slots in a fixed order, so the objective is deterministic.
+// its transition and measurement terms; the per-track sums then run in a
+// fixed order (chunks of a track in parallel, chunk totals in sequence), so
+// the objective is deterministic.
 #pragma once
 
 #include "slot_kernels.hpp"
@@ -77,22 +78,38 @@ __global__ __launch_bounds__(kSlotBlock) void k_objective_slots(CostArgs a) {
 }
 
 constexpr int kTrackSumB = 256;
+constexpr int64_t kSumChunk = 4096;   // slots per partial sum
 
-// cost[t] = sum of slot_cost over the slots of track t (one workgroup per track).
-static __global__ __launch_bounds__(kTrackSumB) void k_track_sums(const double* slot_cost, const int64_t* slot_off,
-                                                                  double* cost) {
+// Per-track sums in a fixed order, in two steps so that a long track is
+// spread over many workgroups: workgroup (t, c) sums chunk c of track t
+// (kSumChunk slots) into partial[c * ntracks + t] (0 past the track's end),
+// then one lane per track adds its chunks in order.
+static __global__ __launch_bounds__(kTrackSumB) void k_track_partials(const double* v, const int64_t* slot_off,
+                                                                      int ntracks, double* partial) {
   __shared__ double red[kTrackSumB];
   const int t = blockIdx.x;
-  const int64_t lo = slot_off[t], hi = slot_off[t + 1];
+  const int64_t c = blockIdx.y;
+  const int64_t end = slot_off[t + 1];
+  const int64_t lo = slot_off[t] + c * kSumChunk;
+  const int64_t hi = lo + kSumChunk < end ? lo + kSumChunk : end;
   double s = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kTrackSumB) s += slot_cost[i];
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kTrackSumB) s += v[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = kTrackSumB / 2; w > 0; w >>= 1) {
     if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) cost[t] = red[0];
+  if (threadIdx.x == 0) partial[c * ntracks + t] = red[0];
+}
+
+static __global__ __launch_bounds__(kTrackSumB) void k_track_totals(const double* partial, int ntracks, int nchunks,
+                                                                    double* out) {
+  const int t = int(blockIdx.x) * kTrackSumB + int(threadIdx.x);
+  if (t >= ntracks) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += partial[size_t(c) * ntracks + t];
+  out[t] = s;
 }
 
 // ---------------------------------------------------------------------------
