@@ -116,6 +116,8 @@ class Engine final : public EngineBase {
     sched_lanes = sched_.B;
     sched_slots = sched_.K;
     sched_tiles = tiles_;
+    // the sequential path walks slots one lane per track: plain slot order
+    map_ = SlotMap{sched_.B, seq_ ? 1 : sched_.K};
     std::vector<unsigned char> flags(S, 0);
     std::vector<int> track(S, 0);
     for (int i = 0; i < ntracks; ++i) {
@@ -149,7 +151,7 @@ class Engine final : public EngineBase {
     for (int t = 0; t < ntracks; ++t)
       for (int64_t k = 1; k < slot_off_[t + 1] - slot_off_[t]; ++k) {
         const int64_t s = slot_off_[t] + k, row = pb.offsets[t] + k - 1;
-        for (int i = 0; i < P; ++i) yslot[size_t(i) * stride + s] = R(pb.y[row * P + i]);
+        for (int i = 0; i < P; ++i) yslot[size_t(i) * stride + map_.col(s)] = R(pb.y[row * P + i]);
       }
     // device plan
     hipError_t e = hipSuccess;
@@ -239,7 +241,7 @@ class Engine final : public EngineBase {
       H2D(dm, mean.data(), sizeof(R) * mean.size());
       H2D(dc, cov.data(), sizeof(R) * cov.size());
       if (e == hipSuccess)
-        hipLaunchKernelGGL((k_pack<N, R>), dim3(grid), dim3(kSlotBlock), 0, stream, S, stride,
+        hipLaunchKernelGGL((k_pack<N, R>), dim3(grid), dim3(kSlotBlock), 0, stream, S, stride, map_,
                            static_cast<const R*>(dm), static_cast<const R*>(dc), Place{N, 0},
                            static_cast<R*>(d_traj_[0]));
       if (e == hipSuccess) e = hipGetLastError();
@@ -288,6 +290,12 @@ class Engine final : public EngineBase {
     return e;
   }
 
+  // grid of one lane per column of the per-slot arrays (padding included)
+  dim3 col_grid() const {
+    const int64_t cols = map_.K == 1 ? S : tiles_ * int64_t(sched_.B) * sched_.K;
+    return dim3(unsigned((cols + kSlotBlock - 1) / kSlotBlock));
+  }
+
   SlotArgs slot_args(int cur) const {
     SlotArgs a{};
     a.S = S;
@@ -309,6 +317,7 @@ class Engine final : public EngineBase {
     a.rule = rule_;
     a.lm = lm_;
     a.lm_track = lm_track_;
+    a.map = map_;
     return a;
   }
 
@@ -342,6 +351,7 @@ class Engine final : public EngineBase {
     a.rule = rule_;
     a.lm = lm_;
     a.lm_track = lm_track_;
+    a.map = map_;
     return a;
   }
 
@@ -431,7 +441,7 @@ class Engine final : public EngineBase {
         hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R>), grid, block, lds_filter(), stream, a);
       });
     } else {
-      const dim3 sgrid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
+      const dim3 sgrid = col_grid();
       const SlotArgs sa = slot_args(0);
       timed("linearize", S, [&] { launch_linearize(sa, sgrid); });
       timed("forward_up", S, [&] {
@@ -591,6 +601,7 @@ class Engine final : public EngineBase {
     la.filt = d_filt_;
     la.rule = rule_;
     la.slot_ll = d_slot_cost_;
+    la.map = map_;
     if (seq_) {
       // linearise, filter (the smoothed output goes to the spare trajectory
       // buffer and is discarded), then the predictive densities
@@ -613,7 +624,7 @@ class Engine final : public EngineBase {
       la.trans = d_trans_;
       la.lin = lin_ == SM_LIN_TAYLOR ? nullptr : d_lin_;
     }
-    hipLaunchKernelGGL((k_loglik_slots<Model, R>), grid, dim3(kSlotBlock), 0, stream, la);
+    hipLaunchKernelGGL((k_loglik_slots<Model, R>), col_grid(), dim3(kSlotBlock), 0, stream, la);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "filtering pass"));
     st = track_sums_to_host(loglik, "log-likelihood");
@@ -633,7 +644,7 @@ class Engine final : public EngineBase {
     if (lin_ == SM_LIN_TAYLOR) {
       hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R>), grid, block, lds_filter(), stream, a);
     } else {
-      launch_linearize(slot_args(cur_), dim3(unsigned((S + kSlotBlock - 1) / kSlotBlock)));
+      launch_linearize(slot_args(cur_), col_grid());
       hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R>), grid, block, lds_filter(), stream, a);
     }
     scan_tiles<FOp>(ta_f_, tc_f_, kFilterNames);
@@ -658,7 +669,8 @@ class Engine final : public EngineBase {
     a.wr = d_wr_;
     a.wp0 = d_wp0_;
     a.slot_cost = d_slot_cost_;
-    hipLaunchKernelGGL((k_objective_slots<Model, R>), dim3(unsigned((S + kSlotBlock - 1) / kSlotBlock)),
+    a.map = map_;
+    hipLaunchKernelGGL((k_objective_slots<Model, R>), col_grid(),
                        dim3(kSlotBlock), 0, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "objective"));
@@ -715,8 +727,8 @@ class Engine final : public EngineBase {
     std::memcpy(h_reject_, reject, ntracks);
     hipError_t e = hipMemcpyAsync(d_reject_, h_reject_, ntracks, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL((k_restore_tracks<R>), dim3(unsigned((S + kSlotBlock - 1) / kSlotBlock)), dim3(kSlotBlock),
-                         0, stream, S, stride, kTrajW, static_cast<const int*>(d_track_),
+      hipLaunchKernelGGL((k_restore_tracks<R>), col_grid(), dim3(kSlotBlock),
+                         0, stream, S, stride, map_, kTrajW, static_cast<const int*>(d_track_),
                          static_cast<const unsigned char*>(d_reject_), static_cast<const R*>(d_saved_),
                          static_cast<R*>(d_traj_[cur_]));
       e = hipGetLastError();
@@ -738,11 +750,11 @@ class Engine final : public EngineBase {
   void unpack_host(const std::vector<R>& h, double* mean, double* cov) const {
     for (int64_t s = 0; s < S; ++s) {
       if (mean)
-        for (int i = 0; i < N; ++i) mean[size_t(s) * N + i] = double(h[size_t(i) * stride + s]);
+        for (int i = 0; i < N; ++i) mean[size_t(s) * N + i] = double(h[size_t(i) * stride + map_.col(s)]);
       if (cov)
         for (int i = 0; i < N; ++i)
           for (int j = 0; j < N; ++j)
-            cov[(size_t(s) * N + i) * N + j] = double(h[size_t(N + sym_index<N>(i, j)) * stride + s]);
+            cov[(size_t(s) * N + i) * N + j] = double(h[size_t(N + sym_index<N>(i, j)) * stride + map_.col(s)]);
     }
   }
 
@@ -750,7 +762,7 @@ class Engine final : public EngineBase {
 
   sm_status result_device_placed(void* mean, void* cov, int ld, int off) override {
     const dim3 grid(unsigned((S + kSlotBlock - 1) / kSlotBlock));
-    hipLaunchKernelGGL((k_unpack<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride,
+    hipLaunchKernelGGL((k_unpack<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, map_,
                        static_cast<const R*>(d_traj_[cur_]), static_cast<R*>(mean), static_cast<R*>(cov),
                        Place{ld, off});
     const hipError_t e = hipGetLastError();
@@ -770,17 +782,17 @@ class Engine final : public EngineBase {
     const R* m = static_cast<const R*>(mean);
     const Place pl{ld, off};
     if (cov) {
-      hipLaunchKernelGGL((k_pack<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, static_cast<const R*>(cov),
+      hipLaunchKernelGGL((k_pack<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, map_, m, static_cast<const R*>(cov),
                          pl, traj);
     } else if (cov_const) {
       SymConst<N, R> c;
       for (int i = 0; i < N; ++i)
         for (int j = i; j < N; ++j)
           c.v[sym_index<N>(i, j)] = R(0.5 * (cov_const[i * N + j] + cov_const[j * N + i]));
-      hipLaunchKernelGGL((k_pack_const<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, pl, c, traj);
+      hipLaunchKernelGGL((k_pack_const<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, map_, m, pl, c, traj);
     } else {
       hipLaunchKernelGGL((k_broadcast_prior<N, R>), grid, dim3(kSlotBlock), 0, stream, slot_args(cur_), traj);
-      hipLaunchKernelGGL((k_set_mean<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, m, pl, traj);
+      hipLaunchKernelGGL((k_set_mean<N, R>), grid, dim3(kSlotBlock), 0, stream, S, stride, map_, m, pl, traj);
     }
     hipLaunchKernelGGL(k_fill_u64, dim3((ntracks + 256) / 256), dim3(256), 0, stream, delta_bits,
                        int64_t(ntracks + 1), 0ull);
@@ -799,6 +811,7 @@ class Engine final : public EngineBase {
   SigmaRule rule_{1.0, 1.0};
   double lm_ = 0.0;
   double* lm_track_ = nullptr;          // per-track damping while adaptive damping runs
+  SlotMap map_{64, 1};                  // slot -> column of the per-slot arrays
   int cur_ = 0;
   Schedule sched_;
   int64_t tiles_ = 0;

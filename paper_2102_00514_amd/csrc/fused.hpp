@@ -33,6 +33,30 @@ namespace pks {
 
 enum : unsigned { kSlotFirst = 1u, kSlotLast = 2u };
 
+// Column of slot s in the per-slot arrays.  A tile of B lanes x K slots
+// stores the j-th of lane l's K consecutive slots at column
+// tile * B * K + j * B + l: for each j the lanes of a wavefront touch
+// consecutive columns (coalesced), and every lane still owns a contiguous run
+// of slots for its sequential fold.  K = 1 is the identity.
+struct SlotMap {
+  int B, K;
+  PKS_HD int64_t col(int64_t s) const {
+    if (K == 1) return s;
+    const int64_t bk = int64_t(B) * K;
+    const int64_t t = s / bk, r = s - t * bk;
+    const int64_t l = r / K;
+    return t * bk + (r - l * K) * B + l;
+  }
+  // inverse: the slot stored at column c (>= S for the padding of the last tile)
+  PKS_HD int64_t slot(int64_t c) const {
+    if (K == 1) return c;
+    const int64_t bk = int64_t(B) * K;
+    const int64_t t = c / bk, r = c - t * bk;
+    const int64_t j = r / B;
+    return t * bk + (r - j * B) * K + j;
+  }
+};
+
 struct FusedArgs {
   int64_t S;            // real slots
   size_t stride;        // row stride of every slot array (>= padded slots)
@@ -58,6 +82,7 @@ struct FusedArgs {
   SigmaRule rule;
   double lm;            // Levenberg-Marquardt damping lambda (0 = undamped)
   const double* lm_track;  // optional [ntracks]: per-track damping, replaces lm
+  SlotMap map;          // slot -> column of the per-slot arrays
 };
 
 // Linearisation arrays written by the separate linearisation pass: transition
@@ -93,7 +118,7 @@ PKS_DEV bool lm_damp_slot(const FusedArgs& a, int64_t s, typename FilterOp<N, R>
   const double lam = a.lm_track ? a.lm_track[a.track[s]] : a.lm;
   if (!(lam > 0.0)) return true;
   R xb[N];
-  ld_vec<N>(static_cast<const R*>(a.traj), a.stride, s, xb);
+  ld_vec<N>(static_cast<const R*>(a.traj), a.stride, a.map.col(s), xb);
   const bool ok = lm_damp_element<N, R>(R(lam), xb, e.A, e.b, e.C, e.eta, e.J);
   if (!ok) e.b[0] = quiet_nan<R>();
   return ok;
@@ -123,40 +148,41 @@ PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename Filter
     return;
   }
   R F[N][N], c[N], Qp[N][N], H[P][N], d[P], Rp[P][P], yt[P];
+  const int64_t cp = a.map.col(s - 1), cs = a.map.col(s);
   if constexpr (SRC == kStoredLin) {
     // transition into s from slot s-1, measurement model at s (LinLayout of the
     // linearisation pass; its first rows are the TransLayout rows)
     using LL = LinLayout<N, P>;
     const R* lin = static_cast<const R*>(a.trans);
-    ld_mat<N, N>(lin + LL::kF * st, st, s - 1, F);
-    ld_vec<N>(lin + LL::kc * st, st, s - 1, c);
-    ld_sym<N>(lin + LL::kQ * st, st, s - 1, Qp);
-    ld_mat<P, N>(lin + LL::kH * st, st, s, H);
-    ld_vec<P>(lin + LL::kd * st, st, s, d);
-    ld_sym<P>(lin + LL::kR * st, st, s, Rp);
-    ld_vec<P>(lin + LL::ky * st, st, s, yt);
+    ld_mat<N, N>(lin + LL::kF * st, st, cp, F);
+    ld_vec<N>(lin + LL::kc * st, st, cp, c);
+    ld_sym<N>(lin + LL::kQ * st, st, cp, Qp);
+    ld_mat<P, N>(lin + LL::kH * st, st, cs, H);
+    ld_vec<P>(lin + LL::kd * st, st, cs, d);
+    ld_sym<P>(lin + LL::kR * st, st, cs, Rp);
+    ld_vec<P>(lin + LL::ky * st, st, cs, yt);
   } else {
     const Model md{static_cast<const R*>(a.params)};
     const R* traj = static_cast<const R*>(a.traj);
     {
       R xp[N], Pp[N][N], Qm[N][N];
-      ld_vec<N>(traj, st, s - 1, xp);
+      ld_vec<N>(traj, st, cp, xp);
       set_zero<N>(Pp);
       const R* Qg = static_cast<const R*>(a.Q);
       PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) Qm[i][j] = Qg[i * N + j];
       linearize_f<Model, R>(md, kTaylor, a.rule, Qm, xp, Pp, F, c, Qp);
       R* tr = static_cast<R*>(a.trans);
-      st_mat<N, N>(tr + TL::kF * st, st, s - 1, F);
-      st_vec<N>(tr + TL::kc * st, st, s - 1, c);
-      st_sym<N>(tr + TL::kQ * st, st, s - 1, Qp);
+      st_mat<N, N>(tr + TL::kF * st, st, cp, F);
+      st_vec<N>(tr + TL::kc * st, st, cp, c);
+      st_sym<N>(tr + TL::kQ * st, st, cp, Qp);
     }
     {
       R x[N], Px[N][N], Rm[P][P], y[P];
-      ld_vec<N>(traj, st, s, x);
+      ld_vec<N>(traj, st, cs, x);
       set_zero<N>(Px);
       const R* Rg = static_cast<const R*>(a.R);
       PKS_UNROLL for (int i = 0; i < P; ++i) PKS_UNROLL for (int j = 0; j < P; ++j) Rm[i][j] = Rg[i * P + j];
-      ld_vec<P>(static_cast<const R*>(a.yslot), st, s, y);
+      ld_vec<P>(static_cast<const R*>(a.yslot), st, cs, y);
       linearize_h<Model, R>(md, kTaylor, a.rule, Rm, x, Px, y, H, d, Rp, yt);
     }
   }
@@ -174,26 +200,27 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t base = (tile * B + lane) * a.K;
+  const int64_t cbase = tile * B * a.K + lane;   // column of slot base + j: cbase + j * B
   if (tile == 0)
     for (int i = lane; i <= a.ntracks; i += B) a.delta_bits[i] = 0ull;
   R* felem = static_cast<R*>(a.felem);
   typename Op::Elem acc;
   if (a.K == 1) {
     build_filter_element<Model, SRC, R>(a, base, acc);
-    Op::store(felem, a.stride, base, acc);
+    Op::store(felem, a.stride, cbase, acc);
   } else {
     // build and store all K elements first, then fold them back from memory:
     // the running aggregate is never live while a slot is linearised
     for (int j = 0; j < a.K; ++j) {
       typename Op::Elem e;
       build_filter_element<Model, SRC, R>(a, base + j, e);
-      Op::store(felem, a.stride, base + j, e);
+      Op::store(felem, a.stride, cbase + int64_t(j) * B, e);
     }
-    Op::load(felem, a.stride, base, acc);
+    Op::load(felem, a.stride, cbase, acc);
   }
   for (int j = 1; j < a.K; ++j) {
     typename Op::Elem e, r;
-    Op::load(felem, a.stride, base + j, e);
+    Op::load(felem, a.stride, cbase + int64_t(j) * B, e);
     Op::combine(acc, e, r);
     acc = r;
   }
@@ -235,11 +262,12 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
     }
   }
   typename SOp::Elem sacc;
+  const int64_t cbase = tile * B * a.K + lane;
   for (int j = 0; j < a.K; ++j) {
-    const int64_t s = base + j;
+    const int64_t s = base + j, cs = cbase + int64_t(j) * B;
     {
       typename FOp::Elem e;
-      FOp::load(static_cast<const R*>(a.felem), st, s, e);
+      FOp::load(static_cast<const R*>(a.felem), st, cs, e);
       if (have) {
         typename FOp::Carry n;
         FOp::apply(c, e, n);
@@ -249,7 +277,7 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
         have = true;
       }
     }
-    if (a.filt) FOp::store(static_cast<R*>(a.filt), st, s, c);
+    if (a.filt) FOp::store(static_cast<R*>(a.filt), st, cs, c);
     typename SOp::Elem se;
     const unsigned fl = s < a.S ? a.flags[s] : (kSlotFirst | kSlotLast);
     if (fl & kSlotLast) {
@@ -261,13 +289,13 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
     } else {
       const R* tr = static_cast<const R*>(a.trans);
       R F[N][N], cc[N], Qp[N][N];
-      ld_mat<N, N>(tr + TL::kF * st, st, s, F);
-      ld_vec<N>(tr + TL::kc * st, st, s, cc);
-      ld_sym<N>(tr + TL::kQ * st, st, s, Qp);
+      ld_mat<N, N>(tr + TL::kF * st, st, cs, F);
+      ld_vec<N>(tr + TL::kc * st, st, cs, cc);
+      ld_sym<N>(tr + TL::kQ * st, st, cs, Qp);
       const bool ok = smoother_element<N, R>(c.b, c.C, F, cc, Qp, se.E, se.g, se.L);
       if (!ok) se.g[0] = quiet_nan<R>();
     }
-    SOp::store(static_cast<R*>(a.selem), st, s, se);
+    SOp::store(static_cast<R*>(a.selem), st, cs, se);
     // paper order: sacc covers earlier slots, so sacc <- sacc (x) se, i.e. the
     // scan-order combine with se first
     if (j == 0) {
@@ -295,7 +323,6 @@ __global__ __launch_bounds__(B) void k_forward_down_filter(FusedArgs a) {
   using FOp = FilterOp<N, R>;
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
-  const int64_t base = (tile * B + lane) * a.K;
   typename FOp::Carry c;
   bool have = false;
   if (tile > 0) {
@@ -314,10 +341,11 @@ __global__ __launch_bounds__(B) void k_forward_down_filter(FusedArgs a) {
       have = true;
     }
   }
+  const int64_t cbase = tile * B * a.K + lane;
   for (int j = 0; j < a.K; ++j) {
-    const int64_t s = base + j;
+    const int64_t cs = cbase + int64_t(j) * B;
     typename FOp::Elem e;
-    FOp::load(static_cast<const R*>(a.felem), a.stride, s, e);
+    FOp::load(static_cast<const R*>(a.felem), a.stride, cs, e);
     if (have) {
       typename FOp::Carry n;
       FOp::apply(c, e, n);
@@ -326,7 +354,7 @@ __global__ __launch_bounds__(B) void k_forward_down_filter(FusedArgs a) {
       FOp::to_carry(e, c);
       have = true;
     }
-    FOp::store(static_cast<R*>(a.filt), a.stride, s, c);
+    FOp::store(static_cast<R*>(a.filt), a.stride, cs, c);
   }
 }
 
@@ -374,10 +402,11 @@ __global__ __launch_bounds__(B) void k_backward_down(FusedArgs a) {
   }
   R* traj = static_cast<R*>(a.traj);
   unsigned long long lane_max = 0ull;
+  const int64_t cbase = tile * B * a.K + lane;
   for (int j = a.K - 1; j >= 0; --j) {
-    const int64_t s = base + j;
+    const int64_t s = base + j, cs = cbase + int64_t(j) * B;
     typename SOp::Elem e;
-    SOp::load(static_cast<const R*>(a.selem), st, s, e);
+    SOp::load(static_cast<const R*>(a.selem), st, cs, e);
     if (have) {
       typename SOp::Carry n;
       SOp::apply(c, e, n);
@@ -390,12 +419,12 @@ __global__ __launch_bounds__(B) void k_backward_down(FusedArgs a) {
       double m = 0.0;
       bool nan = false;
       PKS_UNROLL for (int i = 0; i < N; ++i) {
-        const double dlt = fabs(double(c.g[i]) - double(traj[i * st + s]));
+        const double dlt = fabs(double(c.g[i]) - double(traj[i * st + cs]));
         nan = nan || !(dlt == dlt);
         m = dlt > m ? dlt : m;
       }
       const unsigned long long b = order_bits(nan ? __builtin_nan("") : m);
-      SOp::store(traj, st, s, c);
+      SOp::store(traj, st, cs, c);
       if (s_track < 0) atomicMax(&a.delta_bits[a.track[s]], b);
       lane_max = b > lane_max ? b : lane_max;
     }

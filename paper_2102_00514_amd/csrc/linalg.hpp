@@ -11,6 +11,7 @@
 namespace pks {
 
 #define PKS_DEV __device__ __forceinline__
+#define PKS_HD __host__ __device__ __forceinline__
 #define PKS_UNROLL _Pragma("unroll")
 
 // Number of entries of an upper-packed symmetric N x N matrix.

@@ -33,7 +33,8 @@ struct CostArgs {
   const void* wq;       // N x N row-major lower triangular
   const void* wr;       // P x P
   const void* wp0;      // [ntracks][N][N]
-  double* slot_cost;    // [S]
+  double* slot_cost;    // [S], slot order
+  SlotMap map;          // slot -> column of the per-slot arrays
 };
 
 template <int N, typename R>
@@ -47,14 +48,17 @@ PKS_DEV R half_sq_whitened(const R* W, const R (&r)[N]) {
   return R(0.5) * s;
 }
 
+// One lane per column of the per-slot arrays, launched over the padded
+// column range; the result goes to slot order.
 template <class Model, typename R>
 __global__ __launch_bounds__(kSlotBlock) void k_objective_slots(CostArgs a) {
   constexpr int N = Model::N, P = Model::P;
-  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  const int64_t cs = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  const int64_t s = a.map.slot(cs);
   if (s >= a.S) return;
   const R* traj = static_cast<const R*>(a.traj);
   R x[N], r[N];
-  ld_vec<N>(traj, a.stride, s, x);
+  ld_vec<N>(traj, a.stride, cs, x);
   R c;
   if (a.flags[s] & kSlotFirst) {
     const int tr = a.track[s];
@@ -65,12 +69,12 @@ __global__ __launch_bounds__(kSlotBlock) void k_objective_slots(CostArgs a) {
   } else {
     const Model md{static_cast<const R*>(a.params)};
     R xp[N], fx[N], hx[P], y[P], e[P];
-    ld_vec<N>(traj, a.stride, s - 1, xp);
+    ld_vec<N>(traj, a.stride, a.map.col(s - 1), xp);
     md.f(xp, fx);
     PKS_UNROLL for (int i = 0; i < N; ++i) r[i] = x[i] - fx[i];
     c = half_sq_whitened<N, R>(static_cast<const R*>(a.wq), r);
     md.h(x, hx);
-    ld_vec<P>(static_cast<const R*>(a.yslot), a.stride, s, y);
+    ld_vec<P>(static_cast<const R*>(a.yslot), a.stride, cs, y);
     PKS_UNROLL for (int i = 0; i < P; ++i) e[i] = Model::kAngular ? wrap_pi<R>(y[i] - hx[i]) : y[i] - hx[i];
     c += half_sq_whitened<P, R>(static_cast<const R*>(a.wr), e);
   }
@@ -134,7 +138,8 @@ struct LoglikArgs {
   const void* lin;      // optional LinLayout rows with the stored measurement linearisation
   const void* filt;     // [N + s(N)][stride] filtered moments
   SigmaRule rule;
-  double* slot_ll;      // [S]
+  double* slot_ll;      // [S], slot order
+  SlotMap map;          // slot -> column of the per-slot arrays
 };
 
 template <class Model, typename R>
@@ -142,38 +147,39 @@ __global__ __launch_bounds__(kSlotBlock) void k_loglik_slots(LoglikArgs a) {
   constexpr int N = Model::N, P = Model::P;
   using TL = TransLayout<N>;
   using LL = LinLayout<N, P>;
-  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  const int64_t s = a.map.slot(int64_t(blockIdx.x) * kSlotBlock + threadIdx.x);
   if (s >= a.S) return;
   if (a.flags[s] & kSlotFirst) {
     a.slot_ll[s] = 0.0;
     return;
   }
   const size_t st = a.stride;
+  const int64_t cp = a.map.col(s - 1), cs = a.map.col(s);
   R F[N][N], c[N], Qp[N][N], H[P][N], d[P], Rp[P][P], yt[P];
   const R* tr = static_cast<const R*>(a.trans);
-  ld_mat<N, N>(tr + TL::kF * st, st, s - 1, F);
-  ld_vec<N>(tr + TL::kc * st, st, s - 1, c);
-  ld_sym<N>(tr + TL::kQ * st, st, s - 1, Qp);
+  ld_mat<N, N>(tr + TL::kF * st, st, cp, F);
+  ld_vec<N>(tr + TL::kc * st, st, cp, c);
+  ld_sym<N>(tr + TL::kQ * st, st, cp, Qp);
   if (a.lin) {
     const R* lin = static_cast<const R*>(a.lin);
-    ld_mat<P, N>(lin + LL::kH * st, st, s, H);
-    ld_vec<P>(lin + LL::kd * st, st, s, d);
-    ld_sym<P>(lin + LL::kR * st, st, s, Rp);
-    ld_vec<P>(lin + LL::ky * st, st, s, yt);
+    ld_mat<P, N>(lin + LL::kH * st, st, cs, H);
+    ld_vec<P>(lin + LL::kd * st, st, cs, d);
+    ld_sym<P>(lin + LL::kR * st, st, cs, Rp);
+    ld_vec<P>(lin + LL::ky * st, st, cs, yt);
   } else {
     const Model md{static_cast<const R*>(a.params)};
     R x[N], Px[N][N], Rm[P][P], y[P];
-    ld_vec<N>(static_cast<const R*>(a.traj), st, s, x);
+    ld_vec<N>(static_cast<const R*>(a.traj), st, cs, x);
     set_zero<N>(Px);
     const R* Rg = static_cast<const R*>(a.R);
     PKS_UNROLL for (int i = 0; i < P; ++i) PKS_UNROLL for (int j = 0; j < P; ++j) Rm[i][j] = Rg[i * P + j];
-    ld_vec<P>(static_cast<const R*>(a.yslot), st, s, y);
+    ld_vec<P>(static_cast<const R*>(a.yslot), st, cs, y);
     linearize_h<Model, R>(md, kTaylor, a.rule, Rm, x, Px, y, H, d, Rp, yt);
   }
   const R* filt = static_cast<const R*>(a.filt);
   R xf[N], Pf[N][N], mp[N], Pp[N][N];
-  ld_vec<N>(filt, st, s - 1, xf);
-  ld_sym<N>(filt + N * st, st, s - 1, Pf);
+  ld_vec<N>(filt, st, cp, xf);
+  ld_sym<N>(filt + N * st, st, cp, Pf);
   mat_vec<N, N>(F, xf, mp);
   PKS_UNROLL for (int i = 0; i < N; ++i) mp[i] += c[i];
   sandwich_add<N, N>(F, Pf, Qp, Pp);
@@ -205,12 +211,13 @@ __global__ __launch_bounds__(kSlotBlock) void k_loglik_slots(LoglikArgs a) {
 // Puts back the saved trajectory (all `words` rows) at the slots of the tracks
 // whose damped step was not taken.
 template <typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_restore_tracks(int64_t S, size_t stride, int words, const int* track,
-                                                               const unsigned char* reject, const R* saved,
-                                                               R* traj) {
-  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+__global__ __launch_bounds__(kSlotBlock) void k_restore_tracks(int64_t S, size_t stride, SlotMap map, int words,
+                                                               const int* track, const unsigned char* reject,
+                                                               const R* saved, R* traj) {
+  const int64_t cs = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  const int64_t s = map.slot(cs);
   if (s >= S || !reject[track[s]]) return;
-  for (int w = 0; w < words; ++w) traj[size_t(w) * stride + s] = saved[size_t(w) * stride + s];
+  for (int w = 0; w < words; ++w) traj[size_t(w) * stride + cs] = saved[size_t(w) * stride + cs];
 }
 
 }  // namespace pks

@@ -33,15 +33,19 @@ struct SlotArgs {
   SigmaRule rule;
   double lm;            // Levenberg-Marquardt damping lambda (0 = undamped)
   const double* lm_track;  // optional [ntracks]: per-track damping, replaces lm
+  SlotMap map;          // slot -> column of the per-slot arrays
 };
 
 constexpr int kSlotBlock = 256;
 
+// One lane per column of the per-slot arrays (coalesced), launched over the
+// padded column range.
 template <class Model, int LIN, typename R>
 __global__ __launch_bounds__(kSlotBlock) void k_linearize(SlotArgs a) {
   constexpr int N = Model::N, P = Model::P;
   using LL = LinLayout<N, P>;
-  const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  const int64_t cs = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
+  const int64_t s = a.map.slot(cs);
   if (s >= a.S) return;
   const unsigned fl = a.flags[s];
   const R* traj = static_cast<const R*>(a.traj);
@@ -49,28 +53,28 @@ __global__ __launch_bounds__(kSlotBlock) void k_linearize(SlotArgs a) {
   const size_t st = a.stride;
   Model md{static_cast<const R*>(a.params)};
   R xb[N], Pb[N][N];
-  ld_vec<N>(traj, st, s, xb);
-  if constexpr (LIN != kTaylor) ld_sym<N>(traj + N * st, st, s, Pb);
+  ld_vec<N>(traj, st, cs, xb);
+  if constexpr (LIN != kTaylor) ld_sym<N>(traj + N * st, st, cs, Pb);
   else set_zero<N>(Pb);
   if (!(fl & kSlotLast)) {
     R Qm[N][N], F[N][N], c[N], Qp[N][N];
     PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) Qm[i][j] = static_cast<const R*>(a.Q)[i * N + j];
     const bool ok = linearize_f<Model, R>(md, LIN, a.rule, Qm, xb, Pb, F, c, Qp);
     if (!ok) c[0] = quiet_nan<R>();
-    st_mat<N, N>(lin + LL::kF * st, st, s, F);
-    st_vec<N>(lin + LL::kc * st, st, s, c);
-    st_sym<N>(lin + LL::kQ * st, st, s, Qp);
+    st_mat<N, N>(lin + LL::kF * st, st, cs, F);
+    st_vec<N>(lin + LL::kc * st, st, cs, c);
+    st_sym<N>(lin + LL::kQ * st, st, cs, Qp);
   }
   if (!(fl & kSlotFirst)) {
     R Rm[P][P], y[P], H[P][N], d[P], Rp[P][P], yt[P];
     PKS_UNROLL for (int i = 0; i < P; ++i) PKS_UNROLL for (int j = 0; j < P; ++j) Rm[i][j] = static_cast<const R*>(a.R)[i * P + j];
-    ld_vec<P>(static_cast<const R*>(a.yslot), st, s, y);
+    ld_vec<P>(static_cast<const R*>(a.yslot), st, cs, y);
     const bool ok = linearize_h<Model, R>(md, LIN, a.rule, Rm, xb, Pb, y, H, d, Rp, yt);
     if (!ok) d[0] = quiet_nan<R>();
-    st_mat<P, N>(lin + LL::kH * st, st, s, H);
-    st_vec<P>(lin + LL::kd * st, st, s, d);
-    st_sym<P>(lin + LL::kR * st, st, s, Rp);
-    st_vec<P>(lin + LL::ky * st, st, s, yt);
+    st_mat<P, N>(lin + LL::kH * st, st, cs, H);
+    st_vec<P>(lin + LL::kd * st, st, cs, d);
+    st_sym<P>(lin + LL::kR * st, st, cs, Rp);
+    st_vec<P>(lin + LL::ky * st, st, cs, yt);
   }
 }
 
@@ -94,8 +98,9 @@ __global__ __launch_bounds__(kSlotBlock) void k_delta(SlotArgs a) {
     const R* n = static_cast<const R*>(a.traj_out);
     double m = 0.0;
     bool nan = false;
+    const int64_t cs = a.map.col(s);
     PKS_UNROLL for (int i = 0; i < N; ++i) {
-      const double d = fabs(double(n[i * a.stride + s]) - double(o[i * a.stride + s]));
+      const double d = fabs(double(n[i * a.stride + cs]) - double(o[i * a.stride + cs]));
       nan = nan || !(d == d);
       m = d > m ? d : m;
     }
@@ -129,8 +134,9 @@ __global__ __launch_bounds__(kSlotBlock) void k_broadcast_prior(SlotArgs a, R* t
   constexpr int W = N + sym_size<N>();
   const R* m0 = static_cast<const R*>(a.m0);
   const R* P0 = static_cast<const R*>(a.P0);
-  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * a.stride + s] = m0[i * a.tstride + tr];
-  PKS_UNROLL for (int i = 0; i < W - N; ++i) traj[(N + i) * a.stride + s] = P0[i * a.tstride + tr];
+  const int64_t cs = a.map.col(s);
+  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * a.stride + cs] = m0[i * a.tstride + tr];
+  PKS_UNROLL for (int i = 0; i < W - N; ++i) traj[(N + i) * a.stride + cs] = P0[i * a.tstride + tr];
 }
 
 // Placement of an N-state block inside a caller's state of dimension ld:
@@ -141,29 +147,29 @@ struct Place {
 
 // Packed device trajectory -> caller layout: mean [S][ld], cov [S][ld][ld].
 template <int N, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_unpack(int64_t S, size_t stride, const R* traj, R* mean, R* cov,
-                                                       Place pl) {
+__global__ __launch_bounds__(kSlotBlock) void k_unpack(int64_t S, size_t stride, SlotMap map, const R* traj, R* mean,
+                                                       R* cov, Place pl) {
   const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
   if (s >= S) return;
-  const int64_t row = s * pl.ld + pl.off;
-  if (mean) PKS_UNROLL for (int i = 0; i < N; ++i) mean[row + i] = traj[i * stride + s];
+  const int64_t row = s * pl.ld + pl.off, cs = map.col(s);
+  if (mean) PKS_UNROLL for (int i = 0; i < N; ++i) mean[row + i] = traj[i * stride + cs];
   if (cov)
     PKS_UNROLL for (int i = 0; i < N; ++i)
       PKS_UNROLL for (int j = 0; j < N; ++j)
-        cov[(row + i) * pl.ld + pl.off + j] = traj[(N + sym_index<N>(i, j)) * stride + s];
+        cov[(row + i) * pl.ld + pl.off + j] = traj[(N + sym_index<N>(i, j)) * stride + cs];
 }
 
 // Caller layout -> packed device trajectory (initial trajectory given by the caller).
 template <int N, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_pack(int64_t S, size_t stride, const R* mean, const R* cov, Place pl,
-                                                     R* traj) {
+__global__ __launch_bounds__(kSlotBlock) void k_pack(int64_t S, size_t stride, SlotMap map, const R* mean, const R* cov,
+                                                     Place pl, R* traj) {
   const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
   if (s >= S) return;
-  const int64_t row = s * pl.ld + pl.off;
-  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[row + i];
+  const int64_t row = s * pl.ld + pl.off, cs = map.col(s);
+  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + cs] = mean[row + i];
   PKS_UNROLL for (int i = 0; i < N; ++i)
     PKS_UNROLL for (int j = i; j < N; ++j)
-      traj[(N + sym_index<N>(i, j)) * stride + s] =
+      traj[(N + sym_index<N>(i, j)) * stride + cs] =
           R(0.5) * (cov[(row + i) * pl.ld + pl.off + j] + cov[(row + j) * pl.ld + pl.off + i]);
 }
 
@@ -176,20 +182,23 @@ struct SymConst {
 // Caller means (device, placed by pl) -> packed trajectory; the covariance of
 // every slot is the constant c.
 template <int N, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_pack_const(int64_t S, size_t stride, const R* mean, Place pl,
-                                                           SymConst<N, R> c, R* traj) {
+__global__ __launch_bounds__(kSlotBlock) void k_pack_const(int64_t S, size_t stride, SlotMap map, const R* mean,
+                                                           Place pl, SymConst<N, R> c, R* traj) {
   const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
   if (s >= S) return;
-  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[s * pl.ld + pl.off + i];
-  PKS_UNROLL for (int i = 0; i < sym_size<N>(); ++i) traj[(N + i) * stride + s] = c.v[i];
+  const int64_t cs = map.col(s);
+  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + cs] = mean[s * pl.ld + pl.off + i];
+  PKS_UNROLL for (int i = 0; i < sym_size<N>(); ++i) traj[(N + i) * stride + cs] = c.v[i];
 }
 
 // Caller means (device, placed by pl) -> the mean rows of the packed trajectory only.
 template <int N, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_set_mean(int64_t S, size_t stride, const R* mean, Place pl, R* traj) {
+__global__ __launch_bounds__(kSlotBlock) void k_set_mean(int64_t S, size_t stride, SlotMap map, const R* mean,
+                                                         Place pl, R* traj) {
   const int64_t s = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
   if (s >= S) return;
-  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + s] = mean[s * pl.ld + pl.off + i];
+  const int64_t cs = map.col(s);
+  PKS_UNROLL for (int i = 0; i < N; ++i) traj[i * stride + cs] = mean[s * pl.ld + pl.off + i];
 }
 
 // ---------------------------------------------------------------------------
@@ -214,20 +223,20 @@ __global__ __launch_bounds__(64) void k_sequential(SlotArgs a, const int64_t* sl
   const double lam = a.lm_track ? a.lm_track[tr] : a.lm;
   if (lam > 0.0) {
     R xb[N];
-    ld_vec<N>(traj, st, s0, xb);
+    ld_vec<N>(traj, st, a.map.col(s0), xb);
     if (!lm_damp_moments<N, R>(R(lam), xb, m, Pm)) m[0] = quiet_nan<R>();
   }
-  st_vec<N>(filt, st, s0, m);
-  st_sym<N>(filt + N * st, st, s0, Pm);
+  st_vec<N>(filt, st, a.map.col(s0), m);
+  st_sym<N>(filt + N * st, st, a.map.col(s0), Pm);
   for (int64_t s = s0 + 1; s < s1; ++s) {
     R F[N][N], c[N], Qp[N][N], H[P][N], d[P], Rp[P][P], yt[P];
-    ld_mat<N, N>(lin + LL::kF * st, st, s - 1, F);
-    ld_vec<N>(lin + LL::kc * st, st, s - 1, c);
-    ld_sym<N>(lin + LL::kQ * st, st, s - 1, Qp);
-    ld_mat<P, N>(lin + LL::kH * st, st, s, H);
-    ld_vec<P>(lin + LL::kd * st, st, s, d);
-    ld_sym<P>(lin + LL::kR * st, st, s, Rp);
-    ld_vec<P>(lin + LL::ky * st, st, s, yt);
+    ld_mat<N, N>(lin + LL::kF * st, st, a.map.col(s - 1), F);
+    ld_vec<N>(lin + LL::kc * st, st, a.map.col(s - 1), c);
+    ld_sym<N>(lin + LL::kQ * st, st, a.map.col(s - 1), Qp);
+    ld_mat<P, N>(lin + LL::kH * st, st, a.map.col(s), H);
+    ld_vec<P>(lin + LL::kd * st, st, a.map.col(s), d);
+    ld_sym<P>(lin + LL::kR * st, st, a.map.col(s), Rp);
+    ld_vec<P>(lin + LL::ky * st, st, a.map.col(s), yt);
     // predict
     R mp[N], Pp[N][N];
     mat_vec<N, N>(F, m, mp);
@@ -264,11 +273,11 @@ __global__ __launch_bounds__(64) void k_sequential(SlotArgs a, const int64_t* sl
     }
     if (lam > 0.0) {
       R xb[N];
-      ld_vec<N>(traj, st, s, xb);
+      ld_vec<N>(traj, st, a.map.col(s), xb);
       if (!lm_damp_moments<N, R>(R(lam), xb, m, Pm)) m[0] = quiet_nan<R>();
     }
-    st_vec<N>(filt, st, s, m);
-    st_sym<N>(filt + N * st, st, s, Pm);
+    st_vec<N>(filt, st, a.map.col(s), m);
+    st_sym<N>(filt + N * st, st, a.map.col(s), Pm);
   }
   // RTS: xbar_T = x*_T, then backwards
   R xs[N], Ps[N][N];
@@ -276,15 +285,15 @@ __global__ __launch_bounds__(64) void k_sequential(SlotArgs a, const int64_t* sl
     xs[i] = m[i];
     PKS_UNROLL for (int j = 0; j < N; ++j) Ps[i][j] = Pm[i][j];
   }
-  st_vec<N>(out, st, s1 - 1, xs);
-  st_sym<N>(out + N * st, st, s1 - 1, Ps);
+  st_vec<N>(out, st, a.map.col(s1 - 1), xs);
+  st_sym<N>(out + N * st, st, a.map.col(s1 - 1), Ps);
   for (int64_t s = s1 - 2; s >= s0; --s) {
     R F[N][N], c[N], Qp[N][N], xf[N], Pf[N][N];
-    ld_mat<N, N>(lin + LL::kF * st, st, s, F);
-    ld_vec<N>(lin + LL::kc * st, st, s, c);
-    ld_sym<N>(lin + LL::kQ * st, st, s, Qp);
-    ld_vec<N>(filt, st, s, xf);
-    ld_sym<N>(filt + N * st, st, s, Pf);
+    ld_mat<N, N>(lin + LL::kF * st, st, a.map.col(s), F);
+    ld_vec<N>(lin + LL::kc * st, st, a.map.col(s), c);
+    ld_sym<N>(lin + LL::kQ * st, st, a.map.col(s), Qp);
+    ld_vec<N>(filt, st, a.map.col(s), xf);
+    ld_sym<N>(filt + N * st, st, a.map.col(s), Pf);
     R E[N][N], g[N], L[N][N];
     const bool ok = smoother_element<N, R>(xf, Pf, F, c, Qp, E, g, L);
     // xbar_k = g + E xbar_{k+1},  Pbar_k = L + E Pbar_{k+1} E^T
@@ -299,8 +308,8 @@ __global__ __launch_bounds__(64) void k_sequential(SlotArgs a, const int64_t* sl
       xs[i] = nx[i];
       PKS_UNROLL for (int j = 0; j < N; ++j) Ps[i][j] = nP[i][j];
     }
-    st_vec<N>(out, st, s, xs);
-    st_sym<N>(out + N * st, st, s, Ps);
+    st_vec<N>(out, st, a.map.col(s), xs);
+    st_sym<N>(out + N * st, st, a.map.col(s), Ps);
   }
 }
 
