@@ -208,6 +208,17 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
   if (a.K == 1) {
     build_filter_element<Model, SRC, R>(a, base, acc);
     Op::store(felem, a.stride, cbase, acc);
+  } else if constexpr (SRC == kStoredLin) {
+    // elements from stored linearisations are cheap to build: fold as they come
+    build_filter_element<Model, SRC, R>(a, base, acc);
+    Op::store(felem, a.stride, cbase, acc);
+    for (int j = 1; j < a.K; ++j) {
+      typename Op::Elem e, r;
+      build_filter_element<Model, SRC, R>(a, base + j, e);
+      Op::store(felem, a.stride, cbase + int64_t(j) * B, e);
+      Op::combine(acc, e, r);
+      acc = r;
+    }
   } else {
     // build and store all K elements first, then fold them back from memory:
     // the running aggregate is never live while a slot is linearised
@@ -217,12 +228,12 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
       Op::store(felem, a.stride, cbase + int64_t(j) * B, e);
     }
     Op::load(felem, a.stride, cbase, acc);
-  }
-  for (int j = 1; j < a.K; ++j) {
-    typename Op::Elem e, r;
-    Op::load(felem, a.stride, cbase + int64_t(j) * B, e);
-    Op::combine(acc, e, r);
-    acc = r;
+    for (int j = 1; j < a.K; ++j) {
+      typename Op::Elem e, r;
+      Op::load(felem, a.stride, cbase + int64_t(j) * B, e);
+      Op::combine(acc, e, r);
+      acc = r;
+    }
   }
   typename Op::Elem ex;
   bool has_ex;
