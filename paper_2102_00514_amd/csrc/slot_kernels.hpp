@@ -41,7 +41,7 @@ constexpr int kSlotBlock = 256;
 // One lane per column of the per-slot arrays (coalesced), launched over the
 // padded column range.
 template <class Model, int LIN, typename R>
-__global__ __launch_bounds__(kSlotBlock) void k_linearize(SlotArgs a) {
+__global__ __launch_bounds__(kSlotBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_linearize(SlotArgs a) {
   constexpr int N = Model::N, P = Model::P;
   using LL = LinLayout<N, P>;
   const int64_t cs = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
