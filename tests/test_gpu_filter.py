@@ -74,6 +74,23 @@ def test_ragged_linear_batch_is_exact_marginal_likelihood(B, scan):
         assert_filter_parity(mean[sl], cov[sl], ll[i], ref, what=f"{scan} linear track {i} T={pb.lengths[i]}")
 
 
+@pytest.mark.parametrize("lanes,slots", [(64, 8), (256, 3)])
+def test_ragged_batch_with_lane_runs(B, lanes, slots):
+    pb = wl.concat_tracks([wl.ct_bearings(T, seed=40 + T) for T in (1, 7, 130, 2, 700)], "ragged")
+    with B.Smoother(pb, n_iter=1, lin="cubature", tile_lanes=lanes, lane_slots=slots) as sm:
+        mean, cov, ll = sm.filter()
+        J = sm.objective()
+    so = pb.slot_offsets()
+    for i in range(pb.n_tracks):
+        tr = pb.track(i)
+        sl = slice(so[i], so[i + 1])
+        assert_filter_parity(mean[sl], cov[sl], ll[i], oracle.filter_loglik(tr, "cubature"),
+                             what=f"{lanes}x{slots} track {i}")
+        x0 = np.broadcast_to(tr.m0[0], (so[i + 1] - so[i], 5))
+        ref = oracle.map_cost(tr, x0)
+        assert abs(J[i] - ref) <= 1e-12 * abs(ref)
+
+
 def test_pass_leaves_the_iteration_state(B):
     pb = wl.config_c1()
     with B.Smoother(pb, n_iter=2) as a, B.Smoother(pb, n_iter=2) as b:

@@ -243,6 +243,23 @@ def test_adaptive_batch_matches_oracle(B):
         assert_parity(mean[sl], cov[sl], ref, tol=1e-8, what=f"held-out track {idx[i]} adaptive")
 
 
+def test_adaptive_batch_with_lane_runs(B):
+    """The damping schedule with several slots per lane (restore by column)."""
+    idx = (145, 3, 38)
+    pb = wl.concat_tracks([wl.config_c4(i, 1, held_out=True) for i in idx], "held-out")
+    with B.Smoother(pb, n_iter=1, tile_lanes=64, lane_slots=8) as sm:
+        run, first, cost = sm.iterate_lm(1e-2, 10.0, 1e-6, 60)
+        mean, cov = sm.result()
+    so = pb.slot_offsets()
+    for i in range(pb.n_tracks):
+        tr = pb.track(i)
+        ref = oracle.lm_adaptive(tr, 1e-2, 10.0, 1e-6, run, stop=False)
+        print(f"64x8 track {idx[i]}: first gpu {first[i]} oracle {ref['first']}", flush=True)
+        assert first[i] == ref["first"] > 0
+        sl = slice(so[i], so[i + 1])
+        assert_parity(mean[sl], cov[sl], ref, tol=1e-8, what=f"64x8 adaptive track {idx[i]}")
+
+
 def test_adaptive_stacked_blocks_match_dense_oracle(B):
     pb = wl.config_c5_single(200)
     with B.Smoother(pb, n_iter=1) as sm:

@@ -122,6 +122,22 @@ def test_ragged_batch_equals_single_tracks(B):
         assert abs(deltas[i] - ref["deltas"][-1]) <= 1e-6 * ref["deltas"][-1] + 1e-12
 
 
+@pytest.mark.parametrize("lanes,slots", [(64, 8), (256, 3)])
+@pytest.mark.parametrize("lin", ["taylor", "cubature"])
+def test_ragged_batch_with_lane_runs(B, lanes, slots, lin):
+    """Tracks start and end inside a lane's run of slots and inside a tile;
+    the tile-transposed columns must give every track its own result."""
+    pb = wl.concat_tracks([wl.ct_bearings(T, seed=20 + T) for T in (1, 6, 7, 8, 130, 2, 700, 3)], "ragged")
+    M = 3
+    mean, cov, _, deltas = run_gpu(B, pb, M, lin, tile_lanes=lanes, lane_slots=slots)
+    so = pb.slot_offsets()
+    for i in range(pb.n_tracks):
+        ref = oracle.smoother(pb.track(i), M, lin)
+        sl = slice(so[i], so[i + 1])
+        assert_parity(mean[sl], cov[sl], ref, what=f"{lanes}x{slots} {lin} track {i} T={pb.lengths[i]}")
+        assert abs(deltas[i] - ref["deltas"][-1]) <= 1e-6 * ref["deltas"][-1] + 1e-12
+
+
 def test_deterministic(B):
     pb = wl.config_c2(4096)
     a = run_gpu(B, pb, 3, "cubature")
