@@ -250,7 +250,7 @@ def damping_section(n_batch: int, tol: float = 1e-6, max_iter: int = 50) -> dict
 
 def c2_sweep(args) -> None:
     """T = 2^10..2^15 (prefixes of the seed-0 track): ms per iteration of the
-    GPU parallel path (Taylor and cubature, FP64; Taylor FP32), of the GPU
+    GPU parallel path (Taylor and cubature, FP64 and FP32), of the GPU
     sequential path (one lane runs the Kalman filter and RTS smoother), and
     of the CPU oracle (one thread, Taylor), each at its autotuned schedule.
     Prints one JSON line whose value is the parallel FP64 Taylor rate at the
@@ -262,7 +262,7 @@ def c2_sweep(args) -> None:
     stream = torch.cuda.current_stream()
     rows = []
     cases = [("taylor", "f64", "parallel"), ("cubature", "f64", "parallel"), ("taylor", "f32", "parallel"),
-             ("taylor", "f64", "sequential"), ("cubature", "f64", "sequential")]
+             ("cubature", "f32", "parallel"), ("taylor", "f64", "sequential"), ("cubature", "f64", "sequential")]
     for e in range(10, 16):
         T = 2 ** e
         pb = wl.config_c2(T)
