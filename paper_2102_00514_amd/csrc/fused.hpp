@@ -205,35 +205,16 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
     for (int i = lane; i <= a.ntracks; i += B) a.delta_bits[i] = 0ull;
   R* felem = static_cast<R*>(a.felem);
   typename Op::Elem acc;
-  if (a.K == 1) {
-    build_filter_element<Model, SRC, R>(a, base, acc);
-    Op::store(felem, a.stride, cbase, acc);
-  } else if constexpr (SRC == kStoredLin) {
-    // elements from stored linearisations are cheap to build: fold as they come
-    build_filter_element<Model, SRC, R>(a, base, acc);
-    Op::store(felem, a.stride, cbase, acc);
-    for (int j = 1; j < a.K; ++j) {
-      typename Op::Elem e, r;
-      build_filter_element<Model, SRC, R>(a, base + j, e);
-      Op::store(felem, a.stride, cbase + int64_t(j) * B, e);
-      Op::combine(acc, e, r);
-      acc = r;
-    }
-  } else {
-    // build and store all K elements first, then fold them back from memory:
-    // the running aggregate is never live while a slot is linearised
-    for (int j = 0; j < a.K; ++j) {
-      typename Op::Elem e;
-      build_filter_element<Model, SRC, R>(a, base + j, e);
-      Op::store(felem, a.stride, cbase + int64_t(j) * B, e);
-    }
-    Op::load(felem, a.stride, cbase, acc);
-    for (int j = 1; j < a.K; ++j) {
-      typename Op::Elem e, r;
-      Op::load(felem, a.stride, cbase + int64_t(j) * B, e);
-      Op::combine(acc, e, r);
-      acc = r;
-    }
+  // each lane folds its K elements as they are built (and stores them for the
+  // down-sweep)
+  build_filter_element<Model, SRC, R>(a, base, acc);
+  Op::store(felem, a.stride, cbase, acc);
+  for (int j = 1; j < a.K; ++j) {
+    typename Op::Elem e, r;
+    build_filter_element<Model, SRC, R>(a, base + j, e);
+    Op::store(felem, a.stride, cbase + int64_t(j) * B, e);
+    Op::combine(acc, e, r);
+    acc = r;
   }
   typename Op::Elem ex;
   bool has_ex;
