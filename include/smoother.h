@@ -136,8 +136,9 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
 
 /* Scan-schedule autotuner: for every candidate schedule (tile_lanes 64 or
  * 256, lane_slots 1, 2, 4 or 8) builds a handle for *pb on hip_stream, runs
- * one warm-up iteration and then `iters` timed iterations (HIP events around
- * the graph replays), releases the handle, and returns the fastest schedule in
+ * one warm-up iteration and then three timed rounds of `iters` iterations (HIP
+ * events around the graph replays; the best round counts), releases the
+ * handle, and returns the fastest schedule in
  * *tile_lanes / *lane_slots and its time per iteration in *ms_per_iter
  * (nullable).  pb->tile_lanes, lane_slots and n_iter are ignored; the result
  * is meant for the same fields of the problem given to smoother_init.

@@ -201,6 +201,14 @@ PKS_DEV void block_scan(R* lds, int lane, const R* E, size_t estride, int64_t m,
   bool has_ex;
   block_ladder<Op, B, true, R>(lds, v, ex, has_ex, int64_t(lane & ~63) * K < m);
   if (!valid) return;
+  if (K == 1) {
+    // v is the inclusive prefix of this lane's position, and it starts at a
+    // carry-form element, so its carry part is the result
+    typename Op::Carry c;
+    Op::to_carry(v, c);
+    Op::store(out, ostride, reverse ? m - 1 - first : first, c);
+    return;
+  }
   typename Op::Carry c;
   bool have = false;
   if (has_ex) {

@@ -283,26 +283,30 @@ sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iter
         sm_problem q = *pb;
         q.tile_lanes = lanes;
         q.lane_slots = slots;
-        q.n_iter = iters + 1;
         std::unique_ptr<pks::EngineBase> eng(pks::make_engine(q.model, q.precision, q.nx, q.ny, q.lin));
         if (!eng) {
           last = SM_EINVAL;
           last_err = "no kernel for this configuration";
           continue;
         }
+        q.n_iter = 3 * iters + 1;
         sm_status st = eng->setup(q, stream);
         if (st == SM_OK) st = eng->iterate(1);                  // warm-up (and graph capture)
+        // best of three timed rounds of `iters` iterations (candidates a few
+        // percent apart would otherwise swap places from run to run)
         float ms = 0.f;
-        if (st == SM_OK) {
+        for (int round = 0; round < 3 && st == SM_OK; ++round) {
+          float t = 0.f;
           he = hipEventRecord(a, stream);
           if (he == hipSuccess) st = eng->iterate(iters);
           if (he == hipSuccess && st == SM_OK) he = hipEventRecord(b, stream);
           if (he == hipSuccess && st == SM_OK) he = hipEventSynchronize(b);
-          if (he == hipSuccess && st == SM_OK) he = hipEventElapsedTime(&ms, a, b);
+          if (he == hipSuccess && st == SM_OK) he = hipEventElapsedTime(&t, a, b);
           if (he != hipSuccess) {
             st = SM_EDEVICE;
             eng->err = pks::hip_msg(he, "autotune timing");
           }
+          if (round == 0 || t < ms) ms = t;
         }
         (void)hipStreamSynchronize(stream);   // nothing of this candidate in flight when it is released
         if (st != SM_OK) {            // e.g. a schedule that does not fit the memory cap
