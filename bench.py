@@ -53,13 +53,16 @@ def algorithmic_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: 
     tr = n * n + n + s                  # transition (F, c, Q') kept for the smoothing elements
     lin_words = n * n + n + s + p * n + p + sp + p
     xin = n + (s if lin != "taylor" else 0)   # linearisation point (mean [+ covariance])
+    # With K = 1 the down-sweeps start from each lane's inclusive prefix, so the
+    # per-slot elements are neither stored nor reloaded.
+    ke = 1 if K > 1 else 0
     words = {
-        # linearise + filtering element + lane fold / ladder
-        "forward_up": (xin + p + tr if lin == "taylor" else lin_words) + fe + fe / K,
-        # carries + smoothing element + reverse lane fold / ladder
-        "forward_down_backward_up": fe + fe / K + tr + se + se / K,
+        # linearise + filtering element (stored for K > 1) + lane prefix
+        "forward_up": (xin + p + tr if lin == "taylor" else lin_words) + ke * fe + fe / K,
+        # carries + smoothing element (stored for K > 1) + reverse lane prefix
+        "forward_down_backward_up": ke * fe + fe / K + tr + ke * se + se / K,
         # reverse carries, new trajectory in place, convergence statistic (reads old means)
-        "backward_down": se + se / K + n + car,
+        "backward_down": ke * se + se / K + n + car,
         "tiles_up_filter": fe + fe / 2, "tiles_top_filter": fe + car, "tiles_down_filter": fe + fe / 2 + car,
         # (per tile aggregate: read once, write its carry)
         "tiles_up_smoother": se + se / 2, "tiles_top_smoother": se + car, "tiles_down_smoother": se + se / 2 + car,

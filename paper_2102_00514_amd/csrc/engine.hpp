@@ -186,8 +186,12 @@ class Engine final : public EngineBase {
         A(&d_lin_, sizeof(R) * LL::kWords * stride);
         d_trans_ = d_lin_;
       }
-      A(&d_felem_, sizeof(R) * FOp::kElemWords * stride);
-      A(&d_selem_, sizeof(R) * SOp::kElemWords * stride);
+      if (sched_.K > 1) {
+        // per-slot elements; with one slot per lane the down-sweeps start from
+        // the lanes' inclusive prefixes instead
+        A(&d_felem_, sizeof(R) * FOp::kElemWords * stride);
+        A(&d_selem_, sizeof(R) * SOp::kElemWords * stride);
+      }
       A(&lx_f_, sizeof(R) * FOp::kElemWords * lanes);
       A(&ta_f_, sizeof(R) * FOp::kElemWords * tiles_);
       A(&tc_f_, sizeof(R) * FOp::kCarryWords * tiles_);

@@ -205,10 +205,10 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
     for (int i = lane; i <= a.ntracks; i += B) a.delta_bits[i] = 0ull;
   R* felem = static_cast<R*>(a.felem);
   typename Op::Elem acc;
-  // each lane folds its K elements as they are built (and stores them for the
-  // down-sweep)
+  // each lane folds its K elements as they are built (and, for K > 1, stores
+  // them for the down-sweep)
   build_filter_element<Model, SRC, R>(a, base, acc);
-  Op::store(felem, a.stride, cbase, acc);
+  if (a.K > 1) Op::store(felem, a.stride, cbase, acc);
   for (int j = 1; j < a.K; ++j) {
     typename Op::Elem e, r;
     build_filter_element<Model, SRC, R>(a, base + j, e);
@@ -219,8 +219,38 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
   typename Op::Elem ex;
   bool has_ex;
   block_ladder<Op, B, true, R>(lds, acc, ex, has_ex);
-  if (has_ex) Op::store(static_cast<R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
+  // K = 1: the lane's inclusive prefix goes to the down-sweep, which then
+  // needs neither the element nor a second carry application; K > 1: the
+  // exclusive prefix, continued there over the stored elements
+  if (a.K == 1) Op::store(static_cast<R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, acc);
+  else if (has_ex) Op::store(static_cast<R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
   if (lane == B - 1) Op::store(static_cast<R*>(a.ta_f), size_t(a.tiles), tile, acc);
+}
+
+// Carry at the start of a lane's run in a forward down-sweep: tile carry (x)
+// the lane prefix handed over by k_forward_up (inclusive for K = 1, so the
+// result is already the filtered moments of the lane's slot).
+template <int N, int B, typename R>
+PKS_DEV void lane_filter_carry(const FusedArgs& a, int64_t tile, int lane, typename FilterOp<N, R>::Carry& c,
+                               bool& have) {
+  using FOp = FilterOp<N, R>;
+  have = false;
+  if (tile > 0) {
+    FOp::load(static_cast<const R*>(a.tc_f), size_t(a.tiles), tile - 1, c);
+    have = true;
+  }
+  if (a.K == 1 || lane > 0) {
+    typename FOp::Elem p;
+    FOp::load(static_cast<const R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, p);
+    if (have) {
+      typename FOp::Carry n;
+      FOp::apply(c, p, n);
+      c = n;
+    } else {
+      FOp::to_carry(p, c);
+      have = true;
+    }
+  }
 }
 
 template <class Model, int B, typename R>
@@ -236,28 +266,13 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
   const int64_t base = (tile * B + lane) * a.K;
   const size_t st = a.stride;
   typename FOp::Carry c;
-  bool have = false;
-  if (tile > 0) {
-    FOp::load(static_cast<const R*>(a.tc_f), size_t(a.tiles), tile - 1, c);
-    have = true;
-  }
-  if (lane > 0) {
-    typename FOp::Elem ex;
-    FOp::load(static_cast<const R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
-    if (have) {
-      typename FOp::Carry n;
-      FOp::apply(c, ex, n);
-      c = n;
-    } else {
-      FOp::to_carry(ex, c);
-      have = true;
-    }
-  }
+  bool have;
+  lane_filter_carry<N, B, R>(a, tile, lane, c, have);
   typename SOp::Elem sacc;
   const int64_t cbase = tile * B * a.K + lane;
   for (int j = 0; j < a.K; ++j) {
     const int64_t s = base + j, cs = cbase + int64_t(j) * B;
-    {
+    if (a.K > 1) {
       typename FOp::Elem e;
       FOp::load(static_cast<const R*>(a.felem), st, cs, e);
       if (have) {
@@ -287,7 +302,7 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
       const bool ok = smoother_element<N, R>(c.b, c.C, F, cc, Qp, se.E, se.g, se.L);
       if (!ok) se.g[0] = quiet_nan<R>();
     }
-    SOp::store(static_cast<R*>(a.selem), st, cs, se);
+    if (a.K > 1) SOp::store(static_cast<R*>(a.selem), st, cs, se);
     // paper order: sacc covers earlier slots, so sacc <- sacc (x) se, i.e. the
     // scan-order combine with se first
     if (j == 0) {
@@ -303,7 +318,9 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
   typename SOp::Elem ex;
   bool has_ex;
   block_ladder<SOp, B, false, R>(lds, sacc, ex, has_ex);
-  if (has_ex) SOp::store(static_cast<R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, ex);
+  // as in the forward direction: inclusive prefix for K = 1, exclusive otherwise
+  if (a.K == 1) SOp::store(static_cast<R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, sacc);
+  else if (has_ex) SOp::store(static_cast<R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, ex);
   if (rl == B - 1) SOp::store(static_cast<R*>(a.ta_s), size_t(a.tiles), rt, sacc);
 }
 
@@ -316,35 +333,22 @@ __global__ __launch_bounds__(B) void k_forward_down_filter(FusedArgs a) {
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
   typename FOp::Carry c;
-  bool have = false;
-  if (tile > 0) {
-    FOp::load(static_cast<const R*>(a.tc_f), size_t(a.tiles), tile - 1, c);
-    have = true;
-  }
-  if (lane > 0) {
-    typename FOp::Elem ex;
-    FOp::load(static_cast<const R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
-    if (have) {
-      typename FOp::Carry n;
-      FOp::apply(c, ex, n);
-      c = n;
-    } else {
-      FOp::to_carry(ex, c);
-      have = true;
-    }
-  }
+  bool have;
+  lane_filter_carry<N, B, R>(a, tile, lane, c, have);
   const int64_t cbase = tile * B * a.K + lane;
   for (int j = 0; j < a.K; ++j) {
     const int64_t cs = cbase + int64_t(j) * B;
-    typename FOp::Elem e;
-    FOp::load(static_cast<const R*>(a.felem), a.stride, cs, e);
-    if (have) {
-      typename FOp::Carry n;
-      FOp::apply(c, e, n);
-      c = n;
-    } else {
-      FOp::to_carry(e, c);
-      have = true;
+    if (a.K > 1) {
+      typename FOp::Elem e;
+      FOp::load(static_cast<const R*>(a.felem), a.stride, cs, e);
+      if (have) {
+        typename FOp::Carry n;
+        FOp::apply(c, e, n);
+        c = n;
+      } else {
+        FOp::to_carry(e, c);
+        have = true;
+      }
     }
     FOp::store(static_cast<R*>(a.filt), a.stride, cs, c);
   }
@@ -380,7 +384,7 @@ __global__ __launch_bounds__(B) void k_backward_down(FusedArgs a) {
     SOp::load(static_cast<const R*>(a.tc_s), size_t(a.tiles), rt - 1, c);
     have = true;
   }
-  if (rl > 0) {
+  if (a.K == 1 || rl > 0) {
     typename SOp::Elem ex;
     SOp::load(static_cast<const R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, ex);
     if (have) {
@@ -397,15 +401,17 @@ __global__ __launch_bounds__(B) void k_backward_down(FusedArgs a) {
   const int64_t cbase = tile * B * a.K + lane;
   for (int j = a.K - 1; j >= 0; --j) {
     const int64_t s = base + j, cs = cbase + int64_t(j) * B;
-    typename SOp::Elem e;
-    SOp::load(static_cast<const R*>(a.selem), st, cs, e);
-    if (have) {
-      typename SOp::Carry n;
-      SOp::apply(c, e, n);
-      c = n;
-    } else {
-      SOp::to_carry(e, c);
-      have = true;
+    if (a.K > 1) {
+      typename SOp::Elem e;
+      SOp::load(static_cast<const R*>(a.selem), st, cs, e);
+      if (have) {
+        typename SOp::Carry n;
+        SOp::apply(c, e, n);
+        c = n;
+      } else {
+        SOp::to_carry(e, c);
+        have = true;
+      }
     }
     if (s < a.S) {
       double m = 0.0;
