@@ -4,8 +4,9 @@
 //                   its linearisation (Section 3: Taylor evaluated inline, or
 //                   sigma-point regression read from a separate pass), fold
 //                   each lane's K elements,
-//                   Kogge-Stone over the lanes (eq. 15) -> lane exclusive
-//                   prefixes and the tile aggregate.
+//                   Kogge-Stone over the lanes (eq. 15) -> lane prefixes
+//                   (inclusive for K = 1, else exclusive with the elements
+//                   stored) and the tile aggregate.
 //   k_forward_down_backward_up
 //                   apply the tile and lane carries to every slot -> filtered
 //                   x*_k, P*_k; build the smoothing element (eq. 16-18); fold
@@ -13,6 +14,9 @@
 //                   lane prefixes and tile aggregates.
 //   k_backward_down apply the reverse carries -> smoothed xbar_k, Pbar_k,
 //                   written in place, and the convergence statistic.
+//
+// Per-slot arrays use tile-transposed columns (SlotMap) so that, for each of
+// a lane's K slots, a wavefront touches consecutive columns.
 //
 // Between them the tile aggregates are scanned into tile carries by a
 // single-block scan (or the multi-level scan of scan.hpp for many tiles).
