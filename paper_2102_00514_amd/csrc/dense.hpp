@@ -210,8 +210,19 @@ PKS_DEV void vcopy(const R* x, R* y) {
 // --- HBM <-> LDS ------------------------------------------------------------
 template <int LDN, int M, int NC, typename R>
 PKS_DEV void ld_full(const R* g, R* A) {
+  // all global loads are issued before the first LDS store (fixed trip
+  // counts), so one record costs one memory latency, not one per pass
   constexpr int L = ld<LDN>();
-  for (int e = lane(); e < M * NC; e += kWave) A[(e / NC) * L + e % NC] = g[e];
+  constexpr int T = M * NC, RN = (T + kWave - 1) / kWave;
+  R v[RN];
+  PKS_UNROLL for (int r = 0; r < RN; ++r) {
+    const int e = r * kWave + lane();
+    v[r] = e < T ? g[e] : R(0);
+  }
+  PKS_UNROLL for (int r = 0; r < RN; ++r) {
+    const int e = r * kWave + lane();
+    if (e < T) A[(e / NC) * L + e % NC] = v[r];
+  }
 }
 template <int LDN, int M, int NC, typename R>
 PKS_DEV void st_full(const R* A, R* g) {
@@ -221,9 +232,17 @@ PKS_DEV void st_full(const R* A, R* g) {
 template <int LDN, int N, typename R>
 PKS_DEV void ld_symm(const R* g, R* A) {
   constexpr int L = ld<LDN>();
-  for (int e = lane(); e < N * N; e += kWave) {
+  constexpr int T = N * N, RN = (T + kWave - 1) / kWave;
+  R v[RN];
+  PKS_UNROLL for (int r = 0; r < RN; ++r) {
+    const int e = r * kWave + lane();
     const int i = e / N, j = e - i * N;
-    A[i * L + j] = g[sym_index<N>(i, j)];
+    v[r] = e < T ? g[sym_index<N>(i, j)] : R(0);
+  }
+  PKS_UNROLL for (int r = 0; r < RN; ++r) {
+    const int e = r * kWave + lane();
+    const int i = e / N, j = e - i * N;
+    if (e < T) A[i * L + j] = v[r];
   }
 }
 template <int LDN, int N, typename R>
