@@ -224,6 +224,21 @@ PKS_DEV void ld_full(const R* g, R* A) {
     if (e < T) A[(e / NC) * L + e % NC] = v[r];
   }
 }
+// A += g (row-major M x NC in HBM), loads issued first as in ld_full
+template <int LDN, int M, int NC, typename R>
+PKS_DEV void add_full(const R* g, R* A) {
+  constexpr int L = ld<LDN>();
+  constexpr int T = M * NC, RN = (T + kWave - 1) / kWave;
+  R v[RN];
+  PKS_UNROLL for (int r = 0; r < RN; ++r) {
+    const int e = r * kWave + lane();
+    v[r] = e < T ? g[e] : R(0);
+  }
+  PKS_UNROLL for (int r = 0; r < RN; ++r) {
+    const int e = r * kWave + lane();
+    if (e < T) A[(e / NC) * L + e % NC] += v[r];
+  }
+}
 template <int LDN, int M, int NC, typename R>
 PKS_DEV void st_full(const R* A, R* g) {
   constexpr int L = ld<LDN>();
@@ -654,8 +669,7 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
                         Lam, w.v[2], w.m[3], w.m[4], w.m[5], w.v[3], &w.ok);
     R* out = static_cast<R*>(a.trans) + size_t(s) * Lay::kTrans;
     const R* Qm = static_cast<const R*>(a.Q);
-    constexpr int L = ld<N>();
-    for (int e = lane(); e < N * N; e += kWave) Lam[(e / N) * L + e % N] += Qm[e];
+    add_full<N, N, N>(Qm, Lam);
     wsync();
     st_full<N, N, N>(G, out);
     st_v<N>(w.v[1], out + N * N);
@@ -673,8 +687,7 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
     R* out = static_cast<R*>(a.hlin) + size_t(s) * Lay::kHlin;
     const R* Rm = static_cast<const R*>(a.Rm);
     const R* y = static_cast<const R*>(a.y) + size_t(s) * P;
-    constexpr int L = ld<N>();
-    for (int e = lane(); e < P * P; e += kWave) Om[(e / P) * L + e % P] += Rm[e];
+    add_full<N, P, P>(Rm, Om);
     for (int i = lane(); i < P; i += kWave)
       out[P * N + P + Lay::kSP + i] = Model::kAngular ? hc[i] + wrap_pi<R>(y[i] - hc[i]) : y[i];
     wsync();
@@ -687,7 +700,7 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
 // Level 0 of the filtering scan: build the elements of `fan` consecutive
 // slots, store them, and fold them into the chunk aggregate.
 template <class Model, typename R>
-__global__ __launch_bounds__(kWave) void k_dn_forward_up(DnArgs a, int fan, void* agg_out) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_dn_forward_up(DnArgs a, int fan, void* agg_out) {
   using D = Dense<Model, R>;
   constexpr int N = D::N;
   using Lay = typename D::Lay;
