@@ -785,6 +785,7 @@ __global__ __launch_bounds__(kWave) void k_dn_scan_down(DnArgs a, DnLevel lv) {
       D::store_carry(cx, cP, cout + size_t(i) * Lay::kCarry);
       wsync();
     }
+    if (k + 1 == i1 - i0) break;   // the carry past the chunk's last aggregate is not needed
     if (FILT) {
       D::load_felem(in + size_t(i) * RW, rA, rb, rC, re, rJ);
       if (have) {

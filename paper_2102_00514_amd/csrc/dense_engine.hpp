@@ -2,9 +2,11 @@
 // the kernel sequence of one iteration and its HIP graph.
 //
 // Scan hierarchy: level 0 folds `fan0` consecutive slots per wave; every
-// higher level folds `fan` aggregates of the level below, until at most `fan`
+// higher level folds pairs of aggregates of the level below, until at most two
 // remain; a single wave then scans those, and the down-sweeps hand exclusive
-// carries back level by level.
+// carries back level by level.  Pairs keep the critical path of the upper
+// levels at one operator per level: there a level has too few waves to fill
+// the chip, and a fan of f would cost f - 1 dependent combines instead.
 #pragma once
 
 #include <algorithm>
@@ -21,7 +23,8 @@ class DenseEngine final : public EngineBase {
  public:
   static constexpr int N = Model::N, P = Model::P;
   using Lay = dn::Layout<N, P>;
-  static constexpr int kFan = 8;
+  static constexpr int kFan = 8;        // level 0: slots per wave (default)
+  static constexpr int kLevelFan = 2;   // higher levels: aggregates per wave
 
   sm_status setup(const sm_problem& pb, hipStream_t st) override {
     stream = st;
@@ -42,8 +45,8 @@ class DenseEngine final : public EngineBase {
     // scan levels
     int64_t c = (S + fan0_ - 1) / fan0_;
     counts_.push_back(c);
-    while (c > kFan) {
-      c = (c + kFan - 1) / kFan;
+    while (c > kLevelFan) {
+      c = (c + kLevelFan - 1) / kLevelFan;
       counts_.push_back(c);
     }
     sched_tiles = counts_[0];
@@ -164,7 +167,7 @@ class DenseEngine final : public EngineBase {
     const char* down = FILT ? "scan_down_filter" : "scan_down_smoother";
     const size_t top = counts_.size() - 1;
     for (size_t l = 0; l < top; ++l) {
-      const dn::DnLevel lv{agg[l], agg[l + 1], nullptr, nullptr, counts_[l], kFan};
+      const dn::DnLevel lv{agg[l], agg[l + 1], nullptr, nullptr, counts_[l], kLevelFan};
       timed(up, counts_[l], [&] {
         hipLaunchKernelGGL((dn::k_dn_scan_up<Model, FILT, R>), dim3(unsigned(counts_[l + 1])), dim3(dn::kWave), 0,
                            stream, a, lv);
@@ -172,8 +175,8 @@ class DenseEngine final : public EngineBase {
     }
     for (size_t k = 0; k <= top; ++k) {
       const size_t l = top - k;
-      const dn::DnLevel lv{agg[l], nullptr, car[l], l == top ? nullptr : car[l + 1], counts_[l], kFan};
-      const unsigned grid = unsigned((counts_[l] + kFan - 1) / kFan);
+      const dn::DnLevel lv{agg[l], nullptr, car[l], l == top ? nullptr : car[l + 1], counts_[l], kLevelFan};
+      const unsigned grid = unsigned((counts_[l] + kLevelFan - 1) / kLevelFan);
       timed(down, counts_[l], [&] {
         hipLaunchKernelGGL((dn::k_dn_scan_down<Model, FILT, R>), dim3(grid), dim3(dn::kWave), 0, stream, a, lv);
       });
