@@ -1,0 +1,119 @@
+"""Parity at the full workload sizes, in the schedules the benchmark times.
+
+C2 at T = 2^15 is compared slot by slot in test_gpu_parity.  Here:
+  - C3: 4096 ragged coordinated-turn tracks (1.68e7 slots), cubature, FP64,
+    64 lanes x 8 slots;
+  - C5 single: four stacked targets (nx = 20, ny = 8), T = 2^16, unscented;
+  - C5 batch: 256 stacked-target tracks, T_i ~ U{1024..65536} (8.5e6 slots).
+
+Each case runs the whole batch on the device twice:
+  1. iteration 1 from the prior broadcast (the step the benchmark times);
+  2. one more iteration after the sampled tracks' trajectories are replaced by
+     the oracle's iterate 2 (a common input; the other tracks keep the
+     device's iterate 1), compared with the oracle's iterate 3.
+The oracle computes the sampled tracks one by one and every slot of them is
+compared (metric as in test_gpu_parity).  Step 2 is held to the FP64 gate
+1e-9.  Step 1 is held to 1e-8: these priors set the turn rate to zero, so on
+some tracks the first iteration moves the trajectory by hundreds of units
+(C3 track 0, T = 6667: max change 633).  There the parallel scan's FP64 result
+differs from the sequential oracle by 2.2e-9, while the same track from the
+oracle's iterates 2 and 4 agrees to 4e-11 and 7e-12, and every other sampled
+track agrees to 3e-11 at step 1.  On the device every output of every track
+is checked to be finite, every covariance symmetric with a positive diagonal,
+and every per-track change statistic finite.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_00514_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+TOL_FROM_PRIOR = 1e-8
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2102_00514_amd import binding
+    return binding
+
+
+def check_all_slots(mean, cov, deltas, chunk=1 << 20):
+    import torch
+    assert bool(torch.isfinite(mean).all())
+    for a in range(0, cov.shape[0], chunk):   # bounded temporaries next to a large plan
+        c = cov[a:a + chunk]
+        assert bool(torch.isfinite(c).all())
+        assert float((c - c.transpose(1, 2)).abs().max()) == 0.0
+        assert bool((torch.diagonal(c, dim1=1, dim2=2) > 0).all())
+    assert np.all(np.isfinite(deltas))
+
+
+def compare_tracks(pb, mean, cov, deltas, refs, it, tol, what):
+    so = pb.slot_offsets()
+    worst = 0.0
+    for i, ref in refs.items():
+        m = mean[so[i]:so[i + 1]].cpu().numpy()
+        c = cov[so[i]:so[i + 1]].cpu().numpy()
+        em = oracle.mean_error(m, ref["hist_mean"][it])
+        ep = oracle.cov_error(c, ref["hist_cov"][it])
+        print(f"{what} iteration {it + 1}, track {i} T={pb.lengths[i]}: e_m={em:.3e} e_P={ep:.3e}", flush=True)
+        assert em < tol and ep < tol, (what, it + 1, i, em, ep)
+        assert abs(deltas[i] - ref["deltas"][it]) <= 1e-6 * ref["deltas"][it] + 1e-12
+        worst = max(worst, em, ep)
+    return worst
+
+
+def full_size_case(B, pb, lin, tracks, what, **kw):
+    import torch
+    k = 2
+    refs = {int(i): oracle.smoother(pb.track(int(i)), k + 1, lin, history=True) for i in tracks}
+    so = pb.slot_offsets()
+    with B.Smoother(pb, n_iter=k + 1, lin=lin, **kw) as sm:
+        sm.iterate(1)
+        S, _, dev = sm.info()
+        print(f"{what}: {pb.n_tracks} tracks, {S} slots, {dev / 1e9:.1f} GB planned, schedule {sm.schedule()}",
+              flush=True)
+        mean = torch.empty((S, pb.nx), dtype=torch.float64, device="cuda")
+        cov = torch.empty((S, pb.nx, pb.nx), dtype=torch.float64, device="cuda")
+        sm.result_device(mean.data_ptr(), cov.data_ptr())
+        deltas = sm.track_deltas()
+        check_all_slots(mean, cov, deltas)
+        compare_tracks(pb, mean, cov, deltas, refs, 0, TOL_FROM_PRIOR, what)
+        for i, ref in refs.items():
+            mean[so[i]:so[i + 1]] = torch.from_numpy(ref["hist_mean"][k - 1]).to("cuda")
+            cov[so[i]:so[i + 1]] = torch.from_numpy(ref["hist_cov"][k - 1]).to("cuda")
+        torch.cuda.synchronize()
+        sm.set_trajectory_device(mean.data_ptr(), cov.data_ptr())
+        sm.iterate(1)
+        sm.result_device(mean.data_ptr(), cov.data_ptr())
+        deltas = sm.track_deltas()
+        torch.cuda.synchronize()
+        check_all_slots(mean, cov, deltas)
+        compare_tracks(pb, mean, cov, deltas, refs, k, TOL64, what)
+
+
+def sample(pb, n_random, seed):
+    L = pb.lengths
+    picks = {int(np.argmin(L)), int(np.argmax(L))}
+    picks |= set(np.random.default_rng(seed).choice(pb.n_tracks, n_random, replace=False).tolist())
+    return sorted(picks)
+
+
+def test_c3_4096_tracks_64x8(B):
+    pb = wl.config_c3()
+    tracks = sorted(set(sample(pb, 28, 30)) | {0, pb.n_tracks - 1})
+    full_size_case(B, pb, "cubature", tracks, "C3", tile_lanes=64, lane_slots=8)
+
+
+def test_c5_single_T65536(B):
+    full_size_case(B, wl.config_c5_single(), "unscented", [0], "C5 single")
+
+
+def test_c5_batch_256_tracks(B):
+    pb = wl.config_c5_batch()
+    full_size_case(B, pb, "unscented", sample(pb, 1, 50), "C5 batch")
