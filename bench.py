@@ -57,9 +57,8 @@ def algorithmic_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: 
     # per-slot elements are neither stored nor reloaded.
     ke = 1 if K > 1 else 0
     words = {
-        # linearise inline (reads the linearisation point and y, stores F, c, Q')
-        # + filtering element (stored for K > 1) + lane prefix
-        "forward_up": xin + p + tr + ke * fe + fe / K,
+        # linearise + filtering element (stored for K > 1) + lane prefix
+        "forward_up": (xin + p + tr if lin == "taylor" else lin_words) + ke * fe + fe / K,
         # carries + smoothing element (stored for K > 1) + reverse lane prefix
         "forward_down_backward_up": ke * fe + fe / K + tr + ke * se + se / K,
         # reverse carries, new trajectory in place, convergence statistic (reads old means)

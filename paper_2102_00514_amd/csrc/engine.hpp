@@ -181,9 +181,8 @@ class Engine final : public EngineBase {
       if (lin_ == SM_LIN_TAYLOR) {
         A(&d_trans_, sizeof(R) * TL::kWords * stride);
       } else {
-        // the filtering pass runs the sigma-point linearisation as its own
-        // pass; its arrays start with the transition rows that the smoothing
-        // elements read and that the iteration's forward kernel writes
+        // sigma-point linearisation runs as its own pass; its arrays start with
+        // the transition rows the smoothing elements read
         A(&d_lin_, sizeof(R) * LL::kWords * stride);
         d_trans_ = d_lin_;
       }
@@ -279,7 +278,6 @@ class Engine final : public EngineBase {
     };
     set(reinterpret_cast<const void*>(&k_forward_up<Model, kInlineTaylor, B, R>), lds_filter());
     set(reinterpret_cast<const void*>(&k_forward_up<Model, kStoredLin, B, R>), lds_filter());
-    set(reinterpret_cast<const void*>(&k_forward_up<Model, kInlineSlr, B, R>), lds_filter());
     set(reinterpret_cast<const void*>(&k_forward_down_backward_up<Model, B, R>), lds_smoother());
     return e;
   }
@@ -355,7 +353,6 @@ class Engine final : public EngineBase {
     a.tc_s = tc_s_;
     a.delta_bits = delta_bits;
     a.rule = rule_;
-    a.lin_kind = lin_ == SM_LIN_CUBATURE ? int(kCubature) : lin_ == SM_LIN_UNSCENTED ? int(kUnscented) : int(kTaylor);
     a.lm = lm_;
     a.lm_track = lm_track_;
     a.map = map_;
@@ -448,8 +445,11 @@ class Engine final : public EngineBase {
         hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R>), grid, block, lds_filter(), stream, a);
       });
     } else {
+      const dim3 sgrid = col_grid();
+      const SlotArgs sa = slot_args(0);
+      timed("linearize", S, [&] { launch_linearize(sa, sgrid); });
       timed("forward_up", S, [&] {
-        hipLaunchKernelGGL((k_forward_up<Model, kInlineSlr, B, R>), grid, block, lds_filter(), stream, a);
+        hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R>), grid, block, lds_filter(), stream, a);
       });
     }
     scan_tiles<FOp>(ta_f_, tc_f_, kFilterNames);

@@ -1,9 +1,8 @@
 // One iteration of the method in three kernels over tiles of B lanes x K slots.
 //
 //   k_forward_up    build the filtering element of every slot (eq. 13-14) from
-//                   its linearisation (Section 3: Taylor or sigma-point
-//                   regression evaluated inline, or read from a separate
-//                   pass), fold
+//                   its linearisation (Section 3: Taylor evaluated inline, or
+//                   sigma-point regression read from a separate pass), fold
 //                   each lane's K elements,
 //                   Kogge-Stone over the lanes (eq. 15) -> lane prefixes
 //                   (inclusive for K = 1, else exclusive with the elements
@@ -85,7 +84,6 @@ struct FusedArgs {
   void *lx_s, *ta_s, *tc_s;  // same for the reverse scan, indexed by reverse tile
   unsigned long long* delta_bits;  // [ntracks + 1]; entry ntracks = max over tracks
   SigmaRule rule;
-  int lin_kind;         // LinKind of kInlineSlr
   double lm;            // Levenberg-Marquardt damping lambda (0 = undamped)
   const double* lm_track;  // optional [ntracks]: per-track damping, replaces lm
   SlotMap map;          // slot -> column of the per-slot arrays
@@ -114,8 +112,7 @@ struct TransLayout {
 // Where the forward kernel takes each slot's linearisation from.
 enum LinSource : int {
   kInlineTaylor = 0,  // Jacobians evaluated in the kernel; F, c, Q' stored for the smoothing elements
-  kStoredLin = 1,     // read from the arrays a separate linearisation pass wrote
-  kInlineSlr = 2      // sigma-point regression (lin_kind) evaluated in the kernel; F, c, Q' stored
+  kStoredLin = 1      // read from the arrays a separate linearisation pass wrote (sigma-point SLR)
 };
 
 // Levenberg-Marquardt damping of the element of real slot s towards the
@@ -169,23 +166,15 @@ PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename Filter
     ld_sym<P>(lin + LL::kR * st, st, cs, Rp);
     ld_vec<P>(lin + LL::ky * st, st, cs, yt);
   } else {
-    // Taylor or sigma-point regression at the linearisation points (means and,
-    // for the regression, covariances of the previous smoothed trajectory)
-    constexpr bool kSlr = SRC == kInlineSlr;
-    const int lin = kSlr ? a.lin_kind : int(kTaylor);
     const Model md{static_cast<const R*>(a.params)};
     const R* traj = static_cast<const R*>(a.traj);
     {
       R xp[N], Pp[N][N], Qm[N][N];
       ld_vec<N>(traj, st, cp, xp);
-      if constexpr (kSlr) ld_sym<N>(traj + N * st, st, cp, Pp);
-      else set_zero<N>(Pp);
+      set_zero<N>(Pp);
       const R* Qg = static_cast<const R*>(a.Q);
       PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) Qm[i][j] = Qg[i * N + j];
-      const bool okf = linearize_f<Model, R>(md, lin, a.rule, Qm, xp, Pp, F, c, Qp);
-      if constexpr (kSlr) {
-        if (!okf) c[0] = quiet_nan<R>();
-      }
+      linearize_f<Model, R>(md, kTaylor, a.rule, Qm, xp, Pp, F, c, Qp);
       R* tr = static_cast<R*>(a.trans);
       st_mat<N, N>(tr + TL::kF * st, st, cp, F);
       st_vec<N>(tr + TL::kc * st, st, cp, c);
@@ -194,15 +183,11 @@ PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename Filter
     {
       R x[N], Px[N][N], Rm[P][P], y[P];
       ld_vec<N>(traj, st, cs, x);
-      if constexpr (kSlr) ld_sym<N>(traj + N * st, st, cs, Px);
-      else set_zero<N>(Px);
+      set_zero<N>(Px);
       const R* Rg = static_cast<const R*>(a.R);
       PKS_UNROLL for (int i = 0; i < P; ++i) PKS_UNROLL for (int j = 0; j < P; ++j) Rm[i][j] = Rg[i * P + j];
       ld_vec<P>(static_cast<const R*>(a.yslot), st, cs, y);
-      const bool okh = linearize_h<Model, R>(md, lin, a.rule, Rm, x, Px, y, H, d, Rp, yt);
-      if constexpr (kSlr) {
-        if (!okh) d[0] = quiet_nan<R>();
-      }
+      linearize_h<Model, R>(md, kTaylor, a.rule, Rm, x, Px, y, H, d, Rp, yt);
     }
   }
   bool ok = filter_element<N, P, R>(F, c, Qp, H, d, Rp, yt, e.A, e.b, e.C, e.eta, e.J);
