@@ -16,9 +16,9 @@ compared (metric as in test_gpu_parity).  Step 2 is held to the FP64 gate
 1e-9.  Step 1 is held to 1e-8: these priors set the turn rate to zero, so on
 some tracks the first iteration moves the trajectory by hundreds of units
 (C3 track 0, T = 6667: max change 633).  There the parallel scan's FP64 result
-differs from the sequential oracle by 2.2e-9, while the same track from the
-oracle's iterates 2 and 4 agrees to 4e-11 and 7e-12, and every other sampled
-track agrees to 3e-11 at step 1.  On the device every output of every track
+differs from the sequential oracle by 2.2e-9 (the oracle in FP64 and in 80-bit
+agree to 4e-12), while the same track from the oracle's iterate 2 agrees to
+4.3e-11, and every other sampled track agrees to 3e-11 at step 1.  On the device every output of every track
 is checked to be finite, every covariance symmetric with a positive diagonal,
 and every per-track change statistic finite.
 """
