@@ -18,7 +18,9 @@ some tracks the first iteration moves the trajectory by hundreds of units
 (C3 track 0, T = 6667: max change 633).  There the parallel scan's FP64 result
 differs from the sequential oracle by 2.2e-9 (the oracle in FP64 and in 80-bit
 agree to 4e-12), while the same track from the oracle's iterate 2 agrees to
-4.3e-11, and every other sampled track agrees to 3e-11 at step 1.  On the device every output of every track
+4.3e-11, and every other sampled track agrees to 3e-11 at step 1.  The gap is
+the method's in FP64: test_scan_conditioning shows eq. 15 in a tree order
+missing the 80-bit result by 1.9e-8 on the same step.  On the device every output of every track
 is checked to be finite, every covariance symmetric with a positive diagonal,
 and every per-track change statistic finite.
 """
