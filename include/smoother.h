@@ -49,6 +49,11 @@
  *   - Layout: row-major; tracks are concatenated.  Track i has
  *     T_i = offsets[i+1] - offsets[i] >= 1 measurements and T_i + 1 states
  *     (slots) x_0..x_T; state arrays hold the slots of track 0, then track 1, ...
+ *   - Failed tracks: a track whose iterate turns non-finite (for example from
+ *     a broken caller-supplied trajectory) gets a NaN change statistic, and
+ *     the call that asked for the delta returns SM_ENUMERIC; the other tracks
+ *     of the batch are unaffected and their results stay valid, since every
+ *     track's prior and end elements restart both scans (Section 4).
  *   - Streams: all device work of a handle is queued on the stream given to
  *     smoother_init (NULL = the default stream).  One handle per host thread at
  *     a time; handles on different streams are independent.

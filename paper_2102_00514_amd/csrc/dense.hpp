@@ -302,6 +302,33 @@ struct Work {
   int ok;
 };
 
+// --- restarts -------------------------------------------------------------
+// A right operand with A = 0 (filtering) or E = 0 (smoothing) -- a track's
+// prior or end element, or an aggregate that contains one -- yields its own
+// (b, C) resp. (g, L) whatever the left operand holds.  The formulas give that
+// for finite operands; when a failed left operand has turned the result into
+// NaN (0 * NaN), the restart is taken as is, so a failed track never spills
+// into the tracks after it.  Every lane reads the same LDS words, so the
+// branch is uniform; finite results are unchanged bit for bit.
+template <int N, typename R>
+PKS_DEV bool all_zero(const R* A) {
+  bool z = true;
+  for (int e = lane(); e < N * N; e += kWave) z = z && A[(e / N) * ld<N>() + e % N] == R(0);
+  return __all(z);
+}
+
+template <int N, typename R>
+PKS_DEV void take_restart(const R* rA, const R* rb, const R* rC, R* lA, R* lb, R* lC) {
+  constexpr int L = ld<N>();
+  for (int e = lane(); e < N * N; e += kWave) {
+    const int i = e / N, j = e - i * N;
+    if (lA) lA[i * L + j] = R(0);
+    lC[i * L + j] = rC[i * L + j];
+  }
+  for (int i = lane(); i < N; i += kWave) lb[i] = rb[i];
+  wsync();
+}
+
 // --- the filtering operator (eq. 15), symmetric pivot-free form ------------
 // l <- l (x) r with l = (lA, lb, lC, le, lJ), r = (rA, rb, rC, re, rJ);
 // T1..T3 scratch.  Same algebra as FilterOp::combine.
@@ -343,6 +370,7 @@ PKS_DEV void combine_f(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, const R* 
   }
   wsync();
   mm<N, N, N, N, false, false>(rA, T2, (const R*)nullptr, R(1), lA);
+  if (!(lb[0] == lb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, lA, lb, lC);
 }
 
 // Carry (b, C) (x) r: the filtered mean and covariance after element r.
@@ -367,12 +395,16 @@ PKS_DEV void apply_f(R* cb, R* cC, const R* rA, const R* rb, const R* rC, const 
   mm<N, N, N, N, false, false>(rA, T1, (const R*)nullptr, R(1), T3);
   mm<N, N, N, N, false, true>(T3, rA, rC, R(1), cC);
   symmetrize<N, N>(cC);
+  if (!(cb[0] == cb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, (R*)nullptr, cb, cC);
 }
 
 // --- the smoothing operator (eq. 19) ------------------------------------------
 // l <- l (x) r in the paper's order (l earlier in time): (E_l E_r, E_l g_r + g_l, E_l L_r E_l^T + L_l).
 template <int N, typename R>
 PKS_DEV void combine_s(R* lE, R* lg, R* lL, const R* rE, const R* rg, const R* rL, R* T1, R* T2, R* v1) {
+  // E_l = 0 (a track's end element or an aggregate holding one): the result
+  // is l itself; l is updated in place, so the restart is taken up front.
+  if (lE[0] == R(0) && all_zero<N>(lE)) return;
   mm<N, N, N, N, false, false>(lE, rL, (const R*)nullptr, R(1), T1);
   mm<N, N, N, N, false, true>(T1, lE, lL, R(1), lL);
   symmetrize<N, N>(lL);
@@ -391,6 +423,7 @@ PKS_DEV void apply_s(const R* rE, const R* rg, const R* rL, R* cg, R* cL, R* T1,
   symmetrize<N, N>(cL);
   mv<N, N, N, false>(rE, cg, rg, R(1), v1);
   vcopy<N>(v1, cg);
+  if (!(cg[0] == cg[0] && cL[0] == cL[0]) && all_zero<N>(rE)) take_restart<N>(rE, rg, rL, (R*)nullptr, cg, cL);
 }
 
 // --- statistical linear regression (eq. 7-9) of g: R^N -> R^Q at (xbar, Pbar)

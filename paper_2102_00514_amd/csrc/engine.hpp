@@ -100,6 +100,9 @@ class Engine final : public EngineBase {
     n_iter = pb.n_iter;
     lin_ = pb.lin;
     seq_ = pb.scan == SM_SCAN_SEQUENTIAL;
+    // restart tests in the scan operators keep a failed track out of the
+    // tracks after it; a single track has none after it
+    iso_ = pb.n_tracks > 1;
     use_graph_ = pb.use_graph != 0 && !seq_;
     lm_ = pb.lm_lambda;
     rule_.alpha = pb.ut_alpha;
@@ -270,28 +273,26 @@ class Engine final : public EngineBase {
   size_t lds_filter() const { return sizeof(R) * FOp::kElemWords * (sched_.B / 64); }
   size_t lds_smoother() const { return sizeof(R) * SOp::kElemWords * (sched_.B / 64); }
 
-  template <int B>
+  template <int B, bool ISO>
   hipError_t set_lds_limits_b() {
     hipError_t e = hipSuccess;
     auto set = [&](const void* f, size_t bytes) {
       if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
     };
-    set(reinterpret_cast<const void*>(&k_forward_up<Model, kInlineTaylor, B, R>), lds_filter());
-    set(reinterpret_cast<const void*>(&k_forward_up<Model, kStoredLin, B, R>), lds_filter());
-    set(reinterpret_cast<const void*>(&k_forward_down_backward_up<Model, B, R>), lds_smoother());
+    set(reinterpret_cast<const void*>(&k_forward_up<Model, kInlineTaylor, B, R, ISO>), lds_filter());
+    set(reinterpret_cast<const void*>(&k_forward_up<Model, kStoredLin, B, R, ISO>), lds_filter());
+    set(reinterpret_cast<const void*>(&k_forward_down_backward_up<Model, B, R, ISO>), lds_smoother());
+    set(reinterpret_cast<const void*>(&k_scan_single<FilterOp<N, R, ISO>, kTopB, R>),
+        sizeof(R) * FOp::kElemWords * (kTopB / 64));
+    set(reinterpret_cast<const void*>(&k_scan_single<SmootherOp<N, R, ISO>, kTopB, R>),
+        sizeof(R) * SOp::kElemWords * (kTopB / 64));
     return e;
   }
 
   hipError_t set_lds_limits() {
     if (seq_) return hipSuccess;
-    hipError_t e = sched_.B == 64 ? set_lds_limits_b<64>() : set_lds_limits_b<256>();
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_single<FOp, kTopB, R>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(R) * FOp::kElemWords * (kTopB / 64)));
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_single<SOp, kTopB, R>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(R) * SOp::kElemWords * (kTopB / 64)));
-    return e;
+    if (iso_) return sched_.B == 64 ? set_lds_limits_b<64, true>() : set_lds_limits_b<256, true>();
+    return sched_.B == 64 ? set_lds_limits_b<64, false>() : set_lds_limits_b<256, false>();
   }
 
   // grid of one lane per column of the per-slot arrays (padding included)
@@ -434,7 +435,7 @@ class Engine final : public EngineBase {
     });
   }
 
-  template <int B>
+  template <int B, bool ISO>
   void launch_iteration(const FusedArgs& a) {
     static const char* const kFilterNames[3] = {"tiles_up_filter", "tiles_top_filter", "tiles_down_filter"};
     static const char* const kSmootherNames[3] = {"tiles_up_smoother", "tiles_top_smoother",
@@ -442,23 +443,23 @@ class Engine final : public EngineBase {
     const dim3 grid{unsigned(tiles_)}, block{unsigned(B)};
     if (lin_ == SM_LIN_TAYLOR) {
       timed("forward_up", S, [&] {
-        hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R>), grid, block, lds_filter(), stream, a);
+        hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R, ISO>), grid, block, lds_filter(), stream, a);
       });
     } else {
       const dim3 sgrid = col_grid();
       const SlotArgs sa = slot_args(0);
       timed("linearize", S, [&] { launch_linearize(sa, sgrid); });
       timed("forward_up", S, [&] {
-        hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R>), grid, block, lds_filter(), stream, a);
+        hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R, ISO>), grid, block, lds_filter(), stream, a);
       });
     }
-    scan_tiles<FOp>(ta_f_, tc_f_, kFilterNames);
+    scan_tiles<FilterOp<N, R, ISO>>(ta_f_, tc_f_, kFilterNames);
     timed("forward_down_backward_up", S, [&] {
-      hipLaunchKernelGGL((k_forward_down_backward_up<Model, B, R>), grid, block, lds_smoother(), stream, a);
+      hipLaunchKernelGGL((k_forward_down_backward_up<Model, B, R, ISO>), grid, block, lds_smoother(), stream, a);
     });
-    scan_tiles<SOp>(ta_s_, tc_s_, kSmootherNames);
+    scan_tiles<SmootherOp<N, R, ISO>>(ta_s_, tc_s_, kSmootherNames);
     timed("backward_down", S, [&] {
-      hipLaunchKernelGGL((k_backward_down<Model, B, R>), grid, block, 0, stream, a);
+      hipLaunchKernelGGL((k_backward_down<Model, B, R, ISO>), grid, block, 0, stream, a);
     });
   }
 
@@ -511,8 +512,13 @@ class Engine final : public EngineBase {
 
   void launch_parallel_iteration() {
     const FusedArgs a = fused_args();
-    if (sched_.B == 64) launch_iteration<64>(a);
-    else launch_iteration<256>(a);
+    if (iso_) {
+      if (sched_.B == 64) launch_iteration<64, true>(a);
+      else launch_iteration<256, true>(a);
+    } else {
+      if (sched_.B == 64) launch_iteration<64, false>(a);
+      else launch_iteration<256, false>(a);
+    }
   }
 
   // Records one iteration on a private stream (capture is not allowed on the
@@ -623,8 +629,13 @@ class Engine final : public EngineBase {
       a.lm_track = nullptr;
       a.filt = d_filt_;
       a.delta_bits = d_delta_spare_;    // the forward kernel clears its statistic: keep the handle's
-      if (sched_.B == 64) launch_filter_pass<64>(a);
-      else launch_filter_pass<256>(a);
+      if (iso_) {
+        if (sched_.B == 64) launch_filter_pass<64, true>(a);
+        else launch_filter_pass<256, true>(a);
+      } else {
+        if (sched_.B == 64) launch_filter_pass<64, false>(a);
+        else launch_filter_pass<256, false>(a);
+      }
       la.trans = d_trans_;
       la.lin = lin_ == SM_LIN_TAYLOR ? nullptr : d_lin_;
     }
@@ -641,18 +652,18 @@ class Engine final : public EngineBase {
     return SM_OK;
   }
 
-  template <int B>
+  template <int B, bool ISO>
   void launch_filter_pass(const FusedArgs& a) {
     static const char* const kFilterNames[3] = {"tiles_up_filter", "tiles_top_filter", "tiles_down_filter"};
     const dim3 grid{unsigned(tiles_)}, block{unsigned(B)};
     if (lin_ == SM_LIN_TAYLOR) {
-      hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R>), grid, block, lds_filter(), stream, a);
+      hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R, ISO>), grid, block, lds_filter(), stream, a);
     } else {
       launch_linearize(slot_args(cur_), col_grid());
-      hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R>), grid, block, lds_filter(), stream, a);
+      hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R, ISO>), grid, block, lds_filter(), stream, a);
     }
-    scan_tiles<FOp>(ta_f_, tc_f_, kFilterNames);
-    hipLaunchKernelGGL((k_forward_down_filter<Model, B, R>), grid, block, 0, stream, a);
+    scan_tiles<FilterOp<N, R, ISO>>(ta_f_, tc_f_, kFilterNames);
+    hipLaunchKernelGGL((k_forward_down_filter<Model, B, R, ISO>), grid, block, 0, stream, a);
   }
 
   sm_status objective(double* out) override {
@@ -809,6 +820,7 @@ class Engine final : public EngineBase {
  private:
   int lin_ = 0;
   bool seq_ = false;
+  bool iso_ = true;
   bool use_graph_ = false;
   hipGraphExec_t graph_exec_ = nullptr;
   hipStream_t capture_stream_ = nullptr;

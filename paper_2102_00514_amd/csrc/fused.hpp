@@ -195,10 +195,10 @@ PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename Filter
   if (!ok) e.b[0] = quiet_nan<R>();
 }
 
-template <class Model, int SRC, int B, typename R>
+template <class Model, int SRC, int B, typename R, bool ISO = true>
 __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
   constexpr int N = Model::N;
-  using Op = FilterOp<N, R>;
+  using Op = FilterOp<N, R, ISO>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
   const int lane = threadIdx.x;
@@ -234,10 +234,10 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
 // Carry at the start of a lane's run in a forward down-sweep: tile carry (x)
 // the lane prefix handed over by k_forward_up (inclusive for K = 1, so the
 // result is already the filtered moments of the lane's slot).
-template <int N, int B, typename R>
+template <int N, int B, typename R, bool ISO>
 PKS_DEV void lane_filter_carry(const FusedArgs& a, int64_t tile, int lane, typename FilterOp<N, R>::Carry& c,
                                bool& have) {
-  using FOp = FilterOp<N, R>;
+  using FOp = FilterOp<N, R, ISO>;
   have = false;
   if (tile > 0) {
     FOp::load(static_cast<const R*>(a.tc_f), size_t(a.tiles), tile - 1, c);
@@ -257,11 +257,11 @@ PKS_DEV void lane_filter_carry(const FusedArgs& a, int64_t tile, int lane, typen
   }
 }
 
-template <class Model, int B, typename R>
+template <class Model, int B, typename R, bool ISO = true>
 __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
   constexpr int N = Model::N;
-  using FOp = FilterOp<N, R>;
-  using SOp = SmootherOp<N, R>;
+  using FOp = FilterOp<N, R, ISO>;
+  using SOp = SmootherOp<N, R, ISO>;
   using TL = TransLayout<N>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
   const size_t st = a.stride;
   typename FOp::Carry c;
   bool have;
-  lane_filter_carry<N, B, R>(a, tile, lane, c, have);
+  lane_filter_carry<N, B, R, ISO>(a, tile, lane, c, have);
   typename SOp::Elem sacc;
   const int64_t cbase = tile * B * a.K + lane;
   for (int j = 0; j < a.K; ++j) {
@@ -330,15 +330,15 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
 
 // Filtering pass only: forward down-sweep that stores the filtered moments
 // (x*, P*) of every slot (the prefix of the filtering elements, Section 2).
-template <class Model, int B, typename R>
+template <class Model, int B, typename R, bool ISO = true>
 __global__ __launch_bounds__(B) void k_forward_down_filter(FusedArgs a) {
   constexpr int N = Model::N;
-  using FOp = FilterOp<N, R>;
+  using FOp = FilterOp<N, R, ISO>;
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
   typename FOp::Carry c;
   bool have;
-  lane_filter_carry<N, B, R>(a, tile, lane, c, have);
+  lane_filter_carry<N, B, R, ISO>(a, tile, lane, c, have);
   const int64_t cbase = tile * B * a.K + lane;
   for (int j = 0; j < a.K; ++j) {
     const int64_t cs = cbase + int64_t(j) * B;
@@ -363,10 +363,10 @@ PKS_DEV unsigned long long order_bits(double v) {
   return static_cast<unsigned long long>(__double_as_longlong(v == v ? v : __builtin_nan("")));
 }
 
-template <class Model, int B, typename R>
+template <class Model, int B, typename R, bool ISO = true>
 __global__ __launch_bounds__(B) void k_backward_down(FusedArgs a) {
   constexpr int N = Model::N;
-  using SOp = SmootherOp<N, R>;
+  using SOp = SmootherOp<N, R, ISO>;
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t base = (tile * B + lane) * a.K;

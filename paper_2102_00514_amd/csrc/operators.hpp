@@ -25,6 +25,16 @@
 // filtered mean and covariance; a smoothing suffix that ends at an end element
 // (E = 0) is carried as (g, L) = the smoothed mean and covariance.
 //
+// Restarts.  A right operand whose A (filtering) or E (smoothing) is zero --
+// a track's prior or end element, or any aggregate that contains one -- gives
+// exactly (0, b_j, C_j) resp. (0, g_y, L_y) in those blocks, whatever the left
+// operand holds.  The formulas give that only for finite operands (0 * NaN is
+// NaN), so such an operand is taken as the result directly: a failed track
+// never spills into the tracks that follow it in a batch.  eta and J of a
+// restarted filtering result are the right operand's; they never reach b or C
+// of any later result (those read b, C and A of a left operand, and a right
+// operand with A = 0 restarts again).  Other results are unchanged.
+//
 // Scan order.  Both scans run left to right over "scan positions"; the
 // smoothing scan visits slots from last to first, so its scan-order combine of
 // an earlier position x with a later position y is y (x) x in the paper's order.
@@ -35,13 +45,21 @@
 namespace pks {
 
 template <int N, typename R>
+struct FilterElem {
+  R A[N][N], b[N], C[N][N], eta[N], J[N][N];
+};
+template <int N, typename R>
+struct FilterCarry {
+  R b[N], C[N][N];
+};
+
+// kIsolate = false drops the restart test, for scans over a single track
+// (nothing follows a failed track there, and the test costs the ladders a few
+// per cent).
+template <int N, typename R, bool kIsolate = true>
 struct FilterOp {
-  struct Elem {
-    R A[N][N], b[N], C[N][N], eta[N], J[N][N];
-  };
-  struct Carry {
-    R b[N], C[N][N];
-  };
+  using Elem = FilterElem<N, R>;
+  using Carry = FilterCarry<N, R>;
   static constexpr int kS = sym_size<N>();
   static constexpr int kElemWords = N * N + 2 * N + 2 * kS;
   static constexpr int kCarryWords = N + kS;
@@ -90,6 +108,17 @@ struct FilterOp {
     }
   }
 
+  static PKS_DEV bool restarts(const R (&A)[N][N]) {
+    if constexpr (!kIsolate) {
+      return false;
+    } else {
+      if (A[0][0] != R(0)) return false;
+      bool z = true;
+      PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) z &= A[i][j] == R(0);
+      return z;
+    }
+  }
+
   // M = (I + C J)^-1 C, symmetric.  ok = false if C is not positive definite.
   static PKS_DEV bool core(const R (&Ci)[N][N], const R (&Jj)[N][N], R (&M)[N][N]) {
     R U[N][N], Ud[N];
@@ -124,6 +153,10 @@ struct FilterOp {
 
   // out = l (x) r
   static PKS_DEV void combine(const Elem& l, const Elem& r, Elem& o) {
+    if (restarts(r.A)) {
+      o = r;
+      return;
+    }
     R M[N][N];
     const bool ok = core(l.C, r.J, M);
     R Y[N][N], Z[N][N];
@@ -167,6 +200,13 @@ struct FilterOp {
 
   // out = c (x) r for a carry c
   static PKS_DEV void apply(const Carry& c, const Elem& r, Carry& o) {
+    if (restarts(r.A)) {
+      PKS_UNROLL for (int i = 0; i < N; ++i) {
+        o.b[i] = r.b[i];
+        PKS_UNROLL for (int j = 0; j < N; ++j) o.C[i][j] = r.C[i][j];
+      }
+      return;
+    }
     R M[N][N];
     const bool ok = core(c.C, r.J, M);
     R v[N], u[N];
@@ -188,13 +228,18 @@ struct FilterOp {
 };
 
 template <int N, typename R>
+struct SmootherElem {
+  R E[N][N], g[N], L[N][N];
+};
+template <int N, typename R>
+struct SmootherCarry {
+  R g[N], L[N][N];
+};
+
+template <int N, typename R, bool kIsolate = true>
 struct SmootherOp {
-  struct Elem {
-    R E[N][N], g[N], L[N][N];
-  };
-  struct Carry {
-    R g[N], L[N][N];
-  };
+  using Elem = SmootherElem<N, R>;
+  using Carry = SmootherCarry<N, R>;
   static constexpr int kS = sym_size<N>();
   static constexpr int kElemWords = N * N + N + kS;
   static constexpr int kCarryWords = N + kS;
@@ -230,8 +275,28 @@ struct SmootherOp {
       PKS_UNROLL for (int j = 0; j < N; ++j) c.L[i][j] = e.L[i][j];
     }
   }
+  static PKS_DEV bool restarts(const R (&E)[N][N]) {
+    if constexpr (!kIsolate) {
+      return false;
+    } else {
+      if (E[0][0] != R(0)) return false;
+      bool z = true;
+      PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) z &= E[i][j] == R(0);
+      return z;
+    }
+  }
   // Scan order: x precedes y in the scan (x is the later slot); out = y (x) x.
   static PKS_DEV void combine(const Elem& x, const Elem& y, Elem& o) {
+    if (restarts(y.E)) {
+      PKS_UNROLL for (int i = 0; i < N; ++i) {
+        o.g[i] = y.g[i];
+        PKS_UNROLL for (int j = 0; j < N; ++j) {
+          o.E[i][j] = R(0);
+          o.L[i][j] = y.L[i][j];
+        }
+      }
+      return;
+    }
     mat_mul<N, N, N>(y.E, x.E, o.E);
     PKS_UNROLL for (int i = 0; i < N; ++i) {
       R s = y.g[i];
@@ -241,6 +306,13 @@ struct SmootherOp {
     sandwich_add<N, N>(y.E, x.L, y.L, o.L);
   }
   static PKS_DEV void apply(const Carry& c, const Elem& y, Carry& o) {
+    if (restarts(y.E)) {
+      PKS_UNROLL for (int i = 0; i < N; ++i) {
+        o.g[i] = y.g[i];
+        PKS_UNROLL for (int j = 0; j < N; ++j) o.L[i][j] = y.L[i][j];
+      }
+      return;
+    }
     PKS_UNROLL for (int i = 0; i < N; ++i) {
       R s = y.g[i];
       PKS_UNROLL for (int t = 0; t < N; ++t) s += y.E[i][t] * c.g[t];
