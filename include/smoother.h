@@ -171,8 +171,10 @@ sm_status smoother_iterate(smoother_t h, int32_t k, double* max_delta_out, int32
  * as soon as the last track has converged.  *iters_run (nullable) receives the
  * iterations run; track_iters (nullable, host [n_tracks]) the 1-based
  * iteration of this call at which each track first fell below tol, 0 if it
- * did not.  Returns SM_EINVAL for tol <= 0 or max_iter < 1, SM_ENUMERIC when a
- * delta is not finite (outputs hold the iterations run until then). */
+ * did not.  A track whose delta turns non-finite has failed: it is not waited
+ * for (its entry stays 0), the other tracks run on, and the call returns
+ * SM_ENUMERIC with the outputs filled.  Returns SM_EINVAL for tol <= 0 or
+ * max_iter < 1. */
 sm_status smoother_iterate_until(smoother_t h, double tol, int32_t max_iter, int32_t* iters_run,
                                  int32_t* track_iters);
 

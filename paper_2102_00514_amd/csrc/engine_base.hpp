@@ -81,26 +81,34 @@ class EngineBase {
   // Iterations until every track's delta has been below tol once, or max_iter
   // iterations.  first[i] = iteration (1-based, this call) at which track i
   // first fell below tol, 0 if it did not.
+  // A track whose delta turns non-finite has failed: it is no longer waited
+  // for (its first[] stays 0), the other tracks -- unaffected by it, since
+  // track boundaries restart both scans -- run on, and the call then reports
+  // SM_ENUMERIC.
   sm_status iterate_until(double tol, int max_iter, int* run, int32_t* first) {
     std::vector<double> d(ntracks + 1);
-    int left = ntracks;
+    std::vector<unsigned char> failed(ntracks, 0);
+    int left = ntracks, n_failed = 0;
     for (int i = 0; i < ntracks; ++i) first[i] = 0;
     *run = 0;
-    bool finite = true;
     while (*run < max_iter && left > 0) {
       sm_status st = iterate(1);
       if (st == SM_OK) st = track_deltas(d.data());
       if (st != SM_OK) return st;
       *run += 1;
       for (int i = 0; i < ntracks; ++i) {
-        if (!std::isfinite(d[i])) finite = false;
-        if (first[i] == 0 && d[i] < tol) {
+        if (failed[i]) continue;
+        if (!std::isfinite(d[i])) {
+          failed[i] = 1;
+          ++n_failed;
+          if (first[i] == 0) --left;
+        } else if (first[i] == 0 && d[i] < tol) {
           first[i] = *run;
           --left;
         }
       }
-      if (!finite) return fail(SM_ENUMERIC, "non-finite iterate");
     }
+    if (n_failed > 0) return fail(SM_ENUMERIC, "non-finite iterate in " + std::to_string(n_failed) + " track(s)");
     return SM_OK;
   }
 

@@ -88,3 +88,39 @@ def test_dense_stacked_batch(B, slots, bad):
     pb = wl.concat_tracks(parts, "stacked batch")
     out = run_with_failed_track(B, pb, bad, "unscented", lane_slots=slots)
     check_others(pb, bad, "unscented", *out, tol=1e-9)
+
+
+@pytest.mark.parametrize("lanes,slots", [(64, 1), (256, 3)])
+def test_iterate_until_runs_the_other_tracks_on(B, lanes, slots):
+    """smoother_iterate_until with a failed track: the others converge at the
+    iterations they take without it, with the same results bit for bit, and
+    the call reports the failure."""
+    import torch
+    pb = ct_batch()
+    L = pb.lengths
+    so = pb.slot_offsets()
+    bad = 1
+    clean = torch.from_numpy(np.repeat(pb.m0, L + 1, axis=0)).to("cuda", torch.float64)
+    cov = torch.from_numpy(np.repeat(pb.P0, L + 1, axis=0)).to("cuda", torch.float64)
+    broken = clean.clone()
+    broken[so[bad] + 5, 2] = float("inf")
+    torch.cuda.synchronize()
+    kw = dict(n_iter=1, tile_lanes=lanes, lane_slots=slots)
+    with B.Smoother(pb, **kw) as a, B.Smoother(pb, **kw) as b, B.Smoother(pb, **kw) as c:
+        a.set_trajectory_device(broken.data_ptr(), cov.data_ptr())
+        b.set_trajectory_device(clean.data_ptr(), cov.data_ptr())
+        c.set_trajectory_device(clean.data_ptr(), cov.data_ptr())
+        run_a, first_a, ok_a = a.iterate_until(1e-8, 40)
+        run_b, first_b, ok_b = b.iterate_until(1e-8, 40)
+        c.iterate(run_a)
+        ma, ca = a.result()
+        mc, cc = c.result()
+    print(f"failed track {bad}: runs {run_a} / {run_b}, first {list(first_a)} / {list(first_b)}", flush=True)
+    assert ok_b and not ok_a
+    assert first_a[bad] == 0 and first_b[bad] > 0
+    others = [i for i in range(pb.n_tracks) if i != bad]
+    assert all(first_a[i] == first_b[i] > 0 for i in others), (first_a, first_b)
+    assert run_a == max(first_a[i] for i in others)
+    for i in others:
+        sl = slice(so[i], so[i + 1])
+        assert np.array_equal(ma[sl], mc[sl]) and np.array_equal(ca[sl], cc[sl]), i
