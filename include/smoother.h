@@ -220,9 +220,12 @@ sm_status smoother_objective(smoother_t h, double* track_cost);
  * objective.  The problem's lm_lambda is not used during the call and is used
  * again by later calls of smoother_iterate.  Covariances are those of the last
  * kept damped pass; one more smoother_iterate with lm_lambda = 0 gives the
- * undamped ones at the result.  Needs the Taylor linearisation (SM_EINVAL
- * otherwise, or for invalid arguments: lambda0 > 0 and nu > 1 finite, tol > 0,
- * max_iter >= 1).  Waits for the stream twice per pass. */
+ * undamped ones at the result.  A track whose objective is not finite at the
+ * start has failed: it is not waited for (convergence entry 0, cost not
+ * finite), the other tracks run on, and the call returns SM_ENUMERIC with the
+ * outputs filled.  Needs the Taylor linearisation (SM_EINVAL otherwise, or for
+ * invalid arguments: lambda0 > 0 and nu > 1 finite, tol > 0, max_iter >= 1).
+ * Waits for the stream twice per pass. */
 sm_status smoother_iterate_lm(smoother_t h, double lambda0, double nu, double tol, int32_t max_iter,
                               int32_t* iters_run, int32_t* track_iters, double* track_cost);
 

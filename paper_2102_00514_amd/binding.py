@@ -250,14 +250,16 @@ def smoother_objective(h: int) -> np.ndarray:
 def smoother_iterate_lm(h: int, lambda0: float = 1e-2, nu: float = 10.0, tol: float = 1e-6, max_iter: int = 50):
     """Levenberg-Marquardt passes with Marquardt's damping schedule until every
     track has converged (or max_iter).  Returns (passes run, per-track pass of
-    convergence (0 = none), per-track final objective)."""
+    convergence (0 = none), per-track final objective); a failed track (not
+    finite from the start) shows as a non-finite objective."""
     _, T, _ = smoother_info(h)
     run = ctypes.c_int32(0)
     first = np.zeros(T, dtype=np.int32)
     cost = np.empty(T)
-    _check(h, _lib.smoother_iterate_lm(h, lambda0, nu, tol, max_iter, ctypes.byref(run),
-                                       first.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                       cost.ctypes.data_as(_dp)))
+    st = _lib.smoother_iterate_lm(h, lambda0, nu, tol, max_iter, ctypes.byref(run),
+                                  first.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cost.ctypes.data_as(_dp))
+    if st != SM_ENUMERIC:
+        _check(h, st)
     return run.value, first, cost
 
 

@@ -150,8 +150,17 @@ class EngineBase {
     std::vector<unsigned char> reject(ntracks, 0);
     for (int i = 0; i < ntracks; ++i) first[i] = 0;
     *run = 0;
-    int left = ntracks;
+    int left = ntracks, n_failed = 0;
     st = objective(J.data());
+    // a track whose kept objective is not finite cannot recover (a pass is
+    // kept only when its objective does not rise): it has failed and is not
+    // waited for; a non-finite trial pass is simply rejected
+    if (st == SM_OK)
+      for (int i = 0; i < ntracks; ++i)
+        if (!std::isfinite(J[i])) {
+          ++n_failed;
+          --left;
+        }
     while (st == SM_OK && *run < max_iter && left > 0) {
       st = lm_set_lambda(lam.data());
       if (st == SM_OK) st = lm_save();
@@ -182,6 +191,8 @@ class EngineBase {
     if (st == SM_OK) st = off;
     if (cost)
       for (int i = 0; i < ntracks; ++i) cost[i] = J[i];
+    if (st == SM_OK && n_failed > 0)
+      return fail(SM_ENUMERIC, "non-finite objective in " + std::to_string(n_failed) + " track(s)");
     return st;
   }
 

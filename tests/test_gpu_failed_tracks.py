@@ -124,3 +124,33 @@ def test_iterate_until_runs_the_other_tracks_on(B, lanes, slots):
     for i in others:
         sl = slice(so[i], so[i + 1])
         assert np.array_equal(ma[sl], mc[sl]) and np.array_equal(ca[sl], cc[sl]), i
+
+
+def test_iterate_lm_runs_the_other_tracks_on(B):
+    """smoother_iterate_lm with a failed track (objective not finite from the
+    start): the others take the passes they take without it, and the failed
+    track shows as a non-finite objective."""
+    import torch
+    pb = ct_batch()
+    L = pb.lengths
+    so = pb.slot_offsets()
+    bad = 2
+    clean = torch.from_numpy(np.repeat(pb.m0, L + 1, axis=0)).to("cuda", torch.float64)
+    cov = torch.from_numpy(np.repeat(pb.P0, L + 1, axis=0)).to("cuda", torch.float64)
+    broken = clean.clone()
+    broken[so[bad] + 3, 1] = float("nan")
+    torch.cuda.synchronize()
+    with B.Smoother(pb, n_iter=1, tile_lanes=64, lane_slots=2) as a, \
+            B.Smoother(pb, n_iter=1, tile_lanes=64, lane_slots=2) as b:
+        a.set_trajectory_device(broken.data_ptr(), cov.data_ptr())
+        b.set_trajectory_device(clean.data_ptr(), cov.data_ptr())
+        run_a, first_a, cost_a = a.iterate_lm(tol=1e-8, max_iter=40)
+        run_b, first_b, cost_b = b.iterate_lm(tol=1e-8, max_iter=40)
+    print(f"LM, failed track {bad}: passes {run_a} / {run_b}, first {list(first_a)} / {list(first_b)}", flush=True)
+    assert first_a[bad] == 0 and not np.isfinite(cost_a[bad])
+    others = [i for i in range(pb.n_tracks) if i != bad]
+    assert all(first_a[i] == first_b[i] > 0 for i in others), (first_a, first_b)
+    assert run_a == max(first_a[i] for i in others)
+    assert np.all(np.isfinite(cost_a[others]))
+    if run_a == run_b:
+        assert np.array_equal(cost_a[others], cost_b[others])
