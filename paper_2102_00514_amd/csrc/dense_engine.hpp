@@ -2,11 +2,13 @@
 // the kernel sequence of one iteration and its HIP graph.
 //
 // Scan hierarchy: level 0 folds `fan0` consecutive slots per wave; every
-// higher level folds pairs of aggregates of the level below, until at most two
-// remain; a single wave then scans those, and the down-sweeps hand exclusive
-// carries back level by level.  Pairs keep the critical path of the upper
-// levels at one operator per level: there a level has too few waves to fill
-// the chip, and a fan of f would cost f - 1 dependent combines instead.
+// higher level folds pairs of aggregates of the level below (fours for the
+// smoothing scan), until at most that many remain; a single wave then scans
+// those, and the down-sweeps hand exclusive carries back level by level.  Pairs
+// keep the critical path of the upper levels at one operator per level: there a
+// level has too few waves to fill the chip, and a fan of f would cost f - 1
+// dependent combines instead.  The smoothing combine is about a quarter of the
+// filtering one, so there fewer levels (fewer launches) win.
 #pragma once
 
 #include <algorithm>
@@ -25,6 +27,7 @@ class DenseEngine final : public EngineBase {
   using Lay = dn::Layout<N, P>;
   static constexpr int kFan = 8;        // level 0: slots per wave (default)
   static constexpr int kLevelFan = 2;   // higher levels: aggregates per wave
+  static constexpr int kLevelFanS = 4;  // the same for the smoothing scan, whose combine is 4x cheaper
 
   sm_status setup(const sm_problem& pb, hipStream_t st) override {
     stream = st;
@@ -48,6 +51,12 @@ class DenseEngine final : public EngineBase {
     while (c > kLevelFan) {
       c = (c + kLevelFan - 1) / kLevelFan;
       counts_.push_back(c);
+    }
+    c = counts_[0];
+    counts_s_.push_back(c);
+    while (c > kLevelFanS) {
+      c = (c + kLevelFanS - 1) / kLevelFanS;
+      counts_s_.push_back(c);
     }
     sched_tiles = counts_[0];
     // host-side tables
@@ -86,13 +95,16 @@ class DenseEngine final : public EngineBase {
     A(&d_elem_, sizeof(R) * Lay::kFElem * S);
     A(reinterpret_cast<void**>(&delta_bits), sizeof(unsigned long long) * (ntracks + 1));
     for (size_t l = 0; l < counts_.size(); ++l) {
-      void *fa = nullptr, *fc = nullptr, *sa = nullptr, *sc = nullptr;
+      void *fa = nullptr, *fc = nullptr;
       A(&fa, sizeof(R) * Lay::kFElem * counts_[l]);
       A(&fc, sizeof(R) * Lay::kCarry * counts_[l]);
-      A(&sa, sizeof(R) * Lay::kSElem * counts_[l]);
-      A(&sc, sizeof(R) * Lay::kCarry * counts_[l]);
       fagg_.push_back(fa);
       fcar_.push_back(fc);
+    }
+    for (size_t l = 0; l < counts_s_.size(); ++l) {
+      void *sa = nullptr, *sc = nullptr;
+      A(&sa, sizeof(R) * Lay::kSElem * counts_s_[l]);
+      A(&sc, sizeof(R) * Lay::kCarry * counts_s_[l]);
       sagg_.push_back(sa);
       scar_.push_back(sc);
     }
@@ -165,19 +177,21 @@ class DenseEngine final : public EngineBase {
     std::vector<void*>& car = FILT ? fcar_ : scar_;
     const char* up = FILT ? "scan_up_filter" : "scan_up_smoother";
     const char* down = FILT ? "scan_down_filter" : "scan_down_smoother";
-    const size_t top = counts_.size() - 1;
+    const std::vector<int64_t>& counts = FILT ? counts_ : counts_s_;
+    const int fan = FILT ? kLevelFan : kLevelFanS;
+    const size_t top = counts.size() - 1;
     for (size_t l = 0; l < top; ++l) {
-      const dn::DnLevel lv{agg[l], agg[l + 1], nullptr, nullptr, counts_[l], kLevelFan};
-      timed(up, counts_[l], [&] {
-        hipLaunchKernelGGL((dn::k_dn_scan_up<Model, FILT, R>), dim3(unsigned(counts_[l + 1])), dim3(dn::kWave), 0,
+      const dn::DnLevel lv{agg[l], agg[l + 1], nullptr, nullptr, counts[l], fan};
+      timed(up, counts[l], [&] {
+        hipLaunchKernelGGL((dn::k_dn_scan_up<Model, FILT, R>), dim3(unsigned(counts[l + 1])), dim3(dn::kWave), 0,
                            stream, a, lv);
       });
     }
     for (size_t k = 0; k <= top; ++k) {
       const size_t l = top - k;
-      const dn::DnLevel lv{agg[l], nullptr, car[l], l == top ? nullptr : car[l + 1], counts_[l], kLevelFan};
-      const unsigned grid = unsigned((counts_[l] + kLevelFan - 1) / kLevelFan);
-      timed(down, counts_[l], [&] {
+      const dn::DnLevel lv{agg[l], nullptr, car[l], l == top ? nullptr : car[l + 1], counts[l], fan};
+      const unsigned grid = unsigned((counts[l] + fan - 1) / fan);
+      timed(down, counts[l], [&] {
         hipLaunchKernelGGL((dn::k_dn_scan_down<Model, FILT, R>), dim3(grid), dim3(dn::kWave), 0, stream, a, lv);
       });
     }
@@ -301,7 +315,7 @@ class DenseEngine final : public EngineBase {
   int fan0_ = kFan;
   hipGraphExec_t graph_exec_ = nullptr;
   hipStream_t capture_stream_ = nullptr;
-  std::vector<int64_t> counts_;
+  std::vector<int64_t> counts_, counts_s_;   // chunks per scan level (filtering, smoothing)
   std::vector<void*> fagg_, fcar_, sagg_, scar_;
   unsigned char* d_flags_ = nullptr;
   int* d_track_ = nullptr;
