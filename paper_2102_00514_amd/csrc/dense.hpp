@@ -433,10 +433,10 @@ PKS_DEV void apply_s(const R* rE, const R* rg, const R* rL, R* cg, R* cL, R* T1,
 // Lam (Q x Q), zc = g(xbar).  Zp, Zm, D: N x Q scratch; zbar: Q vector.
 template <int N, int Q, bool kAngular, typename R, class Eval>
 PKS_DEV void slr(int lin, SigmaRule rule, const R* xbar, R* Pbar, Eval eval, R* G, R* off, R* Lam, R* zc, R* Zp,
-                 R* Zm, R* D, R* zbar, int* ok) {
+                 R* Zm, R* D, R* zbar, int* ok, bool factored = false) {
   static_assert(2 * N <= kWave, "one sigma point per lane");
   constexpr int L = ld<N>();
-  chol<N, N>(Pbar, ok);
+  if (!factored) chol<N, N>(Pbar, ok);    // else Pbar already holds the factor
   R gamma, w0, wj;
   sigma_weights<N, R>(lin, rule, gamma, w0, wj);
   if (lane() == 0) {
@@ -693,6 +693,7 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
   R* xbar = w.v[0];
   ld_v<N>(tj, xbar);
   wsync();
+  bool factored = false;   // w.m[0] holds the Cholesky factor of Pbar, shared by f and h
   if (!(fl & kSlotLast)) {
     ld_symm<N, N>(tj + N, w.m[0]);
     wsync();
@@ -700,6 +701,7 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
     R* Lam = w.m[2];
     slr<N, N, false, R>(a.lin, a.rule, xbar, w.m[0], [&](const R(&x)[N], R(&z)[N]) { md.f(x, z); }, G, w.v[1],
                         Lam, w.v[2], w.m[3], w.m[4], w.m[5], w.v[3], &w.ok);
+    factored = true;
     R* out = static_cast<R*>(a.trans) + size_t(s) * Lay::kTrans;
     const R* Qm = static_cast<const R*>(a.Q);
     add_full<N, N, N>(Qm, Lam);
@@ -710,13 +712,15 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
     wsync();                      // the stores have read LDS before it is reused
   }
   if (!(fl & kSlotFirst)) {
-    ld_symm<N, N>(tj + N, w.m[0]);
-    wsync();
+    if (!factored) {
+      ld_symm<N, N>(tj + N, w.m[0]);
+      wsync();
+    }
     R* H = w.m[1];
     R* Om = w.m[2];
     R* hc = w.v[2];
     slr<N, P, Model::kAngular, R>(a.lin, a.rule, xbar, w.m[0], [&](const R(&x)[N], R(&z)[P]) { md.h(x, z); }, H,
-                                  w.v[1], Om, hc, w.m[3], w.m[4], w.m[5], w.v[3], &w.ok);
+                                  w.v[1], Om, hc, w.m[3], w.m[4], w.m[5], w.v[3], &w.ok, factored);
     R* out = static_cast<R*>(a.hlin) + size_t(s) * Lay::kHlin;
     const R* Rm = static_cast<const R*>(a.Rm);
     const R* y = static_cast<const R*>(a.y) + size_t(s) * P;
