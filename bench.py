@@ -41,10 +41,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: int, K: int) -> float:
-    """Minimum bytes each kernel family must move per slot: every input it needs
-    read once, every output it produces written once (FP words of `word` bytes).
-    K = slots per lane, so lane-level scan state is amortised over K slots."""
+def scan_bytes_per_slot(n: int, word: int) -> dict:
+    """Algorithmic bytes of the method per slot and iteration: each scan reads
+    its materialised elements once and writes its outputs once.  Forward scan
+    (eq. 15): filtering element (A, b, C, eta, J) in, filtered mean and packed
+    covariance out; reverse scan (eq. 19): smoothing element (E, g, L) in,
+    smoothed mean and packed covariance out."""
+    s = n * (n + 1) // 2
+    fwd = (n * n + 2 * n + 2 * s) + (n + s)
+    rev = (n * n + n + s) + (n + s)
+    return {"forward": fwd * word, "reverse": rev * word, "iteration": (fwd + rev) * word}
+
+
+# Which scan each n = 5 kernel belongs to (its algorithmic bytes are that
+# scan's per slot, or per tile aggregate for the top scans).  The separate
+# sigma-point linearisation pass produces the elements' inputs and is not
+# charged any of the scans' bytes.
+KERNEL_SCAN = {"forward_up": "forward", "tiles_up_filter": "forward",
+               "tiles_top_filter": "forward", "tiles_down_filter": "forward",
+               "forward_down_backward_up": "reverse", "backward_down": "reverse",
+               "tiles_up_smoother": "reverse", "tiles_top_smoother": "reverse", "tiles_down_smoother": "reverse",
+               "sequential": "iteration"}
+
+
+def design_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: int, K: int) -> float:
+    """Bytes each kernel of this design moves per slot when every input it
+    reads is read once and every output it writes is written once, including
+    the intermediates of the design (stored transitions, lane prefixes, stored
+    elements for K > 1).  K = slots per lane, so lane-level scan state is
+    amortised over K slots.  Reported beside the algorithmic bytes."""
     s = n * (n + 1) // 2
     sp = p * (p + 1) // 2
     fe = n * n + 2 * n + 2 * s          # filtering element (A, b, C, eta, J)
@@ -130,15 +155,45 @@ def measured_traffic(key: str):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(pb, lin: str, budget_s: float) -> dict:
-    """The oracle, untuned, on one host core, on a bounded sample of the same
-    workload: one iteration from the prior broadcast per track, track after
-    track (a single track repeats; a track longer than the budget allows is
-    cut to a prefix), until about budget_s seconds have been spent."""
+def host_cpu() -> dict:
+    """CPU model string and logical CPU count of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+_NATIVE_ORACLE = None
+
+
+def native_oracle():
+    """The oracle compiled with -O3 -march=native for this host (built once per run)."""
+    global _NATIVE_ORACLE
+    import tempfile
+
     import oracle
-    t0 = time.perf_counter()
-    steps = iters = 0
-    i = 0
+    if _NATIVE_ORACLE is None:
+        _NATIVE_ORACLE = oracle.build_native(tempfile.mkdtemp(prefix="oracle_native_"))
+        oracle.use_library(_NATIVE_ORACLE)
+    return oracle
+
+
+def cpu_baseline(pb, lin: str, budget_s: float, threads: int = 1) -> dict:
+    """The oracle, untuned (gcc -O3 -march=native), on a bounded sample of the
+    same workload: one iteration from the prior broadcast per track, track
+    after track (a single track repeats; a track longer than the budget allows
+    is cut to a prefix), until about budget_s seconds have been spent.  With
+    threads > 1 independent tracks run on that many host threads at once (the
+    oracle call releases the interpreter lock)."""
+    import threading
+
+    oracle = native_oracle()
     first = pb.track(0)
     T0 = int(first.offsets[1])
     # one-iteration cost probe on a short prefix decides whether the full track fits
@@ -147,24 +202,39 @@ def cpu_baseline(pb, lin: str, budget_s: float) -> dict:
     oracle.smoother(first.prefix(probe_T) if probe_T < T0 else first, 1, lin, filtered=False)
     per_step = (time.perf_counter() - tp) / probe_T
     cut = T0 if per_step * T0 <= budget_s else max(probe_T, int(budget_s / 3 / per_step))
+    lock = threading.Lock()
+    state = {"next": 0, "steps": 0, "iters": 0}
     t0 = time.perf_counter()
-    while True:
-        tr = pb.track(i % pb.n_tracks)
-        T = int(tr.offsets[1])
-        if T > cut:
-            tr, T = tr.prefix(cut), cut
-        oracle.smoother(tr, 1, lin, filtered=False)
-        steps += T
-        iters += 1
-        i += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
+
+    def worker():
+        while True:
+            with lock:
+                if time.perf_counter() - t0 >= budget_s:
+                    return
+                i = state["next"]
+                state["next"] += 1
+            tr = pb.track(i % pb.n_tracks)
+            T = int(tr.offsets[1])
+            if T > cut:
+                tr, T = tr.prefix(cut), cut
+            oracle.smoother(tr, 1, lin, filtered=False)
+            with lock:
+                state["steps"] += T
+                state["iters"] += 1
+
+    pool = [threading.Thread(target=worker) for _ in range(threads)]
+    for t in pool:
+        t.start()
+    for t in pool:
+        t.join()
     dt = time.perf_counter() - t0
-    what = (f"{iters} single-iteration runs over tracks 0..{min(i, pb.n_tracks) - 1}" if pb.n_tracks > 1
-            else f"{iters} iterations")
-    return {"value": steps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what}, {steps} steps{' (prefixes of T=' + str(cut) + ')' if cut < T0 else ''}, "
-                      f"from the prior broadcast ({dt:.1f} s, 1 thread)"}
+    iters, steps = state["iters"], state["steps"]
+    what = (f"{iters} single-iteration runs over tracks 0..{min(state['next'], pb.n_tracks) - 1}"
+            if pb.n_tracks > 1 else f"{iters} iterations")
+    return dict({"value": steps / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+                 "sample": f"{what}, {steps} steps{' (prefixes of T=' + str(cut) + ')' if cut < T0 else ''}, "
+                           f"from the prior broadcast ({dt:.1f} s, {threads} thread{'s' if threads > 1 else ''}, "
+                           f"gcc -O3 -march=native)"}, **host_cpu())
 
 
 def binding_autotune(pb, stream, lin):
@@ -261,7 +331,7 @@ def c2_sweep(args) -> None:
     import torch
     from paper_2102_00514_amd import binding
     from paper_2102_00514_amd import workloads as wl
-    import oracle
+    oracle = native_oracle()
     stream = torch.cuda.current_stream()
     rows = []
     cases = [("taylor", "f64", "parallel"), ("cubature", "f64", "parallel"), ("taylor", "f32", "parallel"),
@@ -307,6 +377,162 @@ def c2_sweep(args) -> None:
         "sweep": rows}), flush=True)
 
 
+WORKLOADS = {
+    "c2": "coordinated-turn + 2 bearings, T={T}, single track",
+    "c3": "4096 coordinated-turn tracks, T_i ~ U{{100..8192}}, 2 bearings, one ragged batch",
+    "c5": "4 stacked coordinated-turn targets (nx=20), 8 bearings, T={T}, single track",
+    "c5batch": "256 tracks of 4 stacked coordinated-turn targets (nx=20), 8 bearings, T_i ~ U{{1024..65536}}, "
+               "one ragged batch",
+}
+DEFAULT_LIN = {"c2": "taylor", "c3": "cubature", "c5": "unscented", "c5batch": "unscented"}
+
+
+def make_workload(name: str, T: int = 0):
+    from paper_2102_00514_amd import workloads as wl
+    if name == "c2":
+        pb = wl.config_c2(T or 2 ** 15)
+    elif name == "c3":
+        pb = wl.config_c3()
+    elif name == "c5":
+        pb = wl.config_c5_single(T or 2 ** 16)
+    else:
+        pb = wl.config_c5_batch()
+    return pb, WORKLOADS[name].format(T=int(pb.offsets[1]))
+
+
+def measure(name: str, pb, desc: str, lin: str, precision: str, steps: int, warmup: int, profile_iters: int,
+            tile_lanes: int = 0, lane_slots: int = 0, autotune: bool = True, check: bool = True) -> dict:
+    """Times `steps` iterations of the captured iteration graph on resident
+    inputs (HIP events on the handle's stream), then a separate pass of
+    `profile_iters` iterations with HIP events around every kernel launch for
+    the roofline of the dominant kernel.  With check, the trajectory after the
+    timed iterations is checked to be finite with symmetric covariances."""
+    import numpy as np
+    import torch
+    from paper_2102_00514_amd import binding
+    T = int(pb.offsets[-1])            # smoothed steps per iteration (all tracks)
+    dense = pb.nx == 20 and lin != "taylor"
+    stream = torch.cuda.current_stream()
+    tuned = None
+    if autotune and not tile_lanes and not lane_slots:
+        lanes_t, slots_t, ms_t = binding.smoother_autotune(pb, stream=stream.cuda_stream,
+                                                           iters=10 if pb.n_slots < 2 ** 20 else 2, lin=lin,
+                                                           precision=precision)
+        tuned = {"tile_lanes": lanes_t, "lane_slots": slots_t, "ms_per_iter": round(ms_t, 6)}
+        log(f"{name}: autotuned schedule: {lanes_t} lanes x {slots_t} slots ({ms_t * 1e3:.1f} us/iteration)")
+        tile_lanes, lane_slots = lanes_t, slots_t
+    sm = binding.Smoother(pb, stream=stream.cuda_stream, n_iter=warmup + steps + profile_iters, lin=lin,
+                          precision=precision, tile_lanes=tile_lanes, lane_slots=lane_slots)
+    S, _, dev_bytes = sm.info()
+    lanes, slots, tiles = sm.schedule()
+    log(f"workload {name}: steps={T} slots={S} lin={lin} precision={precision} device_bytes={dev_bytes} "
+        f"schedule: {tiles} tiles x {lanes} lanes x {slots} slots")
+
+    sm.iterate(warmup, want_delta=False)
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_stop = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    sm.iterate(steps, want_delta=False)
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_start.elapsed_time(t_stop)
+    ms_per_step = ms_total / steps
+    value = T / (ms_per_step * 1e-3)
+    log(f"{name}: timed {steps} iterations: {ms_total:.3f} ms (events), {wall * 1e3:.3f} ms (host wall); "
+        f"{ms_per_step * 1e3:.1f} us/iteration")
+
+    checked = None
+    if check:
+        # the iterate after the timed iterations: finite, symmetric covariances
+        dt = torch.float64 if precision == "f64" else torch.float32
+        mean = torch.empty((S, pb.nx), dtype=dt, device="cuda")
+        cov = torch.empty((S, pb.nx, pb.nx), dtype=dt, device="cuda")
+        sm.result_device(mean.data_ptr(), cov.data_ptr())
+        torch.cuda.synchronize()
+        ok_f = bool(torch.isfinite(mean).all())
+        ok_s = True
+        for a in range(0, S, 1 << 20):          # bounded temporaries next to a large plan
+            c = cov[a:a + (1 << 20)]
+            ok_f = ok_f and bool(torch.isfinite(c).all())
+            ok_s = ok_s and bool((c == c.transpose(1, 2)).all())
+        del cov
+        del mean
+        deltas = sm.track_deltas()
+        checked = {"finite": ok_f, "symmetric": ok_s, "deltas_finite": bool(np.isfinite(deltas).all()),
+                   "iterations_done": warmup + steps}
+        log(f"{name}: trajectory after the timed iterations: {checked}")
+        assert ok_f and ok_s, f"{name}: non-finite or asymmetric trajectory after the timed iterations"
+
+    # per-kernel durations from HIP events around each launch (separate pass)
+    prof = sm.profile(profile_iters)
+    torch.cuda.synchronize()
+    word = 8 if precision == "f64" else 4
+    scan_b = scan_bytes_per_slot(pb.nx, word)
+    rows = []
+    for kname, (launches, tot_ms, positions) in prof.items():
+        per_iter_us = tot_ms * 1e3 / profile_iters
+        if dense:      # per position: floating-point operations
+            upp = dense_flops_per_position(kname, pb.nx, pb.ny)
+            rate = upp * positions / (tot_ms * 1e-3) / 1e12 if tot_ms > 0 else 0.0
+            dpp = upp
+        else:          # per position: the method's bytes; the design's beside them
+            upp = scan_b[KERNEL_SCAN[kname]] if kname in KERNEL_SCAN else 0.0
+            dpp = design_bytes_per_position(kname, pb.nx, pb.ny, lin, word, slots)
+            rate = upp * positions / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+        rows.append((per_iter_us, kname, launches, tot_ms, positions, upp, rate, dpp))
+    rows.sort(reverse=True)
+    unit_pp, unit_rate = ("flop/pos", "TFLOP/s") if dense else ("B/pos", "GB/s")
+    log(f"{'kernel':28s} {'us/iter':>9s} {'launches':>8s} {'avg us':>9s} {unit_pp:>9s} {unit_rate:>8s} "
+        f"{'design B/pos' if not dense else '':>12s}")
+    for per_iter_us, kname, launches, tot_ms, positions, upp, rate, dpp in rows:
+        log(f"{kname:28s} {per_iter_us:9.2f} {launches:8d} {tot_ms * 1e3 / launches:9.2f} {upp:9.0f} {rate:8.2f} "
+            f"{'' if dense else f'{dpp:12.0f}'}")
+    sum_us = sum(r[0] for r in rows)
+    log(f"{name}: sum of kernel time per iteration: {sum_us:.1f} us (vs {ms_per_step * 1e3:.1f} us end to end)")
+    dom = rows[0]
+    avg_launch_s = dom[3] * 1e-3 / dom[2]
+    units_per_launch = dom[5] * dom[4] / dom[2]
+    iteration = None
+    if dense:
+        achieved = units_per_launch / avg_launch_s / 1e12
+        roofline = {"bound": "alu", "kernel": dom[1], "achieved": round(achieved, 4),
+                    "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 6), "traffic": None,
+                    "avg_launch_us": round(avg_launch_s * 1e6, 3), "flops_per_launch": int(units_per_launch)}
+    else:
+        achieved = units_per_launch / avg_launch_s / 1e9
+        traffic = measured_traffic(f"{dom[1]}|T={T}|{lin}|{precision}")
+        design = dom[7] * dom[4] / dom[2]
+        roofline = {"bound": "hbm", "kernel": dom[1], "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                    "traffic": None if traffic is None else int(traffic),
+                    "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": int(units_per_launch),
+                    "bytes_per_slot": dom[5], "slots_per_launch": int(dom[4] / dom[2]),
+                    "design_bytes_per_launch": int(design),
+                    "traffic_over_algorithmic": None if traffic is None else round(traffic / units_per_launch, 4)}
+        it_bytes = scan_b["iteration"] * S
+        iteration = {"bytes_per_slot": scan_b["iteration"], "bytes": int(it_bytes),
+                     "achieved_GBs": round(it_bytes / (ms_per_step * 1e-3) / 1e9, 3),
+                     "frac": round(it_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}
+    res = {"value": round(value, 1), "ms_per_step": round(ms_per_step, 6), "steps": steps, "warmup": warmup,
+           "dtype": precision, "S": S, "T": T, "tracks": pb.n_tracks, "nx": pb.nx, "ny": pb.ny, "lin": lin,
+           "desc": desc, "schedule": {"tiles": tiles, "lanes_per_tile": lanes, "slots_per_lane": slots,
+                                      "autotuned": tuned},
+           "roofline": roofline, "iteration_roofline": iteration, "checked": checked,
+           "kernels_us_per_iter": {r[1]: round(r[0], 3) for r in rows}, "_sm": sm}
+    return res
+
+
+def extra_line(name: str, r: dict, cpu) -> dict:
+    return {"workload": r["desc"], "lin": r["lin"], "dtype": r["dtype"], "value": r["value"], "unit": "steps/s",
+            "ms_per_step": r["ms_per_step"], "steps": r["steps"], "warmup": r["warmup"], "slots": r["S"],
+            "schedule": r["schedule"], "roofline": r["roofline"], "iteration_roofline": r["iteration_roofline"],
+            "checked": r["checked"], "kernels_us_per_iter": r["kernels_us_per_iter"], "cpu_baseline": cpu}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,6 +560,8 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-damping", action="store_true", help="skip the Levenberg-Marquardt comparison")
     ap.add_argument("--damping-tracks", type=int, default=512, help="held-out tracks in the damping comparison")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="c2 only: skip the 4096-track batch and the nx=20 track timed beside the headline")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -342,8 +570,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2102_00514_amd import binding
-    from paper_2102_00514_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -360,95 +586,16 @@ def main():
         c2_sweep(args)
         return
     if args.lin is None:
-        args.lin = {"c2": "taylor", "c3": "cubature", "c5": "unscented", "c5batch": "unscented"}[args.workload]
-    if args.workload == "c2":
-        pb = wl.config_c2(args.T or 2 ** 15)
-        desc = f"coordinated-turn + 2 bearings, T={int(pb.offsets[1])}, single track"
-    elif args.workload == "c3":
-        pb = wl.config_c3()
-        desc = "4096 coordinated-turn tracks, T_i ~ U{100..8192}, 2 bearings, one ragged batch"
-    elif args.workload == "c5":
-        pb = wl.config_c5_single(args.T or 2 ** 16)
-        desc = f"4 stacked coordinated-turn targets (nx=20), 8 bearings, T={int(pb.offsets[1])}, single track"
-    else:
-        pb = wl.config_c5_batch()
-        desc = ("256 tracks of 4 stacked coordinated-turn targets (nx=20), 8 bearings, T_i ~ U{1024..65536}, "
-                "one ragged batch")
-    T = int(pb.offsets[-1])            # smoothed steps per iteration (all tracks)
-    dense = pb.nx == 20 and args.lin != "taylor"
+        args.lin = DEFAULT_LIN[args.workload]
+    pb, desc = make_workload(args.workload, args.T)
     if args.workload != "c2":
         args.no_warm_start = True
         args.no_damping = True
-    stream = torch.cuda.current_stream()
-    total_iters = args.warmup + args.steps + args.profile_iters
-    tuned = None
-    if not args.tile_lanes and not args.lane_slots and not args.no_autotune:
-        lanes_t, slots_t, ms_t = binding.smoother_autotune(pb, stream=stream.cuda_stream,
-                                                           iters=10 if pb.n_slots < 2 ** 20 else 2, lin=args.lin,
-                                                           precision=args.precision)
-        tuned = {"tile_lanes": lanes_t, "lane_slots": slots_t, "ms_per_iter": round(ms_t, 6)}
-        log(f"autotuned schedule: {lanes_t} lanes x {slots_t} slots ({ms_t * 1e3:.1f} us/iteration)")
-        args.tile_lanes, args.lane_slots = lanes_t, slots_t
-    sm = binding.Smoother(pb, stream=stream.cuda_stream, n_iter=total_iters, lin=args.lin,
-                          precision=args.precision, tile_lanes=args.tile_lanes, lane_slots=args.lane_slots)
-    S, _, dev_bytes = sm.info()
-    lanes, slots, tiles = sm.schedule()
-    log(f"workload {args.workload}: steps={T} slots={S} lin={args.lin} precision={args.precision} device_bytes={dev_bytes} "
-        f"schedule: {tiles} tiles x {lanes} lanes x {slots} slots")
-
-    sm.iterate(args.warmup, want_delta=False)
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_stop = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    t_start.record(stream)
-    sm.iterate(args.steps, want_delta=False)
-    t_stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_total = t_start.elapsed_time(t_stop)
-    ms_per_step = ms_total / args.steps
-    value = T / (ms_per_step * 1e-3)
-    log(f"timed {args.steps} iterations: {ms_total:.3f} ms (events), {wall * 1e3:.3f} ms (host wall); "
-        f"{ms_per_step * 1e3:.1f} us/iteration")
-
-    # per-kernel durations from HIP events around each launch (separate pass)
-    prof = sm.profile(args.profile_iters)
-    torch.cuda.synchronize()
-    word = 8 if args.precision == "f64" else 4
-    rows = []
-    for name, (launches, tot_ms, positions) in prof.items():
-        per_iter_us = tot_ms * 1e3 / args.profile_iters
-        if dense:      # per position: floating-point operations
-            upp = dense_flops_per_position(name, pb.nx, pb.ny)
-            rate = upp * positions / (tot_ms * 1e-3) / 1e12 if tot_ms > 0 else 0.0
-        else:          # per position: bytes
-            upp = algorithmic_bytes_per_position(name, pb.nx, pb.ny, args.lin, word, slots)
-            rate = upp * positions / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
-        rows.append((per_iter_us, name, launches, tot_ms, positions, upp, rate))
-    rows.sort(reverse=True)
-    unit_pp, unit_rate = ("flop/pos", "TFLOP/s") if dense else ("B/pos", "GB/s")
-    log(f"{'kernel':28s} {'us/iter':>9s} {'launches':>8s} {'avg us':>9s} {unit_pp:>9s} {unit_rate:>8s}")
-    for per_iter_us, name, launches, tot_ms, positions, upp, rate in rows:
-        log(f"{name:28s} {per_iter_us:9.2f} {launches:8d} {tot_ms * 1e3 / launches:9.2f} {upp:9.0f} {rate:8.2f}")
-    sum_us = sum(r[0] for r in rows)
-    log(f"sum of kernel time per iteration: {sum_us:.1f} us (vs {ms_per_step * 1e3:.1f} us end to end)")
-    dom = rows[0]
-    avg_launch_s = dom[3] * 1e-3 / dom[2]
-    units_per_launch = dom[5] * dom[4] / dom[2]
-    if dense:
-        achieved = units_per_launch / avg_launch_s / 1e12
-        roofline = {"bound": "alu", "kernel": dom[1], "achieved": round(achieved, 4),
-                    "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 6), "traffic": None,
-                    "avg_launch_us": round(avg_launch_s * 1e6, 3), "flops_per_launch": int(units_per_launch)}
-    else:
-        achieved = units_per_launch / avg_launch_s / 1e9
-        traffic = measured_traffic(f"{dom[1]}|T={T}|{args.lin}|{args.precision}")
-        roofline = {"bound": "hbm", "kernel": dom[1], "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                    "traffic": None if traffic is None else int(traffic),
-                    "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": int(units_per_launch)}
+        args.no_extra = True
+    r = measure(args.workload, pb, desc, args.lin, args.precision, args.steps, args.warmup, args.profile_iters,
+                args.tile_lanes, args.lane_slots, autotune=not args.no_autotune)
+    sm = r.pop("_sm")
+    dense = pb.nx == 20 and args.lin != "taylor"
     filter_pass = None
     if not dense:
         # filtering pass with the log marginal likelihood at the current
@@ -464,6 +611,31 @@ def main():
                        "timing": "host wall per call, log-likelihood copied to the host"}
         log(f"filtering pass with log-likelihood: {ms_f * 1e3:.1f} us per call")
     sm.close()
+    del pb
+
+    cpu = None
+    if not args.no_cpu:
+        pb, _ = make_workload(args.workload, args.T)
+        threads = 1 if pb.n_tracks == 1 else (os.cpu_count() or 1)
+        cpu = cpu_baseline(pb, args.lin, args.cpu_seconds, threads=threads)
+        log(f"cpu oracle: {cpu['value']:.4g} steps/s ({cpu['sample']})")
+        del pb
+
+    extra = {}
+    if not args.no_extra:
+        # the other two headline shapes, timed in the same run (fewer iterations)
+        for name, steps, warmup in (("c3", 5, 2), ("c5", 5, 2)):
+            pbx, descx = make_workload(name)
+            rx = measure(name, pbx, descx, DEFAULT_LIN[name], "f64", steps, warmup, 2)
+            rx.pop("_sm").close()
+            cpux = None
+            if not args.no_cpu:
+                threads = 1 if pbx.n_tracks == 1 else (os.cpu_count() or 1)
+                cpux = cpu_baseline(pbx, DEFAULT_LIN[name], min(args.cpu_seconds, 8.0), threads=threads)
+                log(f"{name} cpu oracle: {cpux['value']:.4g} steps/s ({cpux['sample']})")
+            extra[name] = extra_line(name, rx, cpux)
+            del pbx
+            torch.cuda.empty_cache()
 
     warm = None
     if not args.no_warm_start and os.path.exists(args.warm_start_weights):
@@ -482,25 +654,22 @@ def main():
             f"{damping['plain']['ms']:.1f} ms), Levenberg-Marquardt {damping['lm']['converged']:.3f} "
             f"({damping['lm']['passes_mean_converged']:.2f} passes, {damping['lm']['ms']:.1f} ms)")
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(pb, args.lin, args.cpu_seconds)
-        log(f"cpu oracle: {cpu['value']:.4g} steps/s ({cpu['sample']})")
-
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 6),
+        "metric": METRIC, "value": r["value"], "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": f"{desc} ({S} slots), "
+        "config": {"workload": f"{desc} ({r['S']} slots), "
                                f"{'IEKS (Taylor)' if args.lin == 'taylor' else args.lin + ' SLR'}, "
                                f"one iteration per step",
-                   "T": T, "tracks": pb.n_tracks, "nx": pb.nx, "ny": pb.ny, "lin": args.lin,
-                   "parallelism": "time-axis scan, 1 GPU",
-                   "schedule": {"tiles": tiles, "lanes_per_tile": lanes, "slots_per_lane": slots,
-                                "autotuned": tuned}},
-        "roofline": roofline,
+                   "T": r["T"], "tracks": r["tracks"], "nx": r["nx"], "ny": r["ny"], "lin": args.lin,
+                   "parallelism": "time-axis scan, 1 GPU", "schedule": r["schedule"]},
+        "roofline": r["roofline"],
+        "iteration_roofline": r["iteration_roofline"],
         "cpu_baseline": cpu,
+        "checked": r["checked"],
+        "kernels_us_per_iter": r["kernels_us_per_iter"],
+        "extra": extra or None,
         "warm_start": warm,
         "damping": damping,
         "filter_pass": filter_pass,

@@ -48,6 +48,28 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+def build_native(out_dir: str) -> str:
+    """Compile oracle.c (double and long double) with -O3 -march=native for the
+    host it runs on, into out_dir; for timing the oracle on that host.  The
+    portable -O2 build above stays the one the tests load."""
+    path = os.path.join(out_dir, "liboracle_native.so")
+    objs = []
+    for tag, defs in (("f64", []), ("f80", ["-DORC_LONG"])):
+        obj = os.path.join(out_dir, f"oracle_native.{tag}.o")
+        subprocess.run(["gcc", "-O3", "-march=native", "-std=c11", "-fPIC", "-c"] + defs + ["-o", obj, _SRC],
+                       check=True)
+        objs.append(obj)
+    subprocess.run(["gcc", "-shared", "-o", path] + objs + ["-lm"], check=True)
+    return path
+
+
+def use_library(path: str) -> None:
+    """Route every later call through the oracle library at path (same source,
+    other compiler flags)."""
+    global _lib
+    _lib = ctypes.CDLL(path)
+
+
 _lib = None
 
 

@@ -67,14 +67,18 @@ class EngineBase {
   // read through a pinned host buffer.
   virtual sm_status track_deltas(double* out) {
     hipError_t e = hipSuccess;
-    if (!h_delta) e = hipHostMalloc(reinterpret_cast<void**>(&h_delta), sizeof(unsigned long long) * (ntracks + 1),
-                                    hipHostMallocDefault);
+    // an engine on an arena allocates nothing, pinned host memory included
+    std::vector<unsigned long long> pageable(arena ? ntracks + 1 : 0);
+    if (!h_delta && !arena)
+      e = hipHostMalloc(reinterpret_cast<void**>(&h_delta), sizeof(unsigned long long) * (ntracks + 1),
+                        hipHostMallocDefault);
+    unsigned long long* host = arena ? pageable.data() : h_delta;
     if (e == hipSuccess)
-      e = hipMemcpyAsync(h_delta, delta_bits, sizeof(unsigned long long) * (ntracks + 1), hipMemcpyDeviceToHost,
+      e = hipMemcpyAsync(host, delta_bits, sizeof(unsigned long long) * (ntracks + 1), hipMemcpyDeviceToHost,
                          stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "copy of the convergence statistic"));
-    for (int i = 0; i <= ntracks; ++i) std::memcpy(&out[i], &h_delta[i], sizeof(double));
+    for (int i = 0; i <= ntracks; ++i) std::memcpy(&out[i], &host[i], sizeof(double));
     return SM_OK;
   }
 
@@ -99,9 +103,11 @@ class EngineBase {
       for (int i = 0; i < ntracks; ++i) {
         if (failed[i]) continue;
         if (!std::isfinite(d[i])) {
+          // a track that had converged and then fails is reported as failed
           failed[i] = 1;
           ++n_failed;
           if (first[i] == 0) --left;
+          first[i] = 0;
         } else if (first[i] == 0 && d[i] < tol) {
           first[i] = *run;
           --left;
@@ -256,10 +262,27 @@ class EngineBase {
     return st;
   }
 
+  // Device memory of the plan: one hipMalloc per buffer, or, once use_arena
+  // has been called, 256-byte-aligned pieces of that caller-owned region
+  // (never freed by the engine).
+  void use_arena(void* base, size_t bytes) {
+    arena = static_cast<char*>(base);
+    arena_bytes = bytes;
+    arena_used = 0;
+  }
+
   hipError_t dalloc(void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) return hipSuccess;
     if (cap > 0 && int64_t(device_bytes + bytes) > cap) return hipErrorOutOfMemory;
+    if (arena) {
+      const size_t off = (arena_used + 255) & ~size_t(255);
+      if (off > arena_bytes || bytes > arena_bytes - off) return hipErrorOutOfMemory;
+      *p = arena + off;
+      arena_used = off + bytes;
+      device_bytes += bytes;
+      return hipSuccess;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e == hipSuccess) {
       allocs.push_back(*p);
@@ -292,6 +315,8 @@ class EngineBase {
   unsigned long long* delta_bits = nullptr;
   unsigned long long* h_delta = nullptr;   // pinned host copy of delta_bits
   std::vector<void*> allocs;
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
   bool profiling = false;
   std::vector<ProfRec> prof;
 };

@@ -271,8 +271,11 @@ def generate(first: int, count: int, held_out: bool = False, chunk: int = 1024, 
         for j in jobs:
             yield _gen_chunk(j)
         return
+    # The caller has usually initialised the GPU by now; HIP is not fork-safe,
+    # so the workers are spawned (fresh interpreters that only simulate).
+    import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
-    with ProcessPoolExecutor(max_workers=workers) as ex:
+    with ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("spawn")) as ex:
         yield from ex.map(_gen_chunk, jobs)
 
 

@@ -77,7 +77,7 @@ def test_ct_batch(B, lanes, slots, scan, lin, bad):
 def test_fp32(B):
     pb = ct_batch()
     out = run_with_failed_track(B, pb, 1, "taylor", precision="f32")
-    check_others(pb, 1, "taylor", *out, tol=1e-3)
+    check_others(pb, 1, "taylor", *out, tol=1e-4)
 
 
 @pytest.mark.parametrize("slots", [1, 8])

@@ -127,9 +127,10 @@ def test_fp32(B):
         mean, cov, ll = sm.filter()
     ref = oracle.filter_loglik(pb)
     em = oracle.mean_error(mean, ref["filt_mean"])
+    ep = oracle.cov_error(cov, ref["filt_cov"])
     el = abs(ll[0] - ref["loglik"]) / abs(ref["loglik"])
-    print(f"FP32 filter: e_m={em:.3e} e_ll={el:.3e}", flush=True)
-    assert em < 1e-4 and el < 1e-4
+    print(f"FP32 filter: e_m={em:.3e} e_P={ep:.3e} e_ll={el:.3e}", flush=True)
+    assert em < 1e-4 and ep < 1e-4 and el < 1e-4
 
 
 def test_dense_engine_rejects(B):

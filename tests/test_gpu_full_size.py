@@ -12,17 +12,18 @@ Each case runs the whole batch on the device twice:
      the oracle's iterate 2 (a common input; the other tracks keep the
      device's iterate 1), compared with the oracle's iterate 3.
 The oracle computes the sampled tracks one by one and every slot of them is
-compared (metric as in test_gpu_parity).  Step 2 is held to the FP64 gate
-1e-9.  Step 1 is held to 1e-8: these priors set the turn rate to zero, so on
-some tracks the first iteration moves the trajectory by hundreds of units
-(C3 track 0, T = 6667: max change 633).  There the parallel scan's FP64 result
-differs from the sequential oracle by 2.2e-9 (the oracle in FP64 and in 80-bit
-agree to 4e-12), while the same track from the oracle's iterate 2 agrees to
-4.3e-11, and every other sampled track agrees to 3e-11 at step 1.  The gap is
-the method's in FP64: test_scan_conditioning shows eq. 15 in a tree order
-missing the 80-bit result by 1.9e-8 on the same step.  On the device every output of every track
-is checked to be finite, every covariance symmetric with a positive diagonal,
-and every per-track change statistic finite.
+compared (metric as in test_gpu_parity).  Both steps are held to the FP64
+gate 1e-9 on every sampled track, with one named exception: step 1 of C3
+track 0 (T = 6667) is held to 1e-8.  These priors set the turn rate to zero,
+and on that track the first iteration moves the trajectory by 633 units;
+there the parallel scan's FP64 result differs from the sequential oracle by
+2.2e-9 (the oracle in FP64 and in 80-bit agree to 4e-12), while the same
+track from the oracle's iterate 2 agrees to 4.3e-11, and every other sampled
+track agrees to 3e-11 at step 1.  The gap is the method's in FP64:
+test_scan_conditioning shows eq. 15 in a tree order missing the 80-bit
+result by 1.9e-8 on the same step.  On the device every output of every
+track is checked to be finite, every covariance symmetric with a positive
+diagonal, and every per-track change statistic finite.
 """
 import numpy as np
 import pytest
@@ -33,7 +34,9 @@ from paper_2102_00514_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-9
-TOL_FROM_PRIOR = 1e-8
+# (workload, track) -> step-1 gate for the one ill-conditioned first step
+# described above; every other sampled track and step is held to TOL64
+STEP1_EXCEPTIONS = {("C3", 0): 1e-8}
 
 
 @pytest.fixture(scope="module")
@@ -55,10 +58,11 @@ def check_all_slots(mean, cov, deltas, chunk=1 << 20):
     assert np.all(np.isfinite(deltas))
 
 
-def compare_tracks(pb, mean, cov, deltas, refs, it, tol, what):
+def compare_tracks(pb, mean, cov, deltas, refs, it, what):
     so = pb.slot_offsets()
     worst = 0.0
     for i, ref in refs.items():
+        tol = STEP1_EXCEPTIONS.get((what, i), TOL64) if it == 0 else TOL64
         m = mean[so[i]:so[i + 1]].cpu().numpy()
         c = cov[so[i]:so[i + 1]].cpu().numpy()
         em = oracle.mean_error(m, ref["hist_mean"][it])
@@ -85,7 +89,7 @@ def full_size_case(B, pb, lin, tracks, what, **kw):
         sm.result_device(mean.data_ptr(), cov.data_ptr())
         deltas = sm.track_deltas()
         check_all_slots(mean, cov, deltas)
-        compare_tracks(pb, mean, cov, deltas, refs, 0, TOL_FROM_PRIOR, what)
+        compare_tracks(pb, mean, cov, deltas, refs, 0, what)
         for i, ref in refs.items():
             mean[so[i]:so[i + 1]] = torch.from_numpy(ref["hist_mean"][k - 1]).to("cuda")
             cov[so[i]:so[i + 1]] = torch.from_numpy(ref["hist_cov"][k - 1]).to("cuda")
@@ -96,7 +100,7 @@ def full_size_case(B, pb, lin, tracks, what, **kw):
         deltas = sm.track_deltas()
         torch.cuda.synchronize()
         check_all_slots(mean, cov, deltas)
-        compare_tracks(pb, mean, cov, deltas, refs, k, TOL64, what)
+        compare_tracks(pb, mean, cov, deltas, refs, k, what)
 
 
 def sample(pb, n_random, seed):
@@ -118,4 +122,4 @@ def test_c5_single_T65536(B):
 
 def test_c5_batch_256_tracks(B):
     pb = wl.config_c5_batch()
-    full_size_case(B, pb, "unscented", sample(pb, 1, 50), "C5 batch")
+    full_size_case(B, pb, "unscented", sample(pb, 3, 50), "C5 batch")

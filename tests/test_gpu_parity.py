@@ -17,6 +17,7 @@ from paper_2102_00514_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-9
+TOL32 = 1e-4    # the FP32 variant's bar on means and covariances
 
 
 @pytest.fixture(scope="module")
@@ -177,7 +178,7 @@ def test_fp32_variant(B, lin):
     em = oracle.mean_error(mean, ref["mean"])
     ep = oracle.cov_error(cov, ref["cov"])
     print(f"FP32 C1 {lin}: e_m={em:.3e} e_P={ep:.3e}", flush=True)
-    assert em < 1e-4 and ep < 1e-3
+    assert em < TOL32 and ep < TOL32
 
 
 @pytest.mark.parametrize("lin", ["taylor", "cubature"])
@@ -194,7 +195,7 @@ def test_fp32_long_track(B, lin):
         em = oracle.mean_error(mean, ref["hist_mean"][start])
         ep = oracle.cov_error(cov, ref["hist_cov"][start])
         print(f"FP32 T=32768 {lin} iteration {start + 1}: e_m={em:.3e} e_P={ep:.3e}", flush=True)
-        assert em < 1e-4 and ep < 1e-4
+        assert em < TOL32 and ep < TOL32
 
 
 @pytest.mark.parametrize("lanes,slots", [(64, 1), (64, 2), (64, 3), (256, 1), (256, 2), (256, 4), (256, 8)])
