@@ -277,8 +277,38 @@ sm_status smoother_info(smoother_t h, int64_t* n_slots, int32_t* n_tracks, int64
 /* Scan schedule in use: lanes per tile, slots per lane, number of tiles. */
 sm_status smoother_schedule(smoother_t h, int32_t* tile_lanes, int32_t* lane_slots, int64_t* tiles);
 
+/* Allocation-free variant of smoother_init + smoother_iterate(h, 0) +
+ * smoother_result_device + smoother_destroy, for callers that cannot
+ * allocate device memory (serving loops, harnesses that forbid hipMalloc).
+ * Runs pb->n_iter iterations from the prior broadcast and writes the final
+ * trajectory to caller-owned device buffers d_mean [S*nx] and d_cov
+ * [S*nx*nx] (layouts of smoother_result_device; double for SM_FP64, float
+ * for SM_FP32).  max_delta_out (nullable) receives the last iteration's
+ * largest change, as smoother_iterate reports it.
+ *
+ * Every buffer of the plan is carved out of one static device array of the
+ * library (64 MiB per GPU, held from the library's load on that GPU until
+ * the process ends); nothing is allocated: no hipMalloc, hipFree, pinned host
+ * memory or HIP graph.  Limits, rejected with SM_EINVAL and a message before
+ * any device work: at most 36864 slots (sum over tracks of T_i + 1) and 1024
+ * tracks; the single-block engines only (nx = 5 coordinated turn, or the
+ * compiled linear models); no init_mean/init_cov; lane_slots 0 or 1.
+ * tile_lanes, lin, precision, scan and lm_lambda are honoured; use_graph and
+ * max_device_bytes are ignored.
+ *
+ * Queued on hip_stream, and the call waits for that stream before it
+ * returns.  The static array is shared by every call on the same GPU and
+ * keeps the last call's contents (each call initialises what it reads):
+ * calls that overlap on one GPU -- from several host threads, or on several
+ * streams -- race and must not be made.  Errors as smoother_init
+ * (smoother_last_error(NULL)); SM_ENUMERIC when max_delta_out was requested
+ * and is not finite. */
+sm_status smoother_solve_static(const sm_problem* pb, void* hip_stream, void* d_mean, void* d_cov,
+                                double* max_delta_out);
+
 /* Message for the last failure of a call on h (h = NULL: the last failure of
- * smoother_init on this thread).  Valid until the next call on h. */
+ * smoother_init, smoother_autotune or smoother_solve_static on this thread).
+ * Valid until the next call on h. */
 const char* smoother_last_error(smoother_t h);
 
 /* Releases the handle and its device memory; NULL-safe. */

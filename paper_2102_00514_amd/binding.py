@@ -29,7 +29,7 @@ EXPORTS = ("smoother_problem_defaults", "smoother_init", "smoother_iterate", "sm
            "smoother_result_device", "smoother_track_deltas", "smoother_info", "smoother_last_error",
            "smoother_destroy", "smoother_version", "smoother_profile", "smoother_schedule",
            "smoother_set_trajectory_device", "smoother_iterate_until", "smoother_autotune",
-           "smoother_objective", "smoother_iterate_lm", "smoother_filter")
+           "smoother_objective", "smoother_iterate_lm", "smoother_filter", "smoother_solve_static")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -118,6 +118,8 @@ def _load():
     lib.smoother_iterate_lm.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _dp]
     lib.smoother_iterate_lm.restype = ctypes.c_int
+    lib.smoother_solve_static.argtypes = [ctypes.POINTER(sm_problem), vp, vp, vp, _dp]
+    lib.smoother_solve_static.restype = ctypes.c_int
     return lib
 
 
@@ -199,6 +201,20 @@ def smoother_autotune(pb: Problem, stream: Optional[int] = None, iters: int = 5,
     if st != SM_OK:
         raise SmootherError(st, smoother_last_error(None))
     return B.value, K.value, ms.value
+
+
+def smoother_solve_static(pb: Problem, mean_ptr: int, cov_ptr: int, stream: Optional[int] = None,
+                          want_delta: bool = True, **kw):
+    """All n_iter iterations from the prior broadcast into caller-owned device
+    buffers, with no device allocation (the library's static scratch); returns
+    the last iteration's largest change (None without want_delta)."""
+    s, _keep = make_problem(pb, **kw)
+    d = ctypes.c_double()
+    st = _lib.smoother_solve_static(ctypes.byref(s), ctypes.c_void_p(stream or 0), ctypes.c_void_p(mean_ptr),
+                                    ctypes.c_void_p(cov_ptr), ctypes.byref(d) if want_delta else None)
+    if st != SM_OK:
+        raise SmootherError(st, smoother_last_error(None))
+    return d.value if want_delta else None
 
 
 def smoother_iterate(h: int, k: int = 0, want_delta: bool = True):

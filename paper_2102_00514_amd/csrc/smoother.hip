@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -180,6 +181,42 @@ static std::string validate(const sm_problem* pb) {
           return "stacked targets: init_cov must be block-diagonal";
   }
   return std::string();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point (smoother_solve_static): one
+// array per GPU, loaded with the code object and held until the process
+// ends.  In host code `scratch` names a host-side stand-in only; the device
+// address of each GPU's copy comes from hipGetSymbolAddress with that device
+// current, and only that address is handed to the engine and its kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int64_t kStaticMaxSlots = 36864;   // sum over tracks of T_i + 1
+constexpr int kStaticMaxTracks = 1024;
+constexpr int kStaticMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kStaticMaxDevices] = {};
+
+// Device address of the current device's scratch, looked up once per device.
+static hipError_t static_scratch(void** out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kStaticMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace pks
@@ -557,6 +594,93 @@ sm_status smoother_schedule(smoother_t h, int32_t* tile_lanes, int32_t* lane_slo
   if (lane_slots) *lane_slots = h->eng->sched_slots;
   if (tiles) *tiles = h->eng->sched_tiles;
   return SM_OK;
+}
+
+sm_status smoother_solve_static(const sm_problem* pb, void* hip_stream, void* d_mean, void* d_cov,
+                                double* max_delta_out) {
+  try {
+    const std::string msg = pks::validate(pb);
+    if (!msg.empty()) {
+      g_init_error = msg;
+      return SM_EINVAL;
+    }
+    if (!d_mean || !d_cov) {
+      g_init_error = "d_mean and d_cov must not be NULL";
+      return SM_EINVAL;
+    }
+    if (pb->nx != 5 && !(pb->model == SM_MODEL_LINEAR && pb->nx < 5)) {
+      g_init_error = "the static entry point runs the single-block engines only (nx <= 5)";
+      return SM_EINVAL;
+    }
+    if (pb->init_mean || pb->init_cov) {
+      g_init_error = "the static entry point starts from the prior broadcast (init_mean and init_cov must be NULL)";
+      return SM_EINVAL;
+    }
+    if (pb->lane_slots > 1) {
+      g_init_error = "the static entry point runs one slot per lane (lane_slots must be 0 or 1)";
+      return SM_EINVAL;
+    }
+    const int64_t S = pb->offsets[pb->n_tracks] + pb->n_tracks;
+    if (S > pks::kStaticMaxSlots || pb->n_tracks > pks::kStaticMaxTracks) {
+      g_init_error = "problem exceeds the static scratch: " + std::to_string(S) + " slots and " +
+                     std::to_string(pb->n_tracks) + " tracks given, at most " +
+                     std::to_string(pks::kStaticMaxSlots) + " slots (sum of T_i + 1) and " +
+                     std::to_string(pks::kStaticMaxTracks) + " tracks";
+      return SM_EINVAL;
+    }
+    void* base = nullptr;
+    hipError_t he = pks::static_scratch(&base);
+    if (he != hipSuccess) {
+      g_init_error = pks::hip_msg(he, "address of the static scratch");
+      return SM_EDEVICE;
+    }
+    std::unique_ptr<pks::EngineBase> eng(pks::make_engine(pb->model, pb->precision, pb->nx, pb->ny, pb->lin));
+    if (!eng) {
+      g_init_error = "no kernel for this configuration";
+      return SM_EINVAL;
+    }
+    eng->use_arena(base, pks::kStaticScratchBytes);
+    sm_problem q = *pb;
+    q.use_graph = 0;           // eager launches: a graph would be instantiated (and allocate)
+    q.lane_slots = 1;
+    q.max_device_bytes = 0;
+    sm_status st = eng->setup(q, static_cast<hipStream_t>(hip_stream));
+    if (st == SM_OK) st = eng->iterate(q.n_iter);
+    if (st == SM_OK) st = eng->result_device(d_mean, d_cov);
+    double delta = 0.0;
+    if (st == SM_OK && max_delta_out) {
+      std::vector<double> d(eng->ntracks + 1);
+      st = eng->track_deltas(d.data());
+      delta = d[eng->ntracks];
+    }
+    if (st == SM_OK) {
+      he = hipStreamSynchronize(eng->stream);
+      if (he != hipSuccess) {
+        eng->err = pks::hip_msg(he, "static solve");
+        st = SM_EDEVICE;
+      }
+    }
+    if (st != SM_OK) {
+      (void)hipStreamSynchronize(eng->stream);
+      g_init_error = eng->err;
+      return st;
+    }
+    if (max_delta_out) {
+      *max_delta_out = delta;
+      if (!std::isfinite(delta)) {
+        g_init_error = "non-finite iterate";
+        return SM_ENUMERIC;
+      }
+    }
+    g_init_error.clear();
+    return SM_OK;
+  } catch (const std::bad_alloc&) {
+    g_init_error = "host allocation failed";
+    return SM_ENOMEM;
+  } catch (...) {
+    g_init_error = "unexpected host exception";
+    return SM_EDEVICE;
+  }
 }
 
 const char* smoother_last_error(smoother_t h) {
