@@ -75,17 +75,22 @@ def design_bytes_per_position(kernel: str, n: int, p: int, lin: str, word: int, 
     fe = n * n + 2 * n + 2 * s          # filtering element (A, b, C, eta, J)
     se = n * n + n + s                  # smoothing element (E, g, L)
     car = n + s                         # trajectory slot (mean, packed covariance)
-    tr = n * n + n + s                  # transition (F, c, Q') kept for the smoothing elements
+    tr = n * n + n + s                  # transition rows (F, c, Q') of the stored linearisation
     lin_words = n * n + n + s + p * n + p + sp + p
     xin = n + (s if lin != "taylor" else 0)   # linearisation point (mean [+ covariance])
-    # With K = 1 the down-sweeps start from each lane's inclusive prefix, so the
-    # per-slot elements are neither stored nor reloaded.
+    # Filtering elements are never stored: the forward down-sweep builds them
+    # again (K > 1) from the linearisation point (Taylor) or the stored
+    # linearisation (sigma points); Taylor transitions are evaluated again for
+    # the smoothing elements.  With K = 1 the down-sweeps start from each
+    # lane's inclusive prefix; smoothing elements are stored only for K > 1.
     ke = 1 if K > 1 else 0
+    taylor = lin == "taylor"
     words = {
-        # linearise + filtering element (stored for K > 1) + lane prefix
-        "forward_up": (xin + p + tr if lin == "taylor" else lin_words) + ke * fe + fe / K,
-        # carries + smoothing element (stored for K > 1) + reverse lane prefix
-        "forward_down_backward_up": ke * fe + fe / K + tr + ke * se + se / K,
+        # linearisation inputs + lane prefix
+        "forward_up": (xin + p if taylor else lin_words) + fe / K,
+        # linearisation inputs again + carries + smoothing element (K > 1) + reverse lane prefix
+        "forward_down_backward_up": ((n + ke * p) if taylor else (lin_words if ke else tr)) + fe / K
+                                    + ke * se + se / K,
         # reverse carries, new trajectory in place, convergence statistic (reads old means)
         "backward_down": ke * se + se / K + n + car,
         "tiles_up_filter": fe + fe / 2, "tiles_top_filter": fe + car, "tiles_down_filter": fe + fe / 2 + car,
@@ -126,7 +131,7 @@ def dense_flops_per_position(kernel: str, n: int, p: int) -> float:
 
 # Sources of the n = 5 kernels whose HBM traffic is recorded in profiles/
 # (the kernels, their device functions and their launch configuration).
-TRAFFIC_SOURCES = ("fused.hpp", "elements.hpp", "operators.hpp", "linalg.hpp", "models.hpp", "scan.hpp",
+TRAFFIC_SOURCES = ("fused.hpp", "elements.hpp", "operators.hpp", "sqrt.hpp", "linalg.hpp", "models.hpp", "scan.hpp",
                    "slot_kernels.hpp", "engine.hpp", "engine_ct_f64.hip")
 
 

@@ -92,6 +92,16 @@ typedef enum { SM_FP64 = 0, SM_FP32 = 1 } sm_precision;
  * sequential Kalman/RTS recursions, one lane per track (comparison baseline). */
 typedef enum { SM_SCAN_PARALLEL = 0, SM_SCAN_SEQUENTIAL = 1 } sm_scan;
 
+/* How the parallel scans carry the covariance-like blocks of the elements.
+ * SM_FORM_COVARIANCE: as matrices, the elements (A, b, C, eta, J) and
+ * (E, g, L) of eq. 13-19.  SM_FORM_SQRT: as lower-triangular factors
+ * C = U U^T, J = Z Z^T, L = D D^T, with the operators of eq. 15 and eq. 19
+ * rewritten on the factors (new factors from LQ decompositions, no
+ * covariance is formed and re-factorised, no difference of covariances is
+ * taken); algebraically the same results, in more arithmetic.  Outputs are
+ * covariances in both forms. */
+typedef enum { SM_FORM_COVARIANCE = 0, SM_FORM_SQRT = 1 } sm_form;
+
 typedef struct {
   int32_t nx, ny;                 /* state / measurement dimension */
   int32_t n_tracks;               /* >= 1 */
@@ -123,12 +133,17 @@ typedef struct {
                                      through x_k + r, r ~ N(0, I/lm_lambda), with the previous
                                      iterate xbar_k as the value: this adds (lm_lambda/2)|x_k - xbar_k|^2
                                      to the objective.  Fixed points are those of the undamped
-                                     smoother.  Every engine and scan mode supports it. */
+                                     smoother.  Every engine and scan mode supports it with
+                                     SM_FORM_COVARIANCE; SM_FORM_SQRT needs 0. */
+  int32_t form;                   /* sm_form; SM_FORM_SQRT runs on the parallel scan of the
+                                     single-block engines (nx = 5 coordinated turn, the linear
+                                     models) and on stacked targets with the Taylor linearisation,
+                                     without damping; otherwise SM_EINVAL */
 } sm_problem;
 
 /* Fills *pb with defaults: n_tracks = 1, n_iter = 10, lin = SM_LIN_TAYLOR,
  * ut_alpha = 1, ut_beta = 0, ut_kappa = 1, FP64, parallel scan, no init, no cap,
- * automatic scan schedule, HIP-graph replay, no damping. */
+ * automatic scan schedule, HIP-graph replay, no damping, covariance form. */
 void smoother_problem_defaults(sm_problem* pb);
 
 /* Validates the problem on the host (dimensions supported by the compiled

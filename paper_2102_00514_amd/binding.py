@@ -24,6 +24,7 @@ SM_MODEL_LINEAR, SM_MODEL_CT_BEARINGS = 0, 1
 LIN = {"taylor": 0, "cubature": 1, "unscented": 2}
 PRECISION = {"f64": 0, "f32": 1}
 SCAN = {"parallel": 0, "sequential": 1}
+FORM = {"covariance": 0, "sqrt": 1}
 
 EXPORTS = ("smoother_problem_defaults", "smoother_init", "smoother_iterate", "smoother_result",
            "smoother_result_device", "smoother_track_deltas", "smoother_info", "smoother_last_error",
@@ -49,6 +50,7 @@ class sm_problem(ctypes.Structure):
         ("tile_lanes", ctypes.c_int32), ("lane_slots", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("lm_lambda", ctypes.c_double),
+        ("form", ctypes.c_int32),
     ]
 
 
@@ -146,7 +148,7 @@ def smoother_last_error(h=None) -> str:
 def make_problem(pb: Problem, n_iter: int = 10, lin: str = "taylor", precision: str = "f64",
                  scan: str = "parallel", init_mean=None, init_cov=None, ut_alpha=1.0, ut_beta=0.0,
                  ut_kappa=1.0, max_device_bytes: int = 0, tile_lanes: int = 0, lane_slots: int = 0,
-                 use_graph: bool = True, lm_lambda: float = 0.0):
+                 use_graph: bool = True, lm_lambda: float = 0.0, form: str = "covariance"):
     """sm_problem for a workloads.Problem; returns (struct, keep-alive arrays)."""
     s = sm_problem()
     _lib.smoother_problem_defaults(ctypes.byref(s))
@@ -178,6 +180,7 @@ def make_problem(pb: Problem, n_iter: int = 10, lin: str = "taylor", precision: 
     s.tile_lanes, s.lane_slots = tile_lanes, lane_slots
     s.use_graph = int(bool(use_graph))
     s.lm_lambda = lm_lambda
+    s.form = FORM[form]
     return s, keep
 
 

@@ -105,12 +105,19 @@ class Engine final : public EngineBase {
     iso_ = pb.n_tracks > 1;
     use_graph_ = pb.use_graph != 0 && !seq_;
     lm_ = pb.lm_lambda;
+    form_ = pb.form;
     rule_.alpha = pb.ut_alpha;
     rule_.kappa = pb.ut_kappa;
     slot_off_.resize(ntracks + 1);
     for (int i = 0; i <= ntracks; ++i) slot_off_[i] = pb.offsets[i] + i;
     S = slot_off_[ntracks];
     sched_ = choose_schedule(S, pb.tile_lanes, pb.lane_slots);
+    // the square-root form is compiled for 64-lane tiles with the restart
+    // test (its operators are long; one instantiation keeps the build short)
+    if (form_ == SM_FORM_SQRT) {
+      sched_.B = 64;
+      iso_ = true;
+    }
     const int64_t per_tile = int64_t(sched_.B) * sched_.K;
     tiles_ = (S + per_tile - 1) / per_tile;
     const int64_t S_pad = tiles_ * per_tile;
@@ -181,20 +188,17 @@ class Engine final : public EngineBase {
       A(&d_filt_, sizeof(R) * kTrajW * stride);
     } else {
       const size_t lanes = size_t(tiles_) * sched_.B;
-      if (lin_ == SM_LIN_TAYLOR) {
-        A(&d_trans_, sizeof(R) * TL::kWords * stride);
-      } else {
-        // sigma-point linearisation runs as its own pass; its arrays start with
-        // the transition rows the smoothing elements read
+      // Taylor transitions are evaluated again wherever they are needed; the
+      // sigma-point linearisation runs as its own pass, whose arrays start with
+      // the transition rows
+      if (lin_ != SM_LIN_TAYLOR) {
         A(&d_lin_, sizeof(R) * LL::kWords * stride);
         d_trans_ = d_lin_;
       }
-      if (sched_.K > 1) {
-        // per-slot elements; with one slot per lane the down-sweeps start from
-        // the lanes' inclusive prefixes instead
-        A(&d_felem_, sizeof(R) * FOp::kElemWords * stride);
-        A(&d_selem_, sizeof(R) * SOp::kElemWords * stride);
-      }
+      // filtering elements are built again by the down-sweeps, never stored;
+      // smoothing elements are stored for K > 1 (with one slot per lane the
+      // reverse down-sweep starts from the lanes' inclusive prefixes)
+      if (sched_.K > 1) A(&d_selem_, sizeof(R) * SOp::kElemWords * stride);
       A(&lx_f_, sizeof(R) * FOp::kElemWords * lanes);
       A(&ta_f_, sizeof(R) * FOp::kElemWords * tiles_);
       A(&tc_f_, sizeof(R) * FOp::kCarryWords * tiles_);
@@ -273,26 +277,39 @@ class Engine final : public EngineBase {
   size_t lds_filter() const { return sizeof(R) * FOp::kElemWords * (sched_.B / 64); }
   size_t lds_smoother() const { return sizeof(R) * SOp::kElemWords * (sched_.B / 64); }
 
-  template <int B, bool ISO>
+  template <int B, bool ISO, int FORM>
   hipError_t set_lds_limits_b() {
+    using Fm = Form<FORM, N, R, ISO>;
     hipError_t e = hipSuccess;
     auto set = [&](const void* f, size_t bytes) {
       if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
     };
-    set(reinterpret_cast<const void*>(&k_forward_up<Model, kInlineTaylor, B, R, ISO>), lds_filter());
-    set(reinterpret_cast<const void*>(&k_forward_up<Model, kStoredLin, B, R, ISO>), lds_filter());
-    set(reinterpret_cast<const void*>(&k_forward_down_backward_up<Model, B, R, ISO>), lds_smoother());
-    set(reinterpret_cast<const void*>(&k_scan_single<FilterOp<N, R, ISO>, kTopB, R>),
+    set(reinterpret_cast<const void*>(&k_forward_up<Model, kInlineTaylor, B, R, ISO, FORM>), lds_filter());
+    set(reinterpret_cast<const void*>(&k_forward_up<Model, kStoredLin, B, R, ISO, FORM>), lds_filter());
+    set(reinterpret_cast<const void*>(&k_forward_down_backward_up<Model, kInlineTaylor, B, R, ISO, FORM>),
+        lds_smoother());
+    set(reinterpret_cast<const void*>(&k_forward_down_backward_up<Model, kStoredLin, B, R, ISO, FORM>),
+        lds_smoother());
+    set(reinterpret_cast<const void*>(&k_scan_single<typename Fm::FOp, kTopB, R>),
         sizeof(R) * FOp::kElemWords * (kTopB / 64));
-    set(reinterpret_cast<const void*>(&k_scan_single<SmootherOp<N, R, ISO>, kTopB, R>),
+    set(reinterpret_cast<const void*>(&k_scan_single<typename Fm::SOp, kTopB, R>),
         sizeof(R) * SOp::kElemWords * (kTopB / 64));
     return e;
   }
 
+  template <int FORM>
+  hipError_t set_lds_limits_f() {
+    if constexpr (FORM == kFormSqrt) {
+      return set_lds_limits_b<64, true, FORM>();
+    } else {
+      if (iso_) return sched_.B == 64 ? set_lds_limits_b<64, true, FORM>() : set_lds_limits_b<256, true, FORM>();
+      return sched_.B == 64 ? set_lds_limits_b<64, false, FORM>() : set_lds_limits_b<256, false, FORM>();
+    }
+  }
+
   hipError_t set_lds_limits() {
     if (seq_) return hipSuccess;
-    if (iso_) return sched_.B == 64 ? set_lds_limits_b<64, true>() : set_lds_limits_b<256, true>();
-    return sched_.B == 64 ? set_lds_limits_b<64, false>() : set_lds_limits_b<256, false>();
+    return form_ == SM_FORM_SQRT ? set_lds_limits_f<kFormSqrt>() : set_lds_limits_f<kFormCov>();
   }
 
   // grid of one lane per column of the per-slot arrays (padding included)
@@ -343,7 +360,6 @@ class Engine final : public EngineBase {
     a.yslot = d_y_;
     a.traj = d_traj_[0];
     a.trans = d_trans_;
-    a.felem = d_felem_;
     a.selem = d_selem_;
     a.filt = nullptr;
     a.lx_f = lx_f_;
@@ -435,31 +451,38 @@ class Engine final : public EngineBase {
     });
   }
 
-  template <int B, bool ISO>
+  template <int B, bool ISO, int FORM>
   void launch_iteration(const FusedArgs& a) {
+    using Fm = Form<FORM, N, R, ISO>;
     static const char* const kFilterNames[3] = {"tiles_up_filter", "tiles_top_filter", "tiles_down_filter"};
     static const char* const kSmootherNames[3] = {"tiles_up_smoother", "tiles_top_smoother",
                                                   "tiles_down_smoother"};
     const dim3 grid{unsigned(tiles_)}, block{unsigned(B)};
     if (lin_ == SM_LIN_TAYLOR) {
       timed("forward_up", S, [&] {
-        hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R, ISO>), grid, block, lds_filter(), stream, a);
+        hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R, ISO, FORM>), grid, block, lds_filter(), stream,
+                           a);
       });
     } else {
       const dim3 sgrid = col_grid();
       const SlotArgs sa = slot_args(0);
       timed("linearize", S, [&] { launch_linearize(sa, sgrid); });
       timed("forward_up", S, [&] {
-        hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R, ISO>), grid, block, lds_filter(), stream, a);
+        hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R, ISO, FORM>), grid, block, lds_filter(), stream, a);
       });
     }
-    scan_tiles<FilterOp<N, R, ISO>>(ta_f_, tc_f_, kFilterNames);
+    scan_tiles<typename Fm::FOp>(ta_f_, tc_f_, kFilterNames);
     timed("forward_down_backward_up", S, [&] {
-      hipLaunchKernelGGL((k_forward_down_backward_up<Model, B, R, ISO>), grid, block, lds_smoother(), stream, a);
+      if (lin_ == SM_LIN_TAYLOR)
+        hipLaunchKernelGGL((k_forward_down_backward_up<Model, kInlineTaylor, B, R, ISO, FORM>), grid, block,
+                           lds_smoother(), stream, a);
+      else
+        hipLaunchKernelGGL((k_forward_down_backward_up<Model, kStoredLin, B, R, ISO, FORM>), grid, block,
+                           lds_smoother(), stream, a);
     });
-    scan_tiles<SmootherOp<N, R, ISO>>(ta_s_, tc_s_, kSmootherNames);
+    scan_tiles<typename Fm::SOp>(ta_s_, tc_s_, kSmootherNames);
     timed("backward_down", S, [&] {
-      hipLaunchKernelGGL((k_backward_down<Model, B, R, ISO>), grid, block, 0, stream, a);
+      hipLaunchKernelGGL((k_backward_down<Model, B, R, ISO, FORM>), grid, block, 0, stream, a);
     });
   }
 
@@ -510,15 +533,23 @@ class Engine final : public EngineBase {
     return SM_OK;
   }
 
+  template <int FORM>
+  void launch_parallel_iteration_f(const FusedArgs& a) {
+    if constexpr (FORM == kFormSqrt) {
+      launch_iteration<64, true, FORM>(a);
+    } else if (iso_) {
+      if (sched_.B == 64) launch_iteration<64, true, FORM>(a);
+      else launch_iteration<256, true, FORM>(a);
+    } else {
+      if (sched_.B == 64) launch_iteration<64, false, FORM>(a);
+      else launch_iteration<256, false, FORM>(a);
+    }
+  }
+
   void launch_parallel_iteration() {
     const FusedArgs a = fused_args();
-    if (iso_) {
-      if (sched_.B == 64) launch_iteration<64, true>(a);
-      else launch_iteration<256, true>(a);
-    } else {
-      if (sched_.B == 64) launch_iteration<64, false>(a);
-      else launch_iteration<256, false>(a);
-    }
+    if (form_ == SM_FORM_SQRT) launch_parallel_iteration_f<kFormSqrt>(a);
+    else launch_parallel_iteration_f<kFormCov>(a);
   }
 
   // Records one iteration on a private stream (capture is not allowed on the
@@ -605,6 +636,7 @@ class Engine final : public EngineBase {
     la.stride = stride;
     la.flags = d_flags_;
     la.params = d_params_;
+    la.Q = d_Q_;
     la.R = d_R_;
     la.yslot = d_y_;
     la.traj = d_traj_[cur_];
@@ -629,14 +661,9 @@ class Engine final : public EngineBase {
       a.lm_track = nullptr;
       a.filt = d_filt_;
       a.delta_bits = d_delta_spare_;    // the forward kernel clears its statistic: keep the handle's
-      if (iso_) {
-        if (sched_.B == 64) launch_filter_pass<64, true>(a);
-        else launch_filter_pass<256, true>(a);
-      } else {
-        if (sched_.B == 64) launch_filter_pass<64, false>(a);
-        else launch_filter_pass<256, false>(a);
-      }
-      la.trans = d_trans_;
+      if (form_ == SM_FORM_SQRT) launch_filter_pass_f<kFormSqrt>(a);
+      else launch_filter_pass_f<kFormCov>(a);
+      la.trans = d_trans_;            // null for Taylor: the density kernel evaluates the transition
       la.lin = lin_ == SM_LIN_TAYLOR ? nullptr : d_lin_;
     }
     hipLaunchKernelGGL((k_loglik_slots<Model, R>), col_grid(), dim3(kSlotBlock), 0, stream, la);
@@ -652,18 +679,34 @@ class Engine final : public EngineBase {
     return SM_OK;
   }
 
-  template <int B, bool ISO>
+  template <int FORM>
+  void launch_filter_pass_f(const FusedArgs& a) {
+    if constexpr (FORM == kFormSqrt) {
+      launch_filter_pass<64, true, FORM>(a);
+    } else if (iso_) {
+      if (sched_.B == 64) launch_filter_pass<64, true, FORM>(a);
+      else launch_filter_pass<256, true, FORM>(a);
+    } else {
+      if (sched_.B == 64) launch_filter_pass<64, false, FORM>(a);
+      else launch_filter_pass<256, false, FORM>(a);
+    }
+  }
+
+  template <int B, bool ISO, int FORM>
   void launch_filter_pass(const FusedArgs& a) {
     static const char* const kFilterNames[3] = {"tiles_up_filter", "tiles_top_filter", "tiles_down_filter"};
     const dim3 grid{unsigned(tiles_)}, block{unsigned(B)};
     if (lin_ == SM_LIN_TAYLOR) {
-      hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R, ISO>), grid, block, lds_filter(), stream, a);
+      hipLaunchKernelGGL((k_forward_up<Model, kInlineTaylor, B, R, ISO, FORM>), grid, block, lds_filter(), stream, a);
     } else {
       launch_linearize(slot_args(cur_), col_grid());
-      hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R, ISO>), grid, block, lds_filter(), stream, a);
+      hipLaunchKernelGGL((k_forward_up<Model, kStoredLin, B, R, ISO, FORM>), grid, block, lds_filter(), stream, a);
     }
-    scan_tiles<FilterOp<N, R, ISO>>(ta_f_, tc_f_, kFilterNames);
-    hipLaunchKernelGGL((k_forward_down_filter<Model, B, R, ISO>), grid, block, 0, stream, a);
+    scan_tiles<typename Form<FORM, N, R, ISO>::FOp>(ta_f_, tc_f_, kFilterNames);
+    if (lin_ == SM_LIN_TAYLOR)
+      hipLaunchKernelGGL((k_forward_down_filter<Model, kInlineTaylor, B, R, ISO, FORM>), grid, block, 0, stream, a);
+    else
+      hipLaunchKernelGGL((k_forward_down_filter<Model, kStoredLin, B, R, ISO, FORM>), grid, block, 0, stream, a);
   }
 
   sm_status objective(double* out) override {
@@ -693,6 +736,8 @@ class Engine final : public EngineBase {
   }
 
   sm_status lm_mode(bool on) override {
+    if (on && form_ == SM_FORM_SQRT)
+      return fail(SM_EINVAL, "adaptive damping is built for the covariance form of the elements");
     if (on && lin_ != SM_LIN_TAYLOR)
       return fail(SM_EINVAL, "adaptive damping needs the Taylor linearisation (sigma-point iterations minimise "
                              "no fixed objective)");
@@ -826,6 +871,7 @@ class Engine final : public EngineBase {
   hipStream_t capture_stream_ = nullptr;
   SigmaRule rule_{1.0, 1.0};
   double lm_ = 0.0;
+  int form_ = SM_FORM_COVARIANCE;
   double* lm_track_ = nullptr;          // per-track damping while adaptive damping runs
   SlotMap map_{64, 1};                  // slot -> column of the per-slot arrays
   int cur_ = 0;
@@ -848,7 +894,7 @@ class Engine final : public EngineBase {
   unsigned char *d_reject_ = nullptr, *h_reject_ = nullptr;
   unsigned long long* d_delta_spare_ = nullptr;   // statistic cleared by a filtering pass
   std::vector<void*> pinned_;
-  void *d_trans_ = nullptr, *d_felem_ = nullptr, *d_selem_ = nullptr;
+  void *d_trans_ = nullptr, *d_selem_ = nullptr;
   void *lx_f_ = nullptr, *ta_f_ = nullptr, *tc_f_ = nullptr, *lx_s_ = nullptr, *ta_s_ = nullptr, *tc_s_ = nullptr;
 };
 

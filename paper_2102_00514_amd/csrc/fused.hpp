@@ -32,6 +32,7 @@
 #include "elements.hpp"
 #include "operators.hpp"
 #include "scan.hpp"
+#include "sqrt.hpp"
 
 namespace pks {
 
@@ -76,9 +77,8 @@ struct FusedArgs {
   const void* P0;       // [s(N)][ntracks]
   const void* yslot;    // [P][stride]
   void* traj;           // [N + s(N)][stride]  xbar, Pbar (read by the forward kernel, updated in place at the end)
-  void* trans;          // [N*N + N + s(N)][stride]  F_k, c_k, Q'_k of the transition out of slot k
-  void* felem;          // [FilterOp words][stride]
-  void* selem;          // [SmootherOp words][stride]
+  const void* trans;    // sigma points: the linearisation pass's rows (LinLayout); Taylor: null
+  void* selem;          // [SmootherOp words][stride] (K > 1)
   void* filt;           // optional [N + s(N)][stride]  x*, P*
   void *lx_f, *ta_f, *tc_f;  // forward lane exclusives [words][tiles*B], tile aggregates, tile carries
   void *lx_s, *ta_s, *tc_s;  // same for the reverse scan, indexed by reverse tile
@@ -115,6 +115,86 @@ enum LinSource : int {
   kStoredLin = 1      // read from the arrays a separate linearisation pass wrote (sigma-point SLR)
 };
 
+// How the elements carry their covariance-like blocks: as matrices
+// (operators.hpp, eq. 13-19 as printed) or as lower-triangular factors
+// (sqrt.hpp).  Both forms use the same words per element and per carry.
+enum : int { kFormCov = 0, kFormSqrt = 1 };
+
+template <int FORM, int N, typename R, bool ISO>
+struct Form;
+
+template <int N, typename R, bool ISO>
+struct Form<kFormCov, N, R, ISO> {
+  using FOp = FilterOp<N, R, ISO>;
+  using SOp = SmootherOp<N, R, ISO>;
+  template <int P>
+  static PKS_DEV bool element(const R (&F)[N][N], const R (&c)[N], const R (&Qp)[N][N], const R (&H)[P][N],
+                              const R (&d)[P], const R (&Rp)[P][P], const R (&yt)[P], typename FOp::Elem& e) {
+    return filter_element<N, P, R>(F, c, Qp, H, d, Rp, yt, e.A, e.b, e.C, e.eta, e.J);
+  }
+  // prior element (0, m0, P0, 0, 0)
+  static PKS_DEV void prior(const R (&P0)[N][N], typename FOp::Elem& e) {
+    PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) e.C[i][j] = P0[i][j];
+  }
+  static PKS_DEV bool smoother(const typename FOp::Carry& c, const R (&F)[N][N], const R (&cc)[N],
+                               const R (&Qp)[N][N], typename SOp::Elem& se) {
+    return smoother_element<N, R>(c.b, c.C, F, cc, Qp, se.E, se.g, se.L);
+  }
+  // end element (0, x*_T, P*_T)
+  static PKS_DEV void last(const typename FOp::Carry& c, typename SOp::Elem& se) {
+    set_zero<N>(se.E);
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      se.g[i] = c.b[i];
+      PKS_UNROLL for (int k = 0; k < N; ++k) se.L[i][k] = c.C[i][k];
+    }
+  }
+  // mean and packed covariance of a carry into a [N + s(N)] slot array
+  static PKS_DEV void store_moments(R* p, size_t st, size_t i, const typename FOp::Carry& c) {
+    FOp::store(p, st, i, c);
+  }
+  static PKS_DEV void store_moments(R* p, size_t st, size_t i, const typename SOp::Carry& c) {
+    SOp::store(p, st, i, c);
+  }
+};
+
+template <int N, typename R, bool ISO>
+struct Form<kFormSqrt, N, R, ISO> {
+  using FOp = SqrtFilterOp<N, R, ISO>;
+  using SOp = SqrtSmootherOp<N, R, ISO>;
+  template <int P>
+  static PKS_DEV bool element(const R (&F)[N][N], const R (&c)[N], const R (&Qp)[N][N], const R (&H)[P][N],
+                              const R (&d)[P], const R (&Rp)[P][P], const R (&yt)[P], typename FOp::Elem& e) {
+    return sqrt_filter_element<N, P, R>(F, c, Qp, H, d, Rp, yt, e.A, e.b, e.U, e.eta, e.Z);
+  }
+  // prior element (0, m0, chol P0, 0, 0)
+  static PKS_DEV void prior(const R (&P0)[N][N], typename FOp::Elem& e) {
+    if (!chol_lower<N>(P0, e.U)) e.b[0] = quiet_nan<R>();
+  }
+  static PKS_DEV bool smoother(const typename FOp::Carry& c, const R (&F)[N][N], const R (&cc)[N],
+                               const R (&Qp)[N][N], typename SOp::Elem& se) {
+    return sqrt_smoother_element<N, R>(c.b, c.U, F, cc, Qp, se.E, se.g, se.D);
+  }
+  static PKS_DEV void last(const typename FOp::Carry& c, typename SOp::Elem& se) {
+    set_zero<N>(se.E);
+    PKS_UNROLL for (int i = 0; i < N; ++i) {
+      se.g[i] = c.b[i];
+      PKS_UNROLL for (int k = 0; k < N; ++k) se.D[i][k] = c.U[i][k];
+    }
+  }
+  static PKS_DEV void store_moments(R* p, size_t st, size_t i, const typename FOp::Carry& c) {
+    R P[N][N];
+    tril_gram<N>(c.U, P);
+    st_vec<N>(p, st, i, c.b);
+    st_sym<N>(p + N * st, st, i, P);
+  }
+  static PKS_DEV void store_moments(R* p, size_t st, size_t i, const typename SOp::Carry& c) {
+    R P[N][N];
+    tril_gram<N>(c.D, P);
+    st_vec<N>(p, st, i, c.g);
+    st_sym<N>(p + N * st, st, i, P);
+  }
+};
+
 // Levenberg-Marquardt damping of the element of real slot s towards the
 // previous iterate stored in traj (the linearisation point of this iteration).
 template <int N, typename R>
@@ -128,77 +208,150 @@ PKS_DEV bool lm_damp_slot(const FusedArgs& a, int64_t s, typename FilterOp<N, R>
   return ok;
 }
 
-// Filtering element of slot s.
+// Surrogate transition out of the slot at column cs: F, c and Q' (eq. 10
+// evaluated at the linearisation point for Taylor, else the rows the
+// sigma-point linearisation pass stored).  Nothing of it is stored between the
+// kernels: the down-sweep evaluates or reads it again.
 template <class Model, int SRC, typename R>
-PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s, typename FilterOp<Model::N, R>::Elem& e) {
+PKS_DEV void transition_of(const FusedArgs& a, int64_t cs, R (&F)[Model::N][Model::N], R (&c)[Model::N],
+                           R (&Qp)[Model::N][Model::N]) {
   constexpr int N = Model::N, P = Model::P;
-  using TL = TransLayout<N>;
   const size_t st = a.stride;
-  const unsigned fl = s < a.S ? a.flags[s] : (kSlotFirst | kSlotLast);
-  if (fl & kSlotFirst) {
-    set_zero<N>(e.A);
-    set_zero<N>(e.eta);
-    set_zero<N>(e.J);
-    if (s < a.S) {
-      const int tr = a.track[s];
-      ld_vec<N>(static_cast<const R*>(a.m0), size_t(a.ntracks), tr, e.b);
-      ld_sym<N>(static_cast<const R*>(a.P0), size_t(a.ntracks), tr, e.C);
-      if (a.lm > 0.0 || a.lm_track) lm_damp_slot<N, R>(a, s, e);
-    } else {
-      set_zero<N>(e.b);
-      set_zero<N>(e.C);
-      PKS_UNROLL for (int i = 0; i < N; ++i) e.C[i][i] = R(1);
-    }
-    return;
-  }
-  R F[N][N], c[N], Qp[N][N], H[P][N], d[P], Rp[P][P], yt[P];
-  const int64_t cp = a.map.col(s - 1), cs = a.map.col(s);
   if constexpr (SRC == kStoredLin) {
-    // transition into s from slot s-1, measurement model at s (LinLayout of the
-    // linearisation pass; its first rows are the TransLayout rows)
     using LL = LinLayout<N, P>;
     const R* lin = static_cast<const R*>(a.trans);
-    ld_mat<N, N>(lin + LL::kF * st, st, cp, F);
-    ld_vec<N>(lin + LL::kc * st, st, cp, c);
-    ld_sym<N>(lin + LL::kQ * st, st, cp, Qp);
+    ld_mat<N, N>(lin + LL::kF * st, st, cs, F);
+    ld_vec<N>(lin + LL::kc * st, st, cs, c);
+    ld_sym<N>(lin + LL::kQ * st, st, cs, Qp);
+  } else {
+    const Model md{static_cast<const R*>(a.params)};
+    R xp[N], Pp[N][N], Qm[N][N];
+    ld_vec<N>(static_cast<const R*>(a.traj), st, cs, xp);
+    set_zero<N>(Pp);
+    const R* Qg = static_cast<const R*>(a.Q);
+    PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) Qm[i][j] = Qg[i * N + j];
+    linearize_f<Model, R>(md, kTaylor, a.rule, Qm, xp, Pp, F, c, Qp);
+  }
+}
+
+// Prior element (0, m0, P0, 0, 0) of the first slot of a track, or the
+// padding element (0, 0, I, 0, 0).
+template <class Model, typename R, int FORM>
+PKS_DEV void prior_element(const FusedArgs& a, int64_t s, typename Form<FORM, Model::N, R, true>::FOp::Elem& e) {
+  constexpr int N = Model::N;
+  using Fm = Form<FORM, N, R, true>;
+  set_zero<N>(e.A);
+  set_zero<N>(e.eta);
+  R P0[N][N];
+  if (s < a.S) {
+    const int tr = a.track[s];
+    ld_vec<N>(static_cast<const R*>(a.m0), size_t(a.ntracks), tr, e.b);
+    ld_sym<N>(static_cast<const R*>(a.P0), size_t(a.ntracks), tr, P0);
+  } else {
+    set_zero<N>(e.b);
+    set_zero<N>(P0);
+    PKS_UNROLL for (int i = 0; i < N; ++i) P0[i][i] = R(1);
+  }
+  if constexpr (FORM == kFormCov) {
+    set_zero<N>(e.J);
+    Fm::prior(P0, e);
+    if (s < a.S && (a.lm > 0.0 || a.lm_track)) lm_damp_slot<N, R>(a, s, e);
+  } else {
+    set_zero<N>(e.Z);
+    Fm::prior(P0, e);
+  }
+}
+
+// Filtering element of slot s (not the first of its track) from the
+// surrogate transition (F, c, Q') into it.
+template <class Model, int SRC, typename R, int FORM>
+PKS_DEV void filter_element_with(const FusedArgs& a, int64_t s, const R (&F)[Model::N][Model::N],
+                                 const R (&c)[Model::N], const R (&Qp)[Model::N][Model::N],
+                                 typename Form<FORM, Model::N, R, true>::FOp::Elem& e) {
+  constexpr int N = Model::N, P = Model::P;
+  using Fm = Form<FORM, N, R, true>;
+  const size_t st = a.stride;
+  const int64_t cs = a.map.col(s);
+  R H[P][N], d[P], Rp[P][P], yt[P];
+  if constexpr (SRC == kStoredLin) {
+    using LL = LinLayout<N, P>;
+    const R* lin = static_cast<const R*>(a.trans);
     ld_mat<P, N>(lin + LL::kH * st, st, cs, H);
     ld_vec<P>(lin + LL::kd * st, st, cs, d);
     ld_sym<P>(lin + LL::kR * st, st, cs, Rp);
     ld_vec<P>(lin + LL::ky * st, st, cs, yt);
   } else {
     const Model md{static_cast<const R*>(a.params)};
-    const R* traj = static_cast<const R*>(a.traj);
-    {
-      R xp[N], Pp[N][N], Qm[N][N];
-      ld_vec<N>(traj, st, cp, xp);
-      set_zero<N>(Pp);
-      const R* Qg = static_cast<const R*>(a.Q);
-      PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) Qm[i][j] = Qg[i * N + j];
-      linearize_f<Model, R>(md, kTaylor, a.rule, Qm, xp, Pp, F, c, Qp);
-      R* tr = static_cast<R*>(a.trans);
-      st_mat<N, N>(tr + TL::kF * st, st, cp, F);
-      st_vec<N>(tr + TL::kc * st, st, cp, c);
-      st_sym<N>(tr + TL::kQ * st, st, cp, Qp);
-    }
-    {
-      R x[N], Px[N][N], Rm[P][P], y[P];
-      ld_vec<N>(traj, st, cs, x);
-      set_zero<N>(Px);
-      const R* Rg = static_cast<const R*>(a.R);
-      PKS_UNROLL for (int i = 0; i < P; ++i) PKS_UNROLL for (int j = 0; j < P; ++j) Rm[i][j] = Rg[i * P + j];
-      ld_vec<P>(static_cast<const R*>(a.yslot), st, cs, y);
-      linearize_h<Model, R>(md, kTaylor, a.rule, Rm, x, Px, y, H, d, Rp, yt);
-    }
+    R x[N], Px[N][N], Rm[P][P], y[P];
+    ld_vec<N>(static_cast<const R*>(a.traj), st, cs, x);
+    set_zero<N>(Px);
+    const R* Rg = static_cast<const R*>(a.R);
+    PKS_UNROLL for (int i = 0; i < P; ++i) PKS_UNROLL for (int j = 0; j < P; ++j) Rm[i][j] = Rg[i * P + j];
+    ld_vec<P>(static_cast<const R*>(a.yslot), st, cs, y);
+    linearize_h<Model, R>(md, kTaylor, a.rule, Rm, x, Px, y, H, d, Rp, yt);
   }
-  bool ok = filter_element<N, P, R>(F, c, Qp, H, d, Rp, yt, e.A, e.b, e.C, e.eta, e.J);
-  if (a.lm > 0.0 || a.lm_track) ok = lm_damp_slot<N, R>(a, s, e) && ok;
+  bool ok = Fm::template element<P>(F, c, Qp, H, d, Rp, yt, e);
+  if constexpr (FORM == kFormCov) {
+    if (a.lm > 0.0 || a.lm_track) ok = lm_damp_slot<N, R>(a, s, e) && ok;
+  }
   if (!ok) e.b[0] = quiet_nan<R>();
 }
 
-template <class Model, int SRC, int B, typename R, bool ISO = true>
+// Filtering element of slot s.
+template <class Model, int SRC, typename R, int FORM = kFormCov>
+PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s,
+                                  typename Form<FORM, Model::N, R, true>::FOp::Elem& e) {
+  constexpr int N = Model::N;
+  const unsigned fl = s < a.S ? a.flags[s] : (kSlotFirst | kSlotLast);
+  if (fl & kSlotFirst) {
+    prior_element<Model, R, FORM>(a, s, e);
+    return;
+  }
+  R F[N][N], c[N], Qp[N][N];
+  transition_of<Model, SRC, R>(a, a.map.col(s - 1), F, c, Qp);
+  filter_element_with<Model, SRC, R, FORM>(a, s, F, c, Qp, e);
+}
+
+// A lane's walk over its K slots in a forward down-sweep (K > 1): the
+// filtering element of every slot is built again (from the linearisation, as
+// in the up-sweep) and applied to the running carry.  The transition out of
+// each slot is kept for the next slot's element and handed to `visit` with
+// the slot's filtered carry: visit(j, s, cs, carry, flags, F, c, Q').
+template <class Model, int SRC, typename R, bool ISO, int FORM, class Visit>
+PKS_DEV void walk_lane(const FusedArgs& a, int64_t base, int64_t cbase, int B,
+                       typename Form<FORM, Model::N, R, ISO>::FOp::Carry& c, bool have, Visit&& visit) {
+  constexpr int N = Model::N;
+  using FOp = typename Form<FORM, N, R, ISO>::FOp;
+  R Ft[N][N], ct[N], Qt[N][N];   // transition into the current slot, then out of it
+  bool trans_ok = false;
+  for (int j = 0; j < a.K; ++j) {
+    const int64_t s = base + j, cs = cbase + int64_t(j) * B;
+    const unsigned fl = s < a.S ? a.flags[s] : (kSlotFirst | kSlotLast);
+    if (a.K > 1) {
+      typename Form<FORM, N, R, true>::FOp::Elem e;
+      if (fl & kSlotFirst) {
+        prior_element<Model, R, FORM>(a, s, e);
+      } else {
+        if (!trans_ok) transition_of<Model, SRC, R>(a, a.map.col(s - 1), Ft, ct, Qt);
+        filter_element_with<Model, SRC, R, FORM>(a, s, Ft, ct, Qt, e);
+      }
+      if (have) {
+        typename FOp::Carry n;
+        FOp::apply(c, e, n);
+        c = n;
+      } else {
+        FOp::to_carry(e, c);
+        have = true;
+      }
+    }
+    trans_ok = visit(j, s, cs, c, fl, Ft, ct, Qt);
+  }
+}
+
+template <class Model, int SRC, int B, typename R, bool ISO = true, int FORM = kFormCov>
 __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
   constexpr int N = Model::N;
-  using Op = FilterOp<N, R, ISO>;
+  using Op = typename Form<FORM, N, R, ISO>::FOp;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
   const int lane = threadIdx.x;
@@ -207,16 +360,13 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
   const int64_t cbase = tile * B * a.K + lane;   // column of slot base + j: cbase + j * B
   if (tile == 0)
     for (int i = lane; i <= a.ntracks; i += B) a.delta_bits[i] = 0ull;
-  R* felem = static_cast<R*>(a.felem);
   typename Op::Elem acc;
-  // each lane folds its K elements as they are built (and, for K > 1, stores
-  // them for the down-sweep)
-  build_filter_element<Model, SRC, R>(a, base, acc);
-  if (a.K > 1) Op::store(felem, a.stride, cbase, acc);
+  // each lane folds its K elements as they are built; the down-sweep builds
+  // them again rather than reading them back
+  build_filter_element<Model, SRC, R, FORM>(a, base, acc);
   for (int j = 1; j < a.K; ++j) {
     typename Op::Elem e, r;
-    build_filter_element<Model, SRC, R>(a, base + j, e);
-    Op::store(felem, a.stride, cbase + int64_t(j) * B, e);
+    build_filter_element<Model, SRC, R, FORM>(a, base + j, e);
     Op::combine(acc, e, r);
     acc = r;
   }
@@ -225,7 +375,7 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
   block_ladder<Op, B, true, R>(lds, acc, ex, has_ex);
   // K = 1: the lane's inclusive prefix goes to the down-sweep, which then
   // needs neither the element nor a second carry application; K > 1: the
-  // exclusive prefix, continued there over the stored elements
+  // exclusive prefix, continued there over the rebuilt elements
   if (a.K == 1) Op::store(static_cast<R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, acc);
   else if (has_ex) Op::store(static_cast<R*>(a.lx_f), size_t(a.tiles) * B, tile * B + lane, ex);
   if (lane == B - 1) Op::store(static_cast<R*>(a.ta_f), size_t(a.tiles), tile, acc);
@@ -234,10 +384,10 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
 // Carry at the start of a lane's run in a forward down-sweep: tile carry (x)
 // the lane prefix handed over by k_forward_up (inclusive for K = 1, so the
 // result is already the filtered moments of the lane's slot).
-template <int N, int B, typename R, bool ISO>
-PKS_DEV void lane_filter_carry(const FusedArgs& a, int64_t tile, int lane, typename FilterOp<N, R>::Carry& c,
-                               bool& have) {
-  using FOp = FilterOp<N, R, ISO>;
+template <int N, int B, typename R, bool ISO, int FORM = kFormCov>
+PKS_DEV void lane_filter_carry(const FusedArgs& a, int64_t tile, int lane,
+                               typename Form<FORM, N, R, ISO>::FOp::Carry& c, bool& have) {
+  using FOp = typename Form<FORM, N, R, ISO>::FOp;
   have = false;
   if (tile > 0) {
     FOp::load(static_cast<const R*>(a.tc_f), size_t(a.tiles), tile - 1, c);
@@ -257,12 +407,12 @@ PKS_DEV void lane_filter_carry(const FusedArgs& a, int64_t tile, int lane, typen
   }
 }
 
-template <class Model, int B, typename R, bool ISO = true>
+template <class Model, int SRC, int B, typename R, bool ISO = true, int FORM = kFormCov>
 __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
   constexpr int N = Model::N;
-  using FOp = FilterOp<N, R, ISO>;
-  using SOp = SmootherOp<N, R, ISO>;
-  using TL = TransLayout<N>;
+  using Fm = Form<FORM, N, R, ISO>;
+  using FOp = typename Fm::FOp;
+  using SOp = typename Fm::SOp;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
   const int lane = threadIdx.x;
@@ -271,52 +421,37 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
   const size_t st = a.stride;
   typename FOp::Carry c;
   bool have;
-  lane_filter_carry<N, B, R, ISO>(a, tile, lane, c, have);
+  lane_filter_carry<N, B, R, ISO, FORM>(a, tile, lane, c, have);
   typename SOp::Elem sacc;
   const int64_t cbase = tile * B * a.K + lane;
-  for (int j = 0; j < a.K; ++j) {
-    const int64_t s = base + j, cs = cbase + int64_t(j) * B;
-    if (a.K > 1) {
-      typename FOp::Elem e;
-      FOp::load(static_cast<const R*>(a.felem), st, cs, e);
-      if (have) {
-        typename FOp::Carry n;
-        FOp::apply(c, e, n);
-        c = n;
-      } else {
-        FOp::to_carry(e, c);
-        have = true;
-      }
-    }
-    if (a.filt) FOp::store(static_cast<R*>(a.filt), st, cs, c);
-    typename SOp::Elem se;
-    const unsigned fl = s < a.S ? a.flags[s] : (kSlotFirst | kSlotLast);
-    if (fl & kSlotLast) {
-      set_zero<N>(se.E);
-      PKS_UNROLL for (int i = 0; i < N; ++i) {
-        se.g[i] = c.b[i];
-        PKS_UNROLL for (int k = 0; k < N; ++k) se.L[i][k] = c.C[i][k];
-      }
-    } else {
-      const R* tr = static_cast<const R*>(a.trans);
-      R F[N][N], cc[N], Qp[N][N];
-      ld_mat<N, N>(tr + TL::kF * st, st, cs, F);
-      ld_vec<N>(tr + TL::kc * st, st, cs, cc);
-      ld_sym<N>(tr + TL::kQ * st, st, cs, Qp);
-      const bool ok = smoother_element<N, R>(c.b, c.C, F, cc, Qp, se.E, se.g, se.L);
-      if (!ok) se.g[0] = quiet_nan<R>();
-    }
-    if (a.K > 1) SOp::store(static_cast<R*>(a.selem), st, cs, se);
-    // paper order: sacc covers earlier slots, so sacc <- sacc (x) se, i.e. the
-    // scan-order combine with se first
-    if (j == 0) {
-      sacc = se;
-    } else {
-      typename SOp::Elem r;
-      SOp::combine(se, sacc, r);
-      sacc = r;
-    }
-  }
+  walk_lane<Model, SRC, R, ISO, FORM>(
+      a, base, cbase, B, c, have,
+      [&](int j, int64_t s, int64_t cs, const typename FOp::Carry& cj, unsigned fl, R(&F)[N][N], R(&cc)[N],
+          R(&Qp)[N][N]) {
+        if (a.filt) Fm::store_moments(static_cast<R*>(a.filt), st, cs, cj);
+        typename SOp::Elem se;
+        bool loaded = false;
+        if (fl & kSlotLast) {
+          Fm::last(cj, se);
+        } else {
+          transition_of<Model, SRC, R>(a, cs, F, cc, Qp);
+          loaded = true;
+          const bool ok = Fm::smoother(cj, F, cc, Qp, se);
+          if (!ok) se.g[0] = quiet_nan<R>();
+        }
+        if (a.K > 1) SOp::store(static_cast<R*>(a.selem), st, cs, se);
+        // paper order: sacc covers earlier slots, so sacc <- sacc (x) se, i.e.
+        // the scan-order combine with se first
+        if (j == 0) {
+          sacc = se;
+        } else {
+          typename SOp::Elem r;
+          SOp::combine(se, sacc, r);
+          sacc = r;
+        }
+        (void)s;
+        return loaded;
+      });
   const int rl = B - 1 - lane;
   const int64_t rt = a.tiles - 1 - tile;
   typename SOp::Elem ex;
@@ -330,32 +465,24 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
 
 // Filtering pass only: forward down-sweep that stores the filtered moments
 // (x*, P*) of every slot (the prefix of the filtering elements, Section 2).
-template <class Model, int B, typename R, bool ISO = true>
+template <class Model, int SRC, int B, typename R, bool ISO = true, int FORM = kFormCov>
 __global__ __launch_bounds__(B) void k_forward_down_filter(FusedArgs a) {
   constexpr int N = Model::N;
-  using FOp = FilterOp<N, R, ISO>;
+  using Fm = Form<FORM, N, R, ISO>;
+  using FOp = typename Fm::FOp;
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
+  const int64_t base = (tile * B + lane) * a.K;
   typename FOp::Carry c;
   bool have;
-  lane_filter_carry<N, B, R, ISO>(a, tile, lane, c, have);
+  lane_filter_carry<N, B, R, ISO, FORM>(a, tile, lane, c, have);
   const int64_t cbase = tile * B * a.K + lane;
-  for (int j = 0; j < a.K; ++j) {
-    const int64_t cs = cbase + int64_t(j) * B;
-    if (a.K > 1) {
-      typename FOp::Elem e;
-      FOp::load(static_cast<const R*>(a.felem), a.stride, cs, e);
-      if (have) {
-        typename FOp::Carry n;
-        FOp::apply(c, e, n);
-        c = n;
-      } else {
-        FOp::to_carry(e, c);
-        have = true;
-      }
-    }
-    FOp::store(static_cast<R*>(a.filt), a.stride, cs, c);
-  }
+  walk_lane<Model, SRC, R, ISO, FORM>(a, base, cbase, B, c, have,
+                                      [&](int, int64_t, int64_t cs, const typename FOp::Carry& cj, unsigned,
+                                          R(&)[N][N], R(&)[N], R(&)[N][N]) {
+                                        Fm::store_moments(static_cast<R*>(a.filt), a.stride, cs, cj);
+                                        return false;
+                                      });
 }
 
 PKS_DEV unsigned long long order_bits(double v) {
@@ -363,10 +490,11 @@ PKS_DEV unsigned long long order_bits(double v) {
   return static_cast<unsigned long long>(__double_as_longlong(v == v ? v : __builtin_nan("")));
 }
 
-template <class Model, int B, typename R, bool ISO = true>
+template <class Model, int B, typename R, bool ISO = true, int FORM = kFormCov>
 __global__ __launch_bounds__(B) void k_backward_down(FusedArgs a) {
   constexpr int N = Model::N;
-  using SOp = SmootherOp<N, R, ISO>;
+  using Fm = Form<FORM, N, R, ISO>;
+  using SOp = typename Fm::SOp;
   const int lane = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t base = (tile * B + lane) * a.K;
@@ -426,7 +554,7 @@ __global__ __launch_bounds__(B) void k_backward_down(FusedArgs a) {
         m = dlt > m ? dlt : m;
       }
       const unsigned long long b = order_bits(nan ? __builtin_nan("") : m);
-      SOp::store(traj, st, cs, c);
+      Fm::store_moments(traj, st, cs, c);
       if (s_track < 0) atomicMax(&a.delta_bits[a.track[s]], b);
       lane_max = b > lane_max ? b : lane_max;
     }

@@ -131,10 +131,11 @@ struct LoglikArgs {
   size_t stride;
   const unsigned char* flags;
   const void* params;
+  const void* Q;        // N x N
   const void* R;        // P x P
   const void* yslot;    // [P][stride]
-  const void* traj;     // linearisation points (Taylor measurement rows are rebuilt from them)
-  const void* trans;    // transition rows (TransLayout) of each slot
+  const void* traj;     // linearisation points (Taylor rows are rebuilt from them)
+  const void* trans;    // transition rows (TransLayout) of each slot; null: Taylor, rebuilt
   const void* lin;      // optional LinLayout rows with the stored measurement linearisation
   const void* filt;     // [N + s(N)][stride] filtered moments
   SigmaRule rule;
@@ -156,10 +157,21 @@ __global__ __launch_bounds__(kSlotBlock) void k_loglik_slots(LoglikArgs a) {
   const size_t st = a.stride;
   const int64_t cp = a.map.col(s - 1), cs = a.map.col(s);
   R F[N][N], c[N], Qp[N][N], H[P][N], d[P], Rp[P][P], yt[P];
-  const R* tr = static_cast<const R*>(a.trans);
-  ld_mat<N, N>(tr + TL::kF * st, st, cp, F);
-  ld_vec<N>(tr + TL::kc * st, st, cp, c);
-  ld_sym<N>(tr + TL::kQ * st, st, cp, Qp);
+  if (a.trans) {
+    const R* tr = static_cast<const R*>(a.trans);
+    ld_mat<N, N>(tr + TL::kF * st, st, cp, F);
+    ld_vec<N>(tr + TL::kc * st, st, cp, c);
+    ld_sym<N>(tr + TL::kQ * st, st, cp, Qp);
+  } else {
+    // Taylor transition at the linearisation point of slot k-1
+    const Model md{static_cast<const R*>(a.params)};
+    R xp[N], Pz[N][N], Qm[N][N];
+    ld_vec<N>(static_cast<const R*>(a.traj), st, cp, xp);
+    set_zero<N>(Pz);
+    const R* Qg = static_cast<const R*>(a.Q);
+    PKS_UNROLL for (int i = 0; i < N; ++i) PKS_UNROLL for (int j = 0; j < N; ++j) Qm[i][j] = Qg[i * N + j];
+    linearize_f<Model, R>(md, kTaylor, a.rule, Qm, xp, Pz, F, c, Qp);
+  }
   if (a.lin) {
     const R* lin = static_cast<const R*>(a.lin);
     ld_mat<P, N>(lin + LL::kH * st, st, cs, H);

@@ -58,6 +58,8 @@ struct FilterCarry {
 // per cent).
 template <int N, typename R, bool kIsolate = true>
 struct FilterOp {
+  // the scan ladders keep one copy of the operator instead of unrolling it
+  static constexpr bool kCompact = false;
   using Elem = FilterElem<N, R>;
   using Carry = FilterCarry<N, R>;
   static constexpr int kS = sym_size<N>();
@@ -238,6 +240,8 @@ struct SmootherCarry {
 
 template <int N, typename R, bool kIsolate = true>
 struct SmootherOp {
+  // the scan ladders keep one copy of the operator instead of unrolling it
+  static constexpr bool kCompact = false;
   using Elem = SmootherElem<N, R>;
   using Carry = SmootherCarry<N, R>;
   static constexpr int kS = sym_size<N>();

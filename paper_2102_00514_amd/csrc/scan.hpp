@@ -52,7 +52,7 @@ PKS_DEV void block_ladder(R* lds, typename Op::Elem& v, typename Op::Elem& ex, b
   const int qw = FWD ? wl : 63 - wl;        // scan position inside the wavefront
   const int qwave = FWD ? w : NW - 1 - w;   // scan position of the wavefront
   if (active) {
-    PKS_UNROLL for (int d = 1; d < 64; d <<= 1) {
+    auto step = [&](int d) {
       typename Op::Elem left;
       const int src = FWD ? (wl >= d ? wl - d : wl) : (wl + d < 64 ? wl + d : wl);
       Op::shfl(v, src, left);
@@ -61,6 +61,13 @@ PKS_DEV void block_ladder(R* lds, typename Op::Elem& v, typename Op::Elem& ex, b
         Op::combine(left, v, r);
         v = r;
       }
+    };
+    if constexpr (Op::kCompact) {
+      // one copy of a long operator instead of six
+#pragma unroll 1
+      for (int d = 1; d < 64; d <<= 1) step(d);
+    } else {
+      PKS_UNROLL for (int d = 1; d < 64; d <<= 1) step(d);
     }
   }
   typename Op::Elem wp;   // total of the wavefronts before this one (qwave > 0)

@@ -156,6 +156,13 @@ static std::string validate(const sm_problem* pb) {
   if (pb->lane_slots < 0 || pb->lane_slots > 8) return "lane_slots must be in 0..8";
   if (pb->use_graph != 0 && pb->use_graph != 1) return "use_graph must be 0 or 1";
   if (!(pb->lm_lambda >= 0.0) || !std::isfinite(pb->lm_lambda)) return "lm_lambda must be finite and >= 0";
+  if (pb->form != SM_FORM_COVARIANCE && pb->form != SM_FORM_SQRT) return "unknown element form";
+  if (pb->form == SM_FORM_SQRT) {
+    if (pb->scan != SM_SCAN_PARALLEL) return "the square-root form runs on the parallel scan";
+    if (pb->lm_lambda != 0.0) return "the square-root form runs without damping (lm_lambda must be 0)";
+    if (stacked(pb->model, n) && pb->lin != SM_LIN_TAYLOR)
+      return "the square-root form is not built for the full-state (nx = 20 sigma-point) engine";
+  }
   const int64_t S = nmeas + pb->n_tracks;
   if (pb->init_cov && !pb->init_mean) return "init_cov given without init_mean";
   if (pb->init_mean && !all_finite(pb->init_mean, size_t(S) * n)) return "init_mean must be finite";
