@@ -283,6 +283,59 @@ def warm_start_section(weights: str, n_batch: int, n_single: int, lin: str = "ta
             "batch": dict(batch, tracks=n_batch), "single_track": single}
 
 
+def converge_section(pb, lin: str, schedule, tol: float = 1e-6, max_iter: int = 50, n_single: int = 64,
+                     seed: int = 7) -> dict:
+    """Converged-solution wall time of a batch: host wall time of
+    smoother_iterate_until (tol on the largest change of each track, at most
+    max_iter iterations) from the prior broadcast, for the whole batch in one
+    handle (every track iterated until the last has converged), the same with
+    converged tracks taken out of later iterations (freeze_converged), and a
+    seeded sample of n_single tracks run one at a time on the same GPU, scaled
+    to the batch by track count.  Each timed run starts from the prior
+    broadcast after one untimed iteration (graph capture) has been undone."""
+    import numpy as np
+    import torch
+    from paper_2102_00514_amd import binding
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def timed_until(p, **kw):
+        with binding.Smoother(p, stream=stream, n_iter=1, lin=lin, **kw) as sm:
+            S, _, _ = sm.info()
+            m0 = torch.empty((S, p.nx), dtype=torch.float64, device="cuda")
+            sm.result_device(m0.data_ptr(), 0)
+            sm.iterate(1, want_delta=False)                  # warm-up: graph capture
+            sm.set_trajectory_device(m0.data_ptr(), 0)       # back to the prior broadcast (P0 per track)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run, first, _ = sm.iterate_until(tol, max_iter)
+            wall = time.perf_counter() - t0
+        return wall, run, first
+
+    out = {"tol": tol, "max_iter": max_iter, "tracks": pb.n_tracks, "schedule": list(schedule), "lin": lin}
+    for name, fz in (("batched", False), ("batched_freeze", True)):
+        wall, run, first = timed_until(pb, tile_lanes=schedule[0], lane_slots=schedule[1], freeze_converged=fz)
+        conv = first > 0
+        it = np.where(conv, first, max_iter + 1)
+        out[name] = {"ms": round(wall * 1e3, 3), "iterations_run": int(run), "converged": float(conv.mean()),
+                     "iters_mean": float(it.mean()), "iters_median": float(np.median(it)),
+                     "iters_p90": float(np.percentile(it, 90)), "iters_max_converged": int(first.max())}
+        log(f"time to converge ({name}): {wall * 1e3:.1f} ms, {run} iterations, "
+            f"{conv.mean() * 100:.1f}% converged, mean {it.mean():.1f} iterations")
+    idx = np.sort(np.random.default_rng(seed).choice(pb.n_tracks, min(n_single, pb.n_tracks), replace=False))
+    total = 0.0
+    conv_single = 0
+    for i in idx:
+        wall, run, first = timed_until(pb.track(int(i)))
+        total += wall
+        conv_single += int(first[0] > 0)
+    out["per_track"] = {"tracks_sampled": int(len(idx)), "ms_sample": round(total * 1e3, 3),
+                        "ms_scaled_to_batch": round(total * 1e3 * pb.n_tracks / len(idx), 1),
+                        "converged": conv_single / len(idx), "schedule": "default per track"}
+    log(f"time to converge (one track at a time): {total * 1e3:.1f} ms for {len(idx)} tracks, "
+        f"{total * 1e3 * pb.n_tracks / len(idx):.0f} ms scaled to {pb.n_tracks}")
+    return out
+
+
 def damping_section(n_batch: int, tol: float = 1e-6, max_iter: int = 50) -> dict:
     """Undamped iterations vs Levenberg-Marquardt passes with Marquardt's
     damping schedule (lambda0 = 1e-2, nu = 10), both from the prior broadcast,
@@ -531,6 +584,13 @@ def measure(name: str, pb, desc: str, lin: str, precision: str, steps: int, warm
     return res
 
 
+def binding_handle_for_filter(pb, args):
+    import torch
+    from paper_2102_00514_amd import binding
+    return binding.Smoother(pb, stream=torch.cuda.current_stream().cuda_stream, n_iter=1, lin=args.lin,
+                            precision=args.precision, tile_lanes=args.tile_lanes, lane_slots=args.lane_slots)
+
+
 def extra_line(name: str, r: dict, cpu) -> dict:
     return {"workload": r["desc"], "lin": r["lin"], "dtype": r["dtype"], "value": r["value"], "unit": "steps/s",
             "ms_per_step": r["ms_per_step"], "steps": r["steps"], "warmup": r["warmup"], "slots": r["S"],
@@ -600,6 +660,12 @@ def main():
     r = measure(args.workload, pb, desc, args.lin, args.precision, args.steps, args.warmup, args.profile_iters,
                 args.tile_lanes, args.lane_slots, autotune=not args.no_autotune)
     sm = r.pop("_sm")
+    converge = None
+    if args.workload == "c3":
+        sch = r["schedule"]
+        sm.close()
+        converge = converge_section(pb, args.lin, (sch["lanes_per_tile"], sch["slots_per_lane"]))
+        sm = binding_handle_for_filter(pb, args)
     dense = pb.nx == 20 and args.lin != "taylor"
     filter_pass = None
     if not dense:
@@ -633,12 +699,18 @@ def main():
             pbx, descx = make_workload(name)
             rx = measure(name, pbx, descx, DEFAULT_LIN[name], "f64", steps, warmup, 2)
             rx.pop("_sm").close()
+            conv = None
+            if pbx.n_tracks > 1:
+                sch = rx["schedule"]
+                conv = converge_section(pbx, DEFAULT_LIN[name], (sch["lanes_per_tile"], sch["slots_per_lane"]))
             cpux = None
             if not args.no_cpu:
                 threads = 1 if pbx.n_tracks == 1 else (os.cpu_count() or 1)
                 cpux = cpu_baseline(pbx, DEFAULT_LIN[name], min(args.cpu_seconds, 8.0), threads=threads)
                 log(f"{name} cpu oracle: {cpux['value']:.4g} steps/s ({cpux['sample']})")
             extra[name] = extra_line(name, rx, cpux)
+            if conv is not None:
+                extra[name]["time_to_converge"] = conv
             del pbx
             torch.cuda.empty_cache()
 
@@ -674,6 +746,7 @@ def main():
         "cpu_baseline": cpu,
         "checked": r["checked"],
         "kernels_us_per_iter": r["kernels_us_per_iter"],
+        "time_to_converge": converge,
         "extra": extra or None,
         "warm_start": warm,
         "damping": damping,

@@ -139,6 +139,12 @@ typedef struct {
                                      single-block engines (nx = 5 coordinated turn, the linear
                                      models) and on stacked targets with the Taylor linearisation,
                                      without damping; otherwise SM_EINVAL */
+  int32_t freeze_converged;       /* 1: smoother_iterate_until takes every track that has converged
+                                     (or failed) out of its later iterations: the track's result is
+                                     its iterate of the iteration at which it converged, and tiles
+                                     whose tracks are all out are skipped.  Batches on the parallel
+                                     scan of the single-block engines; elsewhere ignored.  0: every
+                                     track is iterated until the last one has converged. */
 } sm_problem;
 
 /* Fills *pb with defaults: n_tracks = 1, n_iter = 10, lin = SM_LIN_TAYLOR,
@@ -181,7 +187,10 @@ sm_status smoother_iterate(smoother_t h, int32_t k, double* max_delta_out, int32
 /* Iteration driver with the convergence rule: runs iterations (as
  * smoother_iterate) until every track's trajectory change
  * max_{k,j} |xbar_k,j^(i) - xbar_k,j^(i-1)| has been below tol at least once,
- * or max_iter iterations have run in this call.  Waits for each iteration's
+ * or max_iter iterations have run in this call.  With the problem's
+ * freeze_converged, a track that has converged is not iterated again in this
+ * call (its trajectory stays the iterate at which it converged); all tracks
+ * are iterated again by later calls.  Waits for each iteration's
  * per-track deltas (one small copy through pinned host memory), so it returns
  * as soon as the last track has converged.  *iters_run (nullable) receives the
  * iterations run; track_iters (nullable, host [n_tracks]) the 1-based
@@ -204,7 +213,8 @@ sm_status smoother_iterate_until(smoother_t h, double tol, int32_t max_iter, int
  * linear model, the exact log marginal likelihood).  Bearing measurements
  * enter unwrapped around h(xbar_k), as in the iteration.  The trajectory, the
  * iteration count and the per-track deltas are unchanged.  Waits for the
- * stream.  SM_EINVAL for the nx = 20 sigma-point engine (not built there). */
+ * stream.  On the nx = 20 sigma-point engine one wavefront builds each slot's
+ * predictive density. */
 sm_status smoother_filter(smoother_t h, double* filt_mean, double* filt_cov, double* track_loglik);
 
 /* MAP objective of the current trajectory of every track (Section 3: the
@@ -214,8 +224,7 @@ sm_status smoother_filter(smoother_t h, double* filt_mean, double* filt_cov, dou
  * bearing residuals y_k - h(x_k) taken modulo 2 pi in [-pi, pi).  Waits for
  * the handle's stream; track_cost is host [n_tracks].  Evaluated in the
  * handle's precision per slot and summed per track in double, in a fixed
- * order.  SM_EINVAL for the nx = 20 sigma-point engine (not built there) or a
- * NULL track_cost. */
+ * order.  SM_EINVAL for a NULL track_cost. */
 sm_status smoother_objective(smoother_t h, double* track_cost);
 
 /* Levenberg-Marquardt iterations (Section 3, the damped Gauss-Newton

@@ -51,6 +51,7 @@ class sm_problem(ctypes.Structure):
         ("use_graph", ctypes.c_int32),
         ("lm_lambda", ctypes.c_double),
         ("form", ctypes.c_int32),
+        ("freeze_converged", ctypes.c_int32),
     ]
 
 
@@ -148,7 +149,8 @@ def smoother_last_error(h=None) -> str:
 def make_problem(pb: Problem, n_iter: int = 10, lin: str = "taylor", precision: str = "f64",
                  scan: str = "parallel", init_mean=None, init_cov=None, ut_alpha=1.0, ut_beta=0.0,
                  ut_kappa=1.0, max_device_bytes: int = 0, tile_lanes: int = 0, lane_slots: int = 0,
-                 use_graph: bool = True, lm_lambda: float = 0.0, form: str = "covariance"):
+                 use_graph: bool = True, lm_lambda: float = 0.0, form: str = "covariance",
+                 freeze_converged: bool = False):
     """sm_problem for a workloads.Problem; returns (struct, keep-alive arrays)."""
     s = sm_problem()
     _lib.smoother_problem_defaults(ctypes.byref(s))
@@ -181,6 +183,7 @@ def make_problem(pb: Problem, n_iter: int = 10, lin: str = "taylor", precision: 
     s.use_graph = int(bool(use_graph))
     s.lm_lambda = lm_lambda
     s.form = FORM[form]
+    s.freeze_converged = int(bool(freeze_converged))
     return s, keep
 
 

@@ -199,6 +199,8 @@ class Engine final : public EngineBase {
       // smoothing elements are stored for K > 1 (with one slot per lane the
       // reverse down-sweep starts from the lanes' inclusive prefixes)
       if (sched_.K > 1) A(&d_selem_, sizeof(R) * SOp::kElemWords * stride);
+      // per-track freeze mask of smoother_iterate_until (all zero otherwise)
+      if (ntracks > 1) A(reinterpret_cast<void**>(&d_frozen_), size_t(ntracks));
       A(&lx_f_, sizeof(R) * FOp::kElemWords * lanes);
       A(&ta_f_, sizeof(R) * FOp::kElemWords * tiles_);
       A(&tc_f_, sizeof(R) * FOp::kCarryWords * tiles_);
@@ -267,6 +269,7 @@ class Engine final : public EngineBase {
     hipLaunchKernelGGL(k_fill_u64, dim3((ntracks + 256) / 256), dim3(256), 0, stream, delta_bits,
                        int64_t(ntracks + 1), 0ull);
     e = hipGetLastError();
+    if (e == hipSuccess && d_frozen_) e = hipMemsetAsync(d_frozen_, 0, size_t(ntracks), stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "initial trajectory"));
     cur_ = 0;
@@ -339,6 +342,7 @@ class Engine final : public EngineBase {
     a.rule = rule_;
     a.lm = lm_;
     a.lm_track = lm_track_;
+    a.frozen = d_frozen_;
     a.map = map_;
     return a;
   }
@@ -372,9 +376,30 @@ class Engine final : public EngineBase {
     a.rule = rule_;
     a.lm = lm_;
     a.lm_track = lm_track_;
+    a.frozen = d_frozen_;
     a.map = map_;
     return a;
   }
+
+  // Tracks taken out of (1) or put back into (0) the iterations; queued on the
+  // stream (the mask is read by the kernels of the following iterations).
+  sm_status set_frozen(const unsigned char* mask) override {
+    if (!d_frozen_) return fail(SM_ESTATE, "freezing needs a batch on the parallel scan");
+    if (!h_frozen_) {
+      const hipError_t e = pinned_alloc(reinterpret_cast<void**>(&h_frozen_), size_t(ntracks));
+      if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "freeze mask"));
+    }
+    // the previous upload may still be reading the pinned buffer
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) {
+      if (mask) std::memcpy(h_frozen_, mask, size_t(ntracks));
+      else std::memset(h_frozen_, 0, size_t(ntracks));
+      e = hipMemcpyAsync(d_frozen_, h_frozen_, size_t(ntracks), hipMemcpyHostToDevice, stream);
+    }
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "freeze mask upload"));
+    return SM_OK;
+  }
+  bool can_freeze() const override { return d_frozen_ != nullptr; }
 
   // Generic multi-level scan of `m` elements stored in scan order (tile aggregates).
   template <class Op>
@@ -659,6 +684,7 @@ class Engine final : public EngineBase {
       FusedArgs a = fused_args();
       a.lm = 0.0;
       a.lm_track = nullptr;
+      a.frozen = nullptr;     // the filtering pass covers every track
       a.filt = d_filt_;
       a.delta_bits = d_delta_spare_;    // the forward kernel clears its statistic: keep the handle's
       if (form_ == SM_FORM_SQRT) launch_filter_pass_f<kFormSqrt>(a);
@@ -728,6 +754,10 @@ class Engine final : public EngineBase {
     a.wp0 = d_wp0_;
     a.slot_cost = d_slot_cost_;
     a.map = map_;
+    a.traj_scale = 1;
+    a.y_scale = 1;
+    a.m0_stride = size_t(ntracks);
+    a.m0_scale = 1;
     hipLaunchKernelGGL((k_objective_slots<Model, R>), col_grid(),
                        dim3(kSlotBlock), 0, stream, a);
     e = hipGetLastError();
@@ -892,6 +922,7 @@ class Engine final : public EngineBase {
   double *d_lam_ = nullptr, *h_lam_ = nullptr;
   void* d_saved_ = nullptr;
   unsigned char *d_reject_ = nullptr, *h_reject_ = nullptr;
+  unsigned char *d_frozen_ = nullptr, *h_frozen_ = nullptr;   // per-track freeze mask (batches)
   unsigned long long* d_delta_spare_ = nullptr;   // statistic cleared by a filtering pass
   std::vector<void*> pinned_;
   void *d_trans_ = nullptr, *d_selem_ = nullptr;

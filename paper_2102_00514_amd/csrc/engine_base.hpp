@@ -89,34 +89,56 @@ class EngineBase {
   // for (its first[] stays 0), the other tracks -- unaffected by it, since
   // track boundaries restart both scans -- run on, and the call then reports
   // SM_ENUMERIC.
-  sm_status iterate_until(double tol, int max_iter, int* run, int32_t* first) {
+  //
+  // With freeze (engines where can_freeze()), a track that has converged or
+  // failed is taken out of the later iterations: its trajectory stays the
+  // iterate of that iteration, and tiles whose tracks are all out are
+  // skipped.  Every track is put back in at the end of the call.
+  sm_status iterate_until(double tol, int max_iter, int* run, int32_t* first, bool freeze = false) {
     std::vector<double> d(ntracks + 1);
-    std::vector<unsigned char> failed(ntracks, 0);
+    std::vector<unsigned char> failed(ntracks, 0), out(ntracks, 0);
     int left = ntracks, n_failed = 0;
     for (int i = 0; i < ntracks; ++i) first[i] = 0;
     *run = 0;
-    while (*run < max_iter && left > 0) {
-      sm_status st = iterate(1);
+    freeze = freeze && can_freeze();
+    sm_status st = freeze ? set_frozen(nullptr) : SM_OK;
+    while (st == SM_OK && *run < max_iter && left > 0) {
+      st = iterate(1);
       if (st == SM_OK) st = track_deltas(d.data());
-      if (st != SM_OK) return st;
+      if (st != SM_OK) break;
       *run += 1;
+      bool changed = false;
       for (int i = 0; i < ntracks; ++i) {
-        if (failed[i]) continue;
+        if (failed[i] || out[i]) continue;
         if (!std::isfinite(d[i])) {
           // a track that had converged and then fails is reported as failed
           failed[i] = 1;
           ++n_failed;
           if (first[i] == 0) --left;
           first[i] = 0;
+          out[i] = freeze;
+          changed = changed || freeze;
         } else if (first[i] == 0 && d[i] < tol) {
           first[i] = *run;
           --left;
+          out[i] = freeze;
+          changed = changed || freeze;
         }
       }
+      if (changed && left > 0) st = set_frozen(out.data());
     }
+    if (freeze) {
+      const sm_status st2 = set_frozen(nullptr);
+      if (st == SM_OK) st = st2;
+    }
+    if (st != SM_OK) return st;
     if (n_failed > 0) return fail(SM_ENUMERIC, "non-finite iterate in " + std::to_string(n_failed) + " track(s)");
     return SM_OK;
   }
+
+  // Per-track freeze mask for iterate_until (nullptr: no track frozen).
+  virtual sm_status set_frozen(const unsigned char*) { return fail(SM_ESTATE, "freezing is not built for this engine"); }
+  virtual bool can_freeze() const { return false; }
 
   // MAP objective (Section 3) of the current trajectory, per track, into a
   // host buffer; waits for the stream.
@@ -315,6 +337,7 @@ class EngineBase {
   unsigned long long* delta_bits = nullptr;
   unsigned long long* h_delta = nullptr;   // pinned host copy of delta_bits
   std::vector<void*> allocs;
+  bool freeze_converged = false;   // iterate_until takes converged tracks out (sm_problem)
   char* arena = nullptr;
   size_t arena_bytes = 0, arena_used = 0;
   bool profiling = false;

@@ -36,7 +36,7 @@
 
 namespace pks {
 
-enum : unsigned { kSlotFirst = 1u, kSlotLast = 2u };
+enum : unsigned { kSlotFirst = 1u, kSlotLast = 2u, kSlotFrozen = 4u };
 
 // Column of slot s in the per-slot arrays.  A tile of B lanes x K slots
 // stores the j-th of lane l's K consecutive slots at column
@@ -86,8 +86,33 @@ struct FusedArgs {
   SigmaRule rule;
   double lm;            // Levenberg-Marquardt damping lambda (0 = undamped)
   const double* lm_track;  // optional [ntracks]: per-track damping, replaces lm
+  const unsigned char* frozen;  // optional [ntracks]: 1 = the track has converged and is not iterated
   SlotMap map;          // slot -> column of the per-slot arrays
 };
+
+// Frozen tracks.  A track that has converged can be taken out of later
+// iterations: its slots then hold the padding elements (0, 0, I, 0, 0) and
+// (0, 0, I), which restart both scans like a prior and an end element, so the
+// tracks around it are unaffected, and its trajectory is not written.  A tile
+// whose slots all belong to frozen tracks is skipped by every kernel; its
+// aggregates are those padding elements.
+enum : int { kTileActive = 0, kTileMixed = 1, kTileFrozen = 2 };
+
+PKS_DEV bool slot_frozen(const FusedArgs& a, int64_t s) { return a.frozen && s < a.S && a.frozen[a.track[s]]; }
+
+// kTileActive / kTileMixed / kTileFrozen for the slots [lo, lo + n) (tracks
+// are contiguous, so the range covers the tracks track[lo]..track[last]).
+PKS_DEV int tile_freeze_state(const FusedArgs& a, int64_t lo, int64_t n) {
+  if (!a.frozen) return kTileActive;
+  const int64_t hi = (lo + n < a.S ? lo + n : a.S) - 1;
+  if (lo > hi) return kTileFrozen;       // padding only
+  bool any_frozen = false, any_active = false;
+  for (int k = a.track[lo]; k <= a.track[hi]; ++k) {
+    if (a.frozen[k]) any_frozen = true;
+    else any_active = true;
+  }
+  return any_active ? (any_frozen ? kTileMixed : kTileActive) : kTileFrozen;
+}
 
 // Linearisation arrays written by the separate linearisation pass: transition
 // out of the slot F (N*N), c (N), Q' (s(N)); measurement at the slot H (P*N),
@@ -237,13 +262,14 @@ PKS_DEV void transition_of(const FusedArgs& a, int64_t cs, R (&F)[Model::N][Mode
 // Prior element (0, m0, P0, 0, 0) of the first slot of a track, or the
 // padding element (0, 0, I, 0, 0).
 template <class Model, typename R, int FORM>
-PKS_DEV void prior_element(const FusedArgs& a, int64_t s, typename Form<FORM, Model::N, R, true>::FOp::Elem& e) {
+PKS_DEV void prior_element(const FusedArgs& a, int64_t s, typename Form<FORM, Model::N, R, true>::FOp::Elem& e,
+                           bool pad = false) {
   constexpr int N = Model::N;
   using Fm = Form<FORM, N, R, true>;
   set_zero<N>(e.A);
   set_zero<N>(e.eta);
   R P0[N][N];
-  if (s < a.S) {
+  if (s < a.S && !pad) {
     const int tr = a.track[s];
     ld_vec<N>(static_cast<const R*>(a.m0), size_t(a.ntracks), tr, e.b);
     ld_sym<N>(static_cast<const R*>(a.P0), size_t(a.ntracks), tr, P0);
@@ -255,7 +281,7 @@ PKS_DEV void prior_element(const FusedArgs& a, int64_t s, typename Form<FORM, Mo
   if constexpr (FORM == kFormCov) {
     set_zero<N>(e.J);
     Fm::prior(P0, e);
-    if (s < a.S && (a.lm > 0.0 || a.lm_track)) lm_damp_slot<N, R>(a, s, e);
+    if (s < a.S && !pad && (a.lm > 0.0 || a.lm_track)) lm_damp_slot<N, R>(a, s, e);
   } else {
     set_zero<N>(e.Z);
     Fm::prior(P0, e);
@@ -303,8 +329,9 @@ PKS_DEV void build_filter_element(const FusedArgs& a, int64_t s,
                                   typename Form<FORM, Model::N, R, true>::FOp::Elem& e) {
   constexpr int N = Model::N;
   const unsigned fl = s < a.S ? a.flags[s] : (kSlotFirst | kSlotLast);
-  if (fl & kSlotFirst) {
-    prior_element<Model, R, FORM>(a, s, e);
+  const bool fz = slot_frozen(a, s);
+  if ((fl & kSlotFirst) || fz) {
+    prior_element<Model, R, FORM>(a, s, e, fz);
     return;
   }
   R F[N][N], c[N], Qp[N][N];
@@ -326,11 +353,12 @@ PKS_DEV void walk_lane(const FusedArgs& a, int64_t base, int64_t cbase, int B,
   bool trans_ok = false;
   for (int j = 0; j < a.K; ++j) {
     const int64_t s = base + j, cs = cbase + int64_t(j) * B;
-    const unsigned fl = s < a.S ? a.flags[s] : (kSlotFirst | kSlotLast);
+    unsigned fl = s < a.S ? a.flags[s] : (kSlotFirst | kSlotLast);
+    if (slot_frozen(a, s)) fl = kSlotFirst | kSlotLast | kSlotFrozen;
     if (a.K > 1) {
       typename Form<FORM, N, R, true>::FOp::Elem e;
       if (fl & kSlotFirst) {
-        prior_element<Model, R, FORM>(a, s, e);
+        prior_element<Model, R, FORM>(a, s, e, (fl & kSlotFrozen) != 0);
       } else {
         if (!trans_ok) transition_of<Model, SRC, R>(a, a.map.col(s - 1), Ft, ct, Qt);
         filter_element_with<Model, SRC, R, FORM>(a, s, Ft, ct, Qt, e);
@@ -360,6 +388,20 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
   const int64_t cbase = tile * B * a.K + lane;   // column of slot base + j: cbase + j * B
   if (tile == 0)
     for (int i = lane; i <= a.ntracks; i += B) a.delta_bits[i] = 0ull;
+  if (a.frozen) {
+    __shared__ int s_state;
+    if (lane == 0) s_state = tile_freeze_state(a, tile * B * a.K, int64_t(B) * a.K);
+    __syncthreads();
+    if (s_state == kTileFrozen) {
+      // the tile's aggregate is the padding element; nothing else is read
+      if (lane == B - 1) {
+        typename Op::Elem e;
+        prior_element<Model, R, FORM>(a, a.S, e, true);
+        Op::store(static_cast<R*>(a.ta_f), size_t(a.tiles), tile, e);
+      }
+      return;
+    }
+  }
   typename Op::Elem acc;
   // each lane folds its K elements as they are built; the down-sweep builds
   // them again rather than reading them back
@@ -419,6 +461,26 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
   const int64_t tile = blockIdx.x;
   const int64_t base = (tile * B + lane) * a.K;
   const size_t st = a.stride;
+  const int rl = B - 1 - lane;
+  const int64_t rt = a.tiles - 1 - tile;
+  if (a.frozen) {
+    __shared__ int s_state;
+    if (lane == 0) s_state = tile_freeze_state(a, tile * B * a.K, int64_t(B) * a.K);
+    __syncthreads();
+    if (s_state == kTileFrozen) {
+      if (rl == B - 1) {
+        typename SOp::Elem se;
+        typename FOp::Carry pc;
+        set_zero<N>(pc.b);
+        typename FOp::Elem pe;
+        prior_element<Model, R, FORM>(a, a.S, pe, true);
+        FOp::to_carry(pe, pc);
+        Fm::last(pc, se);
+        SOp::store(static_cast<R*>(a.ta_s), size_t(a.tiles), rt, se);
+      }
+      return;
+    }
+  }
   typename FOp::Carry c;
   bool have;
   lane_filter_carry<N, B, R, ISO, FORM>(a, tile, lane, c, have);
@@ -428,10 +490,17 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
       a, base, cbase, B, c, have,
       [&](int j, int64_t s, int64_t cs, const typename FOp::Carry& cj, unsigned fl, R(&F)[N][N], R(&cc)[N],
           R(&Qp)[N][N]) {
-        if (a.filt) Fm::store_moments(static_cast<R*>(a.filt), st, cs, cj);
+        if (a.filt && !(fl & kSlotFrozen)) Fm::store_moments(static_cast<R*>(a.filt), st, cs, cj);
         typename SOp::Elem se;
         bool loaded = false;
-        if (fl & kSlotLast) {
+        if (fl & kSlotFrozen) {
+          // padding end element (0, 0, I) in place of the frozen slot's
+          typename FOp::Elem pe;
+          typename FOp::Carry pc;
+          prior_element<Model, R, FORM>(a, a.S, pe, true);
+          FOp::to_carry(pe, pc);
+          Fm::last(pc, se);
+        } else if (fl & kSlotLast) {
           Fm::last(cj, se);
         } else {
           transition_of<Model, SRC, R>(a, cs, F, cc, Qp);
@@ -452,8 +521,6 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
         (void)s;
         return loaded;
       });
-  const int rl = B - 1 - lane;
-  const int64_t rt = a.tiles - 1 - tile;
   typename SOp::Elem ex;
   bool has_ex;
   block_ladder<SOp, B, false, R>(lds, sacc, ex, has_ex);
@@ -503,13 +570,16 @@ __global__ __launch_bounds__(B) void k_backward_down(FusedArgs a) {
   const size_t st = a.stride;
   __shared__ unsigned long long s_max;
   __shared__ int s_track;  // track of every real slot of the block, or -1 if several
+  __shared__ int s_state;
   if (lane == 0) {
     s_max = 0ull;
     const int64_t lo = tile * B * a.K;
     const int64_t hi = (lo + int64_t(B) * a.K < a.S ? lo + int64_t(B) * a.K : a.S) - 1;
     s_track = (lo <= hi && a.track[lo] == a.track[hi]) ? a.track[lo] : -1;
+    s_state = tile_freeze_state(a, lo, int64_t(B) * a.K);
   }
   __syncthreads();
+  if (s_state == kTileFrozen) return;
   typename SOp::Carry c;
   bool have = false;
   if (rt > 0) {
@@ -545,7 +615,7 @@ __global__ __launch_bounds__(B) void k_backward_down(FusedArgs a) {
         have = true;
       }
     }
-    if (s < a.S) {
+    if (s < a.S && !slot_frozen(a, s)) {
       double m = 0.0;
       bool nan = false;
       PKS_UNROLL for (int i = 0; i < N; ++i) {

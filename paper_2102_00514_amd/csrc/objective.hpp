@@ -35,6 +35,13 @@ struct CostArgs {
   const void* wp0;      // [ntracks][N][N]
   double* slot_cost;    // [S], slot order
   SlotMap map;          // slot -> column of the per-slot arrays
+  // Record layouts: entry e of slot s's mean is traj[e * stride + col * traj_scale]
+  // (col = map.col(s)), of its measurement yslot[e * stride + col * y_scale],
+  // entry e of track t's m0 is m0[e * m0_stride + t * m0_scale].  Structure of
+  // arrays: scales 1, m0_stride = ntracks; slot-major records: stride 1.
+  int64_t traj_scale, y_scale;
+  size_t m0_stride;
+  int64_t m0_scale;
 };
 
 template <int N, typename R>
@@ -58,23 +65,23 @@ __global__ __launch_bounds__(kSlotBlock) void k_objective_slots(CostArgs a) {
   if (s >= a.S) return;
   const R* traj = static_cast<const R*>(a.traj);
   R x[N], r[N];
-  ld_vec<N>(traj, a.stride, cs, x);
+  ld_vec<N>(traj, a.stride, cs * a.traj_scale, x);
   R c;
   if (a.flags[s] & kSlotFirst) {
     const int tr = a.track[s];
     R m0[N];
-    ld_vec<N>(static_cast<const R*>(a.m0), size_t(a.ntracks), tr, m0);
+    ld_vec<N>(static_cast<const R*>(a.m0), a.m0_stride, tr * a.m0_scale, m0);
     PKS_UNROLL for (int i = 0; i < N; ++i) r[i] = x[i] - m0[i];
     c = half_sq_whitened<N, R>(static_cast<const R*>(a.wp0) + size_t(tr) * N * N, r);
   } else {
     const Model md{static_cast<const R*>(a.params)};
     R xp[N], fx[N], hx[P], y[P], e[P];
-    ld_vec<N>(traj, a.stride, a.map.col(s - 1), xp);
+    ld_vec<N>(traj, a.stride, a.map.col(s - 1) * a.traj_scale, xp);
     md.f(xp, fx);
     PKS_UNROLL for (int i = 0; i < N; ++i) r[i] = x[i] - fx[i];
     c = half_sq_whitened<N, R>(static_cast<const R*>(a.wq), r);
     md.h(x, hx);
-    ld_vec<P>(static_cast<const R*>(a.yslot), a.stride, cs, y);
+    ld_vec<P>(static_cast<const R*>(a.yslot), a.stride, cs * a.y_scale, y);
     PKS_UNROLL for (int i = 0; i < P; ++i) e[i] = Model::kAngular ? wrap_pi<R>(y[i] - hx[i]) : y[i] - hx[i];
     c += half_sq_whitened<P, R>(static_cast<const R*>(a.wr), e);
   }

@@ -33,6 +33,7 @@ struct SlotArgs {
   SigmaRule rule;
   double lm;            // Levenberg-Marquardt damping lambda (0 = undamped)
   const double* lm_track;  // optional [ntracks]: per-track damping, replaces lm
+  const unsigned char* frozen;  // optional [ntracks]: tracks taken out of the iterations
   SlotMap map;          // slot -> column of the per-slot arrays
 };
 
@@ -47,6 +48,7 @@ __global__ __launch_bounds__(kSlotBlock) __attribute__((amdgpu_waves_per_eu(2)))
   const int64_t cs = int64_t(blockIdx.x) * kSlotBlock + threadIdx.x;
   const int64_t s = a.map.slot(cs);
   if (s >= a.S) return;
+  if (a.frozen && a.frozen[a.track[s]]) return;   // not iterated: its rows stay as they are
   const unsigned fl = a.flags[s];
   const R* traj = static_cast<const R*>(a.traj);
   R* lin = static_cast<R*>(a.lin);

@@ -157,6 +157,7 @@ static std::string validate(const sm_problem* pb) {
   if (pb->use_graph != 0 && pb->use_graph != 1) return "use_graph must be 0 or 1";
   if (!(pb->lm_lambda >= 0.0) || !std::isfinite(pb->lm_lambda)) return "lm_lambda must be finite and >= 0";
   if (pb->form != SM_FORM_COVARIANCE && pb->form != SM_FORM_SQRT) return "unknown element form";
+  if (pb->freeze_converged != 0 && pb->freeze_converged != 1) return "freeze_converged must be 0 or 1";
   if (pb->form == SM_FORM_SQRT) {
     if (pb->scan != SM_SCAN_PARALLEL) return "the square-root form runs on the parallel scan";
     if (pb->lm_lambda != 0.0) return "the square-root form runs without damping (lm_lambda must be 0)";
@@ -276,6 +277,7 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
       g_init_error = eng->err;
       return st;
     }
+    eng->freeze_converged = pb->freeze_converged != 0;
     smoother* h = new smoother();
     h->eng = std::move(eng);
     h->nx = pb->nx;
@@ -428,7 +430,7 @@ sm_status smoother_iterate_until(smoother_t h, double tol, int32_t max_iter, int
     pks::EngineBase& e = *h->eng;
     std::vector<int32_t> first(e.ntracks);
     int run = 0;
-    const sm_status st = e.iterate_until(tol, max_iter, &run, first.data());
+    const sm_status st = e.iterate_until(tol, max_iter, &run, first.data(), e.freeze_converged);
     if (iters_run) *iters_run = run;
     if (track_iters) std::memcpy(track_iters, first.data(), sizeof(int32_t) * e.ntracks);
     if (st != SM_OK) h->err = e.err;

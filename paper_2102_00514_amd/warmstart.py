@@ -226,17 +226,19 @@ def _torch():
 
 def smooth_until_converged(pb: wl.Problem, stream: int, lin: str = "taylor", max_iter: int = 50,
                            tol: float = 1e-6, net: Optional["WarmStartNet"] = None, d_y=None, cov_const=None,
-                           keep_mean: bool = True, schedule=(0, 0)) -> dict:
+                           keep_mean: bool = True, schedule=(0, 0), freeze: bool = False) -> dict:
     """Runs the smoother on a batch until every track's trajectory change has
     been below tol once, or max_iter iterations (smoother_iterate_until).
     With ``net`` the first trajectory comes from the network (measurements d_y
     already on the device, tracks planned with ``net.set_tracks``).  Returns
     per-track iterations to converge (max_iter + 1 = not converged), the wall
     time from the first trajectory to the return of the driver, and the final
-    means on the device.  ``schedule`` = (tile_lanes, lane_slots), 0 = automatic."""
+    means on the device.  ``schedule`` = (tile_lanes, lane_slots), 0 = automatic.
+    With ``freeze`` a converged track is not iterated again (its result is its
+    iterate at convergence) and tiles of converged tracks are skipped."""
     torch = _torch()
     sm = binding.Smoother(pb, stream=stream, n_iter=max_iter, lin=lin, tile_lanes=schedule[0],
-                          lane_slots=schedule[1])
+                          lane_slots=schedule[1], freeze_converged=freeze)
     S, ntr, _ = sm.info()
     torch.cuda.synchronize()
     start = time.perf_counter()
@@ -395,7 +397,9 @@ def time_to_converge(net: WarmStartNet, cov: np.ndarray, pb: wl.Problem, lin: st
     (max_iter + 1 = not converged) and the converged means; ``ms_to_converge``
     is then the best of ``repeats`` timed runs capped at the iteration where
     the last converging track converged (the learned runs include the
-    network's inference and the hand-over of its trajectory).  The distance of
+    network's inference and the hand-over of its trajectory), and
+    ``ms_to_converge_freeze`` the same with every converged track taken out
+    of the later iterations (sm_problem.freeze_converged).  The distance of
     the learned run's converged means to the plain run's is reported per track
     (the plain smoother is the reference)."""
     torch = _torch()
@@ -410,9 +414,12 @@ def time_to_converge(net: WarmStartNet, cov: np.ndarray, pb: wl.Problem, lin: st
         kmax = int(r["iters"][conv].max()) if conv.any() else None
         timed = [smooth_until_converged(pb, stream, lin, kmax, tol, keep_mean=False, **kw)["wall_s"]
                  for _ in range(repeats)] if kmax else []
+        frozen = [smooth_until_converged(pb, stream, lin, kmax, tol, keep_mean=False, freeze=True, **kw)["wall_s"]
+                  for _ in range(repeats)] if kmax and pb.n_tracks > 1 else []
         res[name] = {"iters_mean": float(np.mean(r["iters"])), "iters_median": float(np.median(r["iters"])),
                      "iters_max_converged": kmax, "converged": float(conv.mean()),
                      "ms_to_converge": 1e3 * min(timed) if timed else None,
+                     "ms_to_converge_freeze": 1e3 * min(frozen) if frozen else None,
                      "ms_to_cap": 1e3 * r["wall_s"], "_mean": r["mean"], "_iters": r["iters"]}
     both = (res["plain"]["_iters"] <= max_iter) & (res["learned"]["_iters"] <= max_iter)
     so = pb.slot_offsets()
