@@ -264,6 +264,18 @@ def warm_start_section(weights: str, n_batch: int, n_single: int, lin: str = "ta
     sched_single = binding_autotune(pb.track(0), stream, lin)
     W.time_to_converge(net, cov, pb.track(0), lin, schedule=sched_single)   # warm-up (kernels, allocator)
     batch = W._public(W.time_to_converge(net, cov, pb, lin, schedule=sched_batch))
+    # the network's share of the learned start: inference and hand-over of the batch's trajectory
+    d_y = torch.from_numpy(np.ascontiguousarray(pb.y)).cuda()
+    net.set_tracks(pb.offsets)
+    mean0 = torch.empty((pb.n_slots, pb.nx), dtype=torch.float64, device="cuda")
+    net.trajectory(d_y.data_ptr(), mean0.data_ptr())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        net.trajectory(d_y.data_ptr(), mean0.data_ptr())
+    torch.cuda.synchronize()
+    batch["inference_ms"] = round((time.perf_counter() - t0) * 1e3 / 3, 3)
+    del mean0, d_y
     rows = {"plain": [], "learned": []}
     for i in range(n_single):
         r = W.time_to_converge(net, cov, pb.track(i), lin, repeats=5, schedule=sched_single)
@@ -627,6 +639,8 @@ def main():
     ap.add_argument("--damping-tracks", type=int, default=512, help="held-out tracks in the damping comparison")
     ap.add_argument("--no-extra", action="store_true",
                     help="c2 only: skip the 4096-track batch and the nx=20 track timed beside the headline")
+    ap.add_argument("--no-converge", action="store_true",
+                    help="skip the converged-solution wall times of the batch (c3, and the extra c3 line)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -661,7 +675,7 @@ def main():
                 args.tile_lanes, args.lane_slots, autotune=not args.no_autotune)
     sm = r.pop("_sm")
     converge = None
-    if args.workload == "c3":
+    if args.workload == "c3" and not args.no_converge:
         sch = r["schedule"]
         sm.close()
         converge = converge_section(pb, args.lin, (sch["lanes_per_tile"], sch["slots_per_lane"]))
@@ -700,7 +714,7 @@ def main():
             rx = measure(name, pbx, descx, DEFAULT_LIN[name], "f64", steps, warmup, 2)
             rx.pop("_sm").close()
             conv = None
-            if pbx.n_tracks > 1:
+            if pbx.n_tracks > 1 and not args.no_converge:
                 sch = rx["schedule"]
                 conv = converge_section(pbx, DEFAULT_LIN[name], (sch["lanes_per_tile"], sch["slots_per_lane"]))
             cpux = None

@@ -986,6 +986,92 @@ __global__ __launch_bounds__(kWave) void k_dn_backward_down(DnArgs a, int fan, c
   }
 }
 
+// Filtering pass only (Section 2: the filter is the prefix of the filtering
+// elements): level 0 down-sweep that stores the filtered x*, P* of every slot
+// of the chunk as a trajectory-layout record [slot][kTraj].
+template <class Model, typename R>
+__global__ __launch_bounds__(kWave) void k_dn_forward_down_filter(DnArgs a, int fan, const void* carry_in,
+                                                                  void* filt) {
+  using D = Dense<Model, R>;
+  constexpr int N = D::N;
+  using Lay = typename D::Lay;
+  __shared__ typename D::W w;
+  if (lane() == 0) w.ok = 1;
+  const int64_t c = blockIdx.x;
+  const int64_t s0 = c * fan;
+  const int64_t s1 = min(s0 + fan, a.S);
+  R *cx = w.v[6], *cP = w.m[8];
+  R *rA = w.m[0], *rC = w.m[1], *rJ = w.m[2], *rb = w.v[0], *re = w.v[1];
+  bool have = c > 0;
+  if (have) D::load_carry(static_cast<const R*>(carry_in) + size_t(c) * Lay::kCarry, cx, cP);
+  for (int64_t s = s0; s < s1; ++s) {
+    D::load_felem(static_cast<const R*>(a.elem) + size_t(s) * Lay::kFElem, rA, rb, rC, re, rJ);
+    if (have) {
+      apply_f<N, R>(cx, cP, rA, rb, rC, re, rJ, w.m[3], w.m[4], w.m[5], w.v[2], w.v[3], &w.ok);
+    } else {
+      vcopy<N>(rb, cx);
+      copy<N, N, N, false>(rC, cP);
+    }
+    have = true;
+    D::store_carry(cx, cP, static_cast<R*>(filt) + size_t(s) * Lay::kTraj);
+  }
+}
+
+// Log predictive density of slot s, log N(ytil_s; H_s m-_s + d_s, S_s) with
+// m-_s = F x*_{s-1} + c, P-_s = F P*_{s-1} F^T + Q', S_s = H P-_s H^T + R'
+// (the normalising constants that eq. 14 leaves out; summed over a track they
+// give log p(y_{1:T}) of the linearised model), from the filtered moments of
+// slot s-1; 0 at the first slot of a track.  One slot per workgroup.
+template <class Model, typename R>
+__global__ __launch_bounds__(kWave) void k_dn_loglik(DnArgs a, const void* filt, double* slot_ll) {
+  using D = Dense<Model, R>;
+  constexpr int N = D::N, P = D::P;
+  using Lay = typename D::Lay;
+  constexpr int L = ld<N>();
+  __shared__ typename D::template WorkN<6> w;
+  const int64_t s = blockIdx.x;
+  if (a.flags[s] & kSlotFirst) {
+    if (lane() == 0) slot_ll[s] = 0.0;
+    return;
+  }
+  if (lane() == 0) w.ok = 1;
+  const R* tr = static_cast<const R*>(a.trans) + size_t(s - 1) * Lay::kTrans;
+  const R* hl = static_cast<const R*>(a.hlin) + size_t(s) * Lay::kHlin;
+  const R* fp = static_cast<const R*>(filt) + size_t(s - 1) * Lay::kTraj;
+  R *F = w.m[0], *Pf = w.m[1], *Pp = w.m[2], *HP = w.m[3], *H = w.m[4], *Sx = w.m[5];
+  R *xf = w.v[0], *mp = w.v[1], *c = w.v[2], *d = w.v[3], *yt = w.v[4];
+  ld_full<N, N, N>(tr, F);
+  ld_v<N>(tr + N * N, c);
+  ld_symm<N, N>(tr + N * N + N, Pp);
+  ld_v<N>(fp, xf);
+  ld_symm<N, N>(fp + N, Pf);
+  ld_full<N, P, N>(hl, H);
+  ld_v<P>(hl + P * N, d);
+  ld_symm<N, P>(hl + P * N + P, Sx);
+  ld_v<P>(hl + P * N + P + Lay::kSP, yt);
+  wsync();
+  mm<N, N, N, N, false, false>(F, Pf, (const R*)nullptr, R(1), HP);      // F P*
+  mm<N, N, N, N, false, true>(HP, F, Pp, R(1), Pp);                      // P- = F P* F^T + Q'
+  mv<N, N, N, false>(F, xf, c, R(1), mp);                                // m- = F x* + c
+  mm<N, P, N, N, false, false>(H, Pp, (const R*)nullptr, R(1), HP);      // H P-
+  mm<N, P, N, P, false, true>(HP, H, Sx, R(1), Sx);                      // S = H P- H^T + R'
+  symmetrize<N, P>(Sx);
+  chol<N, P>(Sx, &w.ok);
+  mv<N, P, N, false>(H, mp, yt, R(-1), yt);                              // ytil - H m-
+  for (int i = lane(); i < P; i += kWave) yt[i] -= d[i];
+  wsync();
+  fwd_vec<N, P>(Sx, yt);
+  if (lane() == 0) {
+    double quad = 0.0, logdet = 0.0;
+    for (int i = 0; i < P; ++i) {
+      quad += double(yt[i]) * double(yt[i]);
+      logdet += 2.0 * log(double(Sx[i * L + i]));
+    }
+    constexpr double kLog2Pi = 1.8378770664093454836;
+    slot_ll[s] = w.ok ? -0.5 * (P * kLog2Pi + logdet + quad) : __builtin_nan("");
+  }
+}
+
 // Prior broadcast of the initial trajectory: (m0, P0) of the slot's track.
 template <int N, typename R>
 __global__ void k_dn_prior(int64_t S, const int* track, const R* m0, const R* P0, R* traj) {

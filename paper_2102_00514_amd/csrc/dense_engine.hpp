@@ -16,6 +16,7 @@
 
 #include "dense.hpp"
 #include "engine_base.hpp"
+#include "objective.hpp"
 #include "slot_kernels.hpp"
 
 namespace pks {
@@ -94,6 +95,28 @@ class DenseEngine final : public EngineBase {
     A(&d_hlin_, sizeof(R) * Lay::kHlin * S);
     A(&d_elem_, sizeof(R) * Lay::kFElem * S);
     A(reinterpret_cast<void**>(&delta_bits), sizeof(unsigned long long) * (ntracks + 1));
+    // whitening matrices of Q, R and each P0 for the MAP objective, slot
+    // offsets of the tracks for the per-track sums
+    std::vector<double> w(size_t(N) * N);
+    std::vector<R> wq(size_t(N) * N), wr(size_t(P) * P), wp0(size_t(ntracks) * N * N);
+    if (!whitening(pb.Q, N, w.data())) return fail(SM_EINVAL, "Q is not positive definite");
+    std::copy(w.begin(), w.end(), wq.begin());
+    w.resize(size_t(P) * P);
+    if (!whitening(pb.R, P, w.data())) return fail(SM_EINVAL, "R is not positive definite");
+    std::copy(w.begin(), w.end(), wr.begin());
+    w.resize(size_t(N) * N);
+    for (int t = 0; t < ntracks; ++t) {
+      if (!whitening(pb.P0 + size_t(t) * N * N, N, w.data())) return fail(SM_EINVAL, "P0 is not positive definite");
+      std::copy(w.begin(), w.end(), wp0.begin() + size_t(t) * N * N);
+    }
+    std::vector<int64_t> slot_off(ntracks + 1);
+    for (int i = 0; i <= ntracks; ++i) slot_off[i] = pb.offsets[i] + i;
+    longest_ = 0;
+    for (int i = 0; i < ntracks; ++i) longest_ = std::max<int64_t>(longest_, slot_off[i + 1] - slot_off[i]);
+    A(&d_wq_, sizeof(R) * wq.size());
+    A(&d_wr_, sizeof(R) * wr.size());
+    A(&d_wp0_, sizeof(R) * wp0.size());
+    A(reinterpret_cast<void**>(&d_slot_off_), sizeof(int64_t) * (ntracks + 1));
     for (size_t l = 0; l < counts_.size(); ++l) {
       void *fa = nullptr, *fc = nullptr;
       A(&fa, sizeof(R) * Lay::kFElem * counts_[l]);
@@ -122,6 +145,10 @@ class DenseEngine final : public EngineBase {
     H2D(d_m0_, m0.data(), sizeof(R) * m0.size());
     H2D(d_P0_, P0.data(), sizeof(R) * P0.size());
     H2D(d_y_, ys.data(), sizeof(R) * ys.size());
+    H2D(d_wq_, wq.data(), sizeof(R) * wq.size());
+    H2D(d_wr_, wr.data(), sizeof(R) * wr.size());
+    H2D(d_wp0_, wp0.data(), sizeof(R) * wp0.size());
+    H2D(d_slot_off_, slot_off.data(), sizeof(int64_t) * (ntracks + 1));
     if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "upload of the problem"));
     if (pb.init_mean) {
       std::vector<R> tj(size_t(S) * Lay::kTraj);
@@ -302,6 +329,112 @@ class DenseEngine final : public EngineBase {
     return SM_OK;
   }
 
+  // per-slot and per-track double buffers of the objective and the
+  // log-likelihood, allocated on first use
+  sm_status ensure_sums() {
+    if (d_slot_val_) return SM_OK;
+    sum_chunks_ = int((longest_ + kSumChunk - 1) / kSumChunk);
+    hipError_t e = dalloc(reinterpret_cast<void**>(&d_slot_val_), sizeof(double) * S);
+    if (e == hipSuccess) e = dalloc(reinterpret_cast<void**>(&d_partial_), sizeof(double) * ntracks * sum_chunks_);
+    if (e == hipSuccess) e = dalloc(reinterpret_cast<void**>(&d_track_val_), sizeof(double) * ntracks);
+    if (e != hipSuccess) {
+      d_slot_val_ = nullptr;
+      return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE, hip_msg(e, "per-track sum buffers"));
+    }
+    return SM_OK;
+  }
+
+  // per-slot values (queued) -> per-track sums in a fixed order -> host
+  sm_status track_sums(double* out, const char* what) {
+    hipLaunchKernelGGL(k_track_partials, dim3(unsigned(ntracks), unsigned(sum_chunks_)), dim3(kTrackSumB), 0, stream,
+                       static_cast<const double*>(d_slot_val_), static_cast<const int64_t*>(d_slot_off_), ntracks,
+                       d_partial_);
+    hipLaunchKernelGGL(k_track_totals, dim3(unsigned((ntracks + kTrackSumB - 1) / kTrackSumB)), dim3(kTrackSumB), 0,
+                       stream, static_cast<const double*>(d_partial_), ntracks, sum_chunks_, d_track_val_);
+    std::vector<double> h(ntracks);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_track_val_, sizeof(double) * ntracks, hipMemcpyDeviceToHost,
+                                            stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, what));
+    if (out) std::copy(h.begin(), h.end(), out);
+    return SM_OK;
+  }
+
+  // MAP objective (Section 3) of the current trajectory per track: one lane
+  // per slot on the slot-major records.
+  sm_status objective(double* out) override {
+    sm_status st = ensure_sums();
+    if (st != SM_OK) return st;
+    CostArgs a{};
+    a.S = S;
+    a.stride = 1;
+    a.ntracks = ntracks;
+    a.flags = d_flags_;
+    a.track = d_track_;
+    a.params = d_params_;
+    a.m0 = d_m0_;
+    a.yslot = d_y_;
+    a.traj = d_traj_;
+    a.wq = d_wq_;
+    a.wr = d_wr_;
+    a.wp0 = d_wp0_;
+    a.slot_cost = d_slot_val_;
+    a.map = SlotMap{64, 1};
+    a.traj_scale = Lay::kTraj;
+    a.y_scale = P;
+    a.m0_stride = 1;
+    a.m0_scale = N;
+    hipLaunchKernelGGL((k_objective_slots<Model, R>), dim3(unsigned((S + kSlotBlock - 1) / kSlotBlock)),
+                       dim3(kSlotBlock), 0, stream, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "objective"));
+    return track_sums(out, "objective");
+  }
+
+  // One filtering pass at the current trajectory without damping: the
+  // linearisation and the filtering half of an iteration, the filtered
+  // moments of every slot, and log p(y_{1:T}) of the linearised model per
+  // track.  The trajectory and the change statistics are left as they are.
+  sm_status filter(double* mean, double* cov, double* loglik) override {
+    sm_status st = ensure_sums();
+    if (st != SM_OK) return st;
+    hipError_t e = hipSuccess;
+    if (!d_filt_) e = dalloc(&d_filt_, sizeof(R) * Lay::kTraj * S);
+    if (e != hipSuccess)
+      return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE, hip_msg(e, "filtering pass buffers"));
+    dn::DnArgs a = args();
+    a.lm = 0.0;
+    const unsigned c0 = unsigned(counts_[0]);
+    hipLaunchKernelGGL((dn::k_dn_linearize<Model, R>), dim3(unsigned(S)), dim3(dn::kWave), 0, stream, a);
+    hipLaunchKernelGGL((dn::k_dn_forward_up<Model, R>), dim3(c0), dim3(dn::kWave), 0, stream, a, fan0_, fagg_[0]);
+    const double lm_saved = lm_;
+    lm_ = 0.0;                       // the scan levels take their arguments from args()
+    scan_levels<true>();
+    lm_ = lm_saved;
+    hipLaunchKernelGGL((dn::k_dn_forward_down_filter<Model, R>), dim3(c0), dim3(dn::kWave), 0, stream, a, fan0_,
+                       static_cast<const void*>(fcar_[0]), d_filt_);
+    hipLaunchKernelGGL((dn::k_dn_loglik<Model, R>), dim3(unsigned(S)), dim3(dn::kWave), 0, stream, a,
+                       static_cast<const void*>(d_filt_), d_slot_val_);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "filtering pass"));
+    st = track_sums(loglik, "log-likelihood");
+    if (st != SM_OK || (!mean && !cov)) return st;
+    std::vector<R> h(size_t(S) * Lay::kTraj);
+    e = hipMemcpyAsync(h.data(), d_filt_, sizeof(R) * h.size(), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(SM_EDEVICE, hip_msg(e, "copy of the filtered moments"));
+    for (int64_t sl = 0; sl < S; ++sl) {
+      const R* t = h.data() + size_t(sl) * Lay::kTraj;
+      if (mean)
+        for (int i = 0; i < N; ++i) mean[size_t(sl) * N + i] = double(t[i]);
+      if (cov)
+        for (int i = 0; i < N; ++i)
+          for (int j = 0; j < N; ++j) cov[(size_t(sl) * N + i) * N + j] = double(t[N + sym_index<N>(i, j)]);
+    }
+    return SM_OK;
+  }
+
   ~DenseEngine() override {
     if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
     if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
@@ -321,6 +454,11 @@ class DenseEngine final : public EngineBase {
   int* d_track_ = nullptr;
   void *d_params_ = nullptr, *d_Q_ = nullptr, *d_R_ = nullptr, *d_m0_ = nullptr, *d_P0_ = nullptr, *d_y_ = nullptr;
   void *d_traj_ = nullptr, *d_trans_ = nullptr, *d_hlin_ = nullptr, *d_elem_ = nullptr;
+  void *d_wq_ = nullptr, *d_wr_ = nullptr, *d_wp0_ = nullptr, *d_filt_ = nullptr;
+  int64_t* d_slot_off_ = nullptr;
+  int64_t longest_ = 0;
+  int sum_chunks_ = 1;
+  double *d_slot_val_ = nullptr, *d_partial_ = nullptr, *d_track_val_ = nullptr;
 };
 
 }  // namespace pks
