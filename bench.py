@@ -263,18 +263,22 @@ def warm_start_section(weights: str, n_batch: int, n_single: int, lin: str = "ta
     sched_batch = binding_autotune(pb, stream, lin)
     sched_single = binding_autotune(pb.track(0), stream, lin)
     W.time_to_converge(net, cov, pb.track(0), lin, schedule=sched_single)   # warm-up (kernels, allocator)
-    batch = W._public(W.time_to_converge(net, cov, pb, lin, schedule=sched_batch))
+    batch = W._public(W.time_to_converge(net, cov, pb, lin, schedule=sched_batch, repeats=2, mfma=True))
     # the network's share of the learned start: inference and hand-over of the batch's trajectory
     d_y = torch.from_numpy(np.ascontiguousarray(pb.y)).cuda()
     net.set_tracks(pb.offsets)
     mean0 = torch.empty((pb.n_slots, pb.nx), dtype=torch.float64, device="cuda")
     net.trajectory(d_y.data_ptr(), mean0.data_ptr())
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(3):
-        net.trajectory(d_y.data_ptr(), mean0.data_ptr())
-    torch.cuda.synchronize()
-    batch["inference_ms"] = round((time.perf_counter() - t0) * 1e3 / 3, 3)
+    for fast in (False, True):
+        net.trajectory(d_y.data_ptr(), mean0.data_ptr(), mfma=fast)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            net.trajectory(d_y.data_ptr(), mean0.data_ptr(), mfma=fast)
+        torch.cuda.synchronize()
+        batch["inference_ms_" + ("bf16_mfma" if fast else "fp32")] = round((time.perf_counter() - t0) * 1e3 / 3, 3)
+    batch["inference"] = "learned start inferred with BF16 products on the matrix cores (ws_trajectory_mfma)"
     del mean0, d_y
     rows = {"plain": [], "learned": []}
     for i in range(n_single):

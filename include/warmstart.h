@@ -129,6 +129,13 @@ ws_status ws_predict(ws_t h, const float* d_x, int64_t n_data, const int32_t* d_
  * the layout smoother_set_trajectory_device takes. */
 ws_status ws_trajectory(ws_t h, const double* d_y, double* d_mean);
 
+/* As ws_trajectory, with the network's matrix products on the matrix cores:
+ * operands rounded to BF16 (to nearest even), FP32 accumulation, FP32 bias,
+ * activations and normalisation.  The trajectory is a starting point of the
+ * smoother, so the rounding only moves the start; ws_trajectory stays the
+ * FP32 evaluation the network was trained with. */
+ws_status ws_trajectory_mfma(ws_t h, const double* d_y, double* d_mean);
+
 /* Message of the last failure on h (NULL: last ws_create failure on this thread). */
 const char* ws_last_error(ws_t h);
 

@@ -27,6 +27,12 @@ starts at step 1 + W w, except the last, which starts at max(1, T - W + 1) so
 that it ends at step T (steps past T, in a track shorter than W, repeat y_T).
 Step k of the track is taken from window min((k-1) // W, n_w - 1); slot 0 (the
 initial state) is given the network's estimate for step 1.
+
+Reduced-precision inference: ``forward(..., operand_round=bf16_round)`` rounds
+every weight and every layer input to bfloat16 before its products (the
+products and sums stay in FP64, the bias, ReLU and residual in FP64 on the
+unrounded values), which is what a product on BF16 matrix units with FP32
+accumulation computes up to the order of its sums.
 """
 from __future__ import annotations
 
@@ -84,27 +90,42 @@ def _dilated(h, k, d):
     return out
 
 
-def forward(theta, x, cfg=DEFAULT):
-    """x: [n, 2 ny, W] -> normalised outputs [n, P nx, W/P], cache for backward."""
+def bf16_round(a):
+    """Nearest bfloat16 value (8 significant bits, ties to the even one) of
+    each element of a, taken as an FP32 number first; returned as FP64.
+    bfloat16 is the upper half of the IEEE binary32 encoding, so rounding adds
+    half of the dropped 16-bit unit (minus one when the kept part is even, so
+    that a tie goes to even) and clears the low 16 bits.  Finite inputs only."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(theta, x, cfg=DEFAULT, operand_round=None):
+    """x: [n, 2 ny, W] -> normalised outputs [n, P nx, W/P], cache for backward.
+    operand_round: None, or a function applied to every weight and layer input
+    before its products (bf16_round for the BF16 inference form)."""
+    r = operand_round if operand_round is not None else (lambda v: v)
     P, H = cfg["patch"], cfg["hidden"]
     layers = unpack(np.asarray(theta, dtype=np.float64), cfg)
     n, cin, W = x.shape
     L = W // P
     patches = x.reshape(n, cin, L, P)                       # [n][c][j][u] = x[c][P j + u]
     W0, b0 = layers[0]
-    z0 = np.einsum("ocu,ncju->noj", W0, patches) + b0[None, :, None]
+    z0 = np.einsum("ocu,ncju->noj", r(W0), r(patches)) + b0[None, :, None]
     h = np.maximum(z0, 0.0)
     cache = {"x": x, "h": [h], "a": [h]}
     for l in range(1, H + 1):
         Wl, bl = layers[l]
         d = 2 ** (l - 1)
-        z = bl[None, :, None] + sum(np.einsum("oc,ncj->noj", Wl[:, :, k], _dilated(h, k, d)) for k in range(3))
+        hr = r(h)
+        z = bl[None, :, None] + sum(np.einsum("oc,ncj->noj", r(Wl[:, :, k]), _dilated(hr, k, d)) for k in range(3))
         a = np.maximum(z, 0.0)
         h = h + a
         cache["h"].append(h)
         cache["a"].append(a)
     WH, bH = layers[H + 1]
-    out = np.einsum("qc,ncj->nqj", WH, h) + bH[None, :, None]
+    out = np.einsum("qc,ncj->nqj", r(WH), r(h)) + bH[None, :, None]
     return out, cache
 
 

@@ -49,6 +49,31 @@ struct ConvArgs {
 __device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 __device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
 
+// One reduction stage of a 64 x 64 output tile: As[rr][mm] = A(m0 + mm, r0 + rr),
+// Bs[rb][pp] = B(r0 + rb, p0 + pp), zero outside the matrices.
+__device__ __forceinline__ void stage_tile(const ConvArgs& a, int t, int m0, int p0, int r0,
+                                           float (&As)[kTk][kTile + kPad], float (&Bs)[kTk][kTile]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = t + kThreads * i;
+    // weights: consecutive lanes take consecutive addresses of W in both forms
+    if (a.transposed) {
+      const int mm = e & 63, rr = e >> 6, m = m0 + mm, r = r0 + rr;
+      float v = 0.f;
+      if (m < a.M && r < a.Kr) {
+        const int co = r / a.g.K, k = r - co * a.g.K;
+        v = a.W[(size_t(co) * a.M + m) * a.g.K + k];
+      }
+      As[rr][mm] = v;
+    } else {
+      const int rr = e & 15, mm = e >> 4, m = m0 + mm, r = r0 + rr;
+      As[rr][mm] = (m < a.M && r < a.Kr) ? a.W[size_t(m) * a.Kr + r] : 0.f;
+    }
+    const int pp = e & 63, rb = e >> 6, p = p0 + pp, r = r0 + rb;
+    Bs[rb][pp] = (p < a.N && r < a.Kr) ? gather_at(a.g, r, p) : 0.f;
+  }
+}
+
 // out[m][p] = epilogue(sum_r A(m, r) B(r, p)); grid (ceil(N / 64), ceil(M / 64)).
 template <int EPI>
 __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
@@ -58,25 +83,7 @@ __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
   const int m0 = blockIdx.y * kTile, p0 = blockIdx.x * kTile;
   float acc[4][4] = {};
   for (int r0 = 0; r0 < a.Kr; r0 += kTk) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = t + kThreads * i;
-      // weights: consecutive lanes take consecutive addresses of W in both forms
-      if (a.transposed) {
-        const int mm = e & 63, rr = e >> 6, m = m0 + mm, r = r0 + rr;
-        float v = 0.f;
-        if (m < a.M && r < a.Kr) {
-          const int co = r / a.g.K, k = r - co * a.g.K;
-          v = a.W[(size_t(co) * a.M + m) * a.g.K + k];
-        }
-        As[rr][mm] = v;
-      } else {
-        const int rr = e & 15, mm = e >> 4, m = m0 + mm, r = r0 + rr;
-        As[rr][mm] = (m < a.M && r < a.Kr) ? a.W[size_t(m) * a.Kr + r] : 0.f;
-      }
-      const int pp = e & 63, rb = e >> 6, p = p0 + pp, r = r0 + rb;
-      Bs[rb][pp] = (p < a.N && r < a.Kr) ? gather_at(a.g, r, p) : 0.f;
-    }
+    stage_tile(a, t, m0, p0, r0, As, Bs);
     __syncthreads();
 #pragma unroll
     for (int rr = 0; rr < kTk; ++rr) {
@@ -123,6 +130,75 @@ __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Inference form of the forward convolutions on the matrix cores: the same
+// tiles and staging as k_conv, the products as 16 x 16 x 16 BF16 MFMA with
+// FP32 accumulation (operands rounded to BF16, to nearest even).  Each of the
+// four waves owns a 32 x 32 quarter of the 64 x 64 tile, two by two MFMA
+// blocks.  Operand layout of the MFMA (lane l, element j): A[l % 16][4 (l / 16)
+// + j], B[4 (l / 16) + j][l % 16]; result D[4 (l / 16) + j][l % 16].
+// Forward epilogues only (bias + ReLU, residual, linear).
+// ---------------------------------------------------------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return short(u >> 16);
+}
+
+template <int EPI>
+__global__ __launch_bounds__(kThreads) void k_conv_mfma(ConvArgs a) {
+  static_assert(EPI != kEpiBackward, "forward epilogues only");
+  __shared__ __align__(16) float As[kTk][kTile + kPad];
+  __shared__ __align__(16) float Bs[kTk][kTile];
+  const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
+  const int m0 = blockIdx.y * kTile, p0 = blockIdx.x * kTile;
+  const int mw = (wv >> 1) * 32, nw = (wv & 1) * 32;   // this wave's quarter of the tile
+  const int kq = 4 * (ln >> 4), lr = ln & 15;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int r0 = 0; r0 < a.Kr; r0 += kTk) {
+    stage_tile(a, t, m0, p0, r0, As, Bs);
+    __syncthreads();
+    bf16x4 af[2], bf[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        af[i][j] = to_bf16(As[kq + j][mw + 16 * i + lr]);
+        bf[i][j] = to_bf16(Bs[kq + j][nw + 16 * i + lr]);
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + mw + 16 * i + kq + q, p = p0 + nw + 16 * j + lr;
+        if (m >= a.M || p >= a.N) continue;
+        const size_t o = size_t(m) * a.N + p;
+        float v = acc[i][j][q] + a.bias[m];
+        if (EPI == kEpiLinear) {
+          a.out[o] = v;
+        } else {
+          v = fmaxf(v, 0.f);
+          a.out[o] = v;
+          if (EPI == kEpiResidual) a.out2[o] = a.in2[o] + v;
+        }
+      }
 }
 
 // Weight gradient partials: part[z][m][r] = sum over the z-th chunk of

@@ -173,8 +173,14 @@ struct ws_net {
   }
 
   template <int EPI>
-  void conv(const wsn::ConvArgs& a) {
+  void conv(const wsn::ConvArgs& a, bool mfma = false) {
     const dim3 grid(unsigned((a.N + wsn::kTile - 1) / wsn::kTile), unsigned((a.M + wsn::kTile - 1) / wsn::kTile));
+    if constexpr (EPI != wsn::kEpiBackward) {
+      if (mfma) {
+        hipLaunchKernelGGL(wsn::k_conv_mfma<EPI>, grid, dim3(wsn::kThreads), 0, stream, a);
+        return;
+      }
+    }
     hipLaunchKernelGGL(wsn::k_conv<EPI>, grid, dim3(wsn::kThreads), 0, stream, a);
   }
 
@@ -186,25 +192,27 @@ struct ws_net {
   }
 
   // xb [2 ny][n W] -> out [P nx][n L]; keeps every activation for the backward pass
-  void forward(int n) {
+  // mfma: the inference form of the products (BF16 operands on the matrix
+  // cores, FP32 accumulation); training always runs the FP32 kernels
+  void forward(int n, bool mfma = false) {
     const int N = n * Lpos;
     const int Hn = cfg.hidden;
     {
       const LayerSpec& L = layers[0];
       wsn::ConvArgs a{L.cout, L.cin * L.K, N, theta + L.w_off, 0, theta + L.b_off, gather_of(L, xb, n, false),
                       H[0], nullptr, nullptr, nullptr};
-      conv<wsn::kEpiRelu>(a);
+      conv<wsn::kEpiRelu>(a, mfma);
     }
     for (int l = 1; l <= Hn; ++l) {
       const LayerSpec& L = layers[l];
       wsn::ConvArgs a{L.cout, L.cin * L.K, N, theta + L.w_off, 0, theta + L.b_off, gather_of(L, H[l - 1], n, false),
                       A[l], H[l], H[l - 1], nullptr};
-      conv<wsn::kEpiResidual>(a);
+      conv<wsn::kEpiResidual>(a, mfma);
     }
     const LayerSpec& L = layers[Hn + 1];
     wsn::ConvArgs a{L.cout, L.cin * L.K, N, theta + L.w_off, 0, theta + L.b_off, gather_of(L, H[Hn], n, false),
                     out, nullptr, nullptr, nullptr};
-    conv<wsn::kEpiLinear>(a);
+    conv<wsn::kEpiLinear>(a, mfma);
   }
 
   void wgrad(const LayerSpec& L, const float* D, const wsn::Gather& g, int N) {
@@ -499,7 +507,7 @@ ws_status ws_predict(ws_t h, const float* d_x, int64_t n_data, const int32_t* d_
   return h->sync_and_check("prediction");
 }
 
-ws_status ws_trajectory(ws_t h, const double* d_y, double* d_mean) {
+static ws_status trajectory(ws_t h, const double* d_y, double* d_mean, bool mfma) {
   if (!h) return WS_ESTATE;
   if (!h->n_windows) return h->fail(WS_ESTATE, "no tracks planned (ws_set_tracks)");
   if (!d_y || !d_mean) return h->fail(WS_EINVAL, "null device pointer");
@@ -510,13 +518,17 @@ ws_status ws_trajectory(ws_t h, const double* d_y, double* d_mean) {
     const dim3 grid(unsigned((cnt + 255) / 256));
     hipLaunchKernelGGL(wsn::k_features, grid, dim3(256), 0, h->stream, h->table(), d_y, h->cfg.ny, W, w0, nb, 1,
                        h->xb);
-    h->forward(nb);
+    h->forward(nb, mfma);
     hipLaunchKernelGGL(wsn::k_scatter, grid, dim3(256), 0, h->stream, h->table(), static_cast<const float*>(h->out),
                        w0, nb, W, h->cfg.patch, h->cfg.nx, static_cast<const float*>(h->mu),
                        static_cast<const float*>(h->sigma), d_mean);
   }
   return launch_status(h, "trajectory");
 }
+
+ws_status ws_trajectory(ws_t h, const double* d_y, double* d_mean) { return trajectory(h, d_y, d_mean, false); }
+
+ws_status ws_trajectory_mfma(ws_t h, const double* d_y, double* d_mean) { return trajectory(h, d_y, d_mean, true); }
 
 const char* ws_last_error(ws_t h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 

@@ -34,7 +34,7 @@ from . import workloads as wl
 WS_OK, WS_EINVAL, WS_ENOMEM, WS_EDEVICE, _, WS_ESTATE = range(6)
 WS_EXPORTS = ("ws_config_defaults", "ws_param_count", "ws_create", "ws_set_params", "ws_get_params",
               "ws_set_normalization", "ws_set_tracks", "ws_windows", "ws_labels", "ws_train_step",
-              "ws_gradient", "ws_predict", "ws_trajectory", "ws_last_error", "ws_destroy")
+              "ws_gradient", "ws_predict", "ws_trajectory", "ws_trajectory_mfma", "ws_last_error", "ws_destroy")
 
 _fp = ctypes.POINTER(ctypes.c_float)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -74,8 +74,10 @@ def _setup(lib):
     lib.ws_gradient.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _fp, _fp]
     lib.ws_predict.argtypes = [_vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp]
     lib.ws_trajectory.argtypes = [_vp, _vp, _vp]
+    lib.ws_trajectory_mfma.argtypes = [_vp, _vp, _vp]
     for n in ("ws_create", "ws_set_params", "ws_get_params", "ws_set_normalization", "ws_set_tracks",
-              "ws_windows", "ws_labels", "ws_train_step", "ws_gradient", "ws_predict", "ws_trajectory"):
+              "ws_windows", "ws_labels", "ws_train_step", "ws_gradient", "ws_predict", "ws_trajectory",
+              "ws_trajectory_mfma"):
         getattr(lib, n).restype = ctypes.c_int
     lib.ws_last_error.argtypes = [_vp]
     lib.ws_last_error.restype = ctypes.c_char_p
@@ -192,8 +194,11 @@ class WarmStartNet:
     def predict(self, x_ptr: int, n_data: int, idx_ptr: int, n: int, states_ptr: int) -> None:
         self._check(_lib.ws_predict(self.h, _vp(x_ptr), n_data, _vp(idx_ptr), n, _vp(states_ptr)))
 
-    def trajectory(self, y_ptr: int, mean_ptr: int) -> None:
-        self._check(_lib.ws_trajectory(self.h, _vp(y_ptr), _vp(mean_ptr)))
+    def trajectory(self, y_ptr: int, mean_ptr: int, mfma: bool = False) -> None:
+        """Initial trajectory of the planned tracks; mfma: BF16 products on the
+        matrix cores (ws_trajectory_mfma) instead of the FP32 evaluation."""
+        fn = _lib.ws_trajectory_mfma if mfma else _lib.ws_trajectory
+        self._check(fn(self.h, _vp(y_ptr), _vp(mean_ptr)))
 
     def close(self):
         if getattr(self, "h", None):
@@ -226,7 +231,8 @@ def _torch():
 
 def smooth_until_converged(pb: wl.Problem, stream: int, lin: str = "taylor", max_iter: int = 50,
                            tol: float = 1e-6, net: Optional["WarmStartNet"] = None, d_y=None, cov_const=None,
-                           keep_mean: bool = True, schedule=(0, 0), freeze: bool = False) -> dict:
+                           keep_mean: bool = True, schedule=(0, 0), freeze: bool = False,
+                           mfma: bool = False) -> dict:
     """Runs the smoother on a batch until every track's trajectory change has
     been below tol once, or max_iter iterations (smoother_iterate_until).
     With ``net`` the first trajectory comes from the network (measurements d_y
@@ -245,7 +251,7 @@ def smooth_until_converged(pb: wl.Problem, stream: int, lin: str = "taylor", max
     mean0 = None
     if net is not None:
         mean0 = torch.empty((S, pb.nx), dtype=torch.float64, device="cuda")
-        net.trajectory(d_y.data_ptr(), mean0.data_ptr())
+        net.trajectory(d_y.data_ptr(), mean0.data_ptr(), mfma=mfma)
         sm.set_trajectory_device(mean0.data_ptr(), 0, cov_const)
     run, first, finite = sm.iterate_until(tol, max_iter)
     wall = time.perf_counter() - start
@@ -390,14 +396,16 @@ def load(path: str, stream: Optional[int] = None, max_batch: Optional[int] = Non
 
 
 def time_to_converge(net: WarmStartNet, cov: np.ndarray, pb: wl.Problem, lin: str = "taylor",
-                     max_iter: int = 50, tol: float = 1e-6, repeats: int = 1, schedule=(0, 0)) -> dict:
+                     max_iter: int = 50, tol: float = 1e-6, repeats: int = 1, schedule=(0, 0),
+                     mfma: bool = False) -> dict:
     """Plain (prior broadcast) vs learned first trajectory on the same tracks.
 
     A first run of each start gives the iterations per track to reach tol
     (max_iter + 1 = not converged) and the converged means; ``ms_to_converge``
     is then the best of ``repeats`` timed runs capped at the iteration where
     the last converging track converged (the learned runs include the
-    network's inference and the hand-over of its trajectory), and
+    network's inference -- FP32, or with ``mfma`` BF16 products on the matrix
+    cores -- and the hand-over of its trajectory), and
     ``ms_to_converge_freeze`` the same with every converged track taken out
     of the later iterations (sm_problem.freeze_converged).  The distance of
     the learned run's converged means to the plain run's is reported per track
@@ -407,7 +415,7 @@ def time_to_converge(net: WarmStartNet, cov: np.ndarray, pb: wl.Problem, lin: st
     d_y = torch.from_numpy(np.ascontiguousarray(pb.y)).cuda()
     net.set_tracks(pb.offsets)
     res = {}
-    for name, kw in (("plain", {}), ("learned", {"net": net, "d_y": d_y, "cov_const": cov})):
+    for name, kw in (("plain", {}), ("learned", {"net": net, "d_y": d_y, "cov_const": cov, "mfma": mfma})):
         kw["schedule"] = schedule
         r = smooth_until_converged(pb, stream, lin, max_iter, tol, **kw)
         conv = r["iters"] <= max_iter

@@ -240,3 +240,57 @@ def test_training_gains_over_prior_start(W):
     assert r["distance_to_plain"]["tracks_within_1e-4"] >= 0.9
     net.close()
     torch.cuda.synchronize()
+
+
+def test_mfma_trajectory_matches_oracle(W):
+    """The inference form of the network (ws_trajectory_mfma: BF16 operands on
+    the matrix cores, FP32 accumulation) with the trained weights on 16
+    held-out tracks, against the oracle's forward with every weight and layer
+    input rounded to bfloat16 (products and sums in FP64).
+
+    The kernel rounds FP32 activations, the oracle FP64 ones, so an operand
+    that lies within an FP32 ulp of a bfloat16 rounding boundary can round the
+    other way: that moves a few outputs by up to about 1e-2 sigma (about 1 in
+    1000 outputs by more than 1e-3 sigma), and the mean by a few 1e-6 sigma.
+    Gates: mean below 5e-5 sigma, max below 5e-2 sigma, at most 1% of outputs
+    beyond 1e-3 sigma.  A wrong operand or result layout moves outputs by
+    order one; BF16 rounding itself (the FP64 forward against the rounded one)
+    moves them by 6e-3 sigma on average and 0.1 sigma at most, which the test
+    prints.  The smoother started from either trajectory needs about the same
+    iterations."""
+    import os
+    import torch
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = os.path.join(root, "paper_2102_00514_amd", "weights", "warmstart_ieks.npz")
+    net, cov, _ = W.load(path, stream=torch.cuda.current_stream().cuda_stream)
+    with np.load(path) as z:
+        mu = np.asarray(z["mu"], dtype=np.float64)
+        sigma = np.asarray(z["sigma"], dtype=np.float64)
+    cfgd = onn.DEFAULT
+    pb = wl.config_c4(0, 16, held_out=True)
+    dy = _dev(pb.y)
+    net.set_tracks(pb.offsets)
+    t16 = torch.empty((pb.n_slots, pb.nx), dtype=torch.float64, device="cuda")
+    net.trajectory(dy.data_ptr(), t16.data_ptr(), mfma=True)
+    torch.cuda.synchronize()
+    got = t16.cpu().numpy()
+    x = onn.features(pb.y, pb.offsets, cfgd)
+    theta = net.params().astype(np.float64)
+
+    def traj(rnd):
+        out, _ = onn.forward(theta, x, cfgd, operand_round=rnd)
+        return onn.trajectory(onn.outputs_to_states(out, mu, sigma, cfgd), pb.offsets, cfgd)
+
+    ref16, ref64 = traj(onn.bf16_round), traj(None)
+    d = np.abs(got - ref16) / sigma
+    q = np.abs(ref16 - ref64) / sigma
+    print(f"mfma vs BF16-operand oracle: max {d.max():.3e}, mean {d.mean():.3e}, beyond 1e-3: {np.mean(d > 1e-3):.2e}; "
+          f"BF16 rounding itself: max {q.max():.3e}, mean {q.mean():.3e} (units of sigma)", flush=True)
+    assert np.all(np.isfinite(got))
+    assert d.mean() < 5e-5 and d.max() < 5e-2 and np.mean(d > 1e-3) < 1e-2
+    r32 = W.time_to_converge(net, cov, pb, "taylor")
+    r16 = W.time_to_converge(net, cov, pb, "taylor", mfma=True)
+    print(f"iterations: fp32 start {r32['learned']['iters_mean']:.2f}, mfma start {r16['learned']['iters_mean']:.2f}",
+          flush=True)
+    assert abs(r16["learned"]["iters_mean"] - r32["learned"]["iters_mean"]) <= 1.0
+    net.close()

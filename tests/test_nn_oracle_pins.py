@@ -159,3 +159,53 @@ def test_output_state_maps_are_inverse():
     np.testing.assert_allclose(nn.outputs_to_states(o, mu, sigma), st, rtol=1e-14, atol=1e-14)
     # head channel q = u * nx + i at patch j is step P j + u, state i
     assert o[1, 2 * 5 + 3, 5] == pytest.approx((st[1, 4 * 5 + 2, 3] - mu[3]) / sigma[3])
+
+
+def test_bf16_round_matches_torch():
+    """bf16_round against torch's float32 -> bfloat16 conversion (round to
+    nearest, ties to even), over many magnitudes and on exact ties."""
+    import torch
+    rng = np.random.default_rng(11)
+    v = (rng.standard_normal(20000) * 10.0 ** rng.uniform(-30, 30, 20000)).astype(np.float32)
+    # exact ties: the dropped half is 0x8000, with the kept part even and odd
+    kept = rng.integers(0x3F00, 0x4300, 400, dtype=np.uint32) << 16
+    ties = (kept | 0x8000).view(np.float32)
+    v = np.concatenate([v, ties, -ties, np.float32([0.0, -0.0, 1.0, 65504.0, 3.0e38])])
+    want = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    got = nn.bf16_round(v)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+    # a tie goes to the even neighbour, so half of them round up
+    up = nn.bf16_round(ties) > ties
+    assert 0.3 < up.mean() < 0.7
+
+
+def test_bf16_forward_matches_torch_conv1d():
+    """The BF16-operand forward against torch's conv1d with every weight and
+    every layer input rounded by torch's own bfloat16 conversion."""
+    import torch
+    import torch.nn.functional as F
+    cfg = SMALL
+    rng = np.random.default_rng(12)
+    theta = nn.init_params(rng, cfg, dtype=np.float64)
+    theta[-cfg["patch"] * cfg["nx"]:] = rng.standard_normal(cfg["patch"] * cfg["nx"])
+    x = rng.uniform(-1, 1, (5, 2 * cfg["ny"], cfg["window"]))
+
+    def rb(t):
+        return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    layers = [(torch.from_numpy(np.ascontiguousarray(w, dtype=np.float64)),
+               torch.from_numpy(np.ascontiguousarray(b, dtype=np.float64)))
+              for w, b in nn.unpack(theta, cfg)]
+    W0, b0 = layers[0]
+    h = torch.relu(F.conv1d(rb(torch.from_numpy(x)), rb(W0), b0, stride=cfg["patch"]))
+    for l in range(1, cfg["hidden"] + 1):
+        d = 2 ** (l - 1)
+        Wl, bl = layers[l]
+        h = h + torch.relu(F.conv1d(rb(h), rb(Wl), bl, padding=d, dilation=d))
+    WH, bH = layers[-1]
+    want = F.conv1d(rb(h), rb(WH)[:, :, None], bH).numpy()
+    got, _ = nn.forward(theta, x, cfg, operand_round=nn.bf16_round)
+    assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want))
+    # and it is not the FP64 forward
+    exact, _ = nn.forward(theta, x, cfg)
+    assert np.max(np.abs(got - exact)) > 1e-4 * np.max(np.abs(exact))
