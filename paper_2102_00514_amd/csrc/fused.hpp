@@ -414,7 +414,7 @@ __global__ __launch_bounds__(B) void k_forward_up(FusedArgs a) {
   }
   typename Op::Elem ex;
   bool has_ex;
-  block_ladder<Op, B, true, R>(lds, acc, ex, has_ex);
+  block_ladder<Op, B, true, R>(lds, acc, ex, has_ex, true, a.K > 1);
   // K = 1: the lane's inclusive prefix goes to the down-sweep, which then
   // needs neither the element nor a second carry application; K > 1: the
   // exclusive prefix, continued there over the rebuilt elements
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(B) void k_forward_down_backward_up(FusedArgs a) {
       });
   typename SOp::Elem ex;
   bool has_ex;
-  block_ladder<SOp, B, false, R>(lds, sacc, ex, has_ex);
+  block_ladder<SOp, B, false, R>(lds, sacc, ex, has_ex, true, a.K > 1);
   // as in the forward direction: inclusive prefix for K = 1, exclusive otherwise
   if (a.K == 1) SOp::store(static_cast<R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, sacc);
   else if (has_ex) SOp::store(static_cast<R*>(a.lx_s), size_t(a.tiles) * B, rt * B + rl, ex);

@@ -88,16 +88,18 @@ struct FilterOp {
     st_vec<N>(p, st, i, c.b);
     st_sym<N>(p + N * st, st, i, c.C);
   }
-  // o = e of lane src of this wavefront; every lane must take part.  The
-  // symmetric blocks move their upper triangles only.
-  static PKS_DEV void shfl(const Elem& e, int src, Elem& o) {
+  // o = mv applied to every word of e: a lane move of the wavefront ladder,
+  // in which every lane must take part.  The symmetric blocks move their
+  // upper triangles only.
+  template <class Mv>
+  static PKS_DEV void move(const Elem& e, const Mv& mv, Elem& o) {
     PKS_UNROLL for (int i = 0; i < N; ++i) {
-      o.b[i] = __shfl(e.b[i], src);
-      o.eta[i] = __shfl(e.eta[i], src);
-      PKS_UNROLL for (int j = 0; j < N; ++j) o.A[i][j] = __shfl(e.A[i][j], src);
+      o.b[i] = mv(e.b[i]);
+      o.eta[i] = mv(e.eta[i]);
+      PKS_UNROLL for (int j = 0; j < N; ++j) o.A[i][j] = mv(e.A[i][j]);
       PKS_UNROLL for (int j = i; j < N; ++j) {
-        o.C[i][j] = o.C[j][i] = __shfl(e.C[i][j], src);
-        o.J[i][j] = o.J[j][i] = __shfl(e.J[i][j], src);
+        o.C[i][j] = o.C[j][i] = mv(e.C[i][j]);
+        o.J[i][j] = o.J[j][i] = mv(e.J[i][j]);
       }
     }
   }
@@ -266,11 +268,12 @@ struct SmootherOp {
     st_vec<N>(p, st, i, c.g);
     st_sym<N>(p + N * st, st, i, c.L);
   }
-  static PKS_DEV void shfl(const Elem& e, int src, Elem& o) {
+  template <class Mv>
+  static PKS_DEV void move(const Elem& e, const Mv& mv, Elem& o) {
     PKS_UNROLL for (int i = 0; i < N; ++i) {
-      o.g[i] = __shfl(e.g[i], src);
-      PKS_UNROLL for (int j = 0; j < N; ++j) o.E[i][j] = __shfl(e.E[i][j], src);
-      PKS_UNROLL for (int j = i; j < N; ++j) o.L[i][j] = o.L[j][i] = __shfl(e.L[i][j], src);
+      o.g[i] = mv(e.g[i]);
+      PKS_UNROLL for (int j = 0; j < N; ++j) o.E[i][j] = mv(e.E[i][j]);
+      PKS_UNROLL for (int j = i; j < N; ++j) o.L[i][j] = o.L[j][i] = mv(e.L[i][j]);
     }
   }
   static PKS_DEV void to_carry(const Elem& e, Carry& c) {

@@ -35,28 +35,104 @@ struct ScanArgs {
   size_t ostride;
 };
 
+// Lane moves of the wavefront ladder.  An element crosses lanes as its words
+// do, each 64-bit word as two 32-bit halves; DPP moves run on the VALU of the
+// wavefront's own SIMD, where a shuffle through the LDS crossbar would share
+// the compute unit's LDS bandwidth with the other wavefronts of the block.
+template <int CTRL, int ROWMASK>
+struct DppMove {
+  // lanes without a source read 0 and lanes of rows outside ROWMASK keep an
+  // undefined value: neither is ever combined
+  PKS_DEV static int mv32(int x) { return __builtin_amdgcn_mov_dpp(x, CTRL, ROWMASK, 0xf, true); }
+  PKS_DEV double operator()(double x) const {
+    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(x));
+    const unsigned lo = static_cast<unsigned>(mv32(static_cast<int>(static_cast<unsigned>(u))));
+    const unsigned hi = static_cast<unsigned>(mv32(static_cast<int>(static_cast<unsigned>(u >> 32))));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+  }
+  PKS_DEV float operator()(float x) const { return __int_as_float(mv32(__float_as_int(x))); }
+};
+
+// The value of lane hi_src in lanes of rows 2 and 3, of lane lo_src in rows 0
+// and 1 (v_readlane: a wavefront-uniform read of one lane).
+struct LanePick {
+  int upper;   // this lane is in rows 2 or 3
+  int lo_src, hi_src;
+  PKS_DEV static int rd(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+  PKS_DEV float operator()(float x) const {
+    const int xi = __float_as_int(x);
+    const int a = rd(xi, lo_src), b = rd(xi, hi_src);
+    return __int_as_float(upper ? b : a);
+  }
+  PKS_DEV double operator()(double x) const {
+    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(x));
+    const int lo = static_cast<int>(static_cast<unsigned>(u)), hi = static_cast<int>(static_cast<unsigned>(u >> 32));
+    const unsigned a0 = static_cast<unsigned>(rd(lo, lo_src)), a1 = static_cast<unsigned>(rd(hi, lo_src));
+    const unsigned b0 = static_cast<unsigned>(rd(lo, hi_src)), b1 = static_cast<unsigned>(rd(hi, hi_src));
+    const unsigned long long r = upper ? ((static_cast<unsigned long long>(b1) << 32) | b0)
+                                       : ((static_cast<unsigned long long>(a1) << 32) | a0);
+    return __longlong_as_double(static_cast<long long>(r));
+  }
+};
+
+// One Kogge-Stone step of the wavefront ladder: left = the element of the
+// lane before this one at the step's distance, in scan order.  The wavefront
+// is four rows of 16 lanes.  Steps 0-3 scan each row (distance 1, 2, 4, 8
+// inside the row: DPP row shifts); step 4 hands the total of rows 0 and 2 to
+// rows 1 and 3, step 5 the running total of rows 0-1 to rows 2 and 3 (forward:
+// DPP row broadcasts; reverse, where rows run 3, 2, 1, 0: the totals of rows 3
+// and 1 to rows 2 and 0, then rows 3-2 to rows 1 and 0, by lane reads).
+// Returns whether this lane combines at the step.
+template <class Op, bool FWD>
+PKS_DEV bool ladder_step(int s, int wl, const typename Op::Elem& v, typename Op::Elem& left) {
+  const int in_row = FWD ? (wl & 15) : 15 - (wl & 15);   // scan position inside the row
+  const int row = wl >> 4;
+  const int qrow = FWD ? row : 3 - row;                    // scan position of the row
+  if constexpr (FWD) {
+    switch (s) {
+      case 0: Op::move(v, DppMove<0x111, 0xf>{}, left); break;   // row_shr:1
+      case 1: Op::move(v, DppMove<0x112, 0xf>{}, left); break;   // row_shr:2
+      case 2: Op::move(v, DppMove<0x114, 0xf>{}, left); break;   // row_shr:4
+      case 3: Op::move(v, DppMove<0x118, 0xf>{}, left); break;   // row_shr:8
+      case 4: Op::move(v, DppMove<0x142, 0xa>{}, left); break;   // row_bcast:15 into rows 1, 3
+      default: Op::move(v, DppMove<0x143, 0xc>{}, left); break;  // row_bcast:31 into rows 2, 3
+    }
+  } else {
+    switch (s) {
+      case 0: Op::move(v, DppMove<0x101, 0xf>{}, left); break;   // row_shl:1
+      case 1: Op::move(v, DppMove<0x102, 0xf>{}, left); break;   // row_shl:2
+      case 2: Op::move(v, DppMove<0x104, 0xf>{}, left); break;   // row_shl:4
+      case 3: Op::move(v, DppMove<0x108, 0xf>{}, left); break;   // row_shl:8
+      case 4: Op::move(v, LanePick{row >= 2, 16, 48}, left); break;
+      default: Op::move(v, LanePick{row >= 2, 32, 32}, left); break;
+    }
+  }
+  if (s < 4) return in_row >= (1 << s);
+  return s == 4 ? (qrow & 1) != 0 : qrow >= 2;
+}
+
 // Inclusive scan of the B lane values of a block.  Scan position q = lane
-// (FWD) or B-1-lane (reverse).  Inside a wavefront the Kogge-Stone steps move
-// elements with cross-lane shuffles (no LDS, no barriers); across wavefronts
-// (B > 64) only each wavefront's total goes through LDS: lds holds B/64
-// elements, entry-major with row stride B/64.  On exit v is the inclusive
-// prefix at q and, when has_ex (q > 0), ex the exclusive one.  Invalid lanes
-// must form a suffix of the scan order: no valid lane reads their values.  A
-// wavefront whose lanes are all invalid passes active = false (wavefront-
-// uniform): it skips its combines and only takes part in the barrier.
+// (FWD) or B-1-lane (reverse).  Inside a wavefront the six Kogge-Stone steps
+// of ladder_step move elements between lanes without LDS or barriers; across
+// wavefronts (B > 64) only each wavefront's total goes through LDS: lds holds
+// B/64 elements, entry-major with row stride B/64.  On exit v is the inclusive
+// prefix at q and, when want_ex and has_ex (q > 0), ex the exclusive one.
+// Invalid lanes must form a suffix of the scan order: no valid lane reads
+// their values.  A wavefront whose lanes are all invalid passes active =
+// false (wavefront-uniform): it skips its combines and only takes part in the
+// barrier.
 template <class Op, int B, bool FWD, typename R>
-PKS_DEV void block_ladder(R* lds, typename Op::Elem& v, typename Op::Elem& ex, bool& has_ex, bool active = true) {
+PKS_DEV void block_ladder(R* lds, typename Op::Elem& v, typename Op::Elem& ex, bool& has_ex, bool active = true,
+                          bool want_ex = true) {
   constexpr int NW = B / 64;
   static_assert(B % 64 == 0, "whole wavefronts");
   const int pl = int(threadIdx.x), wl = pl & 63, w = pl >> 6;
   const int qw = FWD ? wl : 63 - wl;        // scan position inside the wavefront
   const int qwave = FWD ? w : NW - 1 - w;   // scan position of the wavefront
   if (active) {
-    auto step = [&](int d) {
+    auto step = [&](int s) {
       typename Op::Elem left;
-      const int src = FWD ? (wl >= d ? wl - d : wl) : (wl + d < 64 ? wl + d : wl);
-      Op::shfl(v, src, left);
-      if (qw >= d) {
+      if (ladder_step<Op, FWD>(s, wl, v, left)) {
         typename Op::Elem r;
         Op::combine(left, v, r);
         v = r;
@@ -65,9 +141,9 @@ PKS_DEV void block_ladder(R* lds, typename Op::Elem& v, typename Op::Elem& ex, b
     if constexpr (Op::kCompact) {
       // one copy of a long operator instead of six
 #pragma unroll 1
-      for (int d = 1; d < 64; d <<= 1) step(d);
+      for (int s = 0; s < 6; ++s) step(s);
     } else {
-      PKS_UNROLL for (int d = 1; d < 64; d <<= 1) step(d);
+      PKS_UNROLL for (int s = 0; s < 6; ++s) step(s);
     }
   }
   typename Op::Elem wp;   // total of the wavefronts before this one (qwave > 0)
@@ -88,9 +164,10 @@ PKS_DEV void block_ladder(R* lds, typename Op::Elem& v, typename Op::Elem& ex, b
     }
   }
   has_ex = false;
-  if (!active) return;
-  const int src = FWD ? (wl > 0 ? wl - 1 : wl) : (wl < 63 ? wl + 1 : wl);
-  Op::shfl(v, src, ex);
+  if (!active || !want_ex) return;
+  // the previous lane's inclusive prefix: wave_shr:1 / wave_shl:1
+  if constexpr (FWD) Op::move(v, DppMove<0x138, 0xf>{}, ex);
+  else Op::move(v, DppMove<0x130, 0xf>{}, ex);
   has_ex = qw > 0;
   if constexpr (NW > 1) {
     if (qw == 0 && qwave > 0) {
@@ -206,7 +283,7 @@ PKS_DEV void block_scan(R* lds, int lane, const R* E, size_t estride, int64_t m,
   }
   typename Op::Elem ex;
   bool has_ex;
-  block_ladder<Op, B, true, R>(lds, v, ex, has_ex, int64_t(lane & ~63) * K < m);
+  block_ladder<Op, B, true, R>(lds, v, ex, has_ex, int64_t(lane & ~63) * K < m, K > 1);
   if (!valid) return;
   if (K == 1) {
     // v is the inclusive prefix of this lane's position, and it starts at a

@@ -145,10 +145,10 @@ PKS_DEV void st_tril(R* __restrict__ base, size_t stride, size_t s, const R (&L)
     PKS_UNROLL for (int j = 0; j <= i; ++j) base[sym_index<N>(j, i) * stride + s] = L[i][j];
 }
 
-template <int N, typename R>
-PKS_DEV void shfl_tril(const R (&L)[N][N], int src, R (&O)[N][N]) {
+template <int N, typename R, class Mv>
+PKS_DEV void move_tril(const R (&L)[N][N], const Mv& mv, R (&O)[N][N]) {
   PKS_UNROLL for (int i = 0; i < N; ++i)
-    PKS_UNROLL for (int j = 0; j < N; ++j) O[i][j] = j <= i ? __shfl(L[i][j], src) : R(0);
+    PKS_UNROLL for (int j = 0; j < N; ++j) O[i][j] = j <= i ? mv(L[i][j]) : R(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -195,14 +195,15 @@ struct SqrtFilterOp {
     st_vec<N>(p, st, i, c.b);
     st_tril<N>(p + N * st, st, i, c.U);
   }
-  static PKS_DEV void shfl(const Elem& e, int src, Elem& o) {
+  template <class Mv>
+  static PKS_DEV void move(const Elem& e, const Mv& mv, Elem& o) {
     PKS_UNROLL for (int i = 0; i < N; ++i) {
-      o.b[i] = __shfl(e.b[i], src);
-      o.eta[i] = __shfl(e.eta[i], src);
-      PKS_UNROLL for (int j = 0; j < N; ++j) o.A[i][j] = __shfl(e.A[i][j], src);
+      o.b[i] = mv(e.b[i]);
+      o.eta[i] = mv(e.eta[i]);
+      PKS_UNROLL for (int j = 0; j < N; ++j) o.A[i][j] = mv(e.A[i][j]);
     }
-    shfl_tril<N>(e.U, src, o.U);
-    shfl_tril<N>(e.Z, src, o.Z);
+    move_tril<N>(e.U, mv, o.U);
+    move_tril<N>(e.Z, mv, o.Z);
   }
   static PKS_DEV void to_carry(const Elem& e, Carry& c) {
     PKS_UNROLL for (int i = 0; i < N; ++i) {
@@ -394,12 +395,13 @@ struct SqrtSmootherOp {
     st_vec<N>(p, st, i, c.g);
     st_tril<N>(p + N * st, st, i, c.D);
   }
-  static PKS_DEV void shfl(const Elem& e, int src, Elem& o) {
+  template <class Mv>
+  static PKS_DEV void move(const Elem& e, const Mv& mv, Elem& o) {
     PKS_UNROLL for (int i = 0; i < N; ++i) {
-      o.g[i] = __shfl(e.g[i], src);
-      PKS_UNROLL for (int j = 0; j < N; ++j) o.E[i][j] = __shfl(e.E[i][j], src);
+      o.g[i] = mv(e.g[i]);
+      PKS_UNROLL for (int j = 0; j < N; ++j) o.E[i][j] = mv(e.E[i][j]);
     }
-    shfl_tril<N>(e.D, src, o.D);
+    move_tril<N>(e.D, mv, o.D);
   }
   static PKS_DEV void to_carry(const Elem& e, Carry& c) {
     PKS_UNROLL for (int i = 0; i < N; ++i) {
