@@ -99,7 +99,10 @@ typedef enum { SM_SCAN_PARALLEL = 0, SM_SCAN_SEQUENTIAL = 1 } sm_scan;
  * rewritten on the factors (new factors from LQ decompositions, no
  * covariance is formed and re-factorised, no difference of covariances is
  * taken); algebraically the same results, in more arithmetic.  Outputs are
- * covariances in both forms. */
+ * covariances in both forms.  Eq. 15 needs I + C_i J_j invertible, not C_i
+ * positive definite: the factor form takes a positive semi-definite Q, whose
+ * zero-variance directions become zero columns of the factor of Q', while
+ * the covariance form factorises C_i and needs Q positive definite. */
 typedef enum { SM_FORM_COVARIANCE = 0, SM_FORM_SQRT = 1 } sm_form;
 
 typedef struct {
@@ -109,7 +112,9 @@ typedef struct {
   int32_t model;                  /* sm_model */
   const double* params;           /* host [n_params], see sm_model */
   int32_t n_params;
-  const double* Q;                /* host [nx*nx], symmetric positive definite */
+  const double* Q;                /* host [nx*nx], symmetric positive definite; with
+                                     SM_FORM_SQRT positive semi-definite (a state component
+                                     without process noise; the MAP objective then refuses) */
   const double* R;                /* host [ny*ny], symmetric positive definite */
   const double* m0;               /* host [n_tracks*nx] */
   const double* P0;               /* host [n_tracks*nx*nx], each symmetric positive definite */
@@ -224,7 +229,8 @@ sm_status smoother_filter(smoother_t h, double* filt_mean, double* filt_cov, dou
  * bearing residuals y_k - h(x_k) taken modulo 2 pi in [-pi, pi).  Waits for
  * the handle's stream; track_cost is host [n_tracks].  Evaluated in the
  * handle's precision per slot and summed per track in double, in a fixed
- * order.  SM_EINVAL for a NULL track_cost. */
+ * order.  SM_EINVAL for a NULL track_cost, or when Q is not positive definite
+ * (the process residuals are weighed by Q^-1). */
 sm_status smoother_objective(smoother_t h, double* track_cost);
 
 /* Levenberg-Marquardt iterations (Section 3, the damped Gauss-Newton

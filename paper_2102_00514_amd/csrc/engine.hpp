@@ -17,6 +17,7 @@
 // cross -- A, eta, J of a filtering prefix -- never reach the outputs).
 #pragma once
 
+#include <limits>
 #include <memory>
 
 #include "engine_base.hpp"
@@ -147,7 +148,12 @@ class Engine final : public EngineBase {
     // whitening matrices of Q, R and each P0 for the MAP objective
     std::vector<double> w(size_t(N) * N);
     std::vector<R> wq(size_t(N) * N), wr(size_t(P) * P), wp0(size_t(ntracks) * N * N);
-    if (!whitening(pb.Q, N, w.data())) return fail(SM_EINVAL, "Q is not positive definite");
+    if (!whitening(pb.Q, N, w.data())) {
+      if (pb.form != SM_FORM_SQRT) return fail(SM_EINVAL, "Q is not positive definite");
+      // a positive semi-definite Q (factor form): the MAP objective, the only
+      // user of this whitening, is refused for it
+      std::fill(w.begin(), w.end(), std::numeric_limits<double>::quiet_NaN());
+    }
     std::copy(w.begin(), w.end(), wq.begin());
     w.resize(size_t(P) * P);
     if (!whitening(pb.R, P, w.data())) return fail(SM_EINVAL, "R is not positive definite");

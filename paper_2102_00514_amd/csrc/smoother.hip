@@ -52,6 +52,41 @@ static bool host_spd(const double* A, int n, double* worst_asym = nullptr) {
   return true;
 }
 
+// Symmetric positive semi-definite: a Cholesky factorisation in which a pivot
+// at or below 1e-12 times the largest diagonal entry is a direction without
+// variance.  Its remaining column must then vanish up to what such a pivot
+// allows (at most sqrt(1e-12) times the largest diagonal entry, with a
+// margin): [[0, 1], [1, 1]] is rejected.
+static bool host_psd(const double* A, int n) {
+  std::vector<double> L(size_t(n) * n, 0.0);
+  double scale = 0.0, dmax = 0.0;
+  for (int i = 0; i < n * n; ++i) {
+    if (!std::isfinite(A[i])) return false;
+    scale = std::max(scale, std::fabs(A[i]));
+  }
+  for (int i = 0; i < n; ++i) {
+    dmax = std::max(dmax, A[i * n + i]);
+    for (int j = i + 1; j < n; ++j)
+      if (std::fabs(A[i * n + j] - A[j * n + i]) > 1e-9 * std::max(scale, 1e-300)) return false;
+  }
+  const double tiny = 1e-12 * dmax;
+  for (int j = 0; j < n; ++j) {
+    double s = A[j * n + j];
+    for (int t = 0; t < j; ++t) s -= L[j * n + t] * L[j * n + t];
+    if (s < -tiny) return false;
+    const bool live = s > tiny;
+    const double d = live ? std::sqrt(s) : 0.0;
+    L[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[i * n + j];
+      for (int t = 0; t < j; ++t) v -= L[i * n + t] * L[j * n + t];
+      if (!live && std::fabs(v) > 2e-6 * dmax) return false;
+      L[i * n + j] = live ? v / d : 0.0;
+    }
+  }
+  return true;
+}
+
 static bool all_finite(const double* p, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -137,7 +172,10 @@ static std::string validate(const sm_problem* pb) {
   }
   if (!all_finite(pb->params, size_t(pb->n_params))) return "params must be finite";
   if (!pb->Q || !pb->R || !pb->m0 || !pb->P0 || !pb->y) return "Q, R, m0, P0 and y must not be NULL";
-  if (!host_spd(pb->Q, n)) return "Q must be symmetric positive definite";
+  if (pb->form == SM_FORM_SQRT ? !host_psd(pb->Q, n) : !host_spd(pb->Q, n))
+    return pb->form == SM_FORM_SQRT ? "Q must be symmetric positive semi-definite"
+                                    : "Q must be symmetric positive definite (the square-root form takes a "
+                                      "positive semi-definite Q)";
   if (!host_spd(pb->R, p)) return "R must be symmetric positive definite";
   if (!all_finite(pb->m0, size_t(pb->n_tracks) * n)) return "m0 must be finite";
   for (int t = 0; t < pb->n_tracks; ++t)
@@ -235,6 +273,7 @@ struct smoother {
   int nx = 0;
   int precision = SM_FP64;
   bool blocks = false;    // stacked targets run as separate blocks
+  bool q_definite = true; // Q positive definite (the MAP objective needs Q^-1)
 };
 
 using pks::g_init_error;
@@ -282,6 +321,7 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
     h->eng = std::move(eng);
     h->nx = pb->nx;
     h->precision = pb->precision;
+    h->q_definite = pks::host_spd(pb->Q, pb->nx);
     h->blocks = pks::stacked(pb->model, pb->nx) && pb->lin == SM_LIN_TAYLOR;
     *out = h;
     g_init_error.clear();
@@ -457,6 +497,10 @@ sm_status smoother_objective(smoother_t h, double* track_cost) {
   if (!h || !h->eng) return SM_ESTATE;
   if (!track_cost) {
     h->err = "track_cost is NULL";
+    return SM_EINVAL;
+  }
+  if (!h->q_definite) {
+    h->err = "the MAP objective weighs the process residuals by Q^-1: it needs a positive definite Q";
     return SM_EINVAL;
   }
   try {

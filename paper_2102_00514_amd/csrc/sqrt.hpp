@@ -120,6 +120,37 @@ PKS_DEV bool chol_lower(const R (&A)[N][N], R (&L)[N][N]) {
   return ok;
 }
 
+// Lower-triangular factor L L^T = A of a symmetric positive semi-definite A
+// (a transition covariance Q' with a noise-free state component).  A pivot at
+// or below 64 eps times the largest diagonal entry is a direction without
+// variance: its column is set to zero, which tria and the operators on
+// factors accept (eq. 15 needs I + C_i J_j invertible, not C_i definite).
+// For a well-conditioned positive definite A no pivot is that small and the
+// result is chol_lower's.  Returns false if a pivot is below minus that bound
+// or not finite.
+template <int N, typename R>
+PKS_DEV bool chol_lower_psd(const R (&A)[N][N], R (&L)[N][N]) {
+  constexpr R kEps = sizeof(R) == 8 ? R(2.220446049250313e-16) : R(1.1920929e-7);
+  R dmax = R(0);
+  PKS_UNROLL for (int i = 0; i < N; ++i) dmax = A[i][i] > dmax ? A[i][i] : dmax;
+  const R tiny = R(64) * kEps * dmax;
+  bool ok = true;
+  PKS_UNROLL for (int j = 0; j < N; ++j) {
+    R s = A[j][j];
+    PKS_UNROLL for (int t = 0; t < j; ++t) s -= L[j][t] * L[j][t];
+    ok = ok && (s >= -tiny);   // false for NaN
+    const R inv = s > tiny ? rsqrt_nr(s) : R(0);
+    L[j][j] = s * inv;
+    PKS_UNROLL for (int i = j + 1; i < N; ++i) {
+      R v = A[i][j];
+      PKS_UNROLL for (int t = 0; t < j; ++t) v -= L[i][t] * L[j][t];
+      L[i][j] = v * inv;
+    }
+    PKS_UNROLL for (int i = 0; i < j; ++i) L[i][j] = R(0);
+  }
+  return ok;
+}
+
 // P = L L^T (symmetric), L lower triangular.
 template <int N, typename R>
 PKS_DEV void tril_gram(const R (&L)[N][N], R (&P)[N][N]) {
@@ -464,14 +495,15 @@ struct SqrtSmootherOp {
 // where S1 S1^T = S = H Q' H^T + R', K1 = Q' H^T S1^-T and U U^T = Q' - K S K^T
 // = C; the gain is K = K1 S1^-1.  Then A = F - K H F, b = c + K (y - H c - d),
 // and with Y = S1^-1 H F, w = S1^-1 (y - H c - d): J = Y^T Y, eta = Y^T w, so
-// Z = tria([Y^T, 0]).  Returns false if Q' or R' is not positive definite.
+// Z = tria([Y^T, 0]).  Returns false if Q' is not positive semi-definite or
+// R' not positive definite.
 template <int N, int P, typename R>
 PKS_DEV bool sqrt_filter_element(const R (&F)[N][N], const R (&c)[N], const R (&Qp)[N][N], const R (&H)[P][N],
                                  const R (&d)[P], const R (&Rp)[P][P], const R (&y)[P], R (&A)[N][N], R (&b)[N],
                                  R (&U)[N][N], R (&eta)[N], R (&Z)[N][N]) {
   constexpr int M = P + N;
   R Uq[N][N], Ur[P][P];
-  bool ok = chol_lower<N>(Qp, Uq);
+  bool ok = chol_lower_psd<N>(Qp, Uq);
   ok = chol_lower<P>(Rp, Ur) && ok;
   R X[M][M];
   PKS_UNROLL for (int i = 0; i < P; ++i) {
@@ -537,12 +569,12 @@ PKS_DEV bool sqrt_filter_element(const R (&F)[N][N], const R (&c)[N], const R (&
 // gives Phi Phi^T = F P* F^T + Q', G Phi^T = P* F^T and D D^T = P* - G G^T =
 // P* - E F P* = L (the Schur complement, obtained by orthogonal reductions
 // only), so E = G Phi^-1, g = x* - E (F x* + c).  Returns false if Q' is not
-// positive definite.
+// positive semi-definite.
 template <int N, typename R>
 PKS_DEV bool sqrt_smoother_element(const R (&x)[N], const R (&U)[N][N], const R (&F)[N][N], const R (&c)[N],
                                    const R (&Qp)[N][N], R (&E)[N][N], R (&g)[N], R (&D)[N][N]) {
   R Uq[N][N];
-  const bool ok = chol_lower<N>(Qp, Uq);
+  const bool ok = chol_lower_psd<N>(Qp, Uq);
   R X[2 * N][2 * N];
   PKS_UNROLL for (int i = 0; i < N; ++i)
     PKS_UNROLL for (int j = 0; j < N; ++j) {

@@ -205,3 +205,62 @@ def test_rejected_combinations(B):
     with B.Smoother(pb, form="sqrt") as sm:
         with pytest.raises(B.SmootherError, match="covariance form"):
             sm.iterate_lm(1e-2, 10.0, 1e-6, 3)
+
+
+def _noise_free_turn_rate(T):
+    pb = wl.config_c2(T)
+    pb.Q = pb.Q.copy()
+    pb.Q[4, :] = 0.0
+    pb.Q[:, 4] = 0.0          # the turn rate has no process noise: Q is singular
+    return pb
+
+
+@pytest.mark.parametrize("lin", ["taylor", "cubature"])
+def test_noise_free_component(B, lin):
+    """A state component without process noise (Q positive semi-definite).
+    Eq. 15 needs I + C_i J_j invertible, not C_i definite; the factor form
+    carries the zero-variance direction as a zero column of the factor of Q'.
+    FP64 gate as above; FP32 at the FP32 gate."""
+    pb = _noise_free_turn_rate(700)
+    ref = oracle.smoother(pb, 3, lin)
+    for prec, tol in (("f64", TOL64), ("f32", TOL32)):
+        mean, cov, _, _ = run_gpu(B, pb, 3, lin, form="sqrt", precision=prec)
+        em, ep = errors(mean, cov, ref["mean"], ref["cov"])
+        print(f"noise-free turn rate {lin} {prec}: e_m={em:.3e} e_P={ep:.3e}", flush=True)
+        assert em < tol and ep < tol, (prec, em, ep)
+
+
+def test_rank_deficient_process_noise(B):
+    """A linear model whose Q has rank 2 of 5 (no zero row: the zero-variance
+    directions are mixtures of the components), ragged batch of tracks."""
+    pb = wl.linear_gaussian(5, 2, 400, seed=46, n_tracks=5, t_min=1)
+    L = np.random.default_rng(47).standard_normal((5, 2)) * 0.3
+    pb.Q = L @ L.T
+    mean, cov, _, _ = run_gpu(B, pb, 1, "taylor", form="sqrt")
+    so = pb.slot_offsets()
+    for i in range(pb.n_tracks):
+        ref = oracle.smoother(pb.track(i), 1, "taylor")
+        sl = slice(so[i], so[i + 1])
+        em, ep = errors(mean[sl], cov[sl], ref["mean"], ref["cov"])
+        assert em < TOL64 and ep < TOL64, (i, em, ep)
+
+
+def test_noise_free_component_limits(B):
+    """The covariance form factors C_i and rejects a singular Q; the MAP
+    objective weighs process residuals by Q^-1 and refuses one; an indefinite
+    Q is rejected by both forms."""
+    pb = _noise_free_turn_rate(50)
+    with pytest.raises(B.SmootherError, match="positive definite"):
+        B.Smoother(pb)
+    with B.Smoother(pb, form="sqrt") as sm:
+        sm.iterate(1, want_delta=False)
+        with pytest.raises(B.SmootherError, match="positive definite Q"):
+            sm.objective()
+        _, _, ll = sm.filter()
+        assert np.all(np.isfinite(ll))
+    bad = wl.config_c2(50)
+    bad.Q = bad.Q.copy()
+    bad.Q[4, 4] = -1e-4
+    for form in ("covariance", "sqrt"):
+        with pytest.raises(B.SmootherError, match="Q must be symmetric"):
+            B.Smoother(bad, form=form)

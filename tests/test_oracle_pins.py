@@ -647,3 +647,81 @@ def test_reset_by_prior_element(orc):
     _, b1, C1, _, _ = orc.unpack_filter(with_junk, n)
     _, b2, C2, _, _ = orc.unpack_filter(clean, n)
     assert _rel(b1, b2) < 1e-13 and _rel(C1, C2) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------
+# A state component without process noise (Q positive semi-definite, singular).  Eq. 15
+# needs I + C_i J_j invertible, not C_i positive definite, so the model is valid; the
+# oracle's recursion factors only S and F P F^T + Q, which stay positive definite.  Pinned
+# to the posterior of the dense joint Gaussian of (x_0..x_T, y_1..y_T) conditioned on y
+# (covariance form: no inverse of Q anywhere).
+# ---------------------------------------------------------------------------------------
+def _psd_factor(A):
+    w, V = np.linalg.eigh(A)
+    return V * np.sqrt(np.clip(w, 0.0, None))
+
+
+def _conditioned_joint(F, c, Q, H, d, R, m0, P0, y):
+    """Posterior means and covariances of x_0..x_T given y_1..y_T for x_k = F x_{k-1} + c
+    + N(0, Q), y_k = H x_k + d + N(0, R): stack x and y as affine maps of standard normal
+    noise, then condition the joint Gaussian on y."""
+    T, n, p = len(y), len(m0), H.shape[0]
+    ne = (T + 1) * n + T * p
+    mx = np.zeros((T + 1) * n)
+    Ax = np.zeros(((T + 1) * n, ne))
+    mx[:n] = m0
+    Ax[:n, :n] = _psd_factor(P0)
+    Lq, Lr = _psd_factor(Q), _psd_factor(R)
+    my, Ay = np.zeros(T * p), np.zeros((T * p, ne))
+    for k in range(1, T + 1):
+        xs, xp = slice(k * n, (k + 1) * n), slice((k - 1) * n, k * n)
+        mx[xs] = F @ mx[xp] + c
+        Ax[xs] = F @ Ax[xp]
+        Ax[xs, k * n:(k + 1) * n] += Lq
+        ys = slice((k - 1) * p, k * p)
+        my[ys] = H @ mx[xs] + d
+        Ay[ys] = H @ Ax[xs]
+        Ay[ys, (T + 1) * n + (k - 1) * p:(T + 1) * n + k * p] += Lr
+    Sxy, Syy = Ax @ Ay.T, Ay @ Ay.T
+    G = np.linalg.solve(Syy, Sxy.T).T
+    mean = mx + G @ (np.asarray(y).ravel() - my)
+    cov = Ax @ Ax.T - G @ Sxy.T
+    means = mean.reshape(T + 1, n)
+    covs = np.stack([cov[k * n:(k + 1) * n, k * n:(k + 1) * n] for k in range(T + 1)])
+    return means, covs
+
+
+def _linear_blocks(pb):
+    nx, ny, prm = pb.nx, pb.ny, pb.params
+    F = prm[:nx * nx].reshape(nx, nx)
+    c = prm[nx * nx:nx * nx + nx]
+    H = prm[nx * nx + nx:nx * nx + nx + ny * nx].reshape(ny, nx)
+    d = prm[nx * nx + nx + ny * nx:]
+    return F, c, H, d
+
+
+def test_conditioned_joint_equals_dense_least_squares():
+    """The covariance-form reference against the dense least-squares posterior
+    (information form) on a model where both exist (Q positive definite)."""
+    pb = wl.linear_gaussian(4, 2, 15, seed=40)
+    F, c, H, d = _linear_blocks(pb)
+    m_ls, P_ls = ph.dense_linear_posterior(pb)
+    m_cj, P_cj = _conditioned_joint(F, c, pb.Q, H, d, pb.R, pb.m0[0], pb.P0[0], pb.y)
+    assert np.max(np.abs(m_cj - m_ls)) < 1e-10 * np.max(np.abs(m_ls))
+    assert np.max(np.abs(P_cj - P_ls)) < 1e-10 * np.max(np.abs(P_ls))
+
+
+@pytest.mark.parametrize("rank", [1, 2, 3])
+def test_noise_free_component_equals_conditioned_joint(orc, rank):
+    nx, ny, T = 4, 2, 15
+    pb = wl.linear_gaussian(nx, ny, T, seed=40 + rank)
+    rng = np.random.default_rng(41 + rank)
+    L = rng.standard_normal((nx, rank)) * 0.3
+    pb.Q = L @ L.T                               # rank < nx: singular
+    assert np.linalg.matrix_rank(pb.Q) == rank
+    F, c, H, d = _linear_blocks(pb)
+    m_ref, P_ref = _conditioned_joint(F, c, pb.Q, H, d, pb.R, pb.m0[0], pb.P0[0], pb.y)
+    for lin in ("taylor", "cubature"):
+        r = orc.smoother(pb, 1, lin)
+        assert orc.mean_error(r["mean"], m_ref) < 1e-10, lin
+        assert orc.cov_error(r["cov"], P_ref) < 1e-10, lin
