@@ -201,6 +201,123 @@ __global__ __launch_bounds__(kThreads) void k_conv_mfma(ConvArgs a) {
       }
 }
 
+// ---------------------------------------------------------------------------
+// Inference form of a dilated residual layer, h' = h + relu(b + sum_k W_k h(.
+// + (k - 1) d)), for C channels in and out (C = 128 or 256).  A block takes
+// 128 positions -- whole windows, so every tap that stays inside its window
+// stays inside the tile -- and all C output channels.  Its input tile is read
+// from HBM once, rounded to BF16 and staged position-major in LDS, where one
+// 8-byte read gives an MFMA B fragment (4 consecutive channels at one
+// position); the packed weights give A fragments the same way.  The residual
+// is added from the unrounded FP32 input, and only h' is written (the ReLU
+// part alone is kept by the training form, for the backward pass).
+// Wave w computes rows 32 w .. 32 w + 31 of each 128-row chunk, all 128
+// positions: 2 x 8 blocks of 16 x 16 x 16 BF16 MFMA, FP32 accumulation.
+// grid ceil(N / 128); requires 128 % Lpos == 0 and N % Lpos == 0.
+// ---------------------------------------------------------------------------
+struct ResidualArgs {
+  int N, Lpos, dil;     // positions, positions per window, dilation
+  const short* Wt;      // [C][3][C] BF16 bits: Wt[(m * 3 + k) * C + c] = bf16(W[m][c][k])
+  const float* bias;    // [C]
+  const float* h;       // [C][N] layer input
+  float* out;           // [C][N] layer output h'
+};
+
+constexpr int kResP = 128;   // positions per block of k_residual_mfma
+
+// Wt[(m * 3 + k) * C + c] = bf16(W[(m * C + c) * 3 + k]); grid ceil(3 C^2 / 256).
+__global__ __launch_bounds__(256) void k_pack_residual(const float* W, int C, short* Wt) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= int64_t(3) * C * C) return;
+  const int c = int(e % C), k = int((e / C) % 3);
+  const int64_t m = e / (int64_t(3) * C);
+  Wt[e] = to_bf16(W[(m * C + c) * 3 + k]);
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_residual_mfma(ResidualArgs a) {
+  static_assert(C % 128 == 0, "128-row chunks");
+  constexpr int CP = C + 8;   // LDS row pitch (BF16): rows 16 B apart in bank order
+  __shared__ __align__(16) short Hs[kResP][CP];
+  const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
+  const int64_t p0 = int64_t(blockIdx.x) * kResP;
+  // stage the tile: each thread moves 4 channels x 4 positions per pass
+  // (float4 reads along positions, one 8-byte LDS write per position)
+  for (int b = t; b < (C / 4) * (kResP / 4); b += 256) {
+    const int cb = b / (kResP / 4), pb = b - cb * (kResP / 4);
+    const int c = 4 * cb, p = 4 * pb;
+    const int64_t pp = p0 + p;
+    float v[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (pp + 3 < a.N) {
+        const float4 x = ld4(a.h + int64_t(c + i) * a.N + pp);
+        v[i][0] = x.x; v[i][1] = x.y; v[i][2] = x.z; v[i][3] = x.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[i][j] = pp + j < a.N ? a.h[int64_t(c + i) * a.N + pp + j] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bf16x4 w;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[i] = to_bf16(v[i][j]);
+      *reinterpret_cast<bf16x4*>(&Hs[p + j][c]) = w;
+    }
+  }
+  __syncthreads();
+  const int kq = 4 * (ln >> 4), lr = ln & 15;
+  for (int m0 = 0; m0 < C; m0 += 128) {
+    const int mrow = m0 + 32 * wv + lr;   // A-fragment row of block i: mrow + 16 i
+    f32x4 acc[2][8];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 3; ++k) {
+      const int off = (k - 1) * a.dil;
+      // per position block j: the tap's LDS row and whether it stays in the window
+      int row[8];
+      bool live[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int pl = 16 * j + lr, q = pl % a.Lpos + off;
+        live[j] = q >= 0 && q < a.Lpos;
+        row[j] = live[j] ? pl + off : pl;
+      }
+#pragma unroll 2
+      for (int c0 = 0; c0 < C; c0 += 16) {
+        bf16x4 af[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          af[i] = *reinterpret_cast<const bf16x4*>(a.Wt + (int64_t(mrow + 16 * i) * 3 + k) * C + c0 + kq);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          bf16x4 bv = *reinterpret_cast<const bf16x4*>(&Hs[row[j]][c0 + kq]);
+          if (!live[j]) bv = bf16x4{0, 0, 0, 0};
+#pragma unroll
+          for (int i = 0; i < 2; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bv, acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + 32 * wv + 16 * i + kq + q;
+        const float bm = a.bias[m];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int64_t p = p0 + 16 * j + lr;
+          if (p >= a.N) continue;
+          const int64_t o = int64_t(m) * a.N + p;
+          a.out[o] = a.h[o] + fmaxf(acc[i][j][q] + bm, 0.f);
+        }
+      }
+  }
+}
+
 // Weight gradient partials: part[z][m][r] = sum over the z-th chunk of
 // positions of D[m][p] B(r, p), with r = Kr the bias column (B = 1).
 // grid (ceil((Kr + 1) / 64), ceil(M / 64), chunks).

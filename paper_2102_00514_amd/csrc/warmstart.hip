@@ -76,6 +76,8 @@ struct ws_net {
   float *dh[2] = {nullptr, nullptr}, *dz[2] = {nullptr, nullptr};
   float *part = nullptr, *loss_part = nullptr, *loss = nullptr;
   int* bad_index = nullptr;   // set by the batch gather when an index is out of range
+  short* wt16 = nullptr;      // residual weights packed for k_residual_mfma ([hidden][3 C^2] BF16)
+  bool res_fast = false;      // the inference form runs k_residual_mfma (C = 128 or 256, 128 % Lpos == 0)
   int64_t part_floats = 0;
   int* win_track = nullptr;
   int* win_start = nullptr;
@@ -158,6 +160,9 @@ struct ws_net {
     A_(&loss_part, 1024);
     A_(&loss, 1);
     if (e == hipSuccess) e = alloc(reinterpret_cast<void**>(&bad_index), sizeof(int), allocs);
+    res_fast = (c.width == 128 || c.width == 256) && wsn::kResP % Lpos == 0 && c.hidden > 0;
+    if (res_fast && e == hipSuccess)
+      e = alloc(reinterpret_cast<void**>(&wt16), sizeof(short) * 3 * size_t(c.width) * c.width * c.hidden, allocs);
     if (e != hipSuccess)
       return fail(e == hipErrorOutOfMemory ? WS_ENOMEM : WS_EDEVICE, hip_msg(e, "device allocation"));
     std::vector<float> ones(c.nx, 1.f);
@@ -205,6 +210,15 @@ struct ws_net {
     }
     for (int l = 1; l <= Hn; ++l) {
       const LayerSpec& L = layers[l];
+      if (mfma && res_fast) {
+        // the packed weights come from pack_residual(), run before the batch loop
+        const wsn::ResidualArgs r{N, Lpos, L.dil, wt16 + size_t(l - 1) * 3 * L.cout * L.cout, theta + L.b_off,
+                                  H[l - 1], H[l]};
+        const dim3 grid(unsigned((N + wsn::kResP - 1) / wsn::kResP));
+        if (L.cout == 128) hipLaunchKernelGGL(wsn::k_residual_mfma<128>, grid, dim3(256), 0, stream, r);
+        else hipLaunchKernelGGL(wsn::k_residual_mfma<256>, grid, dim3(256), 0, stream, r);
+        continue;
+      }
       wsn::ConvArgs a{L.cout, L.cin * L.K, N, theta + L.w_off, 0, theta + L.b_off, gather_of(L, H[l - 1], n, false),
                       A[l], H[l], H[l - 1], nullptr};
       conv<wsn::kEpiResidual>(a, mfma);
@@ -213,6 +227,16 @@ struct ws_net {
     wsn::ConvArgs a{L.cout, L.cin * L.K, N, theta + L.w_off, 0, theta + L.b_off, gather_of(L, H[Hn], n, false),
                     out, nullptr, nullptr, nullptr};
     conv<wsn::kEpiLinear>(a, mfma);
+  }
+
+  // BF16 tap-major copies of the residual weights for k_residual_mfma
+  void pack_residual() {
+    for (int l = 1; l <= cfg.hidden; ++l) {
+      const LayerSpec& L = layers[l];
+      const int64_t cnt = int64_t(3) * L.cout * L.cout;
+      hipLaunchKernelGGL(wsn::k_pack_residual, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, stream,
+                         static_cast<const float*>(theta + L.w_off), L.cout, wt16 + size_t(l - 1) * cnt);
+    }
   }
 
   void wgrad(const LayerSpec& L, const float* D, const wsn::Gather& g, int N) {
@@ -512,6 +536,7 @@ static ws_status trajectory(ws_t h, const double* d_y, double* d_mean, bool mfma
   if (!h->n_windows) return h->fail(WS_ESTATE, "no tracks planned (ws_set_tracks)");
   if (!d_y || !d_mean) return h->fail(WS_EINVAL, "null device pointer");
   const int W = h->cfg.window;
+  if (mfma && h->res_fast) h->pack_residual();
   for (int64_t w0 = 0; w0 < h->n_windows; w0 += h->cfg.max_batch) {
     const int nb = int(std::min<int64_t>(h->cfg.max_batch, h->n_windows - w0));
     const int64_t cnt = int64_t(nb) * W;
