@@ -129,6 +129,8 @@ def dense_flops_per_position(kernel: str, n: int, p: int) -> float:
     }[kernel]
 
 
+PROFILE_REPEAT = 8   # launches of a kernel between one pair of HIP events in the profiling pass
+
 # Sources of the n = 5 kernels whose HBM traffic is recorded in profiles/
 # (the kernels, their device functions and their launch configuration).
 TRAFFIC_SOURCES = ("fused.hpp", "elements.hpp", "operators.hpp", "sqrt.hpp", "linalg.hpp", "models.hpp", "scan.hpp",
@@ -258,7 +260,8 @@ def warm_start_section(weights: str, n_batch: int, n_single: int, lin: str = "ta
     from paper_2102_00514_amd import warmstart as W
     from paper_2102_00514_amd import workloads as wl
     stream = torch.cuda.current_stream().cuda_stream
-    net, cov, meta = W.load(weights, stream=stream)
+    # inference in chunks of up to 16384 windows (about 1.7 GB of activations)
+    net, cov, meta = W.load(weights, stream=stream, max_batch=16384)
     pb = wl.config_c4(0, n_batch, held_out=True)
     sched_batch = binding_autotune(pb, stream, lin)
     sched_single = binding_autotune(pb.track(0), stream, lin)
@@ -279,6 +282,7 @@ def warm_start_section(weights: str, n_batch: int, n_single: int, lin: str = "ta
         torch.cuda.synchronize()
         batch["inference_ms_" + ("bf16_mfma" if fast else "fp32")] = round((time.perf_counter() - t0) * 1e3 / 3, 3)
     batch["inference"] = "learned start inferred with BF16 products on the matrix cores (ws_trajectory_mfma)"
+    batch["inference_chunk_windows"] = 16384
     del mean0, d_y
     rows = {"plain": [], "learned": []}
     for i in range(n_single):
@@ -540,8 +544,9 @@ def measure(name: str, pb, desc: str, lin: str, precision: str, steps: int, warm
         log(f"{name}: trajectory after the timed iterations: {checked}")
         assert ok_f and ok_s, f"{name}: non-finite or asymmetric trajectory after the timed iterations"
 
-    # per-kernel durations from HIP events around each launch (separate pass)
-    prof = sm.profile(profile_iters)
+    # per-kernel durations from HIP events around each launch (separate pass;
+    # each launch repeated 8 times between its events, the mean taken)
+    prof = sm.profile(profile_iters, repeat=PROFILE_REPEAT)
     torch.cuda.synchronize()
     word = 8 if precision == "f64" else 4
     scan_b = scan_bytes_per_slot(pb.nx, word)
