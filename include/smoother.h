@@ -301,6 +301,20 @@ typedef struct {
  * records).  The iterations advance the trajectory like any others. */
 sm_status smoother_profile(smoother_t h, int32_t k, sm_kernel_time* out, int32_t cap, int32_t* n_out);
 
+/* As smoother_profile, with every kernel launched `repeat` times (1..64) back
+ * to back between its event pair; total_ms then sums, over the launches
+ * counted in `launches`, the mean duration of the repeats, so the latency of
+ * the event records and of one dispatch is spread over the repeats.  A
+ * kernel that computes its outputs from buffers it does not write leaves the
+ * same result after a repeat (the per-track change statistic is a maximum);
+ * the one kernel that overwrites its input (the nx = 20 engine's forward
+ * down-sweep, which stores each slot's smoothing element over its filtering
+ * element) runs once.  So the trajectory, the deltas and the iteration count
+ * come out as from smoother_iterate(h, k).  SM_EINVAL for repeat outside
+ * 1..64. */
+sm_status smoother_profile_repeat(smoother_t h, int32_t k, int32_t repeat, sm_kernel_time* out, int32_t cap,
+                                  int32_t* n_out);
+
 /* Number of slots S, tracks and the device bytes held by the handle. */
 sm_status smoother_info(smoother_t h, int64_t* n_slots, int32_t* n_tracks, int64_t* device_bytes);
 

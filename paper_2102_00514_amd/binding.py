@@ -30,7 +30,8 @@ EXPORTS = ("smoother_problem_defaults", "smoother_init", "smoother_iterate", "sm
            "smoother_result_device", "smoother_track_deltas", "smoother_info", "smoother_last_error",
            "smoother_destroy", "smoother_version", "smoother_profile", "smoother_schedule",
            "smoother_set_trajectory_device", "smoother_iterate_until", "smoother_autotune",
-           "smoother_objective", "smoother_iterate_lm", "smoother_filter", "smoother_solve_static")
+           "smoother_objective", "smoother_iterate_lm", "smoother_filter", "smoother_solve_static",
+           "smoother_profile_repeat")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -102,6 +103,9 @@ def _load():
     lib.smoother_profile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(sm_kernel_time), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32)]
     lib.smoother_profile.restype = ctypes.c_int
+    lib.smoother_profile_repeat.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(sm_kernel_time),
+                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.smoother_profile_repeat.restype = ctypes.c_int
     lib.smoother_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _i64p]
     lib.smoother_schedule.restype = ctypes.c_int
     lib.smoother_version.argtypes = []
@@ -320,13 +324,17 @@ def smoother_track_deltas(h: int) -> np.ndarray:
     return out
 
 
-def smoother_profile(h: int, k: int) -> dict:
-    """Runs k iterations with per-launch HIP events; returns
+def smoother_profile(h: int, k: int, repeat: int = 1) -> dict:
+    """Runs k iterations with per-launch HIP events (each launch repeated
+    `repeat` times between its events, the mean taken); returns
     {kernel family: (launches, total_ms, positions)}."""
     cap = 64
     recs = (sm_kernel_time * cap)()
     n = ctypes.c_int32(0)
-    _check(h, _lib.smoother_profile(h, k, recs, cap, ctypes.byref(n)))
+    if repeat == 1:
+        _check(h, _lib.smoother_profile(h, k, recs, cap, ctypes.byref(n)))
+    else:
+        _check(h, _lib.smoother_profile_repeat(h, k, repeat, recs, cap, ctypes.byref(n)))
     return {recs[i].name.decode(): (recs[i].launches, recs[i].total_ms, recs[i].positions) for i in range(n.value)}
 
 
@@ -382,8 +390,8 @@ class Smoother:
     def info(self):
         return smoother_info(self.h)
 
-    def profile(self, k: int):
-        return smoother_profile(self.h, k)
+    def profile(self, k: int, repeat: int = 1):
+        return smoother_profile(self.h, k, repeat)
 
     def schedule(self):
         return smoother_schedule(self.h)

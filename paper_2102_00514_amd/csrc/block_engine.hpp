@@ -171,12 +171,12 @@ class BlockEngine final : public EngineBase {
     return SM_OK;
   }
 
-  sm_status profile(int k, sm_kernel_time* out, int cap_out, int* n_out) override {
+  sm_status profile(int k, int repeat, sm_kernel_time* out, int cap_out, int* n_out) override {
     std::vector<sm_kernel_time> acc;
     std::vector<sm_kernel_time> one(64);
     for (auto& b : blocks_) {
       int n = 0;
-      const sm_status s = b->profile(k, one.data(), int(one.size()), &n);
+      const sm_status s = b->profile(k, repeat, one.data(), int(one.size()), &n);
       if (s != SM_OK) return fail(s, b->err);
       for (int i = 0; i < n; ++i) {
         auto it = std::find_if(acc.begin(), acc.end(),

@@ -239,10 +239,14 @@ class DenseEngine final : public EngineBase {
                          fagg_[0]);
     });
     scan_levels<true>();
-    timed("dn_forward_down_backward_up", S, [&] {
-      hipLaunchKernelGGL((dn::k_dn_forward_down_backward_up<Model, R>), dim3(c0), dim3(dn::kWave), 0, stream, a,
-                         fan0_, static_cast<const void*>(fcar_[0]), sagg_[0]);
-    });
+    // stores each slot's smoothing element over its filtering element: one launch even under repeats
+    timed(
+        "dn_forward_down_backward_up", S,
+        [&] {
+          hipLaunchKernelGGL((dn::k_dn_forward_down_backward_up<Model, R>), dim3(c0), dim3(dn::kWave), 0, stream, a,
+                             fan0_, static_cast<const void*>(fcar_[0]), sagg_[0]);
+        },
+        false);
     scan_levels<false>();
     timed("dn_backward_down", S, [&] {
       hipLaunchKernelGGL((dn::k_dn_backward_down<Model, R>), dim3(c0), dim3(dn::kWave), 0, stream, a, fan0_,

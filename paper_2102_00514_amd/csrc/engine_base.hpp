@@ -224,30 +224,39 @@ class EngineBase {
     return st;
   }
 
-  // Per-launch HIP events (only while profiling).
+  // Per-launch HIP events (only while profiling).  With prof_repeat > 1 each
+  // launch runs that many times back to back between its event pair, which
+  // spreads the latency of the event records and of the dispatch over the
+  // repeats.  A kernel that computes its outputs from buffers it does not
+  // write leaves after a repeat what it leaves after one launch (the
+  // per-track change statistic is an atomic maximum); a kernel that
+  // overwrites its own input passes repeatable = false and runs once.
   struct ProfRec {
     const char* name;
     hipEvent_t a, b;
     int64_t positions;
+    int reps;
   };
 
   template <class F>
-  void timed(const char* name, int64_t positions, F&& launch) {
+  void timed(const char* name, int64_t positions, F&& launch, bool repeatable = true) {
     if (!profiling) {
       launch();
       return;
     }
-    ProfRec r{name, nullptr, nullptr, positions};
+    const int reps = repeatable ? prof_repeat : 1;
+    ProfRec r{name, nullptr, nullptr, positions, reps};
     (void)hipEventCreate(&r.a);
     (void)hipEventCreate(&r.b);
     (void)hipEventRecord(r.a, stream);
-    launch();
+    for (int i = 0; i < reps; ++i) launch();
     (void)hipEventRecord(r.b, stream);
     prof.push_back(r);
   }
 
-  virtual sm_status profile(int k, sm_kernel_time* out, int cap_out, int* n_out) {
+  virtual sm_status profile(int k, int repeat, sm_kernel_time* out, int cap_out, int* n_out) {
     prof.clear();
+    prof_repeat = std::max(1, repeat);
     profiling = true;
     sm_status st = iterate(k);
     profiling = false;
@@ -267,7 +276,7 @@ class EngineBase {
         it = acc.end() - 1;
       }
       it->launches += 1;
-      it->total_ms += ms;
+      it->total_ms += ms / r.reps;
       it->positions += r.positions;
     }
     prof.clear();
@@ -341,6 +350,7 @@ class EngineBase {
   char* arena = nullptr;
   size_t arena_bytes = 0, arena_used = 0;
   bool profiling = false;
+  int prof_repeat = 1;
   std::vector<ProfRec> prof;
 };
 

@@ -618,13 +618,18 @@ sm_status smoother_track_deltas(smoother_t h, double* deltas) {
 }
 
 sm_status smoother_profile(smoother_t h, int32_t k, sm_kernel_time* out, int32_t cap, int32_t* n_out) {
+  return smoother_profile_repeat(h, k, 1, out, cap, n_out);
+}
+
+sm_status smoother_profile_repeat(smoother_t h, int32_t k, int32_t repeat, sm_kernel_time* out, int32_t cap,
+                                  int32_t* n_out) {
   if (!h || !h->eng) return SM_ESTATE;
-  if (!out || cap < 1 || k < 1) {
-    h->err = "profile needs k >= 1 and an output array";
+  if (!out || cap < 1 || k < 1 || repeat < 1 || repeat > 64) {
+    h->err = "profile needs k >= 1, 1 <= repeat <= 64 and an output array";
     return SM_EINVAL;
   }
   try {
-    const sm_status st = h->eng->profile(k, out, cap, n_out);
+    const sm_status st = h->eng->profile(k, repeat, out, cap, n_out);
     if (st != SM_OK) h->err = h->eng->err;
     return st;
   } catch (...) {
