@@ -15,6 +15,9 @@ CSRC = os.path.join(PKG, "csrc")
 UNITS = ["smoother.hip", "engine_ct_f64.hip", "engine_ct_f32.hip", "engine_linear_f64.hip",
          "engine_linear_f32.hip", "engine_dense_ct_f64.hip", "warmstart.hip"]
 LIB = os.path.join(PKG, "libsmoother.so")
+# measurement kernels of the nx = 20 engine's matrix products (not linked into LIB)
+PROBE_UNIT = "dense_probe.hip"
+PROBE_LIB = os.path.join(PKG, "libdense_probe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HIP_FLAGS = [
@@ -65,13 +68,31 @@ def build(verbose: bool = False, extra=(), jobs: int = 8) -> str:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("linking libsmoother.so failed")
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose: bool = False) -> str:
+    """libdense_probe.so: the FP64 VALU and MFMA forms of the nx = 20 products."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC, *HIP_FLAGS, "-shared", "-I", os.path.join(ROOT, "include"), "-o", tmp,
+           os.path.join(CSRC, PROBE_UNIT)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("building libdense_probe.so failed")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 def is_stale() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
+    if not os.path.exists(PROBE_LIB) or os.path.getmtime(PROBE_LIB) < t:
+        return True
     return any(os.path.getmtime(s) > t for s in sources())
 
 
