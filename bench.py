@@ -479,7 +479,8 @@ def make_workload(name: str, T: int = 0):
 
 
 def measure(name: str, pb, desc: str, lin: str, precision: str, steps: int, warmup: int, profile_iters: int,
-            tile_lanes: int = 0, lane_slots: int = 0, autotune: bool = True, check: bool = True) -> dict:
+            tile_lanes: int = 0, lane_slots: int = 0, autotune: bool = True, check: bool = True,
+            form: str = "covariance") -> dict:
     """Times `steps` iterations of the captured iteration graph on resident
     inputs (HIP events on the handle's stream), then a separate pass of
     `profile_iters` iterations with HIP events around every kernel launch for
@@ -495,12 +496,12 @@ def measure(name: str, pb, desc: str, lin: str, precision: str, steps: int, warm
     if autotune and not tile_lanes and not lane_slots:
         lanes_t, slots_t, ms_t = binding.smoother_autotune(pb, stream=stream.cuda_stream,
                                                            iters=10 if pb.n_slots < 2 ** 20 else 2, lin=lin,
-                                                           precision=precision)
+                                                           precision=precision, form=form)
         tuned = {"tile_lanes": lanes_t, "lane_slots": slots_t, "ms_per_iter": round(ms_t, 6)}
         log(f"{name}: autotuned schedule: {lanes_t} lanes x {slots_t} slots ({ms_t * 1e3:.1f} us/iteration)")
         tile_lanes, lane_slots = lanes_t, slots_t
     sm = binding.Smoother(pb, stream=stream.cuda_stream, n_iter=warmup + steps + profile_iters, lin=lin,
-                          precision=precision, tile_lanes=tile_lanes, lane_slots=lane_slots)
+                          precision=precision, tile_lanes=tile_lanes, lane_slots=lane_slots, form=form)
     S, _, dev_bytes = sm.info()
     lanes, slots, tiles = sm.schedule()
     log(f"workload {name}: steps={T} slots={S} lin={lin} precision={precision} device_bytes={dev_bytes} "
@@ -583,7 +584,7 @@ def measure(name: str, pb, desc: str, lin: str, precision: str, steps: int, warm
                     "avg_launch_us": round(avg_launch_s * 1e6, 3), "flops_per_launch": int(units_per_launch)}
     else:
         achieved = units_per_launch / avg_launch_s / 1e9
-        traffic = measured_traffic(f"{dom[1]}|T={T}|{lin}|{precision}")
+        traffic = measured_traffic(f"{dom[1]}|T={T}|{lin}|{precision}" + ("|sqrt" if form == "sqrt" else ""))
         design = dom[7] * dom[4] / dom[2]
         roofline = {"bound": "hbm", "kernel": dom[1], "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
@@ -631,6 +632,8 @@ def main():
     ap.add_argument("--lin", default=None, choices=["taylor", "cubature", "unscented"],
                     help="default: taylor (c2), cubature (c3), unscented (c5)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--form", default="covariance", choices=["covariance", "sqrt"],
+                    help="element form: the paper's covariance form or lower-triangular factors")
     ap.add_argument("--profile-iters", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -681,7 +684,7 @@ def main():
         args.no_damping = True
         args.no_extra = True
     r = measure(args.workload, pb, desc, args.lin, args.precision, args.steps, args.warmup, args.profile_iters,
-                args.tile_lanes, args.lane_slots, autotune=not args.no_autotune)
+                args.tile_lanes, args.lane_slots, autotune=not args.no_autotune, form=args.form)
     sm = r.pop("_sm")
     converge = None
     if args.workload == "c3" and not args.no_converge:
@@ -763,7 +766,7 @@ def main():
                                f"{'IEKS (Taylor)' if args.lin == 'taylor' else args.lin + ' SLR'}, "
                                f"one iteration per step",
                    "T": r["T"], "tracks": r["tracks"], "nx": r["nx"], "ny": r["ny"], "lin": args.lin,
-                   "parallelism": "time-axis scan, 1 GPU", "schedule": r["schedule"]},
+                   "form": args.form, "parallelism": "time-axis scan, 1 GPU", "schedule": r["schedule"]},
         "roofline": r["roofline"],
         "iteration_roofline": r["iteration_roofline"],
         "cpu_baseline": cpu,
