@@ -178,6 +178,21 @@ sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out)
 sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iters, int32_t* tile_lanes,
                             int32_t* lane_slots, double* ms_per_iter);
 
+/* As smoother_autotune, through a per-process cache: a problem of the same
+ * shape (device, model, nx, ny, lin, precision, form, freeze_converged,
+ * whether lm_lambda is zero, max_device_bytes, iters, and the track offsets)
+ * seen before
+ * returns the schedule and time measured then, without building a handle;
+ * *from_cache (nullable) is 1 then and 0 after a measurement.  The cache is
+ * shared by the host threads of the process (guarded) and holds one entry
+ * per shape until smoother_autotune_cache_clear.  Errors as
+ * smoother_autotune; failures are not cached. */
+sm_status smoother_autotune_cached(const sm_problem* pb, void* hip_stream, int32_t iters, int32_t* tile_lanes,
+                                   int32_t* lane_slots, double* ms_per_iter, int32_t* from_cache);
+
+/* Empties the cache of smoother_autotune_cached. */
+void smoother_autotune_cache_clear(void);
+
 /* Runs `k` more iterations (k <= 0: the iterations left up to n_iter).  Each
  * iteration re-linearises around the current trajectory (Section 3), builds the
  * filtering elements (eq. 13-14) and combines them with a prefix scan

@@ -31,7 +31,7 @@ EXPORTS = ("smoother_problem_defaults", "smoother_init", "smoother_iterate", "sm
            "smoother_destroy", "smoother_version", "smoother_profile", "smoother_schedule",
            "smoother_set_trajectory_device", "smoother_iterate_until", "smoother_autotune",
            "smoother_objective", "smoother_iterate_lm", "smoother_filter", "smoother_solve_static",
-           "smoother_profile_repeat")
+           "smoother_profile_repeat", "smoother_autotune_cached", "smoother_autotune_cache_clear")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -118,6 +118,12 @@ def _load():
     lib.smoother_autotune.argtypes = [ctypes.POINTER(sm_problem), vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), _dp]
     lib.smoother_autotune.restype = ctypes.c_int
+    lib.smoother_autotune_cached.argtypes = [ctypes.POINTER(sm_problem), vp, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _dp,
+                                             ctypes.POINTER(ctypes.c_int32)]
+    lib.smoother_autotune_cached.restype = ctypes.c_int
+    lib.smoother_autotune_cache_clear.argtypes = []
+    lib.smoother_autotune_cache_clear.restype = None
     lib.smoother_filter.argtypes = [vp, _dp, _dp, _dp]
     lib.smoother_filter.restype = ctypes.c_int
     lib.smoother_objective.argtypes = [vp, _dp]
@@ -211,6 +217,22 @@ def smoother_autotune(pb: Problem, stream: Optional[int] = None, iters: int = 5,
     if st != SM_OK:
         raise SmootherError(st, smoother_last_error(None))
     return B.value, K.value, ms.value
+
+
+def smoother_autotune_cached(pb: Problem, stream: Optional[int] = None, iters: int = 5, **kw):
+    """As smoother_autotune through the library's per-process cache of schedules
+    by problem shape: (tile_lanes, lane_slots, ms per iteration, from_cache)."""
+    s, _keep = make_problem(pb, **kw)
+    B, K, ms, hit = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+    st = _lib.smoother_autotune_cached(ctypes.byref(s), ctypes.c_void_p(stream or 0), iters, ctypes.byref(B),
+                                       ctypes.byref(K), ctypes.byref(ms), ctypes.byref(hit))
+    if st != SM_OK:
+        raise SmootherError(st, smoother_last_error(None))
+    return B.value, K.value, ms.value, bool(hit.value)
+
+
+def smoother_autotune_cache_clear() -> None:
+    _lib.smoother_autotune_cache_clear()
 
 
 def smoother_solve_static(pb: Problem, mean_ptr: int, cov_ptr: int, stream: Optional[int] = None,

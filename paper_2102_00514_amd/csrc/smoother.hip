@@ -428,6 +428,88 @@ sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iter
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+// Schedules found by smoother_autotune_cached, per process.  The time of a
+// schedule depends on the problem's shape, not on its values: the key holds
+// the device, every field that selects kernels or sizes the plan, and an
+// FNV-1a hash of the track offsets.
+struct TuneRec {
+  int32_t lanes, slots;
+  double ms;
+};
+std::mutex g_tune_mutex;
+std::vector<std::pair<std::string, TuneRec>> g_tune_cache;
+
+std::string tune_key(const sm_problem* pb, int32_t iters) {
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* o = reinterpret_cast<const unsigned char*>(pb->offsets);
+  for (size_t i = 0; i < sizeof(int64_t) * size_t(pb->n_tracks + 1); ++i) h = (h ^ o[i]) * 1099511628211ull;
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "d%d m%d n%d p%d t%d l%d pr%d f%d z%d lm%d it%d cap%lld o%016llx", dev, pb->model,
+                pb->nx, pb->ny, pb->n_tracks, pb->lin, pb->precision, pb->form, pb->freeze_converged,
+                pb->lm_lambda != 0.0 ? 1 : 0, iters, static_cast<long long>(pb->max_device_bytes),
+                static_cast<unsigned long long>(h));
+  return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+sm_status smoother_autotune_cached(const sm_problem* pb, void* hip_stream, int32_t iters, int32_t* tile_lanes,
+                                   int32_t* lane_slots, double* ms_per_iter, int32_t* from_cache) {
+  try {
+    if (!pb || !tile_lanes || !lane_slots || iters < 1) {
+      g_init_error = "autotune needs a problem, output pointers and iters >= 1";
+      return SM_EINVAL;
+    }
+    const std::string msg = pks::validate(pb);
+    if (!msg.empty()) {
+      g_init_error = msg;
+      return SM_EINVAL;
+    }
+    const std::string key = tune_key(pb, iters);
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mutex);
+      for (const auto& e : g_tune_cache)
+        if (e.first == key) {
+          *tile_lanes = e.second.lanes;
+          *lane_slots = e.second.slots;
+          if (ms_per_iter) *ms_per_iter = e.second.ms;
+          if (from_cache) *from_cache = 1;
+          g_init_error.clear();
+          return SM_OK;
+        }
+    }
+    double ms = 0.0;
+    const sm_status st = smoother_autotune(pb, hip_stream, iters, tile_lanes, lane_slots, &ms);
+    if (st != SM_OK) return st;
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mutex);
+      g_tune_cache.push_back({key, TuneRec{*tile_lanes, *lane_slots, ms}});
+    }
+    if (ms_per_iter) *ms_per_iter = ms;
+    if (from_cache) *from_cache = 0;
+    return SM_OK;
+  } catch (const std::bad_alloc&) {
+    g_init_error = "host allocation failed";
+    return SM_ENOMEM;
+  } catch (...) {
+    g_init_error = "unexpected host exception";
+    return SM_EDEVICE;
+  }
+}
+
+void smoother_autotune_cache_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_tune_cache.clear();
+}
+
 sm_status smoother_iterate(smoother_t h, int32_t k, double* max_delta_out, int32_t* iters_done_out) {
   if (!h || !h->eng) return SM_ESTATE;
   try {

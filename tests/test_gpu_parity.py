@@ -399,3 +399,23 @@ def test_dense_device_paths_and_graph(B):
         r.iterate(1)
         rm, rc = r.result()
     assert np.array_equal(sm_m, rm) and np.array_equal(sm_c, rc)
+
+
+def test_autotune_cache(B):
+    """smoother_autotune_cached measures a shape once per process: the second
+    call on the same shape (other values) returns the first call's schedule
+    and time from the cache; another shape, another form or a cleared cache
+    measures again; the schedule passes parity."""
+    B.smoother_autotune_cache_clear()
+    pb = wl.config_c2(3000)
+    other_values = wl.ct_bearings(3000, seed=99)
+    first = B.smoother_autotune_cached(pb, iters=3, lin="taylor")
+    again = B.smoother_autotune_cached(other_values, iters=3, lin="taylor")
+    assert not first[3] and again[3] and again[:3] == first[:3]
+    assert not B.smoother_autotune_cached(wl.config_c2(3001), iters=3, lin="taylor")[3]
+    assert not B.smoother_autotune_cached(pb, iters=3, lin="taylor", form="sqrt")[3]
+    B.smoother_autotune_cache_clear()
+    assert not B.smoother_autotune_cached(pb, iters=3, lin="taylor")[3]
+    ref = oracle.smoother(pb, 2, "taylor")
+    mean, cov, _, _ = run_gpu(B, pb, 2, "taylor", tile_lanes=first[0], lane_slots=first[1])
+    assert oracle.mean_error(mean, ref["mean"]) < TOL64 and oracle.cov_error(cov, ref["cov"]) < TOL64
