@@ -456,6 +456,27 @@ def time_to_converge(net: WarmStartNet, cov: np.ndarray, pb: wl.Problem, lin: st
     return res
 
 
+def time_inference(net: WarmStartNet, pb: wl.Problem, repeats: int = 5) -> dict:
+    """Wall time of the initial trajectory of every track of pb (features,
+    network, scatter), FP32 and with BF16 products on the matrix cores: one
+    warm-up call each, then the mean of `repeats` calls between two
+    synchronisations."""
+    torch = _torch()
+    d_y = torch.from_numpy(np.ascontiguousarray(pb.y)).cuda()
+    n_windows = net.set_tracks(pb.offsets)
+    mean0 = torch.empty((pb.n_slots, pb.nx), dtype=torch.float64, device="cuda")
+    out = {"tracks": pb.n_tracks, "windows": n_windows, "chunk_windows": net.cfg.max_batch}
+    for name, mfma in (("fp32", False), ("bf16_mfma", True)):
+        net.trajectory(d_y.data_ptr(), mean0.data_ptr(), mfma=mfma)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            net.trajectory(d_y.data_ptr(), mean0.data_ptr(), mfma=mfma)
+        torch.cuda.synchronize()
+        out[f"ms_{name}"] = round((time.perf_counter() - t0) * 1e3 / repeats, 3)
+    return out
+
+
 def _public(r: dict) -> dict:
     return {k: (_public(v) if isinstance(v, dict) else v) for k, v in r.items() if not k.startswith("_")}
 
@@ -477,6 +498,11 @@ def main(argv=None):
     e.add_argument("--weights", required=True)
     e.add_argument("--tracks", type=int, default=512)
     e.add_argument("--lin", default="taylor", choices=["taylor", "cubature"])
+    i = sub.add_parser("infer", help="time the initial trajectory of held-out tracks (FP32 and BF16 MFMA)")
+    i.add_argument("--weights", required=True)
+    i.add_argument("--tracks", type=int, default=512)
+    i.add_argument("--chunk", type=int, default=16384, help="windows per forward pass (max_batch)")
+    i.add_argument("--repeats", type=int, default=5)
     a = ap.parse_args(argv)
     torch = _torch()
     torch.cuda.set_device(0)
@@ -498,6 +524,11 @@ def main(argv=None):
         del X, LAB
         pb = wl.config_c4(0, a.eval_tracks, held_out=True)
         print(json.dumps({"train": meta, "held_out": _public(time_to_converge(net, cov, pb, a.lin))}))
+    elif a.cmd == "infer":
+        net, _, _ = load(a.weights, stream=stream, max_batch=a.chunk)
+        pb = wl.config_c4(0, a.tracks, held_out=True)
+        print(json.dumps(time_inference(net, pb, a.repeats)))
+        net.close()
     else:
         net, cov, meta = load(a.weights, stream=stream)
         pb = wl.config_c4(0, a.tracks, held_out=True)
