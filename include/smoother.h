@@ -180,8 +180,8 @@ sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iter
 
 /* As smoother_autotune, through a per-process cache: a problem of the same
  * shape (device, model, nx, ny, lin, precision, form, freeze_converged,
- * whether lm_lambda is zero, max_device_bytes, iters, and the track offsets)
- * seen before
+ * whether lm_lambda is zero, use_graph, max_device_bytes, iters, and the
+ * track offsets) seen before
  * returns the schedule and time measured then, without building a handle;
  * *from_cache (nullable) is 1 then and 0 after a measurement.  The cache is
  * shared by the host threads of the process (guarded) and holds one entry

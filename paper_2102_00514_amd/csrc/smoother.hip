@@ -434,8 +434,9 @@ namespace {
 
 // Schedules found by smoother_autotune_cached, per process.  The time of a
 // schedule depends on the problem's shape, not on its values: the key holds
-// the device, every field that selects kernels or sizes the plan, and an
-// FNV-1a hash of the track offsets.
+// the device, every field that selects kernels, sizes the plan or changes how
+// an iteration is launched (graph replay or not), and an FNV-1a hash of the
+// track offsets.
 struct TuneRec {
   int32_t lanes, slots;
   double ms;
@@ -450,10 +451,10 @@ std::string tune_key(const sm_problem* pb, int32_t iters) {
   const unsigned char* o = reinterpret_cast<const unsigned char*>(pb->offsets);
   for (size_t i = 0; i < sizeof(int64_t) * size_t(pb->n_tracks + 1); ++i) h = (h ^ o[i]) * 1099511628211ull;
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "d%d m%d n%d p%d t%d l%d pr%d f%d z%d lm%d it%d cap%lld o%016llx", dev, pb->model,
-                pb->nx, pb->ny, pb->n_tracks, pb->lin, pb->precision, pb->form, pb->freeze_converged,
-                pb->lm_lambda != 0.0 ? 1 : 0, iters, static_cast<long long>(pb->max_device_bytes),
-                static_cast<unsigned long long>(h));
+  std::snprintf(buf, sizeof(buf), "d%d m%d n%d p%d t%d l%d pr%d f%d z%d lm%d g%d it%d cap%lld o%016llx", dev,
+                pb->model, pb->nx, pb->ny, pb->n_tracks, pb->lin, pb->precision, pb->form, pb->freeze_converged,
+                pb->lm_lambda != 0.0 ? 1 : 0, pb->use_graph != 0 ? 1 : 0, iters,
+                static_cast<long long>(pb->max_device_bytes), static_cast<unsigned long long>(h));
   return buf;
 }
 

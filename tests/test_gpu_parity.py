@@ -404,8 +404,8 @@ def test_dense_device_paths_and_graph(B):
 def test_autotune_cache(B):
     """smoother_autotune_cached measures a shape once per process: the second
     call on the same shape (other values) returns the first call's schedule
-    and time from the cache; another shape, another form or a cleared cache
-    measures again; the schedule passes parity."""
+    and time from the cache; another shape, another form, launches without a
+    graph or a cleared cache measure again; the schedule passes parity."""
     B.smoother_autotune_cache_clear()
     pb = wl.config_c2(3000)
     other_values = wl.ct_bearings(3000, seed=99)
@@ -414,6 +414,7 @@ def test_autotune_cache(B):
     assert not first[3] and again[3] and again[:3] == first[:3]
     assert not B.smoother_autotune_cached(wl.config_c2(3001), iters=3, lin="taylor")[3]
     assert not B.smoother_autotune_cached(pb, iters=3, lin="taylor", form="sqrt")[3]
+    assert not B.smoother_autotune_cached(pb, iters=3, lin="taylor", use_graph=False)[3]
     B.smoother_autotune_cache_clear()
     assert not B.smoother_autotune_cached(pb, iters=3, lin="taylor")[3]
     ref = oracle.smoother(pb, 2, "taylor")

@@ -169,7 +169,8 @@ def test_stacked_taylor_blocks(B):
 
 def test_c3_track0_first_iteration(B):
     """The ill-conditioned first step of C3 track 0 (T = 6667, moves by 633),
-    in the benchmark's 64 x 8 schedule, both forms."""
+    in the benchmark's 64 x 8 schedule: the square-root form at the FP64 gate,
+    the covariance form at the named exception's 1e-8."""
     pb = wl.config_c3(n_tracks=1)
     ref = oracle.smoother(pb, 1, "cubature")
     res = {}
@@ -178,7 +179,7 @@ def test_c3_track0_first_iteration(B):
         res[form] = errors(mean, cov, ref["mean"], ref["cov"])
     print(f"C3 track 0 iteration 1: covariance e_m={res['covariance'][0]:.3e} e_P={res['covariance'][1]:.3e}; "
           f"sqrt e_m={res['sqrt'][0]:.3e} e_P={res['sqrt'][1]:.3e}", flush=True)
-    assert max(res["sqrt"]) < 1e-8 and max(res["covariance"]) < 1e-8
+    assert max(res["sqrt"]) < TOL64 and max(res["covariance"]) < 1e-8
 
 
 def test_static_entry_point(B):
