@@ -640,7 +640,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain copy kernel of 256 MiB in, 256 MiB out (counter calibration)")
     ap.add_argument("--tile-lanes", type=int, default=0, help="scan schedule override (64 or 256)")
-    ap.add_argument("--lane-slots", type=int, default=0, help="scan schedule override (1..8)")
+    ap.add_argument("--lane-slots", type=int, default=0, help="scan schedule override (1..32)")
     ap.add_argument("--no-autotune", action="store_true", help="use the default schedule instead of the autotuner's")
     ap.add_argument("--warm-start-weights", default=os.path.join(ROOT, "paper_2102_00514_amd", "weights",
                                                                  "warmstart_ieks.npz"))

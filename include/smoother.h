@@ -129,7 +129,7 @@ typedef struct {
   const double* init_cov;         /* optional host [S*nx*nx]; NULL = P0 broadcast */
   int64_t max_device_bytes;       /* 0 = no cap; otherwise SM_ENOMEM if the plan needs more */
   int32_t tile_lanes;             /* scan schedule: lanes per tile (64 or 256; 0 = auto) */
-  int32_t lane_slots;             /* scan schedule: consecutive slots per lane (1..8; 0 = auto) */
+  int32_t lane_slots;             /* scan schedule: consecutive slots per lane (1..32; 0 = auto) */
   int32_t use_graph;              /* 1: iterations of the parallel path are replayed from a HIP graph
                                      captured on the first call; 0: launched one kernel at a time */
   double lm_lambda;               /* Levenberg-Marquardt damping (Section 3, damped Gauss-Newton
@@ -166,13 +166,16 @@ void smoother_problem_defaults(sm_problem* pb);
 sm_status smoother_init(const sm_problem* pb, void* hip_stream, smoother_t* out);
 
 /* Scan-schedule autotuner: for every candidate schedule (tile_lanes 64 or
- * 256, lane_slots 1, 2, 4 or 8) builds a handle for *pb on hip_stream, runs
+ * 256, lane_slots 1, 2, 4, 8 or 16) builds a handle for *pb on hip_stream, runs
  * one warm-up iteration and then three timed rounds of `iters` iterations (HIP
  * events around the graph replays; the best round counts), releases the
  * handle, and returns the fastest schedule in
  * *tile_lanes / *lane_slots and its time per iteration in *ms_per_iter
  * (nullable).  pb->tile_lanes, lane_slots and n_iter are ignored; the result
- * is meant for the same fields of the problem given to smoother_init.
+ * is meant for the same fields of the problem given to smoother_init.  The
+ * schedule returned is the one the engine ran: the square-root form and the
+ * full-state (nx = 20) engine fix the tile width at 64 lanes, and candidates
+ * that run alike are timed once.
  * Candidates that fail (e.g. over max_device_bytes) are skipped; if none runs,
  * the last failure is returned.  Messages go to smoother_last_error(NULL). */
 sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iters, int32_t* tile_lanes,

@@ -191,7 +191,7 @@ static std::string validate(const sm_problem* pb) {
   if (pb->scan != SM_SCAN_PARALLEL && pb->scan != SM_SCAN_SEQUENTIAL) return "unknown scan mode";
   if (pb->max_device_bytes < 0) return "max_device_bytes must be >= 0";
   if (pb->tile_lanes != 0 && pb->tile_lanes != 64 && pb->tile_lanes != 256) return "tile_lanes must be 0, 64 or 256";
-  if (pb->lane_slots < 0 || pb->lane_slots > 8) return "lane_slots must be in 0..8";
+  if (pb->lane_slots < 0 || pb->lane_slots > 32) return "lane_slots must be in 0..32";
   if (pb->use_graph != 0 && pb->use_graph != 1) return "use_graph must be 0 or 1";
   if (!(pb->lm_lambda >= 0.0) || !std::isfinite(pb->lm_lambda)) return "lm_lambda must be finite and >= 0";
   if (pb->form != SM_FORM_COVARIANCE && pb->form != SM_FORM_SQRT) return "unknown element form";
@@ -364,8 +364,11 @@ sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iter
     int best_b = 0, best_k = 0;
     sm_status last = SM_OK;
     std::string last_err;
+    // schedules as the engines run them: the square-root form and the
+    // full-state engine fix the tile width, so two candidates can be one
+    std::vector<std::pair<int, int>> timed;
     for (const int lanes : {64, 256}) {
-      for (const int slots : {1, 2, 4, 8}) {
+      for (const int slots : {1, 2, 4, 8, 16}) {
         sm_problem q = *pb;
         q.tile_lanes = lanes;
         q.lane_slots = slots;
@@ -377,7 +380,12 @@ sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iter
         }
         q.n_iter = 3 * iters + 1;
         sm_status st = eng->setup(q, stream);
-        if (st == SM_OK) st = eng->iterate(1);                  // warm-up (and graph capture)
+        if (st == SM_OK) {
+          const std::pair<int, int> actual{eng->sched_lanes, eng->sched_slots};
+          if (std::find(timed.begin(), timed.end(), actual) != timed.end()) continue;
+          timed.push_back(actual);
+          st = eng->iterate(1);                                 // warm-up (and graph capture)
+        }
         // best of three timed rounds of `iters` iterations (candidates a few
         // percent apart would otherwise swap places from run to run)
         float ms = 0.f;
@@ -403,8 +411,8 @@ sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iter
         const double per = double(ms) / iters;
         if (best < 0.0 || per < best) {
           best = per;
-          best_b = lanes;
-          best_k = slots;
+          best_b = eng->sched_lanes;
+          best_k = eng->sched_slots;
         }
       }
     }

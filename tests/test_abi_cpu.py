@@ -111,6 +111,8 @@ def test_rejects_bad_options():
     pb = _c1()
     _expect_einval(pb, "unscented", lin="unscented", ut_alpha=1.0, ut_kappa=-5.0)
     _expect_einval(pb, "n_iter", n_iter=-1)
+    _expect_einval(pb, "lane_slots", lane_slots=33)
+    _expect_einval(pb, "tile_lanes", tile_lanes=100)
     S = pb.n_slots
     _expect_einval(pb, "init_mean", init_mean=np.full((S, 5), np.inf))
     bad_cov = np.tile(np.eye(5), (S, 1, 1))

@@ -123,7 +123,7 @@ def test_ragged_batch_equals_single_tracks(B):
         assert abs(deltas[i] - ref["deltas"][-1]) <= 1e-6 * ref["deltas"][-1] + 1e-12
 
 
-@pytest.mark.parametrize("lanes,slots", [(64, 8), (256, 3)])
+@pytest.mark.parametrize("lanes,slots", [(64, 8), (256, 3), (64, 16)])
 @pytest.mark.parametrize("lin", ["taylor", "cubature"])
 def test_ragged_batch_with_lane_runs(B, lanes, slots, lin):
     """Tracks start and end inside a lane's run of slots and inside a tile;
@@ -198,7 +198,8 @@ def test_fp32_long_track(B, lin):
         assert em < TOL32 and ep < TOL32
 
 
-@pytest.mark.parametrize("lanes,slots", [(64, 1), (64, 2), (64, 3), (256, 1), (256, 2), (256, 4), (256, 8)])
+@pytest.mark.parametrize("lanes,slots", [(64, 1), (64, 2), (64, 3), (64, 16), (64, 32), (256, 1), (256, 2), (256, 4),
+                                         (256, 8), (256, 16)])
 @pytest.mark.parametrize("T", [1, 5, 200, 3000])
 def test_schedules(B, lanes, slots, T):
     """Every (lanes per tile, slots per lane) gives the oracle's result,
@@ -278,10 +279,13 @@ def test_iterate_until_matches_manual_loop(B):
 def test_autotune_picks_a_valid_schedule(B):
     pb = wl.config_c2(3000)
     lanes, slots, ms = B.smoother_autotune(pb, iters=3, lin="cubature")
-    assert lanes in (64, 256) and slots in (1, 2, 4, 8) and ms > 0
+    assert lanes in (64, 256) and slots in (1, 2, 4, 8, 16) and ms > 0
     ref = oracle.smoother(pb, 2, "cubature")
     mean, cov, _, _ = run_gpu(B, pb, 2, "cubature", tile_lanes=lanes, lane_slots=slots)
     assert_parity(mean, cov, ref, what=f"autotuned {lanes}x{slots}")
+    # the square-root form runs 64-lane tiles whatever the candidate says: the
+    # schedule returned is the one the engine ran
+    assert B.smoother_autotune(pb, iters=1, lin="cubature", form="sqrt")[0] == 64
     with pytest.raises(B.SmootherError):          # no schedule fits in 1 MB
         B.smoother_autotune(pb, iters=1, max_device_bytes=1 << 20)
 
@@ -358,7 +362,7 @@ def test_dense_stacked_sigma_points_match_oracle(B, lin):
         assert_parity(mean, cov, one, what=f"dense n=20 T=300 {lin} iteration {start + 1}")
 
 
-@pytest.mark.parametrize("slots", [1, 2, 8])
+@pytest.mark.parametrize("slots", [1, 2, 8, 16, 32])
 def test_dense_schedules_and_ragged_batch(B, slots):
     sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (8, 2))
     parts = [wl.stacked_ct(T, np.random.default_rng([56, T]), sensors=sensors) for T in (1, 9, 70)]
