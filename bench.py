@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 METRIC = "smoothed steps/sec per iteration at T=2^15 FP64; time-to-converge learned vs plain"
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -578,9 +579,11 @@ def measure(name: str, pb, desc: str, lin: str, precision: str, steps: int, warm
     iteration = None
     if dense:
         achieved = units_per_launch / avg_launch_s / 1e12
+        # the full-state engine's linearisation computes in FP64 at either precision
+        peak = FP32_VECTOR_PEAK_TFLOPS if precision == "f32" and dom[1] != "dn_linearize" else FP64_VECTOR_PEAK_TFLOPS
         roofline = {"bound": "alu", "kernel": dom[1], "achieved": round(achieved, 4),
-                    "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 6), "traffic": None,
+                    "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 6), "traffic": None,
                     "avg_launch_us": round(avg_launch_s * 1e6, 3), "flops_per_launch": int(units_per_launch)}
     else:
         achieved = units_per_launch / avg_launch_s / 1e9
@@ -720,23 +723,25 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        # the other two headline shapes, timed in the same run (fewer iterations)
-        for name, steps, warmup in (("c3", 5, 2), ("c5", 5, 2)):
+        # the other two headline shapes, timed in the same run (fewer iterations),
+        # and the full-state shape's FP32 variant
+        for key, name, prec, steps, warmup in (("c3", "c3", "f64", 5, 2), ("c5", "c5", "f64", 5, 2),
+                                               ("c5_f32", "c5", "f32", 5, 2)):
             pbx, descx = make_workload(name)
-            rx = measure(name, pbx, descx, DEFAULT_LIN[name], "f64", steps, warmup, 2)
+            rx = measure(name, pbx, descx, DEFAULT_LIN[name], prec, steps, warmup, 2)
             rx.pop("_sm").close()
             conv = None
             if pbx.n_tracks > 1 and not args.no_converge:
                 sch = rx["schedule"]
                 conv = converge_section(pbx, DEFAULT_LIN[name], (sch["lanes_per_tile"], sch["slots_per_lane"]))
             cpux = None
-            if not args.no_cpu:
+            if not args.no_cpu and prec == "f64":
                 threads = 1 if pbx.n_tracks == 1 else (os.cpu_count() or 1)
                 cpux = cpu_baseline(pbx, DEFAULT_LIN[name], min(args.cpu_seconds, 8.0), threads=threads)
                 log(f"{name} cpu oracle: {cpux['value']:.4g} steps/s ({cpux['sample']})")
-            extra[name] = extra_line(name, rx, cpux)
+            extra[key] = extra_line(name, rx, cpux)
             if conv is not None:
-                extra[name]["time_to_converge"] = conv
+                extra[key]["time_to_converge"] = conv
             del pbx
             torch.cuda.empty_cache()
 

@@ -35,9 +35,11 @@
  *                         rounding); off-block covariance outputs are zero.
  *                         Sigma-point rules couple stacked targets through
  *                         their regression residuals; with them, four targets
- *                         and eight sensors (nx = 20, ny = 8, FP64, any SPD Q,
- *                         R, P0) run on an engine of the full state in which
- *                         one wavefront cooperates on each element.
+ *                         and eight sensors (nx = 20, ny = 8, FP64 or FP32,
+ *                         any SPD Q, R, P0) run on an engine of the full state
+ *                         in which one wavefront cooperates on each element;
+ *                         its FP32 form keeps records, elements and scans in
+ *                         FP32 and computes the regression in FP64.
  *
  * Conventions shared by every call:
  *   - Status: every call returns sm_status and never aborts or throws across the

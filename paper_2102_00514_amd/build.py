@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 UNITS = ["smoother.hip", "engine_ct_f64.hip", "engine_ct_f32.hip", "engine_linear_f64.hip",
-         "engine_linear_f32.hip", "engine_dense_ct_f64.hip", "warmstart.hip"]
+         "engine_linear_f32.hip", "engine_dense_ct_f64.hip", "engine_dense_ct_f32.hip", "warmstart.hip"]
 LIB = os.path.join(PKG, "libsmoother.so")
 # measurement kernels of the nx = 20 engine's matrix products (not linked into LIB)
 PROBE_UNIT = "dense_probe.hip"

@@ -242,8 +242,10 @@ PKS_DEV void vcopy(const R* x, R* y) {
 }
 
 // --- HBM <-> LDS ------------------------------------------------------------
-template <int LDN, int M, int NC, typename R>
-PKS_DEV void ld_full(const R* g, R* A) {
+// The element type in HBM (RG) may differ from the one in LDS (R): the FP32
+// engine's linearisation works in FP64 on its FP32 records.
+template <int LDN, int M, int NC, typename RG, typename R>
+PKS_DEV void ld_full(const RG* g, R* A) {
   // all global loads are issued before the first LDS store (fixed trip
   // counts), so one record costs one memory latency, not one per pass
   constexpr int L = ld<LDN>();
@@ -251,7 +253,7 @@ PKS_DEV void ld_full(const R* g, R* A) {
   R v[RN];
   PKS_UNROLL for (int r = 0; r < RN; ++r) {
     const int e = r * kWave + lane();
-    v[r] = e < T ? g[e] : R(0);
+    v[r] = e < T ? R(g[e]) : R(0);
   }
   PKS_UNROLL for (int r = 0; r < RN; ++r) {
     const int e = r * kWave + lane();
@@ -259,34 +261,34 @@ PKS_DEV void ld_full(const R* g, R* A) {
   }
 }
 // A += g (row-major M x NC in HBM), loads issued first as in ld_full
-template <int LDN, int M, int NC, typename R>
-PKS_DEV void add_full(const R* g, R* A) {
+template <int LDN, int M, int NC, typename RG, typename R>
+PKS_DEV void add_full(const RG* g, R* A) {
   constexpr int L = ld<LDN>();
   constexpr int T = M * NC, RN = (T + kWave - 1) / kWave;
   R v[RN];
   PKS_UNROLL for (int r = 0; r < RN; ++r) {
     const int e = r * kWave + lane();
-    v[r] = e < T ? g[e] : R(0);
+    v[r] = e < T ? R(g[e]) : R(0);
   }
   PKS_UNROLL for (int r = 0; r < RN; ++r) {
     const int e = r * kWave + lane();
     if (e < T) A[(e / NC) * L + e % NC] += v[r];
   }
 }
-template <int LDN, int M, int NC, typename R>
-PKS_DEV void st_full(const R* A, R* g) {
+template <int LDN, int M, int NC, typename R, typename RG>
+PKS_DEV void st_full(const R* A, RG* g) {
   constexpr int L = ld<LDN>();
-  for (int e = lane(); e < M * NC; e += kWave) g[e] = A[(e / NC) * L + e % NC];
+  for (int e = lane(); e < M * NC; e += kWave) g[e] = RG(A[(e / NC) * L + e % NC]);
 }
-template <int LDN, int N, typename R>
-PKS_DEV void ld_symm(const R* g, R* A) {
+template <int LDN, int N, typename RG, typename R>
+PKS_DEV void ld_symm(const RG* g, R* A) {
   constexpr int L = ld<LDN>();
   constexpr int T = N * N, RN = (T + kWave - 1) / kWave;
   R v[RN];
   PKS_UNROLL for (int r = 0; r < RN; ++r) {
     const int e = r * kWave + lane();
     const int i = e / N, j = e - i * N;
-    v[r] = e < T ? g[sym_index<N>(i, j)] : R(0);
+    v[r] = e < T ? R(g[sym_index<N>(i, j)]) : R(0);
   }
   PKS_UNROLL for (int r = 0; r < RN; ++r) {
     const int e = r * kWave + lane();
@@ -294,21 +296,21 @@ PKS_DEV void ld_symm(const R* g, R* A) {
     if (e < T) A[i * L + j] = v[r];
   }
 }
-template <int LDN, int N, typename R>
-PKS_DEV void st_symm(const R* A, R* g) {
+template <int LDN, int N, typename R, typename RG>
+PKS_DEV void st_symm(const R* A, RG* g) {
   constexpr int L = ld<LDN>();
   for (int e = lane(); e < N * N; e += kWave) {
     const int i = e / N, j = e - i * N;
-    if (j >= i) g[sym_index<N>(i, j)] = A[i * L + j];
+    if (j >= i) g[sym_index<N>(i, j)] = RG(A[i * L + j]);
   }
 }
-template <int N, typename R>
-PKS_DEV void ld_v(const R* g, R* x) {
-  for (int i = lane(); i < N; i += kWave) x[i] = g[i];
+template <int N, typename RG, typename R>
+PKS_DEV void ld_v(const RG* g, R* x) {
+  for (int i = lane(); i < N; i += kWave) x[i] = R(g[i]);
 }
-template <int N, typename R>
-PKS_DEV void st_v(const R* x, R* g) {
-  for (int i = lane(); i < N; i += kWave) g[i] = x[i];
+template <int N, typename R, typename RG>
+PKS_DEV void st_v(const R* x, RG* g) {
+  for (int i = lane(); i < N; i += kWave) g[i] = RG(x[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -511,7 +513,8 @@ PKS_DEV void slr(int lin, SigmaRule rule, const R* xbar, R* Pbar, Eval eval, R* 
     if (b < a) continue;
     R s = R(0);
     for (int j = 0; j < N; ++j)
-      s += (Zp[j * L + a] - zbar[a]) * (Zp[j * L + b] - zbar[b]) + (Zm[j * L + a] - zbar[a]) * (Zm[j * L + b] - zbar[b]);
+      s += (Zp[j * L + a] - zbar[a]) * (Zp[j * L + b] - zbar[b]) +
+           (Zm[j * L + a] - zbar[a]) * (Zm[j * L + b] - zbar[b]);
     s = s * wj + w0 * (zc[a] - zbar[a]) * (zc[b] - zbar[b]);
     Lam[a * L + b] = s;
   }
@@ -548,6 +551,9 @@ struct DnArgs {
   const void* params;
   const void* Q;                // N x N full
   const void* Rm;               // P x P full
+  const double* params64;       // the same three in FP64, for the linearisation
+  const double* Q64;
+  const double* Rm64;
   const void* m0;               // [track][N]
   const void* P0;               // [track][N][N] full
   const void* y;                // [slot][P] (slot 0 of a track unused)
@@ -557,6 +563,14 @@ struct DnArgs {
   void* elem;                   // [slot][kFElem]; smoothing elements reuse it
   unsigned long long* delta_bits;
   double lm;                    // Levenberg-Marquardt damping lambda (0 = undamped)
+};
+
+// The same model in another precision (model templates are <N, P, real>).
+template <class M, typename T>
+struct WithReal;
+template <template <int, int, typename> class Mt, int N, int P, typename R, typename T>
+struct WithReal<Mt<N, P, R>, T> {
+  using type = Mt<N, P, T>;
 };
 
 struct DnLevel {
@@ -714,31 +728,35 @@ struct Dense {
 // first) at the current trajectory; one slot per workgroup.
 template <class Model, typename R>
 __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
-  using D = Dense<Model, R>;
+  // The regression runs in FP64 whatever the records' type R: in FP32 its
+  // sums of sigma-point images (z-bar - G x-bar, Phi - D^T D) would cost more
+  // accuracy than the FP32 scan itself.
+  using RC = double;
+  using MC = typename WithReal<Model, RC>::type;
+  using D = Dense<MC, RC>;
   constexpr int N = D::N, P = D::P;
   using Lay = typename D::Lay;
   __shared__ typename D::template WorkN<6> w;
   const int64_t s = blockIdx.x;
   if (s >= a.S) return;
   if (lane() == 0) w.ok = 1;
-  const Model md{static_cast<const R*>(a.params)};
+  const MC md{a.params64};
   const unsigned fl = a.flags[s];
   const R* tj = static_cast<const R*>(a.traj) + size_t(s) * Lay::kTraj;
-  R* xbar = w.v[0];
+  RC* xbar = w.v[0];
   ld_v<N>(tj, xbar);
   wsync();
   bool factored = false;   // w.m[0] holds the Cholesky factor of Pbar, shared by f and h
   if (!(fl & kSlotLast)) {
     ld_symm<N, N>(tj + N, w.m[0]);
     wsync();
-    R* G = w.m[1];
-    R* Lam = w.m[2];
-    slr<N, N, false, R>(a.lin, a.rule, xbar, w.m[0], [&](const R(&x)[N], R(&z)[N]) { md.f(x, z); }, G, w.v[1],
-                        Lam, w.v[2], w.m[3], w.m[4], w.m[5], w.v[3], &w.ok);
+    RC* G = w.m[1];
+    RC* Lam = w.m[2];
+    slr<N, N, false, RC>(a.lin, a.rule, xbar, w.m[0], [&](const RC(&x)[N], RC(&z)[N]) { md.f(x, z); }, G, w.v[1],
+                         Lam, w.v[2], w.m[3], w.m[4], w.m[5], w.v[3], &w.ok);
     factored = true;
     R* out = static_cast<R*>(a.trans) + size_t(s) * Lay::kTrans;
-    const R* Qm = static_cast<const R*>(a.Q);
-    add_full<N, N, N>(Qm, Lam);
+    add_full<N, N, N>(a.Q64, Lam);
     wsync();
     st_full<N, N, N>(G, out);
     st_v<N>(w.v[1], out + N * N);
@@ -750,17 +768,16 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
       ld_symm<N, N>(tj + N, w.m[0]);
       wsync();
     }
-    R* H = w.m[1];
-    R* Om = w.m[2];
-    R* hc = w.v[2];
-    slr<N, P, Model::kAngular, R>(a.lin, a.rule, xbar, w.m[0], [&](const R(&x)[N], R(&z)[P]) { md.h(x, z); }, H,
-                                  w.v[1], Om, hc, w.m[3], w.m[4], w.m[5], w.v[3], &w.ok, factored);
+    RC* H = w.m[1];
+    RC* Om = w.m[2];
+    RC* hc = w.v[2];
+    slr<N, P, MC::kAngular, RC>(a.lin, a.rule, xbar, w.m[0], [&](const RC(&x)[N], RC(&z)[P]) { md.h(x, z); }, H,
+                                w.v[1], Om, hc, w.m[3], w.m[4], w.m[5], w.v[3], &w.ok, factored);
     R* out = static_cast<R*>(a.hlin) + size_t(s) * Lay::kHlin;
-    const R* Rm = static_cast<const R*>(a.Rm);
     const R* y = static_cast<const R*>(a.y) + size_t(s) * P;
-    add_full<N, P, P>(Rm, Om);
+    add_full<N, P, P>(a.Rm64, Om);
     for (int i = lane(); i < P; i += kWave)
-      out[P * N + P + Lay::kSP + i] = Model::kAngular ? hc[i] + wrap_pi<R>(y[i] - hc[i]) : y[i];
+      out[P * N + P + Lay::kSP + i] = R(MC::kAngular ? hc[i] + wrap_pi<RC>(RC(y[i]) - hc[i]) : RC(y[i]));
     wsync();
     st_full<N, P, N>(H, out);
     st_v<P>(w.v[1], out + P * N);

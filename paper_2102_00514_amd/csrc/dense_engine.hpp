@@ -87,6 +87,9 @@ class DenseEngine final : public EngineBase {
     A(&d_params_, sizeof(R) * prm.size());
     A(&d_Q_, sizeof(R) * Q.size());
     A(&d_R_, sizeof(R) * Rm.size());
+    A(reinterpret_cast<void**>(&d_params64_), sizeof(double) * size_t(pb.n_params));   // the linearisation's
+    A(reinterpret_cast<void**>(&d_Q64_), sizeof(double) * N * N);                       // FP64 copies
+    A(reinterpret_cast<void**>(&d_R64_), sizeof(double) * P * P);
     A(&d_m0_, sizeof(R) * m0.size());
     A(&d_P0_, sizeof(R) * P0.size());
     A(&d_y_, sizeof(R) * ys.size());
@@ -142,6 +145,9 @@ class DenseEngine final : public EngineBase {
     H2D(d_params_, prm.data(), sizeof(R) * prm.size());
     H2D(d_Q_, Q.data(), sizeof(R) * Q.size());
     H2D(d_R_, Rm.data(), sizeof(R) * Rm.size());
+    H2D(d_params64_, pb.params, sizeof(double) * size_t(pb.n_params));
+    H2D(d_Q64_, pb.Q, sizeof(double) * N * N);
+    H2D(d_R64_, pb.R, sizeof(double) * P * P);
     H2D(d_m0_, m0.data(), sizeof(R) * m0.size());
     H2D(d_P0_, P0.data(), sizeof(R) * P0.size());
     H2D(d_y_, ys.data(), sizeof(R) * ys.size());
@@ -186,6 +192,9 @@ class DenseEngine final : public EngineBase {
     a.params = d_params_;
     a.Q = d_Q_;
     a.Rm = d_R_;
+    a.params64 = d_params64_;
+    a.Q64 = d_Q64_;
+    a.Rm64 = d_R64_;
     a.m0 = d_m0_;
     a.P0 = d_P0_;
     a.y = d_y_;
@@ -457,6 +466,7 @@ class DenseEngine final : public EngineBase {
   unsigned char* d_flags_ = nullptr;
   int* d_track_ = nullptr;
   void *d_params_ = nullptr, *d_Q_ = nullptr, *d_R_ = nullptr, *d_m0_ = nullptr, *d_P0_ = nullptr, *d_y_ = nullptr;
+  double *d_params64_ = nullptr, *d_Q64_ = nullptr, *d_R64_ = nullptr;
   void *d_traj_ = nullptr, *d_trans_ = nullptr, *d_hlin_ = nullptr, *d_elem_ = nullptr;
   void *d_wq_ = nullptr, *d_wr_ = nullptr, *d_wp0_ = nullptr, *d_filt_ = nullptr;
   int64_t* d_slot_off_ = nullptr;

@@ -360,5 +360,6 @@ EngineBase* make_engine_ct_f32(int nx, int ny);
 EngineBase* make_engine_linear_f64(int nx, int ny);
 EngineBase* make_engine_linear_f32(int nx, int ny);
 EngineBase* make_engine_dense_ct_f64(int nx, int ny);
+EngineBase* make_engine_dense_ct_f32(int nx, int ny);
 
 }  // namespace pks

@@ -110,7 +110,8 @@ static bool stacked(int model, int nx) { return model == SM_MODEL_CT_BEARINGS &&
 // engine of the full state.
 static EngineBase* make_engine(int model, int precision, int nx, int ny, int lin) {
   if (stacked(model, nx)) {
-    if (lin != SM_LIN_TAYLOR) return precision == SM_FP64 ? make_engine_dense_ct_f64(nx, ny) : nullptr;
+    if (lin != SM_LIN_TAYLOR)
+      return precision == SM_FP64 ? make_engine_dense_ct_f64(nx, ny) : make_engine_dense_ct_f32(nx, ny);
     BlockEngine* e = new BlockEngine(&make_dense_engine);
     e->set_precision_word(precision == SM_FP64 ? sizeof(double) : sizeof(float));
     return e;
@@ -122,8 +123,8 @@ static bool supported(int model, int nx, int ny, int lin, int precision) {
   if (model == SM_MODEL_CT_BEARINGS) {
     if (nx == 5) return ny == 2;
     if (!stacked(model, nx)) return false;
-    // sigma points: the compiled full-state engine (four targets, eight sensors, FP64)
-    if (lin != SM_LIN_TAYLOR) return nx == 20 && ny == 8 && precision == SM_FP64;
+    // sigma points: the compiled full-state engine (four targets, eight sensors)
+    if (lin != SM_LIN_TAYLOR) return nx == 20 && ny == 8;
     // Taylor: two sensors per target, blocks run on the (5, 2) kernels
     return nx / 5 <= kMaxTargets && ny == 2 * (nx / 5);
   }

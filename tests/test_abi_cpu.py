@@ -211,8 +211,6 @@ def test_stacked_targets_validation():
 
 
 def test_dense_stacked_scope():
-    pb = wl.config_c5_single(10)
-    _expect_einval(pb, "unsupported", lin="unscented", precision="f32")     # full-state engine is FP64
     sensors = np.random.default_rng(1).uniform(-2, 2, (6, 2))
     pb3 = wl.stacked_ct(10, np.random.default_rng(2), sensors=sensors, n_targets=3, n_sensors=6)
     _expect_einval(pb3, "unsupported", lin="cubature")                      # only (20, 8) is compiled

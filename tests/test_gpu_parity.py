@@ -362,6 +362,49 @@ def test_dense_stacked_sigma_points_match_oracle(B, lin):
         assert_parity(mean, cov, one, what=f"dense n=20 T=300 {lin} iteration {start + 1}")
 
 
+# FP32 full-state engine one iteration from a far iterate at T >= 4096: the
+# FP32 scan's own rounding (its operands stored in FP32) sets this floor
+TOL32_DENSE_FAR = 3e-4
+
+
+def _dense_one_iteration(B, pb, lin, start, **kw):
+    ref = oracle.smoother(pb, start + 1, lin, history=True, filtered=False)
+    im = None if start == 0 else ref["hist_mean"][start - 1]
+    ic = None if start == 0 else ref["hist_cov"][start - 1]
+    mean, cov, _, _ = run_gpu(B, pb, 1, lin, init_mean=im, init_cov=ic, **kw)
+    return mean, cov, {"mean": ref["hist_mean"][start], "cov": ref["hist_cov"][start]}
+
+
+@pytest.mark.parametrize("lin", ["unscented", "cubature"])
+def test_dense_fp32(B, lin):
+    """FP32 variant of the full-state engine: records, elements and scans in
+    FP32, the sigma-point regression in FP64 on the FP32 trajectory.  T = 300
+    from the prior and from the oracle's iterate 2, T = 4096 from the prior at
+    the FP32 gate; T = 4096 from iterate 2 at the far-iterate gate."""
+    for T, start, tol in ((300, 0, TOL32), (300, 2, TOL32), (4096, 0, TOL32), (4096, 2, TOL32_DENSE_FAR)):
+        mean, cov, one = _dense_one_iteration(B, wl.config_c5_single(T), lin, start, precision="f32")
+        assert_parity(mean, cov, one, tol=tol, what=f"dense n=20 FP32 T={T} {lin} iteration {start + 1}")
+
+
+def test_dense_fp32_c5_from_the_prior(B):
+    """The C5 shape (T = 2^16, unscented) in FP32, iteration 1 from the prior."""
+    mean, cov, one = _dense_one_iteration(B, wl.config_c5_single(), "unscented", 0, precision="f32")
+    assert_parity(mean, cov, one, tol=TOL32, what="dense n=20 FP32 T=65536 unscented iteration 1")
+
+
+def test_dense_fp32_ragged_batch(B):
+    sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (8, 2))
+    parts = [wl.stacked_ct(T, np.random.default_rng([56, T]), sensors=sensors) for T in (1, 9, 70)]
+    pb = wl.concat_tracks(parts, "stacked batch")
+    M = 3
+    mean, cov, _, _ = run_gpu(B, pb, M, "unscented", precision="f32")
+    so = pb.slot_offsets()
+    for i in range(pb.n_tracks):
+        ref = oracle.smoother(pb.track(i), M, "unscented")
+        sl = slice(so[i], so[i + 1])
+        assert_parity(mean[sl], cov[sl], ref, tol=TOL32, what=f"dense FP32 M={M} track {i} T={pb.lengths[i]}")
+
+
 @pytest.mark.parametrize("slots", [1, 2, 8, 16, 32])
 def test_dense_schedules_and_ragged_batch(B, slots):
     sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (8, 2))
