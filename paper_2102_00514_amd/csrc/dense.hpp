@@ -45,27 +45,41 @@ template <int LDN, int M, int K, int NC, bool TA, bool TB, typename R>
 PKS_DEV void mm(const R* A, const R* B, const R* C0, R sgn, R* C) {
   constexpr int L = ld<LDN>();
   if constexpr (sizeof(R) == 8 && M == 20 && K == 20 && NC == 20) {
+    // Every LDS read is unconditional and issued before the first MFMA: rows
+    // and columns past 19 of the padded operands read row or column 19 and
+    // are replaced by zero with a select, and result elements past 19 (and
+    // their C0 reads) go to column 20 of the rows, the unused padding of the
+    // LDS layout, instead of being skipped behind branches.
     const int r = lane() & 15, kq = lane() >> 4;
-    f64x4 acc[2][2];
-    PKS_UNROLL for (int i = 0; i < 2; ++i) PKS_UNROLL for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double av[5][2], bv[5][2];
     PKS_UNROLL for (int ks = 0; ks < 5; ++ks) {
       const int k = 4 * ks + kq;   // < 20
-      double av[2], bv[2];
       PKS_UNROLL for (int t = 0; t < 2; ++t) {
-        const int i = 16 * t + r;
-        av[t] = i < 20 ? double(TA ? A[k * L + i] : A[i * L + k]) : 0.0;
-        bv[t] = i < 20 ? double(TB ? B[i * L + k] : B[k * L + i]) : 0.0;
+        const int i = 16 * t + r, ic = i < 20 ? i : 19;
+        const double a = double(TA ? A[k * L + ic] : A[ic * L + k]);
+        const double b = double(TB ? B[ic * L + k] : B[k * L + ic]);
+        av[ks][t] = i < 20 ? a : 0.0;
+        bv[ks][t] = i < 20 ? b : 0.0;
       }
-      PKS_UNROLL for (int ti = 0; ti < 2; ++ti)
-        PKS_UNROLL for (int tj = 0; tj < 2; ++tj)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
     }
+    int at[2][2][4];
+    R c0[2][2][4];
     PKS_UNROLL for (int ti = 0; ti < 2; ++ti)
       PKS_UNROLL for (int tj = 0; tj < 2; ++tj)
         PKS_UNROLL for (int q = 0; q < 4; ++q) {
           const int i = 16 * ti + 4 * q + kq, j = 16 * tj + r;
-          if (i < 20 && j < 20) C[i * L + j] = (C0 ? C0[i * L + j] : R(0)) + sgn * R(acc[ti][tj][q]);
+          at[ti][tj][q] = (i < 20 && j < 20) ? i * L + j : (i < 20 ? i : i - 20) * L + 20;
+          c0[ti][tj][q] = C0 ? C0[at[ti][tj][q]] : R(0);
         }
+    f64x4 acc[2][2];
+    PKS_UNROLL for (int i = 0; i < 2; ++i) PKS_UNROLL for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    PKS_UNROLL for (int ks = 0; ks < 5; ++ks)
+      PKS_UNROLL for (int ti = 0; ti < 2; ++ti)
+        PKS_UNROLL for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][ti], bv[ks][tj], acc[ti][tj], 0, 0, 0);
+    PKS_UNROLL for (int ti = 0; ti < 2; ++ti)
+      PKS_UNROLL for (int tj = 0; tj < 2; ++tj)
+        PKS_UNROLL for (int q = 0; q < 4; ++q) C[at[ti][tj][q]] = c0[ti][tj][q] + sgn * R(acc[ti][tj][q]);
     wsync();
     return;
   }
@@ -206,13 +220,22 @@ PKS_DEV void fwd_vec(const R* Lc, R* x) {
 // A <- (A + A^T) / 2
 template <int LDN, int N, typename R>
 PKS_DEV void symmetrize(R* A) {
+  // all reads issued before the first store (one LDS latency, not one per pass);
+  // each pair (i < j) belongs to one lane
   constexpr int L = ld<LDN>();
-  for (int e = lane(); e < N * N; e += kWave) {
+  constexpr int T = N * N, RN = (T + kWave - 1) / kWave;
+  R v[RN];
+  PKS_UNROLL for (int r = 0; r < RN; ++r) {
+    const int e = r * kWave + lane();
     const int i = e / N, j = e - i * N;
-    if (j > i) {
-      const R v = R(0.5) * (A[i * L + j] + A[j * L + i]);
-      A[i * L + j] = v;
-      A[j * L + i] = v;
+    v[r] = (e < T && j > i) ? R(0.5) * (A[i * L + j] + A[j * L + i]) : R(0);
+  }
+  PKS_UNROLL for (int r = 0; r < RN; ++r) {
+    const int e = r * kWave + lane();
+    const int i = e / N, j = e - i * N;
+    if (e < T && j > i) {
+      A[i * L + j] = v[r];
+      A[j * L + i] = v[r];
     }
   }
   wsync();
@@ -220,10 +243,19 @@ PKS_DEV void symmetrize(R* A) {
 
 template <int LDN, int M, int NC, bool TR, typename R>
 PKS_DEV void copy(const R* A, R* B) {   // B = op(A), M x NC
+  // all reads issued before the first store, as in symmetrize
   constexpr int L = ld<LDN>();
-  for (int e = lane(); e < M * NC; e += kWave) {
+  constexpr int T = M * NC, RN = (T + kWave - 1) / kWave;
+  R v[RN];
+  PKS_UNROLL for (int r = 0; r < RN; ++r) {
+    const int e = r * kWave + lane();
     const int i = e / NC, j = e - i * NC;
-    B[i * L + j] = TR ? A[j * L + i] : A[i * L + j];
+    v[r] = e < T ? (TR ? A[j * L + i] : A[i * L + j]) : R(0);
+  }
+  PKS_UNROLL for (int r = 0; r < RN; ++r) {
+    const int e = r * kWave + lane();
+    const int i = e / NC, j = e - i * NC;
+    if (e < T) B[i * L + j] = v[r];
   }
   wsync();
 }
