@@ -31,16 +31,48 @@ PKS_DEV void wsync() { __syncthreads(); }     // workgroups are a single wave
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// The VALU form of mm below: each lane computes a 2 x 4 block of C, so every
+// LDS word it loads feeds two or four multiply-adds.
+template <int LDN, int M, int K, int NC, bool TA, bool TB, typename R>
+PKS_DEV void mm_valu(const R* A, const R* B, const R* C0, R sgn, R* C) {
+  constexpr int L = ld<LDN>();
+  constexpr int TR = 2, TC = 4;
+  constexpr int MR = (M + TR - 1) / TR, MC = (NC + TC - 1) / TC;
+  for (int t = lane(); t < MR * MC; t += kWave) {
+    const int i0 = (t / MC) * TR, j0 = (t % MC) * TC;
+    R acc[TR][TC];
+    PKS_UNROLL for (int r = 0; r < TR; ++r) PKS_UNROLL for (int c = 0; c < TC; ++c) acc[r][c] = R(0);
+#pragma unroll 4
+    for (int k = 0; k < K; ++k) {
+      R a[TR], b[TC];
+      PKS_UNROLL for (int r = 0; r < TR; ++r) {
+        const int i = i0 + r;
+        a[r] = (M % TR == 0 || i < M) ? (TA ? A[k * L + i] : A[i * L + k]) : R(0);
+      }
+      PKS_UNROLL for (int c = 0; c < TC; ++c) {
+        const int j = j0 + c;
+        b[c] = (NC % TC == 0 || j < NC) ? (TB ? B[j * L + k] : B[k * L + j]) : R(0);
+      }
+      PKS_UNROLL for (int r = 0; r < TR; ++r) PKS_UNROLL for (int c = 0; c < TC; ++c)
+        acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    }
+    PKS_UNROLL for (int r = 0; r < TR; ++r) PKS_UNROLL for (int c = 0; c < TC; ++c) {
+      const int i = i0 + r, j = j0 + c;
+      if ((M % TR == 0 || i < M) && (NC % TC == 0 || j < NC))
+        C[i * L + j] = (C0 ? C0[i * L + j] : R(0)) + sgn * acc[r][c];
+    }
+  }
+  wsync();
+}
+
 // C = C0 + sgn * op(A) op(B), op(A) M x K, op(B) K x NC.  C may alias C0 but
 // not A or B.  C0 may be null (zero).  FP64 20 x 20 x 20 (the full-state
 // blocks): v_mfma_f64_16x16x4f64 on the product padded to 32 x 32, 2 x 2
 // output tiles, 5 steps of 4 along the reduction; lane l feeds A[l % 16][l /
 // 16] and B[l / 16][l % 16] and receives D[4 q + l / 16][l % 16], q = 0..3.
 // Two LDS words per 2048 flops against six per eight multiply-adds on the
-// VALU: 0.66 against 1.19 ns per product over 2048 wavefronts, 0.70 against
-// 1.06 us on one wavefront (libdense_probe.so).  Other shapes: each lane
-// computes a 2 x 4 block of C, so every LDS word it loads feeds two or four
-// multiply-adds.
+// VALU (mm_valu, measured against it by libdense_probe.so).  Other shapes and
+// FP32: mm_valu.
 template <int LDN, int M, int K, int NC, bool TA, bool TB, typename R>
 PKS_DEV void mm(const R* A, const R* B, const R* C0, R sgn, R* C) {
   constexpr int L = ld<LDN>();
@@ -83,33 +115,7 @@ PKS_DEV void mm(const R* A, const R* B, const R* C0, R sgn, R* C) {
     wsync();
     return;
   }
-  constexpr int TR = 2, TC = 4;
-  constexpr int MR = (M + TR - 1) / TR, MC = (NC + TC - 1) / TC;
-  for (int t = lane(); t < MR * MC; t += kWave) {
-    const int i0 = (t / MC) * TR, j0 = (t % MC) * TC;
-    R acc[TR][TC];
-    PKS_UNROLL for (int r = 0; r < TR; ++r) PKS_UNROLL for (int c = 0; c < TC; ++c) acc[r][c] = R(0);
-#pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-      R a[TR], b[TC];
-      PKS_UNROLL for (int r = 0; r < TR; ++r) {
-        const int i = i0 + r;
-        a[r] = (M % TR == 0 || i < M) ? (TA ? A[k * L + i] : A[i * L + k]) : R(0);
-      }
-      PKS_UNROLL for (int c = 0; c < TC; ++c) {
-        const int j = j0 + c;
-        b[c] = (NC % TC == 0 || j < NC) ? (TB ? B[j * L + k] : B[k * L + j]) : R(0);
-      }
-      PKS_UNROLL for (int r = 0; r < TR; ++r) PKS_UNROLL for (int c = 0; c < TC; ++c)
-        acc[r][c] = fma(a[r], b[c], acc[r][c]);
-    }
-    PKS_UNROLL for (int r = 0; r < TR; ++r) PKS_UNROLL for (int c = 0; c < TC; ++c) {
-      const int i = i0 + r, j = j0 + c;
-      if ((M % TR == 0 || i < M) && (NC % TC == 0 || j < NC))
-        C[i * L + j] = (C0 ? C0[i * L + j] : R(0)) + sgn * acc[r][c];
-    }
-  }
-  wsync();
+  mm_valu<LDN, M, K, NC, TA, TB, R>(A, B, C0, sgn, C);
 }
 
 // y = y0 + sgn * op(A) x, op(A) M x K.  y may alias y0 but not x.
