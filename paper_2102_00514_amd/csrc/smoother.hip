@@ -383,7 +383,10 @@ sm_status smoother_autotune(const sm_problem* pb, void* hip_stream, int32_t iter
         sm_status st = eng->setup(q, stream);
         if (st == SM_OK) {
           const std::pair<int, int> actual{eng->sched_lanes, eng->sched_slots};
-          if (std::find(timed.begin(), timed.end(), actual) != timed.end()) continue;
+          if (std::find(timed.begin(), timed.end(), actual) != timed.end()) {
+            (void)hipStreamSynchronize(stream);   // setup's work done before the handle is released
+            continue;
+          }
           timed.push_back(actual);
           st = eng->iterate(1);                                 // warm-up (and graph capture)
         }

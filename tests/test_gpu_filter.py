@@ -159,6 +159,30 @@ def test_dense_engine(B, lin, fan):
         assert_filter_parity(mean[sl], cov[sl], ll[i], ref, what=f"n=20 {lin} fan {fan} track {i} after 2 iterations")
 
 
+def test_dense_engine_fp32(B):
+    """The FP32 form of the nx = 20 engine: filtered moments and log-likelihood
+    at the prior, per track of a ragged batch.  The log-likelihood is held to
+    1e-4; the filtered moments to 1e-3: a tree-order FP32 prefix scan loses
+    more on them than the smoother does on its output, and on the 130-step
+    track FP32 storage of the scan's operands alone (each combine exact, on
+    the CPU with the oracle's operators) already costs 1.0e-4 on the means and
+    2.1e-4 on the covariances."""
+    sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (8, 2))
+    parts = [wl.stacked_ct(T, np.random.default_rng([58, T]), sensors=sensors) for T in (40, 1, 130)]
+    pb = wl.concat_tracks(parts, "stacked batch")
+    so = pb.slot_offsets()
+    with B.Smoother(pb, n_iter=1, lin="unscented", precision="f32") as sm:
+        mean, cov, ll = sm.filter()
+    for i in range(pb.n_tracks):
+        sl = slice(so[i], so[i + 1])
+        ref = oracle.filter_loglik(pb.track(i), "unscented")
+        em = oracle.mean_error(mean[sl], ref["filt_mean"])
+        ep = oracle.cov_error(cov[sl], ref["filt_cov"])
+        el = abs(ll[i] - ref["loglik"]) / max(abs(ref["loglik"]), 1.0)
+        print(f"n=20 FP32 filter track {i}: e_m={em:.3e} e_P={ep:.3e} e_ll={el:.3e}", flush=True)
+        assert em < 1e-3 and ep < 1e-3 and el < 1e-4
+
+
 def test_dense_engine_objective(B):
     sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (8, 2))
     parts = [wl.stacked_ct(T, np.random.default_rng([59, T]), sensors=sensors) for T in (60, 1, 17)]
