@@ -32,8 +32,8 @@ sampled C5 batch tracks take this path at step 2:
 One named exception to the gate: step 1 of C3 track 0 (T = 6667) is held to
 1e-8.  These priors set the turn rate to zero, and on that track the first
 iteration moves the trajectory by 633 units; there the parallel scan's FP64
-result differs from the sequential oracle by 6.6e-9 (2.3e-9 for the track
-alone, whose 14 tiles take the single-block top scan instead of the batch's
+result differs from the sequential oracle by 6.6e-9 (3.6e-9 for the track
+alone, whose 7 tiles take the single-block top scan instead of the batch's
 multi-level one; the oracle in FP64 and in 80-bit agree to 4e-12), while the same track from the oracle's iterate 2
 agrees to 4.3e-11, and every other sampled C3 track agrees to 1.3e-10 at
 step 1.  The gap is the method's in FP64: test_scan_conditioning shows

@@ -169,13 +169,13 @@ def test_stacked_taylor_blocks(B):
 
 def test_c3_track0_first_iteration(B):
     """The ill-conditioned first step of C3 track 0 (T = 6667, moves by 633),
-    in the benchmark's 64 x 8 schedule: the square-root form at the FP64 gate,
+    in the benchmark's 64 x 16 schedule: the square-root form at the FP64 gate,
     the covariance form at the named exception's 1e-8."""
     pb = wl.config_c3(n_tracks=1)
     ref = oracle.smoother(pb, 1, "cubature")
     res = {}
     for form in ("covariance", "sqrt"):
-        mean, cov, _, _ = run_gpu(B, pb, 1, "cubature", form=form, tile_lanes=64, lane_slots=8)
+        mean, cov, _, _ = run_gpu(B, pb, 1, "cubature", form=form, tile_lanes=64, lane_slots=16)
         res[form] = errors(mean, cov, ref["mean"], ref["cov"])
     print(f"C3 track 0 iteration 1: covariance e_m={res['covariance'][0]:.3e} e_P={res['covariance'][1]:.3e}; "
           f"sqrt e_m={res['sqrt'][0]:.3e} e_P={res['sqrt'][1]:.3e}", flush=True)
