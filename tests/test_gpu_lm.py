@@ -309,3 +309,33 @@ def test_adaptive_needs_taylor_and_objective_engine(B):
     with B.Smoother(wl.config_c5_single(20), n_iter=1, lin="unscented") as sm:
         with pytest.raises(B.SmootherError, match="not built"):
             sm.iterate_lm()
+
+
+def _c5_batch_track(i):
+    """Track i of the C5 batch on its own: its length, states and noises come
+    from default_rng([5, 1 + i]) in the batch's order (stacked_ct draws the
+    same; only the rounding of the noise products may differ)."""
+    rng = np.random.default_rng([5, 1 + i])
+    T = int(rng.integers(1024, 2 ** 16 + 1))
+    sensors = np.random.default_rng([5, 0]).uniform(-2.0, 2.0, (8, 2))
+    return wl.stacked_ct(T, rng, sensors=sensors)
+
+
+def test_damping_holds_a_diverging_stacked_track(B):
+    """C5 batch track 180 (T = 62736, four targets, unscented) diverges under
+    the undamped iteration: its means pass 1e4 within two iterations.  With a
+    fixed damping lambda = 10 (Section 3's damped extension) the iterates stay
+    bounded, and the device's third damped iterate equals the oracle's."""
+    pb = _c5_batch_track(180)
+    assert pb.lengths[0] == 62736
+    mean, _, _ = run_gpu(B, pb, 2, "unscented")
+    undamped = float(np.nanmax(np.abs(mean)))
+    M, lam = 3, 10.0
+    ref = oracle.smoother(pb, M, "unscented", lm_lambda=lam, filtered=False)
+    mean, cov, deltas = run_gpu(B, pb, M, "unscented", lm_lambda=lam)
+    damped = float(np.max(np.abs(mean)))
+    print(f"track 180: max |mean| undamped after 2 iterations {undamped:.3e}, damped (lambda={lam}) after {M} "
+          f"{damped:.3e}", flush=True)
+    assert undamped > 1e4 and damped < 100.0
+    assert_parity(mean, cov, ref, what=f"track 180 damped lambda={lam} M={M}")
+    assert abs(deltas[0] - ref["deltas"][-1]) <= 1e-6 * ref["deltas"][-1] + 1e-12
