@@ -736,14 +736,17 @@ def main():
     extra = {}
     if not args.no_extra:
         # the other two headline shapes, timed in the same run (fewer iterations),
-        # and the full-state shape's FP32 variant
+        # the full-state shape's FP32 variant, and the full-state batch (256
+        # tracks, 161 GB of device memory; its fixed default schedule, since
+        # trying five would build five such plans)
         for key, name, prec, steps, warmup in (("c3", "c3", "f64", 5, 2), ("c5", "c5", "f64", 5, 2),
-                                               ("c5_f32", "c5", "f32", 5, 2)):
+                                               ("c5_f32", "c5", "f32", 5, 2), ("c5batch", "c5batch", "f64", 3, 1)):
             pbx, descx = make_workload(name)
-            rx = measure(name, pbx, descx, DEFAULT_LIN[name], prec, steps, warmup, 2)
+            rx = measure(name, pbx, descx, DEFAULT_LIN[name], prec, steps, warmup, 1 if key == "c5batch" else 2,
+                         autotune=key != "c5batch")
             rx.pop("_sm").close()
             conv = None
-            if pbx.n_tracks > 1 and not args.no_converge:
+            if key == "c3" and not args.no_converge:     # the batch the time-to-converge comparison is on
                 sch = rx["schedule"]
                 conv = converge_section(pbx, DEFAULT_LIN[name], (sch["lanes_per_tile"], sch["slots_per_lane"]))
             cpux = None
