@@ -447,27 +447,29 @@ PKS_DEV void combine_f(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, const R* 
   if (!(lb[0] == lb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, lA, lb, lC);
 }
 
-// Carry (b, C) (x) r: the filtered mean and covariance after element r.
+// Carry (b, C) (x) r: the filtered mean and covariance after element r.  The
+// carry's covariance holds its Cholesky factor and then M while the result is
+// formed, and rJ holds G and its factor, so one scratch matrix T suffices
+// (fewer live matrices, more waves per CU); rJ is destroyed.
 template <int N, typename R>
-PKS_DEV void apply_f(R* cb, R* cC, const R* rA, const R* rb, const R* rC, const R* re, const R* rJ, R* T1, R* T2,
-                     R* T3, R* v1, R* v2, int* ok) {
-  copy<N, N, N, false>(cC, T1);
-  chol<N, N>(T1, ok);
-  mm<N, N, N, N, false, false>(rJ, T1, (const R*)nullptr, R(1), T2);
-  mm<N, N, N, N, true, false>(T1, T2, (const R*)nullptr, R(1), T3);
-  for (int i = lane(); i < N; i += kWave) T3[i * ld<N>() + i] += R(1);
+PKS_DEV void apply_f(R* cb, R* cC, const R* rA, const R* rb, const R* rC, const R* re, R* rJ, R* T, R* v1, R* v2,
+                     int* ok) {
+  mv<N, N, N, false>(rJ, cb, re, R(-1), v1);            // v = eta - J b, before rJ is reused
+  chol<N, N>(cC, ok);                                   // U
+  mm<N, N, N, N, false, false>(rJ, cC, (const R*)nullptr, R(1), T);      // J U
+  mm<N, N, N, N, true, false>(cC, T, (const R*)nullptr, R(1), rJ);       // U^T J U
+  for (int i = lane(); i < N; i += kWave) rJ[i * ld<N>() + i] += R(1);  // G
   wsync();
-  chol<N, N>(T3, ok);
-  copy<N, N, N, true>(T1, T2);
-  fwd<N, N, N>(T3, T2);
-  mm<N, N, N, N, true, false>(T2, T2, (const R*)nullptr, R(1), T1);      // M
-  mv<N, N, N, false>(rJ, cb, re, R(-1), v1);            // v
-  mv<N, N, N, false>(T1, v1, (const R*)nullptr, R(1), v2);               // u
+  chol<N, N>(rJ, ok);                                   // Lg
+  copy<N, N, N, true>(cC, T);                           // U^T
+  fwd<N, N, N>(rJ, T);                                  // W = Lg^-1 U^T
+  mm<N, N, N, N, true, false>(T, T, (const R*)nullptr, R(1), cC);        // M = W^T W
+  mv<N, N, N, false>(cC, v1, (const R*)nullptr, R(1), v2);               // u = M v
   for (int i = lane(); i < N; i += kWave) v1[i] = cb[i] + v2[i];
   wsync();
   mv<N, N, N, false>(rA, v1, rb, R(1), cb);
-  mm<N, N, N, N, false, false>(rA, T1, (const R*)nullptr, R(1), T3);
-  mm<N, N, N, N, false, true>(T3, rA, rC, R(1), cC);
+  mm<N, N, N, N, false, false>(rA, cC, (const R*)nullptr, R(1), T);      // A M
+  mm<N, N, N, N, false, true>(T, rA, rC, R(1), cC);     // A M A^T + C
   symmetrize<N, N>(cC);
   if (!(cb[0] == cb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, (R*)nullptr, cb, cC);
 }
@@ -853,7 +855,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
 // Up-sweep of a scan level: fold `fan` consecutive aggregates.  FILT selects
 // the operator (filtering: records of kFElem words; smoothing: kSElem).
 template <class Model, bool FILT, typename R>
-__global__ __launch_bounds__(kWave) void k_dn_scan_up(DnArgs a, DnLevel lv) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_dn_scan_up(DnArgs a, DnLevel lv) {
   using D = Dense<Model, R>;
   constexpr int N = D::N;
   using Lay = typename D::Lay;
@@ -888,12 +890,12 @@ __global__ __launch_bounds__(kWave) void k_dn_scan_up(DnArgs a, DnLevel lv) {
 // smoothing runs backward (the last element overall has none: it ends at a
 // last slot).
 template <class Model, bool FILT, typename R>
-__global__ __launch_bounds__(kWave) void k_dn_scan_down(DnArgs a, DnLevel lv) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_dn_scan_down(DnArgs a, DnLevel lv) {
   using D = Dense<Model, R>;
   constexpr int N = D::N;
   using Lay = typename D::Lay;
   constexpr int RW = FILT ? Lay::kFElem : Lay::kSElem;
-  __shared__ typename D::template WorkN<7> w;
+  __shared__ typename D::template WorkN<5> w;
   if (lane() == 0) w.ok = 1;
   const int64_t c = blockIdx.x;
   const int64_t i0 = c * lv.fan;
@@ -901,7 +903,7 @@ __global__ __launch_bounds__(kWave) void k_dn_scan_down(DnArgs a, DnLevel lv) {
   const int64_t nchunks = (lv.n + lv.fan - 1) / lv.fan;
   const R* in = static_cast<const R*>(lv.in);
   R* cout = static_cast<R*>(lv.carry_out);
-  R *cx = w.v[6], *cP = w.m[6];
+  R *cx = w.v[6], *cP = w.m[4];
   R *rA = w.m[0], *rC = w.m[1], *rJ = w.m[2], *rb = w.v[0], *re = w.v[1];
   bool have = FILT ? c > 0 : c < nchunks - 1;
   if (have) D::load_carry(static_cast<const R*>(lv.carry_in) + size_t(c) * Lay::kCarry, cx, cP);
@@ -915,7 +917,7 @@ __global__ __launch_bounds__(kWave) void k_dn_scan_down(DnArgs a, DnLevel lv) {
     if (FILT) {
       D::load_felem(in + size_t(i) * RW, rA, rb, rC, re, rJ);
       if (have) {
-        apply_f<N, R>(cx, cP, rA, rb, rC, re, rJ, w.m[3], w.m[4], w.m[5], w.v[2], w.v[3], &w.ok);
+        apply_f<N, R>(cx, cP, rA, rb, rC, re, rJ, w.m[3], w.v[2], w.v[3], &w.ok);
       } else {
         vcopy<N>(rb, cx);
         copy<N, N, N, false>(rC, cP);
@@ -938,41 +940,42 @@ __global__ __launch_bounds__(kWave) void k_dn_scan_down(DnArgs a, DnLevel lv) {
 // element (eq. 17-18, stored over the filtering element) and the chunk's
 // smoothing aggregate.
 template <class Model, typename R>
-__global__ __launch_bounds__(kWave) void k_dn_forward_down_backward_up(DnArgs a, int fan, const void* carry_in,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_dn_forward_down_backward_up(DnArgs a, int fan, const void* carry_in,
                                                                        void* sagg_out) {
   using D = Dense<Model, R>;
   constexpr int N = D::N;
   using Lay = typename D::Lay;
   constexpr int L = ld<N>();
-  __shared__ typename D::W w;
+  __shared__ typename D::template WorkN<7> w;
   if (lane() == 0) w.ok = 1;
   const int64_t c = blockIdx.x;
   const int64_t s0 = c * fan;
   const int64_t s1 = min(s0 + fan, a.S);
-  R *cx = w.v[6], *cP = w.m[8];                       // filtered mean / covariance (carry)
+  R *cx = w.v[6], *cP = w.m[4];                       // filtered mean / covariance (carry)
   R *rA = w.m[0], *rC = w.m[1], *rJ = w.m[2], *rb = w.v[0], *re = w.v[1];
-  R *sE = w.m[6], *sL = w.m[7], *sg = w.v[7];          // smoothing aggregate
+  R *sE = w.m[5], *sL = w.m[6], *sg = w.v[7];          // smoothing aggregate
   bool have = c > 0;
   if (have) D::load_carry(static_cast<const R*>(carry_in) + size_t(c) * Lay::kCarry, cx, cP);
   for (int64_t s = s0; s < s1; ++s) {
     R* rec = static_cast<R*>(a.elem) + size_t(s) * Lay::kFElem;
     D::load_felem(rec, rA, rb, rC, re, rJ);
     if (have) {
-      apply_f<N, R>(cx, cP, rA, rb, rC, re, rJ, w.m[3], w.m[4], w.m[5], w.v[2], w.v[3], &w.ok);
+      apply_f<N, R>(cx, cP, rA, rb, rC, re, rJ, w.m[3], w.v[2], w.v[3], &w.ok);
     } else {
       vcopy<N>(rb, cx);
       copy<N, N, N, false>(rC, cP);
     }
     have = true;
-    // smoothing element of slot s into (eE, eg, eL) = (rA, rb, rC)
-    R *eE = rA, *eg = rb, *eL = rC;
+    // smoothing element of slot s into (eE, eg, eL) = (m[2], rb, rC): the
+    // filtering element is spent (rJ is F below, then E)
+    R *eE = w.m[2], *eg = rb, *eL = rC;
     if (a.flags[s] & kSlotLast) {
       zero<N, N, N>(eE);
       vcopy<N>(cx, eg);
       copy<N, N, N, false>(cP, eL);
     } else {
       const R* tr = static_cast<const R*>(a.trans) + size_t(s) * Lay::kTrans;
-      R *F = w.m[2], *FP = w.m[3], *Pp = w.m[4], *V = w.m[3];
+      R *F = w.m[2], *FP = w.m[3], *Pp = w.m[0], *V = w.m[3];
       R *r = w.v[2], *t = w.v[3];
       ld_full<N, N, N>(tr, F);
       ld_symm<N, N>(tr + N * N + N, Pp);
@@ -997,7 +1000,7 @@ __global__ __launch_bounds__(kWave) void k_dn_forward_down_backward_up(DnArgs a,
       copy<N, N, N, false>(eL, sL);
       vcopy<N>(eg, sg);
     } else {
-      combine_s<N, R>(sE, sg, sL, eE, eg, eL, w.m[3], w.m[4], w.v[2]);
+      combine_s<N, R>(sE, sg, sL, eE, eg, eL, w.m[0], w.m[3], w.v[2]);
     }
   }
   (void)L;
@@ -1079,24 +1082,24 @@ __global__ __launch_bounds__(kWave) void k_dn_backward_down(DnArgs a, int fan, c
 // elements): level 0 down-sweep that stores the filtered x*, P* of every slot
 // of the chunk as a trajectory-layout record [slot][kTraj].
 template <class Model, typename R>
-__global__ __launch_bounds__(kWave) void k_dn_forward_down_filter(DnArgs a, int fan, const void* carry_in,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_dn_forward_down_filter(DnArgs a, int fan, const void* carry_in,
                                                                   void* filt) {
   using D = Dense<Model, R>;
   constexpr int N = D::N;
   using Lay = typename D::Lay;
-  __shared__ typename D::W w;
+  __shared__ typename D::template WorkN<5> w;
   if (lane() == 0) w.ok = 1;
   const int64_t c = blockIdx.x;
   const int64_t s0 = c * fan;
   const int64_t s1 = min(s0 + fan, a.S);
-  R *cx = w.v[6], *cP = w.m[8];
+  R *cx = w.v[6], *cP = w.m[4];
   R *rA = w.m[0], *rC = w.m[1], *rJ = w.m[2], *rb = w.v[0], *re = w.v[1];
   bool have = c > 0;
   if (have) D::load_carry(static_cast<const R*>(carry_in) + size_t(c) * Lay::kCarry, cx, cP);
   for (int64_t s = s0; s < s1; ++s) {
     D::load_felem(static_cast<const R*>(a.elem) + size_t(s) * Lay::kFElem, rA, rb, rC, re, rJ);
     if (have) {
-      apply_f<N, R>(cx, cP, rA, rb, rC, re, rJ, w.m[3], w.m[4], w.m[5], w.v[2], w.v[3], &w.ok);
+      apply_f<N, R>(cx, cP, rA, rb, rC, re, rJ, w.m[3], w.v[2], w.v[3], &w.ok);
     } else {
       vcopy<N>(rb, cx);
       copy<N, N, N, false>(rC, cP);

@@ -111,10 +111,10 @@ __global__ __launch_bounds__(64) void k_phases(unsigned long long* out, int reps
     PHASE(7, (pks::dn::symmetrize<N, N>(lJ)))
     PHASE(8, (pks::dn::combine_f<N, double>(lA, w.v[0], lC, w.v[1], lJ, rA, w.v[2], rC, w.v[3], rJ, T1, T2, T3,
                                              w.v[4], w.v[5], &w.ok)))
+    pks::dn::copy<N, N, N, false>(rJ, T3);   // apply_f destroys its J operand
     spd(lC, 2.0, 0.3);
     __syncthreads();
-    PHASE(9, (pks::dn::apply_f<N, double>(w.v[0], lC, rA, w.v[2], rC, w.v[3], rJ, T1, T2, T3, w.v[4], w.v[5],
-                                           &w.ok)))
+    PHASE(9, (pks::dn::apply_f<N, double>(w.v[0], lC, rA, w.v[2], rC, w.v[3], T3, T1, w.v[4], w.v[5], &w.ok)))
     spd(lA, 0.5, 0.05);
     __syncthreads();
     PHASE(10, (pks::dn::combine_s<N, double>(lA, w.v[0], lC, rA, w.v[2], rC, T1, T2, w.v[4])))
