@@ -506,7 +506,9 @@ PKS_DEV void apply_s(const R* rE, const R* rg, const R* rL, R* cg, R* cL, R* T1,
 // with the symmetric sigma-point set of elements.hpp (slr): one sigma point
 // per lane.  Inputs xbar (LDS vector) and Pbar (LDS matrix, destroyed: it
 // becomes its Cholesky factor).  Outputs G (Q x N, LDS), off = zbar - G xbar,
-// Lam (Q x Q), zc = g(xbar).  Zp, Zm, D: N x Q scratch; zbar: Q vector.
+// Lam (Q x Q), zc = g(xbar).  Zp, Zm, D: N x Q scratch; zbar: Q vector.  D may
+// be Zp and G may be Zm (D is formed in place once Phi has read the images,
+// G once D is done with them), so the regression fits in four matrices.
 template <int N, int Q, bool kAngular, typename R, class Eval>
 PKS_DEV void slr(int lin, SigmaRule rule, const R* xbar, R* Pbar, Eval eval, R* G, R* off, R* Lam, R* zc, R* Zp,
                  R* Zm, R* D, R* zbar, int* ok, bool factored = false) {
@@ -542,11 +544,6 @@ PKS_DEV void slr(int lin, SigmaRule rule, const R* xbar, R* Pbar, Eval eval, R* 
     zbar[q] = w0 * zc[q] + wj * s;
   }
   wsync();
-  const R wg = wj * gamma;
-  for (int e = lane(); e < N * Q; e += kWave) {
-    const int j = e / Q, q = e - j * Q;
-    D[j * L + q] = wg * (Zp[j * L + q] - Zm[j * L + q]);
-  }
   // Lambda = Phi - D^T D, Phi = sum_j w_j (Z_j - zbar)(Z_j - zbar)^T
   for (int e = lane(); e < Q * Q; e += kWave) {
     const int a = e / Q, b = e - a * Q;
@@ -557,6 +554,12 @@ PKS_DEV void slr(int lin, SigmaRule rule, const R* xbar, R* Pbar, Eval eval, R* 
            (Zm[j * L + a] - zbar[a]) * (Zm[j * L + b] - zbar[b]);
     s = s * wj + w0 * (zc[a] - zbar[a]) * (zc[b] - zbar[b]);
     Lam[a * L + b] = s;
+  }
+  wsync();
+  const R wg = wj * gamma;
+  for (int e = lane(); e < N * Q; e += kWave) {
+    const int j = e / Q, q = e - j * Q;
+    D[j * L + q] = wg * (Zp[j * L + q] - Zm[j * L + q]);
   }
   wsync();
   for (int e = lane(); e < Q * Q; e += kWave) {
@@ -776,7 +779,7 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
   using D = Dense<MC, RC>;
   constexpr int N = D::N, P = D::P;
   using Lay = typename D::Lay;
-  __shared__ typename D::template WorkN<6> w;
+  __shared__ typename D::template WorkN<4> w;   // Pbar's factor; images and D; images and G; Lambda
   const int64_t s = blockIdx.x;
   if (s >= a.S) return;
   if (lane() == 0) w.ok = 1;
@@ -790,10 +793,10 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
   if (!(fl & kSlotLast)) {
     ld_symm<N, N>(tj + N, w.m[0]);
     wsync();
-    RC* G = w.m[1];
-    RC* Lam = w.m[2];
+    RC* G = w.m[2];
+    RC* Lam = w.m[3];
     slr<N, N, false, RC>(a.lin, a.rule, xbar, w.m[0], [&](const RC(&x)[N], RC(&z)[N]) { md.f(x, z); }, G, w.v[1],
-                         Lam, w.v[2], w.m[3], w.m[4], w.m[5], w.v[3], &w.ok);
+                         Lam, w.v[2], w.m[1], w.m[2], w.m[1], w.v[3], &w.ok);
     factored = true;
     R* out = static_cast<R*>(a.trans) + size_t(s) * Lay::kTrans;
     add_full<N, N, N>(a.Q64, Lam);
@@ -808,11 +811,11 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
       ld_symm<N, N>(tj + N, w.m[0]);
       wsync();
     }
-    RC* H = w.m[1];
-    RC* Om = w.m[2];
+    RC* H = w.m[2];
+    RC* Om = w.m[3];
     RC* hc = w.v[2];
     slr<N, P, MC::kAngular, RC>(a.lin, a.rule, xbar, w.m[0], [&](const RC(&x)[N], RC(&z)[P]) { md.h(x, z); }, H,
-                                w.v[1], Om, hc, w.m[3], w.m[4], w.m[5], w.v[3], &w.ok, factored);
+                                w.v[1], Om, hc, w.m[1], w.m[2], w.m[1], w.v[3], &w.ok, factored);
     R* out = static_cast<R*>(a.hlin) + size_t(s) * Lay::kHlin;
     const R* y = static_cast<const R*>(a.y) + size_t(s) * P;
     add_full<N, P, P>(a.Rm64, Om);
