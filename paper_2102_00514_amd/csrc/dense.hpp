@@ -371,6 +371,7 @@ struct Layout {
 template <int N, typename R, int NM>
 struct Work {
   static constexpr int MW = mat_words<N>();
+  static constexpr int kNM = NM;
   R m[NM][MW];
   R v[8][N];       // vectors
   int ok;
@@ -472,6 +473,50 @@ PKS_DEV void apply_f(R* cb, R* cC, const R* rA, const R* rb, const R* rC, const 
   mm<N, N, N, N, false, true>(T, rA, rC, R(1), cC);     // A M A^T + C
   symmetrize<N, N>(cC);
   if (!(cb[0] == cb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, (R*)nullptr, cb, cC);
+}
+
+// l <- l (x) r as combine_f, in two scratch matrices instead of three: l's C
+// holds its Cholesky factor and then M, rC holds G, its factor and Y, rJ holds
+// A_j M, and C_j is read back from gC (the right element's record in global
+// memory, written before the call; symmetric packed) when the result's C is
+// formed.  rJ and rC are destroyed (rC ends holding C_j again).  The same
+// operations on the same values as combine_f, so the same results bit for bit.
+template <int N, typename R, typename RG>
+PKS_DEV void combine_f_lean(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, const R* rb, R* rC, const R* re,
+                            R* rJ, const RG* gC, R* T, R* v1, R* v2, int* ok) {
+  mv<N, N, N, false>(rJ, lb, re, R(-1), v1);            // v = eta_j - J b_i
+  chol<N, N>(lC, ok);                                   // U
+  mm<N, N, N, N, false, false>(rJ, lC, (const R*)nullptr, R(1), T);      // J U
+  mm<N, N, N, N, true, false>(lC, T, (const R*)nullptr, R(1), rC);       // U^T J U
+  for (int i = lane(); i < N; i += kWave) rC[i * ld<N>() + i] += R(1);  // G
+  wsync();
+  chol<N, N>(rC, ok);                                   // Lg
+  copy<N, N, N, true>(lC, T);                           // U^T
+  fwd<N, N, N>(rC, T);                                  // W = Lg^-1 U^T
+  mm<N, N, N, N, true, false>(T, T, (const R*)nullptr, R(1), lC);        // M = W^T W
+  mm<N, N, N, N, false, false>(rJ, lA, (const R*)nullptr, R(1), rC);     // Y = J A_i
+  mm<N, N, N, N, false, false>(lC, rC, (const R*)nullptr, R(1), T);      // Z = M Y
+  mv<N, N, N, false>(lC, v1, (const R*)nullptr, R(1), v2);               // u = M v
+  mm<N, N, N, N, true, false>(lA, rC, lJ, R(1), lJ);
+  mm<N, N, N, N, true, false>(rC, T, lJ, R(-1), lJ);
+  mv<N, N, N, true>(lA, v1, le, R(1), le);
+  mv<N, N, N, true>(rC, v2, le, R(-1), le);
+  symmetrize<N, N>(lJ);
+  for (int i = lane(); i < N; i += kWave) v1[i] = lb[i] + v2[i];
+  wsync();
+  mv<N, N, N, false>(rA, v1, rb, R(1), lb);
+  mm<N, N, N, N, false, false>(rA, lC, (const R*)nullptr, R(1), rJ);     // A_j M
+  ld_symm<N, N>(gC, rC);                                // C_j
+  wsync();
+  mm<N, N, N, N, false, true>(rJ, rA, rC, R(1), lC);
+  symmetrize<N, N>(lC);
+  for (int e = lane(); e < N * N; e += kWave) {
+    const int i = e / N, j = e - i * N;
+    T[i * ld<N>() + j] = lA[i * ld<N>() + j] - T[i * ld<N>() + j];
+  }
+  wsync();
+  mm<N, N, N, N, false, false>(rA, T, (const R*)nullptr, R(1), lA);
+  if (!(lb[0] == lb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, lA, lb, lC);
 }
 
 // --- the smoothing operator (eq. 19) ------------------------------------------
@@ -633,8 +678,15 @@ struct Dense {
   template <int NM>
   using WorkN = Work<N, R, NM>;
 
-  // element a_s into (A, b, C, eta, J) in the given LDS buffers
-  static PKS_DEV void build_element(const DnArgs& a, int64_t s, W& w, R* A, R* b, R* C, R* e, R* J) {
+  // element a_s into (A, b, C, eta, J) in the given LDS buffers, with one
+  // scratch matrix T: F and Q' are read into A's and C's buffers (A and C are
+  // formed over them), S and H into rows 0..P-1 and P..2P-1 of J's buffer (J
+  // is formed last), H Q' and H F into the same rows of T.  A work area of
+  // nine matrices also takes the Levenberg-Marquardt damping (w.m[6..8]).
+  template <class WT>
+  static PKS_DEV void build_element(const DnArgs& a, int64_t s, WT& w, R* T, R* A, R* b, R* C, R* e, R* J) {
+    static_assert(2 * P <= N, "S and H share one matrix buffer");
+    constexpr int L = ld<N>();
     const unsigned fl = a.flags[s];
     if (fl & kSlotFirst) {
       const int tr = a.track[s];
@@ -644,19 +696,21 @@ struct Dense {
       ld_full<N, N, N>(static_cast<const R*>(a.P0) + size_t(tr) * N * N, C);
       for (int i = lane(); i < N; i += kWave) e[i] = R(0);
       wsync();
-      if (a.lm > 0.0) lm_damp(a, s, w, A, b, C, e, J);
+      if constexpr (WT::kNM >= 9) {
+        if (a.lm > 0.0) lm_damp(a, s, w, A, b, C, e, J);
+      }
       return;
     }
     // transition out of slot s - 1, measurement at slot s
     const R* tr = static_cast<const R*>(a.trans) + size_t(s - 1) * Lay::kTrans;
     const R* hl = static_cast<const R*>(a.hlin) + size_t(s) * Lay::kHlin;
-    R* F = w.m[6];
-    R* Qp = w.m[7];
-    R* H = w.m[8];
+    R* F = A;
+    R* Qp = C;
+    R* Sx = J;          // P x P
+    R* H = J + P * L;   // P x N
     R* c = w.v[4];
     R* d = w.v[5];
     R* yt = w.v[6];
-    R* Sx = J;          // P x P scratch (J is written last)
     ld_full<N, N, N>(tr, F);
     ld_v<N>(tr + N * N, c);
     ld_symm<N, N>(tr + N * N + N, Qp);
@@ -665,8 +719,8 @@ struct Dense {
     ld_symm<N, P>(hl + P * N + P, Sx);
     ld_v<P>(hl + P * N + P + Lay::kSP, yt);
     wsync();
-    R* HQ = C;          // P x N
-    R* HF = A;          // P x N  (A is formed from F and the scratch at the end)
+    R* HQ = T;          // P x N
+    R* HF = T + P * L;  // P x N
     mm<N, P, N, N, false, false>(H, Qp, (const R*)nullptr, R(1), HQ);
     mm<N, P, N, N, false, false>(H, F, (const R*)nullptr, R(1), HF);
     mm<N, P, N, P, false, true>(HQ, H, Sx, R(1), Sx);                      // S = H Q' H^T + R'
@@ -679,15 +733,14 @@ struct Dense {
     fwd_vec<N, P>(Sx, yt);                                                  // ws = Ls^-1 w
     mv<N, N, P, true>(HQ, yt, c, R(1), b);                                  // b = c + Zs^T ws
     mv<N, N, P, true>(HF, yt, (const R*)nullptr, R(1), e);                  // eta = Ys^T ws
-    mm<N, N, P, N, true, false>(HQ, HF, F, R(-1), H);                       // A = F - Zs^T Ys  (into H)
-    mm<N, N, P, N, true, false>(HQ, HQ, Qp, R(-1), F);                      // C = Q' - Zs^T Zs (into F)
-    mm<N, N, P, N, true, false>(HF, HF, (const R*)nullptr, R(1), Qp);       // J = Ys^T Ys (into Qp)
-    copy<N, N, N, false>(H, A);
-    copy<N, N, N, false>(F, C);
-    copy<N, N, N, false>(Qp, J);
+    mm<N, N, P, N, true, false>(HQ, HF, F, R(-1), A);                       // A = F - Zs^T Ys
+    mm<N, N, P, N, true, false>(HQ, HQ, Qp, R(-1), C);                      // C = Q' - Zs^T Zs
+    mm<N, N, P, N, true, false>(HF, HF, (const R*)nullptr, R(1), J);       // J = Ys^T Ys
     symmetrize<N, N>(C);
     symmetrize<N, N>(J);
-    if (a.lm > 0.0) lm_damp(a, s, w, A, b, C, e, J);
+    if constexpr (WT::kNM >= 9) {
+      if (a.lm > 0.0) lm_damp(a, s, w, A, b, C, e, J);
+    }
   }
 
   // Levenberg-Marquardt damping of the element of slot s (Section 3, damped
@@ -697,7 +750,8 @@ struct Dense {
   //   A -= lambda Z^T V,  b += lambda Z^T v,  C -= lambda Z^T Z,
   //   J += lambda V^T V,  eta += lambda V^T v.
   // Scratch: w.m[6..8], w.v[4] (free once the element is built).
-  static PKS_DEV void lm_damp(const DnArgs& a, int64_t s, W& w, R* A, R* b, R* C, R* e, R* J) {
+  template <class WT>
+  static PKS_DEV void lm_damp(const DnArgs& a, int64_t s, WT& w, R* A, R* b, R* C, R* e, R* J) {
     constexpr int L = ld<N>();
     const R lam = R(a.lm);
     const R* xbar = static_cast<const R*>(a.traj) + size_t(s) * Lay::kTraj;
@@ -829,17 +883,20 @@ __global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
 }
 
 // Level 0 of the filtering scan: build the elements of `fan` consecutive
-// slots, store them, and fold them into the chunk aggregate.
-template <class Model, typename R>
+// slots, store them, and fold them into the chunk aggregate.  The aggregate,
+// the element being folded in and one scratch matrix take seven matrices
+// (24.8 KB in FP64: six waves per CU); the damped form (kDamp, lambda > 0)
+// has two more for the damping.
+template <class Model, typename R, bool kDamp>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_dn_forward_up(DnArgs a, int fan, void* agg_out) {
   using D = Dense<Model, R>;
   constexpr int N = D::N;
   using Lay = typename D::Lay;
-  __shared__ typename D::W w;
+  __shared__ typename D::template WorkN<kDamp ? 9 : 7> w;
   if (lane() == 0) w.ok = 1;
   const int64_t s0 = int64_t(blockIdx.x) * fan;
   const int64_t s1 = min(s0 + fan, a.S);
-  R *lA = w.m[0], *lC = w.m[1], *lJ = w.m[2], *rA = w.m[3], *rC = w.m[4], *rJ = w.m[5];
+  R *lA = w.m[0], *lC = w.m[1], *lJ = w.m[2], *rA = w.m[3], *rJ = w.m[4], *rC = w.m[5], *T = w.m[6];
   R *lb = w.v[0], *le = w.v[1], *rb = w.v[2], *re = w.v[3];
   for (int64_t s = s0; s < s1; ++s) {
     R* A = s == s0 ? lA : rA;
@@ -847,10 +904,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
     R* J = s == s0 ? lJ : rJ;
     R* b = s == s0 ? lb : rb;
     R* e = s == s0 ? le : re;
-    D::build_element(a, s, w, A, b, C, e, J);
-    D::store_felem(A, b, C, e, J, static_cast<R*>(a.elem) + size_t(s) * Lay::kFElem);
+    R* rec = static_cast<R*>(a.elem) + size_t(s) * Lay::kFElem;
+    D::build_element(a, s, w, T, A, b, C, e, J);
+    D::store_felem(A, b, C, e, J, rec);
     if (s > s0)
-      combine_f<N, R>(lA, lb, lC, le, lJ, rA, rb, rC, re, rJ, w.m[6], w.m[7], w.m[8], w.v[4], w.v[5], &w.ok);
+      combine_f_lean<N, R>(lA, lb, lC, le, lJ, rA, rb, rC, re, rJ, rec + N * N + N, T, w.v[4], w.v[5], &w.ok);
   }
   D::store_felem(lA, lb, lC, le, lJ, static_cast<R*>(agg_out) + size_t(blockIdx.x) * Lay::kFElem);
 }

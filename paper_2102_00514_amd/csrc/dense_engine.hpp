@@ -244,8 +244,12 @@ class DenseEngine final : public EngineBase {
       hipLaunchKernelGGL((dn::k_dn_linearize<Model, R>), dim3(unsigned(S)), dim3(dn::kWave), 0, stream, a);
     });
     timed("dn_forward_up", S, [&] {
-      hipLaunchKernelGGL((dn::k_dn_forward_up<Model, R>), dim3(c0), dim3(dn::kWave), 0, stream, a, fan0_,
-                         fagg_[0]);
+      if (a.lm > 0.0)
+        hipLaunchKernelGGL((dn::k_dn_forward_up<Model, R, true>), dim3(c0), dim3(dn::kWave), 0, stream, a, fan0_,
+                           fagg_[0]);
+      else
+        hipLaunchKernelGGL((dn::k_dn_forward_up<Model, R, false>), dim3(c0), dim3(dn::kWave), 0, stream, a, fan0_,
+                           fagg_[0]);
     });
     scan_levels<true>();
     // stores each slot's smoothing element over its filtering element: one launch even under repeats
@@ -420,7 +424,8 @@ class DenseEngine final : public EngineBase {
     a.lm = 0.0;
     const unsigned c0 = unsigned(counts_[0]);
     hipLaunchKernelGGL((dn::k_dn_linearize<Model, R>), dim3(unsigned(S)), dim3(dn::kWave), 0, stream, a);
-    hipLaunchKernelGGL((dn::k_dn_forward_up<Model, R>), dim3(c0), dim3(dn::kWave), 0, stream, a, fan0_, fagg_[0]);
+    hipLaunchKernelGGL((dn::k_dn_forward_up<Model, R, false>), dim3(c0), dim3(dn::kWave), 0, stream, a, fan0_,
+                       fagg_[0]);   // a.lm is 0 here
     const double lm_saved = lm_;
     lm_ = 0.0;                       // the scan levels take their arguments from args()
     scan_levels<true>();
