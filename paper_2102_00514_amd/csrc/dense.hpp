@@ -475,6 +475,35 @@ PKS_DEV void apply_f(R* cb, R* cC, const R* rA, const R* rb, const R* rC, const 
   if (!(cb[0] == cb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, (R*)nullptr, cb, cC);
 }
 
+// apply_f with C_j read from gC (the element's record in global memory,
+// symmetric packed) only for the last step, into rJ's buffer: the element
+// occupies two LDS matrices (rA, rJ) and the call one scratch matrix T.  rJ
+// is destroyed.  The same operations on the same values as apply_f.
+template <int N, typename R, typename RG>
+PKS_DEV void apply_f_lean(R* cb, R* cC, const R* rA, const R* rb, const RG* gC, const R* re, R* rJ, R* T, R* v1,
+                          R* v2, int* ok) {
+  mv<N, N, N, false>(rJ, cb, re, R(-1), v1);            // v = eta - J b, before rJ is reused
+  chol<N, N>(cC, ok);                                   // U
+  mm<N, N, N, N, false, false>(rJ, cC, (const R*)nullptr, R(1), T);      // J U
+  mm<N, N, N, N, true, false>(cC, T, (const R*)nullptr, R(1), rJ);       // U^T J U
+  for (int i = lane(); i < N; i += kWave) rJ[i * ld<N>() + i] += R(1);  // G
+  wsync();
+  chol<N, N>(rJ, ok);                                   // Lg
+  copy<N, N, N, true>(cC, T);                           // U^T
+  fwd<N, N, N>(rJ, T);                                  // W = Lg^-1 U^T
+  mm<N, N, N, N, true, false>(T, T, (const R*)nullptr, R(1), cC);        // M = W^T W
+  mv<N, N, N, false>(cC, v1, (const R*)nullptr, R(1), v2);               // u = M v
+  for (int i = lane(); i < N; i += kWave) v1[i] = cb[i] + v2[i];
+  wsync();
+  mv<N, N, N, false>(rA, v1, rb, R(1), cb);
+  mm<N, N, N, N, false, false>(rA, cC, (const R*)nullptr, R(1), T);      // A M
+  ld_symm<N, N>(gC, rJ);                                // C
+  wsync();
+  mm<N, N, N, N, false, true>(T, rA, rJ, R(1), cC);     // A M A^T + C
+  symmetrize<N, N>(cC);
+  if (!(cb[0] == cb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rJ, (R*)nullptr, cb, cC);
+}
+
 // l <- l (x) r as combine_f, in two scratch matrices instead of three: l's C
 // holds its Cholesky factor and then M, rC holds G, its factor and Y, rJ holds
 // A_j M, and C_j is read back from gC (the right element's record in global
@@ -521,6 +550,7 @@ PKS_DEV void combine_f_lean(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, cons
 
 // --- the smoothing operator (eq. 19) ------------------------------------------
 // l <- l (x) r in the paper's order (l earlier in time): (E_l E_r, E_l g_r + g_l, E_l L_r E_l^T + L_l).
+// T1 and T2 are scratch and may be the same matrix.
 template <int N, typename R>
 PKS_DEV void combine_s(R* lE, R* lg, R* lL, const R* rE, const R* rg, const R* rL, R* T1, R* T2, R* v1) {
   // E_l = 0 (a track's end element or an aggregate holding one): the result
@@ -1007,36 +1037,42 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
   constexpr int N = D::N;
   using Lay = typename D::Lay;
   constexpr int L = ld<N>();
-  __shared__ typename D::template WorkN<7> w;
+  __shared__ typename D::template WorkN<6> w;
   if (lane() == 0) w.ok = 1;
   const int64_t c = blockIdx.x;
   const int64_t s0 = c * fan;
   const int64_t s1 = min(s0 + fan, a.S);
-  R *cx = w.v[6], *cP = w.m[4];                       // filtered mean / covariance (carry)
-  R *rA = w.m[0], *rC = w.m[1], *rJ = w.m[2], *rb = w.v[0], *re = w.v[1];
-  R *sE = w.m[5], *sL = w.m[6], *sg = w.v[7];          // smoothing aggregate
+  R *cx = w.v[6], *cP = w.m[3];                       // filtered mean / covariance (carry)
+  R *rA = w.m[0], *rJ = w.m[1], *T = w.m[2], *rb = w.v[0], *re = w.v[1];
+  R *sE = w.m[4], *sL = w.m[5], *sg = w.v[7];          // smoothing aggregate
   bool have = c > 0;
   if (have) D::load_carry(static_cast<const R*>(carry_in) + size_t(c) * Lay::kCarry, cx, cP);
   for (int64_t s = s0; s < s1; ++s) {
     R* rec = static_cast<R*>(a.elem) + size_t(s) * Lay::kFElem;
-    D::load_felem(rec, rA, rb, rC, re, rJ);
+    const R* recC = rec + N * N + N;                   // the element's C stays in the record
+    ld_full<N, N, N>(rec, rA);
+    ld_v<N>(rec + N * N, rb);
+    ld_v<N>(rec + N * N + N + Lay::kS, re);
+    ld_symm<N, N>(rec + N * N + 2 * N + Lay::kS, rJ);
+    wsync();
     if (have) {
-      apply_f<N, R>(cx, cP, rA, rb, rC, re, rJ, w.m[3], w.v[2], w.v[3], &w.ok);
+      apply_f_lean<N, R>(cx, cP, rA, rb, recC, re, rJ, T, w.v[2], w.v[3], &w.ok);
     } else {
       vcopy<N>(rb, cx);
-      copy<N, N, N, false>(rC, cP);
+      ld_symm<N, N>(recC, cP);
+      wsync();
     }
     have = true;
-    // smoothing element of slot s into (eE, eg, eL) = (m[2], rb, rC): the
-    // filtering element is spent (rJ is F below, then E)
-    R *eE = w.m[2], *eg = rb, *eL = rC;
+    // smoothing element of slot s into (eE, eg, eL) = (m[0], rb, m[1]): the
+    // filtering element is spent
+    R *eE = w.m[0], *eg = rb, *eL = w.m[1];
     if (a.flags[s] & kSlotLast) {
       zero<N, N, N>(eE);
       vcopy<N>(cx, eg);
       copy<N, N, N, false>(cP, eL);
     } else {
       const R* tr = static_cast<const R*>(a.trans) + size_t(s) * Lay::kTrans;
-      R *F = w.m[2], *FP = w.m[3], *Pp = w.m[0], *V = w.m[3];
+      R *F = w.m[1], *FP = w.m[2], *Pp = w.m[0], *V = w.m[2];
       R *r = w.v[2], *t = w.v[3];
       ld_full<N, N, N>(tr, F);
       ld_symm<N, N>(tr + N * N + N, Pp);
@@ -1061,7 +1097,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
       copy<N, N, N, false>(eL, sL);
       vcopy<N>(eg, sg);
     } else {
-      combine_s<N, R>(sE, sg, sL, eE, eg, eL, w.m[0], w.m[3], w.v[2]);
+      combine_s<N, R>(sE, sg, sL, eE, eg, eL, T, T, w.v[2]);
     }
   }
   (void)L;
