@@ -951,7 +951,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
   constexpr int N = D::N;
   using Lay = typename D::Lay;
   constexpr int RW = FILT ? Lay::kFElem : Lay::kSElem;
-  __shared__ typename D::template WorkN<FILT ? 9 : 6> w;
+  __shared__ typename D::template WorkN<FILT ? 7 : 6> w;
   if (lane() == 0) w.ok = 1;
   const int64_t i0 = int64_t(blockIdx.x) * lv.fan;
   const int64_t i1 = min(i0 + lv.fan, lv.n);
@@ -960,9 +960,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
   if (FILT) {
     D::load_felem(in + size_t(i0) * RW, w.m[0], w.v[0], w.m[1], w.v[1], w.m[2]);
     for (int64_t i = i0 + 1; i < i1; ++i) {
-      D::load_felem(in + size_t(i) * RW, w.m[3], w.v[2], w.m[4], w.v[3], w.m[5]);
-      combine_f<N, R>(w.m[0], w.v[0], w.m[1], w.v[1], w.m[2], w.m[3], w.v[2], w.m[4], w.v[3], w.m[5], w.m[6],
-                      w.m[7], w.m[8], w.v[4], w.v[5], &w.ok);
+      // the right operand's C stays in its record until the combine's last step
+      const R* g = in + size_t(i) * RW;
+      ld_full<N, N, N>(g, w.m[3]);
+      ld_v<N>(g + N * N, w.v[2]);
+      ld_v<N>(g + N * N + N + Lay::kS, w.v[3]);
+      ld_symm<N, N>(g + N * N + 2 * N + Lay::kS, w.m[5]);
+      wsync();
+      combine_f_lean<N, R>(w.m[0], w.v[0], w.m[1], w.v[1], w.m[2], w.m[3], w.v[2], w.m[4], w.v[3], w.m[5],
+                           g + N * N + N, w.m[6], w.v[4], w.v[5], &w.ok);
     }
     D::store_felem(w.m[0], w.v[0], w.m[1], w.v[1], w.m[2], out);
   } else {
