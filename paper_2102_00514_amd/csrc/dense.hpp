@@ -587,32 +587,31 @@ PKS_DEV void apply_s(const R* rE, const R* rg, const R* rL, R* cg, R* cL, R* T1,
 template <int N, int Q, bool kAngular, typename R, class Eval>
 PKS_DEV void slr(int lin, SigmaRule rule, const R* xbar, R* Pbar, Eval eval, R* G, R* off, R* Lam, R* zc, R* Zp,
                  R* Zm, R* D, R* zbar, int* ok, bool factored = false) {
-  static_assert(2 * N <= kWave, "one sigma point per lane");
   constexpr int L = ld<N>();
   if (!factored) chol<N, N>(Pbar, ok);    // else Pbar already holds the factor
   R gamma, w0, wj;
   sigma_weights<N, R>(lin, rule, gamma, w0, wj);
-  if (lane() == 0) {
-    R x[N], z[Q];
-    PKS_UNROLL for (int i = 0; i < N; ++i) x[i] = xbar[i];
-    eval(x, z);
-    PKS_UNROLL for (int q = 0; q < Q; ++q) zc[q] = z[q];
-  }
-  wsync();
-  if (lane() < 2 * N) {
-    const int j = lane() < N ? lane() : lane() - N;
+  // all 2N + 1 points in one pass: lane 2N takes the centre
+  static_assert(2 * N + 1 <= kWave, "one sigma point per lane");
+  if (lane() <= 2 * N) {
+    const bool centre = lane() == 2 * N;
+    const int j = lane() < N ? lane() : (centre ? 0 : lane() - N);
     const R sg = lane() < N ? gamma : -gamma;
     R x[N], z[Q];
-    PKS_UNROLL for (int i = 0; i < N; ++i) x[i] = xbar[i] + sg * Pbar[i * L + j];
+    PKS_UNROLL for (int i = 0; i < N; ++i) x[i] = centre ? xbar[i] : xbar[i] + sg * Pbar[i * L + j];
     eval(x, z);
-    R* out = lane() < N ? Zp : Zm;
-    PKS_UNROLL for (int q = 0; q < Q; ++q) {
-      R v = z[q];
-      if constexpr (kAngular) v = zc[q] + wrap_pi<R>(v - zc[q]);
-      out[j * L + q] = v;
-    }
+    R* out = centre ? zc : (lane() < N ? Zp + j * L : Zm + j * L);
+    PKS_UNROLL for (int q = 0; q < Q; ++q) out[q] = z[q];
   }
   wsync();
+  if constexpr (kAngular) {   // each image on the branch of the centre's
+    for (int e = lane(); e < 2 * N * Q; e += kWave) {
+      const int jj = e / Q, q = e - jj * Q;
+      R* v = (jj < N ? Zp + jj * L : Zm + (jj - N) * L) + q;
+      *v = zc[q] + wrap_pi<R>(*v - zc[q]);
+    }
+    wsync();
+  }
   for (int q = lane(); q < Q; q += kWave) {
     R s = R(0);
     for (int j = 0; j < N; ++j) s += Zp[j * L + q] + Zm[j * L + q];
@@ -854,7 +853,7 @@ struct Dense {
 // Linearisation of f (all but the last slot of a track) and h (all but the
 // first) at the current trajectory; one slot per workgroup.
 template <class Model, typename R>
-__global__ __launch_bounds__(kWave) void k_dn_linearize(DnArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_dn_linearize(DnArgs a) {
   // The regression runs in FP64 whatever the records' type R: in FP32 its
   // sums of sigma-point images (z-bar - G x-bar, Phi - D^T D) would cost more
   // accuracy than the FP32 scan itself.
