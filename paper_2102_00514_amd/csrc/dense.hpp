@@ -917,7 +917,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
 // (24.8 KB in FP64: six waves per CU); the damped form (kDamp, lambda > 0)
 // has two more for the damping.
 template <class Model, typename R, bool kDamp>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_dn_forward_up(DnArgs a, int fan, void* agg_out) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2))) void k_dn_forward_up(DnArgs a, int fan, void* agg_out) {
   using D = Dense<Model, R>;
   constexpr int N = D::N;
   using Lay = typename D::Lay;
@@ -1036,7 +1036,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
 // element (eq. 17-18, stored over the filtering element) and the chunk's
 // smoothing aggregate.
 template <class Model, typename R>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_dn_forward_down_backward_up(DnArgs a, int fan, const void* carry_in,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2))) void k_dn_forward_down_backward_up(DnArgs a, int fan, const void* carry_in,
                                                                        void* sagg_out) {
   using D = Dense<Model, R>;
   constexpr int N = D::N;
