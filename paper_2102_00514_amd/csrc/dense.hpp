@@ -406,7 +406,9 @@ PKS_DEV void take_restart(const R* rA, const R* rb, const R* rC, R* lA, R* lb, R
 
 // --- the filtering operator (eq. 15), symmetric pivot-free form ------------
 // l <- l (x) r with l = (lA, lb, lC, le, lJ), r = (rA, rb, rC, re, rJ);
-// T1..T3 scratch.  Same algebra as FilterOp::combine.
+// T1..T3 scratch.  Same algebra as FilterOp::combine.  The kernels use
+// combine_f_lean below (the same operations in fewer LDS matrices); this
+// all-LDS form is the one the routine-cycle probe times.
 template <int N, typename R>
 PKS_DEV void combine_f(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, const R* rb, const R* rC, const R* re,
                        const R* rJ, R* T1, R* T2, R* T3, R* v1, R* v2, int* ok) {
