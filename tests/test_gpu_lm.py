@@ -150,6 +150,23 @@ def test_dense_sigma_points(B, slots):
         assert_parity(mean, cov, one, what=f"dense n=20 unscented lambda=0.5 slots={slots} iteration {start + 1}")
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-13), ("f32", 1e-6)])
+def test_dense_damped_kernel_at_vanishing_lambda(B, precision, tol):
+    """The n = 20 engine launches a level-0 filtering kernel with a larger LDS
+    work area when lambda > 0 (the damping's scratch) and the seven-matrix one
+    otherwise.  At lambda = 1e-300 the damping changes nothing measurable, so
+    the two kernels must agree on a ragged batch over two iterations."""
+    pb = wl.config_c5_batch(6, 200, 700)
+    kw = dict(lane_slots=4, precision=precision)
+    m0, c0, _ = run_gpu(B, pb, 2, "unscented", **kw)
+    m1, c1, _ = run_gpu(B, pb, 2, "unscented", lm_lambda=1e-300, **kw)
+    em = float(np.max(np.abs(m1 - m0)) / max(1.0, float(np.max(np.abs(m0)))))
+    ep = float(np.max(np.abs(c1 - c0)) / max(1.0, float(np.max(np.abs(c0)))))
+    print(f"damped vs undamped kernel, lambda=1e-300, {precision}: {em:.2e} {ep:.2e}", flush=True)
+    assert np.all(np.isfinite(m0)) and np.all(np.isfinite(c0))
+    assert em < tol and ep < tol, (em, ep)
+
+
 def test_damped_fixed_point_is_undamped_fixed_point(B):
     """Section 3: the damping term vanishes at a fixed point, so damped and
     undamped iterations converge to the same trajectory."""
