@@ -405,142 +405,43 @@ PKS_DEV void take_restart(const R* rA, const R* rb, const R* rC, R* lA, R* lb, R
 }
 
 // --- the filtering operator (eq. 15), symmetric pivot-free form ------------
-// l <- l (x) r with l = (lA, lb, lC, le, lJ), r = (rA, rb, rC, re, rJ);
-// T1..T3 scratch.  Same algebra as FilterOp::combine.  The kernels use
-// combine_f_lean below (the same operations in fewer LDS matrices); this
-// all-LDS form is the one the routine-cycle probe times.
-template <int N, typename R>
-PKS_DEV void combine_f(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, const R* rb, const R* rC, const R* re,
-                       const R* rJ, R* T1, R* T2, R* T3, R* v1, R* v2, int* ok) {
-  copy<N, N, N, false>(lC, T1);
-  chol<N, N>(T1, ok);                                   // U
-  mm<N, N, N, N, false, false>(rJ, T1, (const R*)nullptr, R(1), T2);     // J U
-  mm<N, N, N, N, true, false>(T1, T2, (const R*)nullptr, R(1), T3);      // U^T J U
-  for (int i = lane(); i < N; i += kWave) T3[i * ld<N>() + i] += R(1);  // G
-  wsync();
-  chol<N, N>(T3, ok);                                   // Lg
-  copy<N, N, N, true>(T1, T2);                          // U^T
-  fwd<N, N, N>(T3, T2);                                 // W = Lg^-1 U^T
-  mm<N, N, N, N, true, false>(T2, T2, (const R*)nullptr, R(1), T1);      // M = W^T W
-  mm<N, N, N, N, false, false>(rJ, lA, (const R*)nullptr, R(1), T3);     // Y = J A_i
-  mm<N, N, N, N, false, false>(T1, T3, (const R*)nullptr, R(1), T2);     // Z = M Y
+// l <- l (x) r with l = (lA, lb, lC, le, lJ), r = (rA, rb, C_j, re, rJ).  Same
+// algebra as FilterOp::combine.  l's C holds its Cholesky factor and then M
+// while the result is formed, S holds G, its factor and Y, rJ holds A_j M (rJ
+// and S are destroyed), T is scratch.  C_j enters only the last step:
+// getC(S) returns it as an LDS operand (it may read it into S, free by then).
+template <int N, typename R, class GetC>
+PKS_DEV void combine_f_impl(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, const R* rb, const R* re, R* rJ, R* S,
+                            R* T, R* v1, R* v2, int* ok, GetC getC) {
   mv<N, N, N, false>(rJ, lb, re, R(-1), v1);            // v = eta_j - J b_i
-  mv<N, N, N, false>(T1, v1, (const R*)nullptr, R(1), v2);               // u = M v
+  chol<N, N>(lC, ok);                                   // U
+  mm<N, N, N, N, false, false>(rJ, lC, (const R*)nullptr, R(1), T);      // J U
+  mm<N, N, N, N, true, false>(lC, T, (const R*)nullptr, R(1), S);        // U^T J U
+  for (int i = lane(); i < N; i += kWave) S[i * ld<N>() + i] += R(1);   // G
+  wsync();
+  chol<N, N>(S, ok);                                    // Lg
+  copy<N, N, N, true>(lC, T);                           // U^T
+  fwd<N, N, N>(S, T);                                   // W = Lg^-1 U^T
+  mm<N, N, N, N, true, false>(T, T, (const R*)nullptr, R(1), lC);        // M = W^T W
+  mm<N, N, N, N, false, false>(rJ, lA, (const R*)nullptr, R(1), S);      // Y = J A_i
+  mm<N, N, N, N, false, false>(lC, S, (const R*)nullptr, R(1), T);       // Z = M Y
+  mv<N, N, N, false>(lC, v1, (const R*)nullptr, R(1), v2);               // u = M v
   // J_ij = A_i^T Y - Y^T Z + J_i ; eta_ij = A_i^T v - Y^T u + eta_i
-  mm<N, N, N, N, true, false>(lA, T3, lJ, R(1), lJ);
-  mm<N, N, N, N, true, false>(T3, T2, lJ, R(-1), lJ);
+  mm<N, N, N, N, true, false>(lA, S, lJ, R(1), lJ);
+  mm<N, N, N, N, true, false>(S, T, lJ, R(-1), lJ);
   mv<N, N, N, true>(lA, v1, le, R(1), le);
-  mv<N, N, N, true>(T3, v2, le, R(-1), le);
+  mv<N, N, N, true>(S, v2, le, R(-1), le);
   symmetrize<N, N>(lJ);
   // b_ij = A_j (b_i + u) + b_j
   for (int i = lane(); i < N; i += kWave) v1[i] = lb[i] + v2[i];
   wsync();
   mv<N, N, N, false>(rA, v1, rb, R(1), lb);
   // C_ij = A_j M A_j^T + C_j
-  mm<N, N, N, N, false, false>(rA, T1, (const R*)nullptr, R(1), T3);
-  mm<N, N, N, N, false, true>(T3, rA, rC, R(1), lC);
-  symmetrize<N, N>(lC);
-  // A_ij = A_j (A_i - Z)
-  for (int e = lane(); e < N * N; e += kWave) {
-    const int i = e / N, j = e - i * N;
-    T2[i * ld<N>() + j] = lA[i * ld<N>() + j] - T2[i * ld<N>() + j];
-  }
-  wsync();
-  mm<N, N, N, N, false, false>(rA, T2, (const R*)nullptr, R(1), lA);
-  if (!(lb[0] == lb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, lA, lb, lC);
-}
-
-// Carry (b, C) (x) r: the filtered mean and covariance after element r.  The
-// carry's covariance holds its Cholesky factor and then M while the result is
-// formed, and rJ holds G and its factor, so one scratch matrix T suffices
-// (fewer live matrices, more waves per CU); rJ is destroyed.
-template <int N, typename R>
-PKS_DEV void apply_f(R* cb, R* cC, const R* rA, const R* rb, const R* rC, const R* re, R* rJ, R* T, R* v1, R* v2,
-                     int* ok) {
-  mv<N, N, N, false>(rJ, cb, re, R(-1), v1);            // v = eta - J b, before rJ is reused
-  chol<N, N>(cC, ok);                                   // U
-  mm<N, N, N, N, false, false>(rJ, cC, (const R*)nullptr, R(1), T);      // J U
-  mm<N, N, N, N, true, false>(cC, T, (const R*)nullptr, R(1), rJ);       // U^T J U
-  for (int i = lane(); i < N; i += kWave) rJ[i * ld<N>() + i] += R(1);  // G
-  wsync();
-  chol<N, N>(rJ, ok);                                   // Lg
-  copy<N, N, N, true>(cC, T);                           // U^T
-  fwd<N, N, N>(rJ, T);                                  // W = Lg^-1 U^T
-  mm<N, N, N, N, true, false>(T, T, (const R*)nullptr, R(1), cC);        // M = W^T W
-  mv<N, N, N, false>(cC, v1, (const R*)nullptr, R(1), v2);               // u = M v
-  for (int i = lane(); i < N; i += kWave) v1[i] = cb[i] + v2[i];
-  wsync();
-  mv<N, N, N, false>(rA, v1, rb, R(1), cb);
-  mm<N, N, N, N, false, false>(rA, cC, (const R*)nullptr, R(1), T);      // A M
-  mm<N, N, N, N, false, true>(T, rA, rC, R(1), cC);     // A M A^T + C
-  symmetrize<N, N>(cC);
-  if (!(cb[0] == cb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, (R*)nullptr, cb, cC);
-}
-
-// apply_f with C_j read from gC (the element's record in global memory,
-// symmetric packed) only for the last step, into rJ's buffer: the element
-// occupies two LDS matrices (rA, rJ) and the call one scratch matrix T.  rJ
-// is destroyed.  The same operations on the same values as apply_f.
-template <int N, typename R, typename RG>
-PKS_DEV void apply_f_lean(R* cb, R* cC, const R* rA, const R* rb, const RG* gC, const R* re, R* rJ, R* T, R* v1,
-                          R* v2, int* ok) {
-  mv<N, N, N, false>(rJ, cb, re, R(-1), v1);            // v = eta - J b, before rJ is reused
-  chol<N, N>(cC, ok);                                   // U
-  mm<N, N, N, N, false, false>(rJ, cC, (const R*)nullptr, R(1), T);      // J U
-  mm<N, N, N, N, true, false>(cC, T, (const R*)nullptr, R(1), rJ);       // U^T J U
-  for (int i = lane(); i < N; i += kWave) rJ[i * ld<N>() + i] += R(1);  // G
-  wsync();
-  chol<N, N>(rJ, ok);                                   // Lg
-  copy<N, N, N, true>(cC, T);                           // U^T
-  fwd<N, N, N>(rJ, T);                                  // W = Lg^-1 U^T
-  mm<N, N, N, N, true, false>(T, T, (const R*)nullptr, R(1), cC);        // M = W^T W
-  mv<N, N, N, false>(cC, v1, (const R*)nullptr, R(1), v2);               // u = M v
-  for (int i = lane(); i < N; i += kWave) v1[i] = cb[i] + v2[i];
-  wsync();
-  mv<N, N, N, false>(rA, v1, rb, R(1), cb);
-  mm<N, N, N, N, false, false>(rA, cC, (const R*)nullptr, R(1), T);      // A M
-  ld_symm<N, N>(gC, rJ);                                // C
-  wsync();
-  mm<N, N, N, N, false, true>(T, rA, rJ, R(1), cC);     // A M A^T + C
-  symmetrize<N, N>(cC);
-  if (!(cb[0] == cb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rJ, (R*)nullptr, cb, cC);
-}
-
-// l <- l (x) r as combine_f, in two scratch matrices instead of three: l's C
-// holds its Cholesky factor and then M, rC holds G, its factor and Y, rJ holds
-// A_j M, and C_j is read back from gC (the right element's record in global
-// memory, written before the call; symmetric packed) when the result's C is
-// formed.  rJ and rC are destroyed (rC ends holding C_j again).  The same
-// operations on the same values as combine_f, so the same results bit for bit.
-template <int N, typename R, typename RG>
-PKS_DEV void combine_f_lean(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, const R* rb, R* rC, const R* re,
-                            R* rJ, const RG* gC, R* T, R* v1, R* v2, int* ok) {
-  mv<N, N, N, false>(rJ, lb, re, R(-1), v1);            // v = eta_j - J b_i
-  chol<N, N>(lC, ok);                                   // U
-  mm<N, N, N, N, false, false>(rJ, lC, (const R*)nullptr, R(1), T);      // J U
-  mm<N, N, N, N, true, false>(lC, T, (const R*)nullptr, R(1), rC);       // U^T J U
-  for (int i = lane(); i < N; i += kWave) rC[i * ld<N>() + i] += R(1);  // G
-  wsync();
-  chol<N, N>(rC, ok);                                   // Lg
-  copy<N, N, N, true>(lC, T);                           // U^T
-  fwd<N, N, N>(rC, T);                                  // W = Lg^-1 U^T
-  mm<N, N, N, N, true, false>(T, T, (const R*)nullptr, R(1), lC);        // M = W^T W
-  mm<N, N, N, N, false, false>(rJ, lA, (const R*)nullptr, R(1), rC);     // Y = J A_i
-  mm<N, N, N, N, false, false>(lC, rC, (const R*)nullptr, R(1), T);      // Z = M Y
-  mv<N, N, N, false>(lC, v1, (const R*)nullptr, R(1), v2);               // u = M v
-  mm<N, N, N, N, true, false>(lA, rC, lJ, R(1), lJ);
-  mm<N, N, N, N, true, false>(rC, T, lJ, R(-1), lJ);
-  mv<N, N, N, true>(lA, v1, le, R(1), le);
-  mv<N, N, N, true>(rC, v2, le, R(-1), le);
-  symmetrize<N, N>(lJ);
-  for (int i = lane(); i < N; i += kWave) v1[i] = lb[i] + v2[i];
-  wsync();
-  mv<N, N, N, false>(rA, v1, rb, R(1), lb);
   mm<N, N, N, N, false, false>(rA, lC, (const R*)nullptr, R(1), rJ);     // A_j M
-  ld_symm<N, N>(gC, rC);                                // C_j
-  wsync();
+  const R* rC = getC(S);
   mm<N, N, N, N, false, true>(rJ, rA, rC, R(1), lC);
   symmetrize<N, N>(lC);
+  // A_ij = A_j (A_i - Z)
   for (int e = lane(); e < N * N; e += kWave) {
     const int i = e / N, j = e - i * N;
     T[i * ld<N>() + j] = lA[i * ld<N>() + j] - T[i * ld<N>() + j];
@@ -548,6 +449,77 @@ PKS_DEV void combine_f_lean(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, cons
   wsync();
   mm<N, N, N, N, false, false>(rA, T, (const R*)nullptr, R(1), lA);
   if (!(lb[0] == lb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, lA, lb, lC);
+}
+
+// All operands in LDS; S and T scratch, rJ destroyed.  The routine-cycle probe
+// times this form.
+template <int N, typename R>
+PKS_DEV void combine_f(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, const R* rb, const R* rC, const R* re, R* rJ,
+                       R* S, R* T, R* v1, R* v2, int* ok) {
+  combine_f_impl<N, R>(lA, lb, lC, le, lJ, rA, rb, re, rJ, S, T, v1, v2, ok, [&](R*) { return rC; });
+}
+
+// The kernels' form: C_j stays in the right element's record in global memory
+// (gC, symmetric packed, written before the call) and is read into rC, which
+// serves as S until then; the right element takes two LDS matrices (rA, rJ)
+// plus rC, and the call one scratch matrix T.
+template <int N, typename R, typename RG>
+PKS_DEV void combine_f_lean(R* lA, R* lb, R* lC, R* le, R* lJ, const R* rA, const R* rb, R* rC, const R* re,
+                            R* rJ, const RG* gC, R* T, R* v1, R* v2, int* ok) {
+  combine_f_impl<N, R>(lA, lb, lC, le, lJ, rA, rb, re, rJ, rC, T, v1, v2, ok, [&](R* buf) {
+    ld_symm<N, N>(gC, buf);
+    wsync();
+    return static_cast<const R*>(buf);
+  });
+}
+
+// Carry (b, C) (x) r: the filtered mean and covariance after element r.  The
+// carry's covariance holds its Cholesky factor and then M while the result is
+// formed, rJ holds G and its factor (rJ is destroyed), T is scratch.  The
+// element's C enters only the last step: getC(rJ) returns it as an LDS
+// operand (it may read it into rJ, free by then).
+template <int N, typename R, class GetC>
+PKS_DEV void apply_f_impl(R* cb, R* cC, const R* rA, const R* rb, const R* re, R* rJ, R* T, R* v1, R* v2, int* ok,
+                          GetC getC) {
+  mv<N, N, N, false>(rJ, cb, re, R(-1), v1);            // v = eta - J b, before rJ is reused
+  chol<N, N>(cC, ok);                                   // U
+  mm<N, N, N, N, false, false>(rJ, cC, (const R*)nullptr, R(1), T);      // J U
+  mm<N, N, N, N, true, false>(cC, T, (const R*)nullptr, R(1), rJ);       // U^T J U
+  for (int i = lane(); i < N; i += kWave) rJ[i * ld<N>() + i] += R(1);  // G
+  wsync();
+  chol<N, N>(rJ, ok);                                   // Lg
+  copy<N, N, N, true>(cC, T);                           // U^T
+  fwd<N, N, N>(rJ, T);                                  // W = Lg^-1 U^T
+  mm<N, N, N, N, true, false>(T, T, (const R*)nullptr, R(1), cC);        // M = W^T W
+  mv<N, N, N, false>(cC, v1, (const R*)nullptr, R(1), v2);               // u = M v
+  for (int i = lane(); i < N; i += kWave) v1[i] = cb[i] + v2[i];
+  wsync();
+  mv<N, N, N, false>(rA, v1, rb, R(1), cb);
+  mm<N, N, N, N, false, false>(rA, cC, (const R*)nullptr, R(1), T);      // A M
+  const R* rC = getC(rJ);
+  mm<N, N, N, N, false, true>(T, rA, rC, R(1), cC);     // A M A^T + C
+  symmetrize<N, N>(cC);
+  if (!(cb[0] == cb[0]) && all_zero<N>(rA)) take_restart<N>(rA, rb, rC, (R*)nullptr, cb, cC);
+}
+
+// All operands in LDS; one scratch matrix T, rJ destroyed.
+template <int N, typename R>
+PKS_DEV void apply_f(R* cb, R* cC, const R* rA, const R* rb, const R* rC, const R* re, R* rJ, R* T, R* v1, R* v2,
+                     int* ok) {
+  apply_f_impl<N, R>(cb, cC, rA, rb, re, rJ, T, v1, v2, ok, [&](R*) { return rC; });
+}
+
+// The element's C stays in its record in global memory (gC, symmetric packed)
+// and is read into rJ's buffer for the last step: the element takes two LDS
+// matrices (rA, rJ).
+template <int N, typename R, typename RG>
+PKS_DEV void apply_f_lean(R* cb, R* cC, const R* rA, const R* rb, const RG* gC, const R* re, R* rJ, R* T, R* v1,
+                          R* v2, int* ok) {
+  apply_f_impl<N, R>(cb, cC, rA, rb, re, rJ, T, v1, v2, ok, [&](R* buf) {
+    ld_symm<N, N>(gC, buf);
+    wsync();
+    return static_cast<const R*>(buf);
+  });
 }
 
 // --- the smoothing operator (eq. 19) ------------------------------------------

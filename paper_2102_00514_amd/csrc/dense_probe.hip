@@ -109,8 +109,9 @@ __global__ __launch_bounds__(64) void k_phases(unsigned long long* out, int reps
     PHASE(5, (pks::dn::fwd<N, N, N>(T1, T2)))
     PHASE(6, (pks::dn::mv<N, N, N, false>(rJ, w.v[0], w.v[1], -1.0, w.v[4])))
     PHASE(7, (pks::dn::symmetrize<N, N>(lJ)))
-    PHASE(8, (pks::dn::combine_f<N, double>(lA, w.v[0], lC, w.v[1], lJ, rA, w.v[2], rC, w.v[3], rJ, T1, T2, T3,
-                                             w.v[4], w.v[5], &w.ok)))
+    pks::dn::copy<N, N, N, false>(rJ, T3);   // the combine destroys its J operand
+    PHASE(8, (pks::dn::combine_f<N, double>(lA, w.v[0], lC, w.v[1], lJ, rA, w.v[2], rC, w.v[3], T3, T1, T2, w.v[4],
+                                             w.v[5], &w.ok)))
     pks::dn::copy<N, N, N, false>(rJ, T3);   // apply_f destroys its J operand
     spd(lC, 2.0, 0.3);
     __syncthreads();
